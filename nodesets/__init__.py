@@ -1,0 +1,371 @@
+"""Seeded, synthetic node sets and geometries for the meshless LBM workloads.
+
+This module is the only code shared by the CPU oracle and the GPU library
+tests: it produces *inputs* (node coordinates, node kinds, obstacle lists,
+boundary values, smooth initial fields and noise), and it holds none of the
+method's arithmetic (no equilibria, no collision, no interpolation weights).
+
+The paper's own point clouds (the hybrid Karman set of Sec. 3.1 and the
+porous sample of Sec. 3.2) were never published, so every workload here is a
+synthetic stand-in with the same structure: scattered nodes, local refinement
+near obstacles, boundary nodes placed exactly on no-slip surfaces (Sec. 3.2),
+periodic boxes, and straight Dirichlet boundaries (Sec. 3.1).
+
+Node kinds: 0 = fluid, 1 = node lying on a no-slip surface, 2 = Dirichlet
+node whose populations are overwritten by an equilibrium (Sec. 3.1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+FLUID, WALL, DIRICHLET = 0, 1, 2
+
+
+@dataclasses.dataclass
+class NodeSet:
+    """A scattered node set with its geometry description (all float64)."""
+
+    xy: np.ndarray            # (n, 2) node coordinates
+    kind: np.ndarray          # (n,) uint8 node kind
+    lo: np.ndarray            # (2,) box lower corner
+    hi: np.ndarray            # (2,) box upper corner
+    periodic: tuple           # (bool, bool) periodic along x / y
+    walls_y: tuple = (False, False)   # no-slip straight walls at y=lo[1] / y=hi[1]
+    disks: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3)))
+    bc: np.ndarray | None = None      # (n, 3) (rho_b, ux_b, uy_b), used on kind-2 nodes
+    h: float = 0.0            # reference (bulk) node spacing
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.xy.shape[0])
+
+    def fluid_area(self) -> float:
+        """Analytic area of the fluid region: box minus the obstacle disks."""
+        box = float(np.prod(self.hi - self.lo))
+        return box - float(np.sum(np.pi * self.disks[:, 2] ** 2)) if len(self.disks) else box
+
+    def boundary_values(self) -> np.ndarray:
+        if self.bc is None:
+            bc = np.zeros((self.n, 3))
+            bc[:, 0] = 1.0
+            return bc
+        return self.bc
+
+
+def _grid(lo, hi, h, cell_centred=True):
+    """Points of a square grid of spacing h covering [lo, hi)."""
+    nx = max(1, int(round((hi[0] - lo[0]) / h)))
+    ny = max(1, int(round((hi[1] - lo[1]) / h)))
+    off = 0.5 if cell_centred else 0.0
+    gx = lo[0] + (np.arange(nx) + off) * (hi[0] - lo[0]) / nx
+    gy = lo[1] + (np.arange(ny) + off) * (hi[1] - lo[1]) / ny
+    X, Y = np.meshgrid(gx, gy, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+def _wrap(xy, lo, hi, periodic):
+    out = xy.copy()
+    for d in range(2):
+        if periodic[d]:
+            L = hi[d] - lo[d]
+            out[:, d] = lo[d] + np.mod(out[:, d] - lo[d], L)
+    return out
+
+
+def _in_box(xy, L):
+    """Map coordinates into [0, L) for periodic KD-tree queries."""
+    out = np.mod(xy, L)
+    out[out >= L] = 0.0
+    return out
+
+
+def _min_image(d, L, periodic):
+    d = d.copy()
+    for a in range(2):
+        if periodic[a]:
+            d[..., a] -= L[a] * np.round(d[..., a] / L[a])
+    return d
+
+
+# --------------------------------------------------------------------------
+# Regular and jittered periodic grids
+# --------------------------------------------------------------------------
+
+def regular_grid(n: int, L: float = 1.0) -> NodeSet:
+    """Cell-centred n x n grid on the periodic box [0, L)^2, ordered row-major
+    (node id = iy * n + ix).  With the streaming distance equal to the spacing
+    this is the standard lattice of Sec. 2.1."""
+    lo, hi = np.zeros(2), np.full(2, L)
+    xy = _grid(lo, hi, L / n)
+    return NodeSet(xy=xy, kind=np.zeros(len(xy), np.uint8), lo=lo, hi=hi,
+                   periodic=(True, True), h=L / n, name=f"regular{n}")
+
+
+def jittered_grid(n: int, jitter: float = 0.3, seed: int = 231214789, L: float = 1.0) -> NodeSet:
+    """Cell-centred n x n grid on the periodic box [0, L)^2 with every coordinate
+    moved by an independent uniform offset in [-jitter*h, jitter*h], then
+    wrapped into the box."""
+    ns = regular_grid(n, L)
+    rng = np.random.default_rng(seed)
+    h = L / n
+    xy = ns.xy + rng.uniform(-jitter * h, jitter * h, size=ns.xy.shape)
+    ns.xy = _wrap(xy, ns.lo, ns.hi, ns.periodic)
+    ns.name = f"jittered{n}"
+    return ns
+
+
+def channel(nx: int, ny: int, jitter: float = 0.0, seed: int = 231214789,
+            Lx: float = 1.0, H: float = 1.0) -> NodeSet:
+    """Plane channel [0, Lx) x [0, H], periodic along x, no-slip walls at y=0
+    and y=H with nodes placed exactly on the walls (the arrangement of
+    Sec. 3.2).  Interior rows sit at y = j*H/(ny-1), j = 1..ny-2; interior
+    nodes are optionally jittered."""
+    lo, hi = np.zeros(2), np.array([Lx, H])
+    hx = Lx / nx
+    gx = (np.arange(nx) + 0.5) * hx
+    gy = np.arange(ny) * H / (ny - 1)
+    X, Y = np.meshgrid(gx, gy, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    kind = np.zeros(len(xy), np.uint8)
+    on_wall = (np.isclose(xy[:, 1], 0.0)) | (np.isclose(xy[:, 1], H))
+    kind[on_wall] = WALL
+    if jitter > 0:
+        rng = np.random.default_rng(seed)
+        hy = H / (ny - 1)
+        dj = rng.uniform(-jitter, jitter, size=xy.shape) * np.array([hx, hy])
+        dj[on_wall, 1] = 0.0
+        xy = xy + dj
+        xy = _wrap(xy, lo, hi, (True, False))
+    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(True, False),
+                   walls_y=(True, True), h=H / (ny - 1), name=f"channel{nx}x{ny}")
+
+
+# --------------------------------------------------------------------------
+# Scattered node sets with refinement and obstacles
+# --------------------------------------------------------------------------
+
+def _cleanup(xy, hloc, fixed, lo, hi, periodic, frac=0.45):
+    """Remove non-fixed nodes that sit closer than frac*max(h_i, h_j) to another
+    node (a blue-noise clean-up of the seams between jittered patches).
+    Among a conflicting pair the non-fixed node with the larger index goes."""
+    from scipy.spatial import cKDTree
+
+    L = hi - lo
+    box = [L[0] if periodic[0] else 0, L[1] if periodic[1] else 0]
+    keep = np.ones(len(xy), bool)
+    for _ in range(4):
+        pts = xy[keep]
+        ids = np.nonzero(keep)[0]
+        if any(box):
+            # cKDTree supports periodic boxes only with all positive sizes.
+            bs = np.array([b if b else 1e30 for b in box])
+            q = pts - lo
+            for a in range(2):
+                if box[a]:
+                    q[:, a] = _in_box(q[:, a], box[a])
+            tree = cKDTree(q, boxsize=bs)
+            pairs = tree.query_pairs(r=frac * hloc.max(), output_type="ndarray")
+            dvec = _min_image(pts[pairs[:, 0]] - pts[pairs[:, 1]], L, periodic)
+        else:
+            tree = cKDTree(pts)
+            pairs = tree.query_pairs(r=frac * hloc.max(), output_type="ndarray")
+            dvec = pts[pairs[:, 0]] - pts[pairs[:, 1]]
+        if len(pairs) == 0:
+            break
+        a, b = ids[pairs[:, 0]], ids[pairs[:, 1]]
+        dist = np.hypot(dvec[:, 0], dvec[:, 1])
+        bad = dist < frac * np.maximum(hloc[a], hloc[b])
+        a, b = a[bad], b[bad]
+        if len(a) == 0:
+            break
+        drop = np.where(fixed[b], a, np.where(fixed[a], b, np.maximum(a, b)))
+        drop = drop[~fixed[drop]]
+        if len(drop) == 0:
+            break
+        keep[drop] = False
+    return keep
+
+
+def _circle_nodes(cx, cy, r, h):
+    m = max(8, int(round(2 * np.pi * r / h)))
+    t = 2 * np.pi * np.arange(m) / m
+    return np.stack([cx + r * np.cos(t), cy + r * np.sin(t)], axis=1)
+
+
+def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
+           u_max: float = 0.05, jitter: float = 0.35) -> NodeSet:
+    """Channel 22D x 4.1D with a cylinder of diameter D centred at (2D, 2D).
+
+    Scattered nodes: stratified (jittered) samples at spacing h_b in the bulk
+    and h_f = h_b / 2 (4x the node density) within 1D of the cylinder surface,
+    cleaned of close pairs; nodes exactly on the cylinder surface (spacing h_f,
+    no-slip); Dirichlet nodes on the four straight boundaries (spacing h_b):
+    parabolic inflow/outflow profile with maximum u_max on x=0 and x=22D,
+    zero velocity on y=0 and y=4.1D, unit density (the boundary treatment of
+    Sec. 3.1).  h_b is chosen so that the set holds about n_target nodes."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly = 22.0 * D, 4.1 * D
+    cx, cy, r = 2.0 * D, 2.0 * D, 0.5 * D
+    ring = 1.0 * D
+    a_fine = np.pi * ((r + ring) ** 2 - r ** 2)
+    a_bulk = Lx * Ly - np.pi * (r + ring) ** 2
+    hb = math.sqrt((a_bulk + 4.0 * a_fine) / n_target)
+    hf = 0.5 * hb
+    lo, hi = np.zeros(2), np.array([Lx, Ly])
+
+    # Bulk: jittered grid away from the boundaries.
+    bulk = _grid(lo, hi, hb)
+    bulk = bulk + rng.uniform(-jitter * hb, jitter * hb, size=bulk.shape)
+    rb = np.hypot(bulk[:, 0] - cx, bulk[:, 1] - cy)
+    inside = (bulk[:, 0] > 0.5 * hb) & (bulk[:, 0] < Lx - 0.5 * hb) & \
+             (bulk[:, 1] > 0.5 * hb) & (bulk[:, 1] < Ly - 0.5 * hb)
+    bulk = bulk[inside & (rb > r + ring)]
+    # Fine ring around the cylinder.
+    flo = np.array([cx - r - ring, cy - r - ring])
+    fhi = np.array([cx + r + ring, cy + r + ring])
+    fine = _grid(flo, fhi, hf)
+    fine = fine + rng.uniform(-jitter * hf, jitter * hf, size=fine.shape)
+    rf = np.hypot(fine[:, 0] - cx, fine[:, 1] - cy)
+    fine = fine[(rf > r + 0.5 * hf) & (rf <= r + ring)]
+    # Surface nodes.
+    surf = _circle_nodes(cx, cy, r, hf)
+    # Straight-boundary Dirichlet nodes (corners once).
+    nbx = int(round(Lx / hb))
+    nby = int(round(Ly / hb))
+    xs = np.linspace(0.0, Lx, nbx + 1)
+    ys = np.linspace(0.0, Ly, nby + 1)[1:-1]
+    bnd = np.concatenate([
+        np.stack([xs, np.zeros_like(xs)], 1), np.stack([xs, np.full_like(xs, Ly)], 1),
+        np.stack([np.zeros_like(ys), ys], 1), np.stack([np.full_like(ys, Lx), ys], 1)])
+
+    xy = np.concatenate([bulk, fine, surf, bnd])
+    kind = np.concatenate([np.zeros(len(bulk) + len(fine), np.uint8),
+                           np.full(len(surf), WALL, np.uint8),
+                           np.full(len(bnd), DIRICHLET, np.uint8)])
+    hloc = np.concatenate([np.full(len(bulk), hb), np.full(len(fine), hf),
+                           np.full(len(surf), hf), np.full(len(bnd), hb)])
+    keep = _cleanup(xy, hloc, kind != FLUID, lo, hi, (False, False))
+    xy, kind = xy[keep], kind[keep]
+    bc = np.zeros((len(xy), 3))
+    bc[:, 0] = 1.0
+    d = kind == DIRICHLET
+    inout = d & ((np.isclose(xy[:, 0], 0.0)) | (np.isclose(xy[:, 0], Lx)))
+    y = xy[:, 1]
+    bc[inout, 1] = 4.0 * u_max * y[inout] * (Ly - y[inout]) / Ly ** 2
+    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(False, False),
+                   disks=np.array([[cx, cy, r]]), bc=bc, h=hb, name="karman")
+
+
+def random_disks(phi_target: float, r_min: float, r_max: float, gap: float,
+                 rng, L: float = 1.0, max_tries: int = 200_000) -> np.ndarray:
+    """Random sequential addition of non-overlapping disks in the periodic box
+    [0, L)^2: radii uniform in [r_min, r_max], centres uniform, a candidate is
+    rejected if it comes closer than `gap` to a placed disk (periodic images
+    included).  Stops once the solid fraction reaches 1 - phi_target."""
+    disks = []
+    solid = 0.0
+    target = (1.0 - phi_target) * L * L
+    tries = 0
+    while solid < target and tries < max_tries:
+        tries += 1
+        rr = rng.uniform(r_min, r_max)
+        c = rng.uniform(0.0, L, size=2)
+        ok = True
+        if disks:
+            D = np.asarray(disks)
+            d = D[:, :2] - c
+            d -= L * np.round(d / L)
+            ok = bool(np.all(np.hypot(d[:, 0], d[:, 1]) >= D[:, 2] + rr + gap))
+        if ok:
+            disks.append((c[0], c[1], rr))
+            solid += np.pi * rr * rr
+    return np.asarray(disks, dtype=np.float64).reshape(-1, 3)
+
+
+def porous(n_target: int = 1_000_000, phi: float = 0.7, seed: int = 231214789,
+           r_range=(0.01, 0.03), jitter: float = 0.25, L: float = 1.0,
+           disks: np.ndarray | None = None) -> NodeSet:
+    """Periodic box [0, L)^2 with random non-overlapping disks (porosity phi),
+    fluid nodes on a jittered grid of spacing h ~ sqrt(phi L^2 / n_target), and
+    nodes exactly on every disk surface (no-slip, Sec. 3.2).  Disks keep a gap
+    of at least 2h so every throat holds fluid nodes."""
+    rng = np.random.default_rng(seed)
+    h = math.sqrt(phi * L * L / n_target)
+    if disks is None:
+        disks = random_disks(phi, r_range[0], r_range[1], 2.0 * h, rng, L)
+    lo, hi = np.zeros(2), np.full(2, L)
+    pts = _grid(lo, hi, h)
+    pts = pts + rng.uniform(-jitter * h, jitter * h, size=pts.shape)
+    pts = _wrap(pts, lo, hi, (True, True))
+    # drop grid points inside a disk or closer than h/2 to its surface (periodic)
+    from scipy.spatial import cKDTree
+
+    keep = np.ones(len(pts), bool)
+    if len(disks):
+        tree = cKDTree(_in_box(pts, L), boxsize=L)
+        for lst in tree.query_ball_point(_in_box(disks[:, :2], L), r=disks[:, 2] + 0.5 * h):
+            keep[lst] = False
+    fluid = pts[keep]
+    surf = [_circle_nodes(c[0], c[1], c[2], h) for c in disks]
+    surf = _wrap(np.concatenate(surf), lo, hi, (True, True)) if surf else np.zeros((0, 2))
+    xy = np.concatenate([fluid, surf])
+    kind = np.concatenate([np.zeros(len(fluid), np.uint8), np.full(len(surf), WALL, np.uint8)])
+    hloc = np.full(len(xy), h)
+    keep2 = _cleanup(xy, hloc, kind != FLUID, lo, hi, (True, True), frac=0.35)
+    xy, kind = xy[keep2], kind[keep2]
+    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(True, True),
+                   disks=disks, h=h, name="porous")
+
+
+def porous_batch(n_samples: int = 64, seed: int = 231214789, n_range=(50_000, 400_000),
+                 phi_range=(0.55, 0.85)) -> list:
+    """n_samples porous media with node counts and porosities drawn uniformly
+    from the given ranges (sample s uses seed + s)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=n_samples)
+    phis = rng.uniform(phi_range[0], phi_range[1], size=n_samples)
+    return [porous(int(ns[s]), float(phis[s]), seed=seed + 1 + s) for s in range(n_samples)]
+
+
+# --------------------------------------------------------------------------
+# Fields and masks
+# --------------------------------------------------------------------------
+
+def raster_mask(disks: np.ndarray, res: int = 256, L: float = 1.0) -> np.ndarray:
+    """Solid mask (1 = solid) of periodic disks at pixel centres of a res^2 raster."""
+    c = (np.arange(res) + 0.5) * L / res
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    m = np.zeros((res, res), np.float32)
+    for cx, cy, r in disks:
+        dx = X - cx
+        dy = Y - cy
+        dx -= L * np.round(dx / L)
+        dy -= L * np.round(dy / L)
+        m[(dx * dx + dy * dy) < r * r] = 1.0
+    return m
+
+
+def smooth_fields(xy: np.ndarray, seed: int, amp_u: float = 0.01, amp_rho: float = 1e-3,
+                  L: float = 1.0, modes: int = 3):
+    """Smooth periodic random fields (rho, ux, uy) at the given points: sums of a
+    few low Fourier modes with seeded amplitudes and phases."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for amp, base in ((amp_rho, 1.0), (amp_u, 0.0), (amp_u, 0.0)):
+        f = np.full(len(xy), base)
+        for _ in range(modes):
+            kx, ky = rng.integers(1, 4, size=2)
+            ph = rng.uniform(0, 2 * np.pi)
+            a = rng.uniform(0.3, 1.0) * amp / modes
+            f = f + a * np.sin(2 * np.pi * (kx * xy[:, 0] + ky * xy[:, 1]) / L + ph)
+        out.append(f)
+    return out[0], np.stack([out[1], out[2]], axis=1)
+
+
+def noise(shape, seed: int, amp: float) -> np.ndarray:
+    """Seeded uniform noise in [-amp, amp]."""
+    return np.random.default_rng(seed).uniform(-amp, amp, size=shape)
