@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput of the fused meshless LBM step on one MI355X.
+
+Workload (default): the Karman street channel, 22D x 4.1D with a cylinder of
+diameter D at (2D, 2D), ~4.9e5 scattered nodes with 4x the density within 1D
+of the cylinder, K = 16 nearest-node stencils, streaming-distance scale s = 1
+(Re = 100 from a parabolic inflow u_max = 0.05), BGK, FP32 populations.  A
+"step" is one time step over every node: the fused gather + collision kernel.
+
+Prints one JSON line: MNUPS (10^6 node updates per second), the HBM roofline
+fraction of the step kernel from its algorithmic bytes, and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MNUPS and HBM fraction of fused step; time-to-steady-state plain vs warm-start"
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2312_14789_amd", "csrc", "mlbm_step.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    ent = rec.get(f"{kernel}|{workload}")
+    if not ent or ent.get("source_digest") != kernel_source_digest():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(ns_perm, b, tau, budget_s=15.0):
+    """The oracle's population step (collide all nodes, then stream all nodes)
+    on the full node set, timed on the host; stencil arrays in the oracle's
+    format are taken from the library builder (the oracle's own builder is not
+    part of the step)."""
+    import numpy as np
+
+    from oracle import mlbm as omlbm
+
+    n, K = b["idx"].shape
+    src = np.where((b["bb"][:, None] >> np.arange(8)[None, :]) & 1,
+                   np.array([3, 4, 1, 2, 7, 8, 5, 6])[None, :], np.arange(1, 9)[None, :])
+    st = omlbm.Stencils(idx=b["idx"].astype(np.int64), w=b["w"], src=src, point=None, area=b["area"])
+    f = omlbm.init_populations(np.ones(n), np.zeros((n, 2)))
+    t0 = time.perf_counter()
+    f = omlbm.step(f, ns_perm, st, tau, tau)
+    one = time.perf_counter() - t0
+    steps = max(1, int(budget_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = omlbm.step(f, ns_perm, st, tau, tau)
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt / 1e6, "unit": "MNUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} oracle FP64 steps on all {n} nodes of the same workload "
+                      f"({dt:.1f} s, numpy single thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--s", type=float, default=1.0, help="streaming-distance scale (dx = h/s)")
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16"])
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--xcd", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "halo-exchange design is described but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import nodesets
+    from paper_2312_14789_amd import mlbm as M
+    from paper_2312_14789_amd import units
+
+    storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]
+    t0 = time.time()
+    ns = nodesets.karman()
+    dx = units.delta_x(ns.h, args.s)
+    re = 100.0 * args.s
+    tau = units.tau_for_reynolds(0.05, 1.0, dx, re)
+    K = 16
+    b = M.build_stencils_for(ns, K, dx)
+    perm = b["perm"]
+    print(f"# built {ns.n} nodes, K={K}, dx={dx:.4g}, tau={tau:.4f} in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
+                       storage=storage, tau_plus=tau, tau_minus=tau, bc=ns.boundary_values()[perm],
+                       block=args.block, xcd_remap=args.xcd, scale_exp=12)
+    n = ns.n
+    sim.init_state(np.ones(n), np.zeros((n, 2)))
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    per_launch_s = ms / 1e3 / args.steps
+    _, _, red = sim.macroscopic(dx, want_fields=False)
+    red = red.cpu().numpy()
+    if red[M._lib.RED_N_BAD] != 0:
+        print(f"# warning: {int(red[M._lib.RED_N_BAD])} unstable nodes", file=sys.stderr)
+    mnups = n * args.steps / (ms / 1e3) / 1e6
+    kp = sim.sizes.k_padded
+    bpn = units.algorithmic_bytes_per_node(M.POPULATIONS, storage, kp)
+    achieved = bpn * n / per_launch_s / 1e9
+    workload = f"karman-n{n}-K{K}-s{args.s:g}"
+    kernel = "k_step_pop"
+    traffic = measured_traffic(kernel, workload)
+    out = {
+        "metric": METRIC,
+        "value": round(mnups, 1),
+        "unit": "MNUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16s": "f16(scaled offsets)/f32", "bf16": "bf16/f32"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": "Karman street channel 22Dx4.1D, cylinder D at (2D,2D), "
+                               f"{n} scattered nodes (4x denser within 1D of the cylinder), "
+                               f"K={K}, s={args.s:g} (Re={re:g}), BGK tau={tau:.4f}, "
+                               f"{args.storage} populations",
+                   "nodes": n, "K": K, "s": args.s, "block": args.block, "xcd_remap": args.xcd,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": kernel, "bytes_per_node": bpn,
+                     "avg_launch_us": round(per_launch_s * 1e6, 2)},
+    }
+    if not args.no_cpu_baseline:
+        import copy
+
+        nsp = copy.copy(ns)
+        nsp.xy = ns.xy[perm]
+        nsp.kind = ns.kind[perm]
+        nsp.bc = ns.boundary_values()[perm]
+        out["cpu_baseline"] = cpu_baseline(nsp, b, tau)
+        out["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * mlbm.h - C ABI of the meshless lattice Boltzmann library (libmlbm.so).
+ *
+ * The library implements the time step of the meshless LBM of Strzelczyk &
+ * Matyka, "Modeling inertial flows with meshless Lattice Boltzmann Method"
+ * (arXiv 2312.14789) on one AMD Instinct MI355X (gfx950):
+ *
+ *   - population MLBM: collision (TRT, Sec. 2.1 Eqs. 3-5; BGK when
+ *     tau- = tau+) fused with the semi-Lagrangian streaming of Sec. 2.2
+ *     Eq. 12, in which every population arriving at node x is the weighted
+ *     sum of the post-collision population over the node's stencil, taken at
+ *     the departure point x - dx e_k;
+ *   - MLBM1, the fixed tau = 1 variant (Sec. 2.2, Eqs. 14-15): only density
+ *     and velocity are stored, interpolated to the departure points and
+ *     turned into the next fields through the equilibria;
+ *   - a constant body acceleration g with Guo's second-order forcing, no-slip
+ *     surfaces by (interpolated) bounce-back (Sec. 3.1, Sec. 3.2 Eq. 22) and
+ *     Dirichlet nodes overwritten by an equilibrium (Sec. 3.1).
+ *
+ * Conventions (all entry points):
+ *   - Every function returns MLBM_OK (0) or a negative MLBM_ERR_* code; the
+ *     message of the last failure on the calling thread is returned by
+ *     mlbm_last_error() and stays valid until the next call on that thread.
+ *   - Host pointers are read or written only during the call.  Device
+ *     pointers and the HIP stream are owned by the caller; device work is
+ *     enqueued on the given stream (NULL = the default stream), is
+ *     asynchronous, and the library never synchronises the device nor
+ *     allocates device memory.
+ *   - Node order in every array is the order chosen by mlbm_build_stencils
+ *     (perm[new] = old maps back to the caller's order).
+ *   - Nothing here is thread safe with respect to the same output buffers.
+ */
+#ifndef MLBM_H
+#define MLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define MLBM_OK               0
+#define MLBM_ERR_ARG         -1  /* null pointer, bad size, unsupported value  */
+#define MLBM_ERR_GEOMETRY    -2  /* node inside a solid, K > n, degenerate box */
+#define MLBM_ERR_SINGULAR    -3  /* a local interpolation system is singular   */
+#define MLBM_ERR_HIP         -4  /* a HIP launch or runtime call failed        */
+#define MLBM_ERR_UNSUPPORTED -5  /* variant x storage x K combination missing  */
+
+/* ---- node kinds (geometry) ------------------------------------------------ */
+#define MLBM_FLUID     0  /* ordinary fluid node                                */
+#define MLBM_WALL      1  /* node lying on a no-slip surface (Sec. 3.2)         */
+#define MLBM_DIRICHLET 2  /* populations overwritten by f^eq(rho_b, u_b) (Sec. 3.1) */
+
+/* ---- step variants and state storage -------------------------------------- */
+#define MLBM_POPULATIONS 0  /* population MLBM (Sec. 2.2, Eq. 12)               */
+#define MLBM_FIELDS      1  /* MLBM1, tau = 1, fields only (Sec. 2.2, Eqs. 14-15) */
+
+#define MLBM_F64  0  /* FP64 state, FP64 weights, FP64 arithmetic                 */
+#define MLBM_F32  1  /* FP32 state, FP32 weights, FP32 arithmetic                 */
+#define MLBM_F16S 2  /* FP16 state scaled by 2^scale_exp, FP32 weights/arithmetic */
+#define MLBM_BF16 3  /* BF16 state, FP32 weights and arithmetic                   */
+
+/* ---- geometry and stencil construction (host, FP64) ----------------------- */
+typedef struct mlbm_geometry {
+    int64_t n;               /* number of nodes                                   */
+    const double *xy;        /* host [n][2] node coordinates                      */
+    const uint8_t *kind;     /* host [n] MLBM_FLUID / MLBM_WALL / MLBM_DIRICHLET  */
+    double lo[2], hi[2];     /* box; nodes must lie in [lo, hi]                   */
+    int32_t periodic[2];     /* 1 = periodic along x / y (minimum-image offsets)  */
+    int32_t wall_lo_y;       /* 1 = no-slip wall on the line y = lo[1]            */
+    int32_t wall_hi_y;       /* 1 = no-slip wall on the line y = hi[1]            */
+    int64_t n_disks;         /* number of solid disks                             */
+    const double *disks;     /* host [n_disks][3] (cx, cy, r), periodic images used */
+    double fluid_area;       /* area the quadrature weights sum to (<= 0: box area
+                                minus the disk areas)                             */
+} mlbm_geometry;
+
+typedef struct mlbm_stencil_params {
+    int32_t K;               /* stencil size, 7 <= K <= 32 (nearest nodes, self included) */
+    int32_t reorder;         /* 0 keep the caller's order, 1 Morton (Z) order     */
+    double dx;               /* streaming distance dx > 0, units of xy             */
+    int32_t n_threads;       /* host threads; 0 = all hardware threads            */
+} mlbm_stencil_params;
+
+/* Caller-allocated host outputs of mlbm_build_stencils. */
+typedef struct mlbm_stencils {
+    int64_t *perm;           /* [n]       perm[new] = old                          */
+    int32_t *idx;            /* [n][K]    stencil members (new order), idx[i][0] = i */
+    double *w;               /* [n][8][K] weights of arriving populations k = 1..8 */
+    uint8_t *bb;             /* [n]       bit k-1 set: population k is rebuilt from
+                                          source population k' (bounce-back)      */
+    double *area;            /* [n]       quadrature weight of each node           */
+} mlbm_stencils;
+
+/*
+ * Builds, for every node x_i, the stencil of its K nearest nodes (ties broken
+ * by the offset vector x_j - x_i: dx, then dy; minimum image on periodic
+ * axes) and, for each k = 1..8, the interpolation weights of the cubic
+ * polyharmonic spline with quadratic polynomial augmentation (Sec. 2.2,
+ * Eq. 13) at the departure point x_i - dx e_k (Sec. 2.2, Eq. 12).  When that
+ * point lies inside a solid (a disk, or beyond a no-slip wall), the point
+ * x_i + dx e_k with source population k' is used instead (Sec. 3.2, Eq. 22);
+ * if both are inside, the node itself with source k' (simple bounce-back).
+ * The stencil is shared by the eight departure points of a node (each has
+ * its own weights).  Quadrature weights: squared mean distance to the four
+ * nearest other nodes, halved for MLBM_WALL / MLBM_DIRICHLET nodes, scaled to
+ * sum to geometry->fluid_area.
+ * Errors: MLBM_ERR_ARG (null pointers, K out of range, dx <= 0),
+ * MLBM_ERR_GEOMETRY (K > n, node inside a solid, empty box, node outside the
+ * box), MLBM_ERR_SINGULAR (a local system is singular or fails to reproduce
+ * quadratics to 1e-9; the message names the node and k).
+ */
+int mlbm_build_stencils(const mlbm_geometry *geometry, const mlbm_stencil_params *params,
+                        mlbm_stencils *out);
+
+/* ---- packed device layout ------------------------------------------------- */
+/*
+ * Kp = K rounded up to a multiple of 4 (padding members point at the node
+ * itself with weight 0).  Packed arrays (all little-endian, node index i fast):
+ *   idx    int32  [Kp/4][n][4]
+ *   w      F64 storage: double [8][Kp/2][n][2]; otherwise float [8][Kp/4][n][4]
+ *   flags  uint16 [n]: bits 0-7 = bb, bits 8-9 = kind
+ *   state  (MLBM_POPULATIONS) offsets f_k - omega_k of the post-collision
+ *          populations: T [n][8] for k = 1..8, then T [n] for k = 0;
+ *          (MLBM_FIELDS) T [n][4] = (rho - 1, u_x, u_y, 0);
+ *          T = double / float / half (x 2^scale_exp) / bfloat16 by storage.
+ */
+typedef struct mlbm_sizes {
+    int64_t idx_bytes, w_bytes, flags_bytes, state_bytes;
+    int32_t k_padded;
+} mlbm_sizes;
+
+int mlbm_packed_sizes(int64_t n, int32_t K, int32_t variant, int32_t storage, mlbm_sizes *out);
+
+/*
+ * Host-side packing of the builder's output into the device layout above
+ * (host buffers in and out, sized by mlbm_packed_sizes).  Weights are
+ * rounded to FP32 for every storage except MLBM_F64.
+ * Errors: MLBM_ERR_ARG.
+ */
+int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx, const double *w,
+                       const uint8_t *bb, const uint8_t *kind, void *idx_packed, void *w_packed,
+                       uint16_t *flags);
+
+/* ---- time stepping (device) ------------------------------------------------ */
+typedef struct mlbm_step_params {
+    int32_t variant;         /* MLBM_POPULATIONS or MLBM_FIELDS                    */
+    int32_t storage;         /* MLBM_F64 / MLBM_F32 / MLBM_F16S / MLBM_BF16         */
+    double tau_plus;         /* symmetric relaxation time (> 0.5); MLBM_FIELDS: 1 */
+    double tau_minus;        /* antisymmetric relaxation time; = tau_plus for BGK */
+    double g[2];             /* body acceleration, lattice units                   */
+    int32_t scale_exp;       /* MLBM_F16S: stored value = offset * 2^scale_exp     */
+    int32_t block;           /* threads per workgroup, multiple of 64 in [64, 1024];
+                                0 = 256                                             */
+    int32_t xcd_remap;       /* 1 = give each XCD a contiguous range of node tiles */
+} mlbm_step_params;
+
+typedef struct mlbm_device_state {
+    int64_t n;
+    int32_t K;               /* stencil size before padding                        */
+    const void *idx;         /* device, packed                                     */
+    const void *w;           /* device, packed                                     */
+    const uint16_t *flags;   /* device [n]                                         */
+    const double *bc;        /* device [n][3] (rho_b, ux_b, uy_b), read on Dirichlet
+                                nodes only; may be NULL if there are none          */
+    void *state[2];          /* device ping-pong state buffers (state_bytes each)  */
+    int32_t cur;             /* index (0/1) of the buffer holding the current state;
+                                mlbm_step updates it                                */
+} mlbm_device_state;
+
+/*
+ * Initial state from fields (device FP64 rho [n], u [n][2]): populations are
+ * the equilibrium of (rho, u), collided once (state = post-collision, so the
+ * first step starts with streaming) with Dirichlet nodes overwritten; MLBM1
+ * stores (rho - 1, u) and (rho_b - 1, u_b) on Dirichlet nodes.  Writes
+ * state[cur].  Errors: MLBM_ERR_ARG, MLBM_ERR_UNSUPPORTED, MLBM_ERR_HIP.
+ */
+int mlbm_init_state(const mlbm_step_params *params, mlbm_device_state *state, const double *rho,
+                    const double *u, void *hip_stream);
+
+/*
+ * Advances nsteps >= 0 time steps.  Each step reads state[cur], writes
+ * state[cur ^ 1] (never in place), then flips cur: for every node, stream
+ * (Sec. 2.2, Eq. 12; MLBM1: Eqs. 14-15) and collide (Sec. 2.1, Eq. 3) in one
+ * kernel pass.  Errors: MLBM_ERR_ARG, MLBM_ERR_UNSUPPORTED, MLBM_ERR_HIP.
+ */
+int mlbm_step(const mlbm_step_params *params, mlbm_device_state *state, int32_t nsteps,
+              void *hip_stream);
+
+/* ---- macroscopic fields and reductions (device) ------------------------------ */
+#define MLBM_RED_MASS      0   /* sum A rho                                         */
+#define MLBM_RED_INT_UX    1   /* sum A u_x   (Sec. 3.2, Eq. 23 without 1/phi)      */
+#define MLBM_RED_INT_UY    2   /* sum A u_y                                         */
+#define MLBM_RED_INT_SPEED 3   /* sum A |u|   (Sec. 3.2, Eq. 25 numerator)           */
+#define MLBM_RED_NORM_U2   4   /* sum |u|^2                                         */
+#define MLBM_RED_NORM_DU2  5   /* sum |u - u_prev|^2 (0 if u_prev is NULL)          */
+#define MLBM_RED_FORCE_X   6   /* momentum exchange on no-slip surfaces, lattice units */
+#define MLBM_RED_FORCE_Y   7
+#define MLBM_RED_N_BAD     8   /* number of nodes with non-finite fields or rho <= 0 */
+#define MLBM_RED_FIRST_BAD 9   /* smallest such node index, or n                    */
+#define MLBM_RED_COUNT     10
+
+/* Bytes of the device workspace mlbm_macroscopic needs for n nodes. */
+int64_t mlbm_reduction_workspace_bytes(int64_t n);
+
+/*
+ * Macroscopic fields of state[cur]: rho and u (populations: u = sum e f / rho
+ * - g/2, the half-force-shifted velocity of the pre-collision populations;
+ * Dirichlet nodes report (rho_b, u_b)), written as FP64 to rho_out [n] and
+ * u_out [n][2] when these are non-NULL.  If u_prev (device FP64 [n][2]) is
+ * non-NULL the squared change against it is accumulated and u is then copied
+ * into it.  Reductions over nodes with the quadrature weights area (device
+ * FP64 [n]) are summed in FP64 in a fixed order (bitwise reproducible) and
+ * written to red_out (device FP64 [MLBM_RED_COUNT]).  The force sums, over
+ * every bounced (node, k), e_k' (f_k'^post + f_k^new) A / dx^2.
+ * workspace: device, mlbm_reduction_workspace_bytes(n) bytes.
+ * Errors: MLBM_ERR_ARG, MLBM_ERR_UNSUPPORTED, MLBM_ERR_HIP.
+ */
+int mlbm_macroscopic(const mlbm_step_params *params, const mlbm_device_state *state,
+                     const double *area, double dx, double *rho_out, double *u_out, double *u_prev,
+                     void *workspace, double *red_out, void *hip_stream);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *mlbm_last_error(void);
+
+/* Library version string. */
+const char *mlbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLBM_H */

@@ -1,0 +1,108 @@
+"""ctypes declarations of the C ABI in include/mlbm.h (argument marshalling only).
+
+The shared library is loaded from the package directory; a missing library is
+an error (there is no fallback implementation).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlbm.so")
+
+MLBM_OK = 0
+MLBM_ERR_ARG = -1
+MLBM_ERR_GEOMETRY = -2
+MLBM_ERR_SINGULAR = -3
+MLBM_ERR_HIP = -4
+MLBM_ERR_UNSUPPORTED = -5
+
+FLUID, WALL, DIRICHLET = 0, 1, 2
+POPULATIONS, FIELDS = 0, 1
+F64, F32, F16S, BF16 = 0, 1, 2, 3
+
+RED_MASS, RED_INT_UX, RED_INT_UY, RED_INT_SPEED, RED_NORM_U2, RED_NORM_DU2 = range(6)
+RED_FORCE_X, RED_FORCE_Y, RED_N_BAD, RED_FIRST_BAD, RED_COUNT = 6, 7, 8, 9, 10
+
+_p = ctypes.c_void_p
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("xy", _p), ("kind", _p),
+                ("lo", ctypes.c_double * 2), ("hi", ctypes.c_double * 2),
+                ("periodic", ctypes.c_int32 * 2), ("wall_lo_y", ctypes.c_int32),
+                ("wall_hi_y", ctypes.c_int32), ("n_disks", ctypes.c_int64), ("disks", _p),
+                ("fluid_area", ctypes.c_double)]
+
+
+class StencilParams(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("reorder", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("n_threads", ctypes.c_int32)]
+
+
+class Stencils(ctypes.Structure):
+    _fields_ = [("perm", _p), ("idx", _p), ("w", _p), ("bb", _p), ("area", _p)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("idx_bytes", ctypes.c_int64), ("w_bytes", ctypes.c_int64),
+                ("flags_bytes", ctypes.c_int64), ("state_bytes", ctypes.c_int64),
+                ("k_padded", ctypes.c_int32)]
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("tau_plus", ctypes.c_double), ("tau_minus", ctypes.c_double),
+                ("g", ctypes.c_double * 2), ("scale_exp", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+
+class DeviceState(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("K", ctypes.c_int32), ("idx", _p), ("w", _p),
+                ("flags", _p), ("bc", _p), ("state", _p * 2), ("cur", ctypes.c_int32)]
+
+
+class MlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mlbm error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python paper_2312_14789_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    sig = {
+        "mlbm_build_stencils": (ctypes.c_int, [P(Geometry), P(StencilParams), P(Stencils)]),
+        "mlbm_packed_sizes": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, P(Sizes)]),
+        "mlbm_pack_stencils": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _p, _p,
+                                              _p, _p, _p, _p, _p]),
+        "mlbm_init_state": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, _p, _p]),
+        "mlbm_step": (ctypes.c_int, [P(StepParams), P(DeviceState), ctypes.c_int32, _p]),
+        "mlbm_reduction_workspace_bytes": (ctypes.c_int64, [ctypes.c_int64]),
+        "mlbm_macroscopic": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, ctypes.c_double, _p,
+                                            _p, _p, _p, _p, _p]),
+        "mlbm_last_error": (ctypes.c_char_p, []),
+        "mlbm_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+# every symbol the header declares (checked by the tests)
+EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_init_state",
+           "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
+           "mlbm_version"]
+
+
+def check(rc):
+    if rc != MLBM_OK:
+        raise MlbmError(rc, lib.mlbm_last_error().decode())
+    return rc

@@ -1,0 +1,803 @@
+// Fused meshless LBM step kernels for gfx950 (MI355X) and their C ABI entry
+// points: initial state, time step (population MLBM and MLBM1), macroscopic
+// fields with FP64 reductions.
+//
+// One thread owns one Eulerian node.  Per step it gathers the post-collision
+// state of its K stencil members (Sec. 2.2, Eq. 12), weights them with the
+// node's eight weight sets streamed from HBM (non-temporal, so the L2 keeps
+// the gathered state), then collides in registers (Sec. 2.1, Eqs. 3-4, Guo
+// forcing) and writes its post-collision state to the other buffer.  The
+// state holds offsets from the rest equilibrium (f_k - omega_k, or rho - 1),
+// so rounding in FP32 and 16-bit storage acts on O(u) quantities and the
+// small deviation of FP32 weights from a partition of unity does not act as
+// a mass source.  Node order is Morton order, so stencil members of a
+// wavefront are near each other in memory; with xcd_remap each XCD receives
+// a contiguous range of tiles and its L2 sees the spatial neighbourhood.
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "mlbm.h"
+#include "mlbm_internal.h"
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+// D2Q9 velocity set in the order of Sec. 2.1, Eq. 2.
+__device__ constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+// opposite of population k+1, minus one (populations 1..8 stored at 0..7)
+__device__ constexpr int OPP8[8] = {2, 3, 0, 1, 6, 7, 4, 5};
+
+template <class C>
+__device__ __forceinline__ C omega(int k) {
+    return k == 0 ? C(4) / C(9) : (k < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+// ---- storage formats -------------------------------------------------------
+
+__device__ __forceinline__ float half_to_float(unsigned short h) {
+    return __half2float(__ushort_as_half(h));
+}
+__device__ __forceinline__ unsigned short float_to_half(float f) {
+    return __half_as_ushort(__float2half_rn(f));
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short b) {
+    return __uint_as_float(((unsigned)b) << 16);
+}
+// round to nearest even (finite inputs; NaN stays NaN)
+__device__ __forceinline__ unsigned short float_to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+template <int S> struct Fmt;
+template <> struct Fmt<MLBM_F64> { using C = double; static constexpr int TB = 8; };
+template <> struct Fmt<MLBM_F32> { using C = float; static constexpr int TB = 4; };
+template <> struct Fmt<MLBM_F16S> { using C = float; static constexpr int TB = 2; };
+template <> struct Fmt<MLBM_BF16> { using C = float; static constexpr int TB = 2; };
+
+template <int S>
+__device__ __forceinline__ float dec16(unsigned short v, float inv_scale) {
+    if constexpr (S == MLBM_F16S) return half_to_float(v) * inv_scale;
+    else return bf16_to_float(v);
+}
+template <int S>
+__device__ __forceinline__ unsigned short enc16(float v, float scale) {
+    if constexpr (S == MLBM_F16S) return float_to_half(v * scale);
+    else return float_to_bf16(v);
+}
+
+// eight population offsets (k = 1..8) of node j
+template <int S, class C>
+__device__ __forceinline__ void load8(const void *base, int64_t j, C *o, float inv_scale) {
+    if constexpr (S == MLBM_F64) {
+        const d2 *p = (const d2 *)base + 4 * j;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            d2 v = p[t];
+            o[2 * t] = v.x;
+            o[2 * t + 1] = v.y;
+        }
+    } else if constexpr (S == MLBM_F32) {
+        const f4 *p = (const f4 *)base + 2 * j;
+        f4 a = p[0], b = p[1];
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+        o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+    } else {
+        u4 v = ((const u4 *)base)[j];
+        unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            o[2 * t] = dec16<S>((unsigned short)(w[t] & 0xffff), inv_scale);
+            o[2 * t + 1] = dec16<S>((unsigned short)(w[t] >> 16), inv_scale);
+        }
+    }
+}
+
+template <int S, class C>
+__device__ __forceinline__ void store8(void *base, int64_t j, const C *o, float scale) {
+    if constexpr (S == MLBM_F64) {
+        d2 *p = (d2 *)base + 4 * j;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) p[t] = d2{o[2 * t], o[2 * t + 1]};
+    } else if constexpr (S == MLBM_F32) {
+        f4 *p = (f4 *)base + 2 * j;
+        p[0] = f4{o[0], o[1], o[2], o[3]};
+        p[1] = f4{o[4], o[5], o[6], o[7]};
+    } else {
+        unsigned w[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            w[t] = (unsigned)enc16<S>((float)o[2 * t], scale) | ((unsigned)enc16<S>((float)o[2 * t + 1], scale) << 16);
+        ((u4 *)base)[j] = u4{w[0], w[1], w[2], w[3]};
+    }
+}
+
+// rest-population offset of node j, stored after the [n][8] block
+template <int S, class C>
+__device__ __forceinline__ C load1(const void *base, int64_t n, int64_t j, float inv_scale) {
+    if constexpr (S == MLBM_F64) return ((const double *)base)[8 * n + j];
+    else if constexpr (S == MLBM_F32) return ((const float *)base)[8 * n + j];
+    else return dec16<S>(((const unsigned short *)base)[8 * n + j], inv_scale);
+}
+template <int S, class C>
+__device__ __forceinline__ void store1(void *base, int64_t n, int64_t j, C v, float scale) {
+    if constexpr (S == MLBM_F64) ((double *)base)[8 * n + j] = v;
+    else if constexpr (S == MLBM_F32) ((float *)base)[8 * n + j] = v;
+    else ((unsigned short *)base)[8 * n + j] = enc16<S>((float)v, scale);
+}
+
+// fields (rho - 1, u_x, u_y) of node j
+template <int S, class C>
+__device__ __forceinline__ void load3(const void *base, int64_t j, C *o, float inv_scale) {
+    if constexpr (S == MLBM_F64) {
+        const d2 *p = (const d2 *)base + 2 * j;
+        d2 a = p[0], b = p[1];
+        o[0] = a.x; o[1] = a.y; o[2] = b.x;
+    } else if constexpr (S == MLBM_F32) {
+        f4 a = ((const f4 *)base)[j];
+        o[0] = a.x; o[1] = a.y; o[2] = a.z;
+    } else {
+        u2 v = ((const u2 *)base)[j];
+        o[0] = dec16<S>((unsigned short)(v.x & 0xffff), inv_scale);
+        o[1] = dec16<S>((unsigned short)(v.x >> 16), inv_scale);
+        o[2] = dec16<S>((unsigned short)(v.y & 0xffff), inv_scale);
+    }
+}
+template <int S, class C>
+__device__ __forceinline__ void store3(void *base, int64_t j, const C *o, float scale) {
+    if constexpr (S == MLBM_F64) {
+        d2 *p = (d2 *)base + 2 * j;
+        p[0] = d2{o[0], o[1]};
+        p[1] = d2{o[2], 0.0};
+    } else if constexpr (S == MLBM_F32) {
+        ((f4 *)base)[j] = f4{o[0], o[1], o[2], 0.0f};
+    } else {
+        unsigned a = (unsigned)enc16<S>((float)o[0], scale) | ((unsigned)enc16<S>((float)o[1], scale) << 16);
+        unsigned b = (unsigned)enc16<S>((float)o[2], scale);
+        ((u2 *)base)[j] = u2{a, b};
+    }
+}
+
+// four weights (stencil members 4q..4q+3) of arriving population k+1
+template <int S, int KQ, class C>
+__device__ __forceinline__ void load_w4(const void *w, int64_t n, int64_t i, int k, int q, C *o) {
+    if constexpr (S == MLBM_F64) {
+        const d2 *p = (const d2 *)w;
+        d2 a = __builtin_nontemporal_load(p + ((int64_t)(k * 2 * KQ + 2 * q) * n + i));
+        d2 b = __builtin_nontemporal_load(p + ((int64_t)(k * 2 * KQ + 2 * q + 1) * n + i));
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    } else {
+        const f4 *p = (const f4 *)w;
+        f4 a = __builtin_nontemporal_load(p + ((int64_t)(k * KQ + q) * n + i));
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    }
+}
+
+__device__ __forceinline__ i4 load_idx4(const int *idx, int64_t n, int64_t i, int q) {
+    return __builtin_nontemporal_load((const i4 *)idx + ((int64_t)q * n + i));
+}
+
+// ---- lattice arithmetic in offset form ---------------------------------------
+
+// equilibrium offset f^eq_k - omega_k of (rho, u) (Sec. 2.1, Eq. 7); sgn = -1
+// evaluates the opposite direction k'
+template <class C>
+__device__ __forceinline__ C feq_off(int k, C sgn, C drho, C rho, C ux, C uy) {
+    const C eu = sgn * (C(EX[k]) * ux + C(EY[k]) * uy);
+    const C usq = ux * ux + uy * uy;
+    return omega<C>(k) * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * usq));
+}
+
+// Guo force term F_k (k' for sgn = -1)
+template <class C>
+__device__ __forceinline__ C force_k(int k, C sgn, C rho, C ux, C uy, C gx, C gy) {
+    const C ex = sgn * C(EX[k]), ey = sgn * C(EY[k]);
+    const C eu = ex * ux + ey * uy;
+    const C eg = ex * gx + ey * gy;
+    const C ug = ux * gx + uy * gy;
+    return omega<C>(k) * rho * (C(3) * (eg - ug) + C(9) * eu * eg);
+}
+
+// TRT collision with Guo forcing on offsets f[0..8] (Sec. 2.1, Eqs. 3-4)
+template <class C>
+__device__ __forceinline__ void collide(C *f, C omp, C omm, C gx, C gy) {
+    const C drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const C rho = C(1) + drho;
+    const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const C jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const C inv = C(1) / rho;
+    const C ux = (jx + C(0.5) * rho * gx) * inv;
+    const C uy = (jy + C(0.5) * rho * gy) * inv;
+    const C cp = C(1) - C(0.5) * omp, cm = C(1) - C(0.5) * omm;
+    {
+        const C e0 = feq_off<C>(0, C(1), drho, rho, ux, uy);
+        const C F0 = force_k<C>(0, C(1), rho, ux, uy, gx, gy);
+        f[0] = f[0] - omp * (f[0] - e0) + cp * F0;
+    }
+    constexpr int A[4] = {1, 2, 5, 6};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int a = A[t], b = a + 2;  // b = opposite of a for these four
+        const C ea = feq_off<C>(a, C(1), drho, rho, ux, uy), eb = feq_off<C>(b, C(1), drho, rho, ux, uy);
+        const C Fa = force_k<C>(a, C(1), rho, ux, uy, gx, gy), Fb = force_k<C>(b, C(1), rho, ux, uy, gx, gy);
+        const C fp = C(0.5) * (f[a] + f[b]), fm = C(0.5) * (f[a] - f[b]);
+        const C ep = C(0.5) * (ea + eb), em = C(0.5) * (ea - eb);
+        const C Fp = C(0.5) * (Fa + Fb), Fm = C(0.5) * (Fa - Fb);
+        const C sym = -omp * (fp - ep) + cp * Fp;
+        const C asy = -omm * (fm - em) + cm * Fm;
+        f[a] = f[a] + sym + asy;
+        f[b] = f[b] + sym - asy;
+    }
+}
+
+struct StepArgs {
+    int64_t n;
+    const int *idx;
+    const void *w;
+    const uint16_t *flags;
+    const double *bc;
+    const void *in;
+    void *out;
+    double omp, omm, gx, gy;
+    float scale, inv_scale;
+    int64_t grid8;
+    int xcd;
+};
+
+__device__ __forceinline__ int64_t node_of(const StepArgs &a) {
+    int64_t b = blockIdx.x;
+    if (a.xcd) {
+        const int64_t per = a.grid8 >> 3;
+        b = (b & 7) * per + (b >> 3);
+    }
+    return b * (int64_t)blockDim.x + threadIdx.x;
+}
+
+// ---- population MLBM step ------------------------------------------------------
+
+template <int S, int KQ>
+__global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
+    using C = typename Fmt<S>::C;
+    const int64_t i = node_of(a);
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    const unsigned fl = a.flags[i];
+    const unsigned bb = fl & 0xffu;
+    C f[9];
+    if ((fl >> 8) == MLBM_DIRICHLET) {
+        const C rb = (C)a.bc[3 * i], ub = (C)a.bc[3 * i + 1], vb = (C)a.bc[3 * i + 2];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k] = feq_off<C>(k, C(1), rb - C(1), rb, ub, vb);
+    } else {
+        C acc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = C(0);
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const i4 id = load_idx4(a.idx, n, i, q);
+            C s[4][8];
+            load8<S>(a.in, id.x, s[0], a.inv_scale);
+            load8<S>(a.in, id.y, s[1], a.inv_scale);
+            load8<S>(a.in, id.z, s[2], a.inv_scale);
+            load8<S>(a.in, id.w, s[3], a.inv_scale);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                C wv[4];
+                load_w4<S, KQ>(a.w, n, i, k, q, wv);
+                const bool flip = (bb >> k) & 1u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const C v = flip ? s[j][OPP8[k]] : s[j][k];
+                    acc[k] = fma(wv[j], v, acc[k]);
+                }
+            }
+        }
+        f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) f[k + 1] = acc[k];
+        collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
+    }
+    store8<S>(a.out, i, f + 1, a.scale);
+    store1<S, C>(a.out, n, i, f[0], a.scale);
+}
+
+// ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
+
+template <int S, int KQ>
+__global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
+    using C = typename Fmt<S>::C;
+    const int64_t i = node_of(a);
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    const unsigned fl = a.flags[i];
+    const unsigned bb = fl & 0xffu;
+    C out[3];
+    if ((fl >> 8) == MLBM_DIRICHLET) {
+        out[0] = (C)a.bc[3 * i] - C(1);
+        out[1] = (C)a.bc[3 * i + 1];
+        out[2] = (C)a.bc[3 * i + 2];
+    } else {
+        C ar[8], au[8], av[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ar[k] = au[k] = av[k] = C(0);
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const i4 id = load_idx4(a.idx, n, i, q);
+            C m[4][3];
+            load3<S>(a.in, id.x, m[0], a.inv_scale);
+            load3<S>(a.in, id.y, m[1], a.inv_scale);
+            load3<S>(a.in, id.z, m[2], a.inv_scale);
+            load3<S>(a.in, id.w, m[3], a.inv_scale);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                C wv[4];
+                load_w4<S, KQ>(a.w, n, i, k, q, wv);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    ar[k] = fma(wv[j], m[j][0], ar[k]);
+                    au[k] = fma(wv[j], m[j][1], au[k]);
+                    av[k] = fma(wv[j], m[j][2], av[k]);
+                }
+            }
+        }
+        const C gx = (C)a.gx, gy = (C)a.gy;
+        C own[3];
+        load3<S>(a.in, i, own, a.inv_scale);
+        // rest population from the node's own fields (not interpolated, Sec. 2.2)
+        C sum = feq_off<C>(0, C(1), own[0], C(1) + own[0], own[1], own[2]) +
+                C(0.5) * force_k<C>(0, C(1), C(1) + own[0], own[1], own[2], gx, gy);
+        C jx = C(0), jy = C(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const C sg = ((bb >> k) & 1u) ? C(-1) : C(1);  // source k' on bounce-back
+            const C rho = C(1) + ar[k];
+            const C fk = feq_off<C>(k + 1, sg, ar[k], rho, au[k], av[k]) +
+                         C(0.5) * force_k<C>(k + 1, sg, rho, au[k], av[k], gx, gy);
+            sum += fk;
+            jx += C(EX[k + 1]) * fk;
+            jy += C(EY[k + 1]) * fk;
+        }
+        const C rho = C(1) + sum;
+        out[0] = sum;
+        out[1] = (jx + C(0.5) * rho * gx) / rho;
+        out[2] = (jy + C(0.5) * rho * gy) / rho;
+    }
+    store3<S>(a.out, i, out, a.scale);
+}
+
+// ---- initial state -----------------------------------------------------------------
+
+struct InitArgs {
+    int64_t n;
+    const uint16_t *flags;
+    const double *bc;
+    const double *rho, *u;
+    void *out;
+    double omp, omm, gx, gy;
+    float scale;
+    int variant;
+};
+
+template <int S>
+__global__ void __launch_bounds__(256) k_init(const InitArgs a) {
+    using C = typename Fmt<S>::C;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const bool dir = (a.flags[i] >> 8) == MLBM_DIRICHLET;
+    const double r = dir ? a.bc[3 * i] : a.rho[i];
+    const double ux = dir ? a.bc[3 * i + 1] : a.u[2 * i];
+    const double uy = dir ? a.bc[3 * i + 2] : a.u[2 * i + 1];
+    if (a.variant == MLBM_FIELDS) {
+        C o[3] = {(C)(r - 1.0), (C)ux, (C)uy};
+        store3<S>(a.out, i, o, a.scale);
+        return;
+    }
+    C f[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f[k] = feq_off<C>(k, C(1), (C)(r - 1.0), (C)r, (C)ux, (C)uy);
+    if (!dir) collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
+    store8<S>(a.out, i, f + 1, a.scale);
+    store1<S, C>(a.out, a.n, i, f[0], a.scale);
+}
+
+// ---- macroscopic fields and reductions ------------------------------------------------
+
+constexpr int RED_BLOCK = 256;
+
+struct MacroArgs {
+    int64_t n;
+    const int *idx;
+    const void *w;
+    const uint16_t *flags;
+    const double *bc;
+    const void *state;
+    const double *area;
+    double *rho_out, *u_out, *u_prev;
+    double *ws;
+    double gx, gy, inv_dx2;
+    float inv_scale;
+};
+
+// wave64 then workgroup tree sum in a fixed order; lane 0 of wave 0 holds the result
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int t = 0; t < (int)(blockDim.x >> 6); ++t) s += lds[t];
+    return s;
+}
+__device__ __forceinline__ double block_min(double v, double *lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = v;
+    if (threadIdx.x == 0)
+        for (int t = 0; t < (int)(blockDim.x >> 6); ++t) s = fmin(s, lds[t]);
+    return s;
+}
+
+template <int S, int V, int KQ>
+__global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
+    using C = typename Fmt<S>::C;
+    __shared__ double lds[RED_BLOCK / 64];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[MLBM_RED_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0, (double)a.n};
+    if (i < a.n) {
+        const int64_t n = a.n;
+        const unsigned fl = a.flags[i];
+        const unsigned bb = fl & 0xffu;
+        const bool dir = (fl >> 8) == MLBM_DIRICHLET;
+        double rho, ux, uy;
+        C f[9];
+        C m[3];
+        if constexpr (V == MLBM_POPULATIONS) {
+            load8<S>(a.state, i, f + 1, a.inv_scale);
+            f[0] = load1<S, C>(a.state, n, i, a.inv_scale);
+            double dr = 0, jx = 0, jy = 0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                dr += (double)f[k];
+                jx += EX[k] * (double)f[k];
+                jy += EY[k] * (double)f[k];
+            }
+            rho = 1.0 + dr;
+            ux = jx / rho - 0.5 * a.gx;
+            uy = jy / rho - 0.5 * a.gy;
+        } else {
+            load3<S>(a.state, i, m, a.inv_scale);
+            rho = 1.0 + (double)m[0];
+            ux = (double)m[1];
+            uy = (double)m[2];
+        }
+        if (dir) {
+            rho = a.bc[3 * i];
+            ux = a.bc[3 * i + 1];
+            uy = a.bc[3 * i + 2];
+        }
+        if (a.rho_out) a.rho_out[i] = rho;
+        if (a.u_out) {
+            a.u_out[2 * i] = ux;
+            a.u_out[2 * i + 1] = uy;
+        }
+        if (a.u_prev) {
+            const double dx = ux - a.u_prev[2 * i], dy = uy - a.u_prev[2 * i + 1];
+            v[MLBM_RED_NORM_DU2] = dx * dx + dy * dy;
+            a.u_prev[2 * i] = ux;
+            a.u_prev[2 * i + 1] = uy;
+        }
+        const double A = a.area[i];
+        const double sp = sqrt(ux * ux + uy * uy);
+        v[MLBM_RED_MASS] = A * rho;
+        v[MLBM_RED_INT_UX] = A * ux;
+        v[MLBM_RED_INT_UY] = A * uy;
+        v[MLBM_RED_INT_SPEED] = A * sp;
+        v[MLBM_RED_NORM_U2] = ux * ux + uy * uy;
+        if (!(isfinite(rho) && isfinite(ux) && isfinite(uy) && rho > 0.0)) {
+            v[MLBM_RED_N_BAD] = 1.0;
+            v[MLBM_RED_FIRST_BAD] = (double)i;
+        }
+        if (bb && !dir) {
+            // momentum exchange of every bounced pair (i, k): e_k' (f_k'^post + f_k^new) A / dx^2
+            double Fx = 0, Fy = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (!((bb >> k) & 1u)) continue;
+                const int kp = OPP8[k];  // stored index of k'
+                double fout, fback = 0;
+                if constexpr (V == MLBM_POPULATIONS) {
+                    fout = (double)f[kp + 1] + (double)omega<double>(kp + 1);
+                    double s = 0, sw = 0;
+                    for (int q = 0; q < KQ; ++q) {
+                        const i4 id = load_idx4(a.idx, n, i, q);
+                        C wv[4];
+                        load_w4<S, KQ>(a.w, n, i, k, q, wv);
+                        const int ids[4] = {id.x, id.y, id.z, id.w};
+                        for (int j = 0; j < 4; ++j) {
+                            C sj[8];
+                            load8<S>(a.state, ids[j], sj, a.inv_scale);
+                            s += (double)wv[j] * (double)sj[kp];
+                            sw += (double)wv[j];
+                        }
+                    }
+                    fback = s + sw * (double)omega<double>(kp + 1);
+                } else {
+                    const double r0 = 1.0 + (double)m[0];
+                    fout = omega<double>(kp + 1) +
+                           feq_off<double>(kp + 1, 1.0, (double)m[0], r0, (double)m[1], (double)m[2]) +
+                           0.5 * force_k<double>(kp + 1, 1.0, r0, (double)m[1], (double)m[2], a.gx, a.gy);
+                    double ir = 0, iu = 0, iv = 0;
+                    for (int q = 0; q < KQ; ++q) {
+                        const i4 id = load_idx4(a.idx, n, i, q);
+                        C wv[4];
+                        load_w4<S, KQ>(a.w, n, i, k, q, wv);
+                        const int ids[4] = {id.x, id.y, id.z, id.w};
+                        for (int j = 0; j < 4; ++j) {
+                            C mj[3];
+                            load3<S>(a.state, ids[j], mj, a.inv_scale);
+                            ir += (double)wv[j] * (double)mj[0];
+                            iu += (double)wv[j] * (double)mj[1];
+                            iv += (double)wv[j] * (double)mj[2];
+                        }
+                    }
+                    const double rh = 1.0 + ir;
+                    fback = omega<double>(kp + 1) + feq_off<double>(kp + 1, 1.0, ir, rh, iu, iv) +
+                            0.5 * force_k<double>(kp + 1, 1.0, rh, iu, iv, a.gx, a.gy);
+                }
+                Fx += EX[kp + 1] * (fout + fback);
+                Fy += EY[kp + 1] * (fout + fback);
+            }
+            v[MLBM_RED_FORCE_X] = A * a.inv_dx2 * Fx;
+            v[MLBM_RED_FORCE_Y] = A * a.inv_dx2 * Fy;
+        }
+    }
+    double *dst = a.ws + (int64_t)blockIdx.x * MLBM_RED_COUNT;
+#pragma unroll
+    for (int r = 0; r < MLBM_RED_FIRST_BAD; ++r) {
+        const double s = block_sum(v[r], lds);
+        if (threadIdx.x == 0) dst[r] = s;
+    }
+    const double mn = block_min(v[MLBM_RED_FIRST_BAD], lds);
+    if (threadIdx.x == 0) dst[MLBM_RED_FIRST_BAD] = mn;
+}
+
+// sums the per-block partials in a fixed order
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce_final(const double *ws, int64_t nblocks, double *out) {
+    __shared__ double lds[RED_BLOCK / 64];
+    for (int r = 0; r < MLBM_RED_COUNT; ++r) {
+        double s = r == MLBM_RED_FIRST_BAD ? INFINITY : 0.0;
+        for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
+            const double x = ws[b * MLBM_RED_COUNT + r];
+            s = r == MLBM_RED_FIRST_BAD ? fmin(s, x) : s + x;
+        }
+        const double t = r == MLBM_RED_FIRST_BAD ? block_min(s, lds) : block_sum(s, lds);
+        if (threadIdx.x == 0) out[r] = t;
+    }
+}
+
+// ---- dispatch ---------------------------------------------------------------------------
+
+int check_common(const mlbm_step_params *p, const mlbm_device_state *st) {
+    using mlbm::fail;
+    if (!p || !st) return fail(MLBM_ERR_ARG, "null pointer argument");
+    if (st->n < 1 || st->n > (int64_t)INT32_MAX) return fail(MLBM_ERR_ARG, "node count %lld outside [1, 2^31)", (long long)st->n);
+    if (st->K < 1 || st->K > 32) return fail(MLBM_ERR_ARG, "K=%d outside [1, 32]", st->K);
+    if (p->variant != MLBM_POPULATIONS && p->variant != MLBM_FIELDS) return fail(MLBM_ERR_ARG, "bad variant %d", p->variant);
+    if (p->storage < MLBM_F64 || p->storage > MLBM_BF16) return fail(MLBM_ERR_ARG, "bad storage %d", p->storage);
+    if (!st->flags || !st->state[0] || !st->state[1]) return fail(MLBM_ERR_ARG, "null device buffer");
+    if (st->cur != 0 && st->cur != 1) return fail(MLBM_ERR_ARG, "cur must be 0 or 1");
+    if (p->variant == MLBM_POPULATIONS && !(p->tau_plus > 0.5 && p->tau_minus > 0.5))
+        return fail(MLBM_ERR_ARG, "relaxation times must exceed 1/2");
+    if (p->storage == MLBM_F16S && (p->scale_exp < -30 || p->scale_exp > 30)) return fail(MLBM_ERR_ARG, "scale_exp out of range");
+    return MLBM_OK;
+}
+
+int block_of(const mlbm_step_params *p) {
+    const int b = p->block == 0 ? 256 : p->block;
+    return b;
+}
+
+using StepFn = void (*)(const StepArgs);
+
+template <int S>
+StepFn pick_step(int variant, int kq) {
+#define MLBM_CASE(Q)                                                        \
+    case Q:                                                                 \
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, Q> : (StepFn)k_step_fields<S, Q>;
+    switch (kq) {
+        MLBM_CASE(2)
+        MLBM_CASE(3)
+        MLBM_CASE(4)
+        MLBM_CASE(5)
+        MLBM_CASE(6)
+        MLBM_CASE(7)
+        MLBM_CASE(8)
+        default:
+            return nullptr;
+    }
+#undef MLBM_CASE
+}
+
+StepFn pick_step_any(int storage, int variant, int kq) {
+    switch (storage) {
+        case MLBM_F64: return pick_step<MLBM_F64>(variant, kq);
+        case MLBM_F32: return pick_step<MLBM_F32>(variant, kq);
+        case MLBM_F16S: return pick_step<MLBM_F16S>(variant, kq);
+        case MLBM_BF16: return pick_step<MLBM_BF16>(variant, kq);
+    }
+    return nullptr;
+}
+
+using MacroFn = void (*)(const MacroArgs);
+
+template <int S>
+MacroFn pick_macro(int variant, int kq) {
+#define MLBM_CASE(Q)                                                        \
+    case Q:                                                                 \
+        return variant == MLBM_POPULATIONS ? (MacroFn)k_macro<S, MLBM_POPULATIONS, Q> : (MacroFn)k_macro<S, MLBM_FIELDS, Q>;
+    switch (kq) {
+        MLBM_CASE(2)
+        MLBM_CASE(3)
+        MLBM_CASE(4)
+        MLBM_CASE(5)
+        MLBM_CASE(6)
+        MLBM_CASE(7)
+        MLBM_CASE(8)
+        default:
+            return nullptr;
+    }
+#undef MLBM_CASE
+}
+
+MacroFn pick_macro_any(int storage, int variant, int kq) {
+    switch (storage) {
+        case MLBM_F64: return pick_macro<MLBM_F64>(variant, kq);
+        case MLBM_F32: return pick_macro<MLBM_F32>(variant, kq);
+        case MLBM_F16S: return pick_macro<MLBM_F16S>(variant, kq);
+        case MLBM_BF16: return pick_macro<MLBM_BF16>(variant, kq);
+    }
+    return nullptr;
+}
+
+int hip_check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mlbm::fail(MLBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return MLBM_OK;
+}
+
+}  // namespace
+
+extern "C" int mlbm_init_state(const mlbm_step_params *p, mlbm_device_state *st, const double *rho,
+                               const double *u, void *stream) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    int rc = check_common(p, st);
+    if (rc) return rc;
+    if (!rho || !u) return fail(MLBM_ERR_ARG, "null field pointer");
+    InitArgs a;
+    a.n = st->n;
+    a.flags = st->flags;
+    a.bc = st->bc;
+    a.rho = rho;
+    a.u = u;
+    a.out = st->state[st->cur];
+    a.omp = 1.0 / p->tau_plus;
+    a.omm = 1.0 / p->tau_minus;
+    a.gx = p->g[0];
+    a.gy = p->g[1];
+    a.scale = std::ldexp(1.0f, p->scale_exp);
+    a.variant = p->variant;
+    const int blk = 256;
+    const dim3 grid((unsigned)((st->n + blk - 1) / blk));
+    hipStream_t s = (hipStream_t)stream;
+    switch (p->storage) {
+        case MLBM_F64: hipLaunchKernelGGL(k_init<MLBM_F64>, grid, dim3(blk), 0, s, a); break;
+        case MLBM_F32: hipLaunchKernelGGL(k_init<MLBM_F32>, grid, dim3(blk), 0, s, a); break;
+        case MLBM_F16S: hipLaunchKernelGGL(k_init<MLBM_F16S>, grid, dim3(blk), 0, s, a); break;
+        case MLBM_BF16: hipLaunchKernelGGL(k_init<MLBM_BF16>, grid, dim3(blk), 0, s, a); break;
+    }
+    return hip_check("mlbm_init_state launch");
+}
+
+extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32_t nsteps, void *stream) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    int rc = check_common(p, st);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(MLBM_ERR_ARG, "nsteps must be >= 0");
+    if (!st->idx || !st->w) return fail(MLBM_ERR_ARG, "null stencil buffer");
+    const int blk = block_of(p);
+    if (blk != 64 && blk != 128 && blk != 256) return fail(MLBM_ERR_ARG, "block must be 64, 128 or 256");
+    const int kq = (st->K + 3) / 4;
+    StepFn fn = pick_step_any(p->storage, p->variant, kq);
+    if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
+    if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
+        return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
+    StepArgs a;
+    a.n = st->n;
+    a.idx = (const int *)st->idx;
+    a.w = st->w;
+    a.flags = st->flags;
+    a.bc = st->bc;
+    a.omp = 1.0 / p->tau_plus;
+    a.omm = 1.0 / p->tau_minus;
+    a.gx = p->g[0];
+    a.gy = p->g[1];
+    a.scale = std::ldexp(1.0f, p->scale_exp);
+    a.inv_scale = std::ldexp(1.0f, -p->scale_exp);
+    a.xcd = p->xcd_remap ? 1 : 0;
+    const int64_t nb = (st->n + blk - 1) / blk;
+    a.grid8 = a.xcd ? (nb + 7) / 8 * 8 : nb;
+    hipStream_t s = (hipStream_t)stream;
+    for (int t = 0; t < nsteps; ++t) {
+        a.in = st->state[st->cur];
+        a.out = st->state[st->cur ^ 1];
+        hipLaunchKernelGGL(fn, dim3((unsigned)a.grid8), dim3(blk), 0, s, a);
+        rc = hip_check("mlbm_step launch");
+        if (rc) return rc;
+        st->cur ^= 1;
+    }
+    return MLBM_OK;
+}
+
+extern "C" int64_t mlbm_reduction_workspace_bytes(int64_t n) {
+    if (n < 1) return 0;
+    return ((n + RED_BLOCK - 1) / RED_BLOCK) * MLBM_RED_COUNT * (int64_t)sizeof(double);
+}
+
+extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_state *st, const double *area,
+                                double dx, double *rho_out, double *u_out, double *u_prev, void *workspace,
+                                double *red_out, void *stream) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    int rc = check_common(p, st);
+    if (rc) return rc;
+    if (!area || !workspace || !red_out) return fail(MLBM_ERR_ARG, "null area, workspace or output");
+    if (!st->idx || !st->w) return fail(MLBM_ERR_ARG, "null stencil buffer");
+    if (!(dx > 0.0)) return fail(MLBM_ERR_ARG, "dx must be positive");
+    const int kq = (st->K + 3) / 4;
+    MacroFn fn = pick_macro_any(p->storage, p->variant, kq);
+    if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no macroscopic kernel for storage %d, K=%d", p->storage, st->K);
+    MacroArgs a;
+    a.n = st->n;
+    a.idx = (const int *)st->idx;
+    a.w = st->w;
+    a.flags = st->flags;
+    a.bc = st->bc;
+    a.state = st->state[st->cur];
+    a.area = area;
+    a.rho_out = rho_out;
+    a.u_out = u_out;
+    a.u_prev = u_prev;
+    a.ws = (double *)workspace;
+    a.gx = p->g[0];
+    a.gy = p->g[1];
+    a.inv_dx2 = 1.0 / (dx * dx);
+    a.inv_scale = std::ldexp(1.0f, -p->scale_exp);
+    const int64_t nb = (st->n + RED_BLOCK - 1) / RED_BLOCK;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(RED_BLOCK), 0, s, a);
+    rc = hip_check("mlbm_macroscopic launch");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_BLOCK), 0, s, (const double *)workspace, nb, red_out);
+    return hip_check("mlbm_macroscopic reduction launch");
+}

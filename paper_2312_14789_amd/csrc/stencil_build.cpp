@@ -1,0 +1,517 @@
+// Host FP64 construction of the meshless stencils and interpolation weights,
+// and host packing into the device layout (see include/mlbm.h).
+//
+// Per node x_i: the K nearest nodes (cell-list search, minimum image on
+// periodic axes, ties broken by the offset vector), the departure point of
+// each arriving population k = 1..8 at x_i - dx e_k (Sec. 2.2, Eq. 12), moved
+// to the mirrored point x_i + dx e_k with source population k' when it falls
+// inside a solid (Sec. 3.2, Eq. 22), and the weights of the cubic
+// polyharmonic spline interpolant with quadratic augmentation (Sec. 2.2,
+// Eq. 13) evaluated there.  The (K+6)x(K+6) interpolation matrix depends only
+// on the stencil, so it is factorised once per node (LU with partial
+// pivoting) and solved for the eight departure points.
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "mlbm.h"
+#include "mlbm_internal.h"
+
+namespace {
+
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPPOSITE[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr int MAXK = 32;
+constexpr int NPOLY = 6;
+
+struct Box {
+    double lo[2], hi[2], len[2];
+    bool per[2];
+    bool wall_lo, wall_hi;
+    double tol;
+};
+
+inline void min_image(const Box &b, double &dx, double &dy) {
+    if (b.per[0]) {
+        if (dx > 0.5 * b.len[0]) dx -= b.len[0];
+        else if (dx < -0.5 * b.len[0]) dx += b.len[0];
+    }
+    if (b.per[1]) {
+        if (dy > 0.5 * b.len[1]) dy -= b.len[1];
+        else if (dy < -0.5 * b.len[1]) dy += b.len[1];
+    }
+}
+
+// Uniform grid of cells over the box holding point ids (CSR layout).
+struct CellGrid {
+    int nx = 1, ny = 1;
+    double cx = 1, cy = 1;
+    std::vector<int64_t> start, items;
+
+    int cell_x(const Box &b, double x) const {
+        int i = (int)std::floor((x - b.lo[0]) / cx);
+        return std::min(std::max(i, 0), nx - 1);
+    }
+    int cell_y(const Box &b, double y) const {
+        int j = (int)std::floor((y - b.lo[1]) / cy);
+        return std::min(std::max(j, 0), ny - 1);
+    }
+    void build(const Box &b, const double *pts, int64_t stride, int64_t m, double cell) {
+        nx = std::max(1, (int)std::floor(b.len[0] / cell));
+        ny = std::max(1, (int)std::floor(b.len[1] / cell));
+        nx = std::min(nx, 1 << 14);
+        ny = std::min(ny, 1 << 14);
+        cx = b.len[0] / nx;
+        cy = b.len[1] / ny;
+        std::vector<int64_t> count((size_t)nx * ny + 1, 0);
+        std::vector<int32_t> cid(m);
+        for (int64_t p = 0; p < m; ++p) {
+            int c = cell_y(b, pts[p * stride + 1]) * nx + cell_x(b, pts[p * stride]);
+            cid[p] = c;
+            count[c + 1]++;
+        }
+        for (size_t c = 0; c < (size_t)nx * ny; ++c) count[c + 1] += count[c];
+        start = count;
+        items.assign(m, 0);
+        std::vector<int64_t> fill(count.begin(), count.end() - 1);
+        for (int64_t p = 0; p < m; ++p) items[fill[cid[p]]++] = p;
+    }
+};
+
+struct Cand {
+    double r2, dx, dy;
+    int64_t j;
+};
+
+inline bool cand_less(const Cand &a, const Cand &b) {
+    if (a.r2 != b.r2) return a.r2 < b.r2;
+    if (a.dx != b.dx) return a.dx < b.dx;
+    return a.dy < b.dy;
+}
+
+struct Builder {
+    const mlbm_geometry *g;
+    Box box;
+    int K;
+    double dx;
+    CellGrid nodes, disks;
+    double rmax = 0;
+
+    // ---- K nearest neighbours --------------------------------------------
+    void nearest(int64_t i, std::vector<Cand> &cand, Cand *out) const {
+        const double xi = g->xy[2 * i], yi = g->xy[2 * i + 1];
+        cand.clear();
+        const int ci = nodes.cell_x(box, xi), cj = nodes.cell_y(box, yi);
+        const double cmin = std::min(nodes.cx, nodes.cy);
+        const int rmax_ring = std::max(nodes.nx, nodes.ny);
+        bool brute = false;
+        for (int r = 0;; ++r) {
+            if ((box.per[0] && 2 * r + 1 > nodes.nx) || (box.per[1] && 2 * r + 1 > nodes.ny) ||
+                r > rmax_ring) {
+                brute = true;
+                break;
+            }
+            for (int dj = -r; dj <= r; ++dj) {
+                for (int di = -r; di <= r; ++di) {
+                    if (std::max(std::abs(di), std::abs(dj)) != r) continue;
+                    int a = ci + di, b = cj + dj;
+                    if (box.per[0]) a = (a % nodes.nx + nodes.nx) % nodes.nx;
+                    else if (a < 0 || a >= nodes.nx) continue;
+                    if (box.per[1]) b = (b % nodes.ny + nodes.ny) % nodes.ny;
+                    else if (b < 0 || b >= nodes.ny) continue;
+                    const int c = b * nodes.nx + a;
+                    for (int64_t q = nodes.start[c]; q < nodes.start[c + 1]; ++q) {
+                        const int64_t j = nodes.items[q];
+                        double ddx = g->xy[2 * j] - xi, ddy = g->xy[2 * j + 1] - yi;
+                        min_image(box, ddx, ddy);
+                        cand.push_back({ddx * ddx + ddy * ddy, ddx, ddy, j});
+                    }
+                }
+            }
+            if ((int)cand.size() >= K) {
+                std::nth_element(cand.begin(), cand.begin() + (K - 1), cand.end(), cand_less);
+                const double kth = cand[K - 1].r2;
+                const double reach = r * cmin;
+                if (kth < reach * reach) break;
+            }
+        }
+        if (brute) {
+            cand.clear();
+            for (int64_t j = 0; j < g->n; ++j) {
+                double ddx = g->xy[2 * j] - xi, ddy = g->xy[2 * j + 1] - yi;
+                min_image(box, ddx, ddy);
+                cand.push_back({ddx * ddx + ddy * ddy, ddx, ddy, j});
+            }
+        }
+        std::partial_sort(cand.begin(), cand.begin() + K, cand.end(), cand_less);
+        std::copy(cand.begin(), cand.begin() + K, out);
+    }
+
+    // ---- solids ------------------------------------------------------------
+    bool inside_solid(double px, double py) const {
+        if (box.wall_lo && py < box.lo[1] - box.tol) return true;
+        if (box.wall_hi && py > box.hi[1] + box.tol) return true;
+        if (g->n_disks == 0) return false;
+        const int ci = disks.cell_x(box, px), cj = disks.cell_y(box, py);
+        for (int dj = -1; dj <= 1; ++dj) {
+            for (int di = -1; di <= 1; ++di) {
+                int a = ci + di, b = cj + dj;
+                if (box.per[0]) a = (a % disks.nx + disks.nx) % disks.nx;
+                else if (a < 0 || a >= disks.nx) continue;
+                if (box.per[1]) b = (b % disks.ny + disks.ny) % disks.ny;
+                else if (b < 0 || b >= disks.ny) continue;
+                const int c = b * disks.nx + a;
+                for (int64_t q = disks.start[c]; q < disks.start[c + 1]; ++q) {
+                    const double *d = g->disks + 3 * disks.items[q];
+                    double ddx = px - d[0], ddy = py - d[1];
+                    min_image(box, ddx, ddy);
+                    const double r = d[2] - box.tol;
+                    if (ddx * ddx + ddy * ddy < r * r) return true;
+                }
+            }
+        }
+        return false;
+    }
+
+    // ---- local interpolation -----------------------------------------------
+    static void poly2(double x, double y, double *p) {
+        p[0] = 1.0;
+        p[1] = x;
+        p[2] = y;
+        p[3] = x * x;
+        p[4] = x * y;
+        p[5] = y * y;
+    }
+
+    // LU factorisation with partial pivoting of the m x m row-major matrix a.
+    // Returns false if a pivot vanishes relative to the largest entry.
+    static bool lu(double *a, int *piv, int m) {
+        double amax = 0;
+        for (int t = 0; t < m * m; ++t) amax = std::max(amax, std::fabs(a[t]));
+        for (int c = 0; c < m; ++c) {
+            int p = c;
+            double best = std::fabs(a[c * m + c]);
+            for (int r = c + 1; r < m; ++r) {
+                const double v = std::fabs(a[r * m + c]);
+                if (v > best) { best = v; p = r; }
+            }
+            if (!(best > 1e-13 * amax)) return false;
+            piv[c] = p;
+            if (p != c)
+                for (int t = 0; t < m; ++t) std::swap(a[c * m + t], a[p * m + t]);
+            const double inv = 1.0 / a[c * m + c];
+            for (int r = c + 1; r < m; ++r) {
+                const double l = a[r * m + c] * inv;
+                a[r * m + c] = l;
+                if (l != 0.0)
+                    for (int t = c + 1; t < m; ++t) a[r * m + t] -= l * a[c * m + t];
+            }
+        }
+        return true;
+    }
+
+    // Solves with the factors of lu(): row interchanges first (the stored
+    // multipliers were swapped with their rows), then L, then U.
+    static void lu_solve(const double *a, const int *piv, int m, double *b) {
+        for (int c = 0; c < m; ++c)
+            if (piv[c] != c) std::swap(b[c], b[piv[c]]);
+        for (int c = 0; c < m; ++c)
+            for (int r = c + 1; r < m; ++r) b[r] -= a[r * m + c] * b[c];
+        for (int r = m - 1; r >= 0; --r) {
+            double s = b[r];
+            for (int t = r + 1; t < m; ++t) s -= a[r * m + t] * b[t];
+            b[r] = s / a[r * m + r];
+        }
+    }
+
+    // Stencil, weights, bounce-back bits and unnormalised area of node i.
+    // Returns MLBM_OK or an error code with the message recorded in err.
+    int node(int64_t i, std::vector<Cand> &cand, Cand *st, double *w, uint8_t *bbits,
+             double *area, std::string &err) const {
+        nearest(i, cand, st);
+        if (st[0].j != i || (K > 1 && st[1].r2 == 0.0)) {
+            err = "duplicate node coordinates at node " + std::to_string(i);
+            return MLBM_ERR_GEOMETRY;
+        }
+        // quadrature weight: squared mean distance to the 4 nearest other nodes
+        double s = 0;
+        for (int t = 1; t <= 4; ++t) s += std::hypot(st[t].dx, st[t].dy);
+        const double mean = s / 4.0;
+        *area = mean * mean * (g->kind[i] != MLBM_FLUID ? 0.5 : 1.0);
+
+        double R = 0;
+        for (int j = 0; j < K; ++j) R = std::max(R, std::hypot(st[j].dx, st[j].dy));
+        const int m = K + NPOLY;
+        double A[(MAXK + NPOLY) * (MAXK + NPOLY)];
+        int piv[MAXK + NPOLY];
+        double xs[MAXK], ys[MAXK];
+        for (int j = 0; j < K; ++j) {
+            xs[j] = st[j].dx / R;
+            ys[j] = st[j].dy / R;
+        }
+        for (int r = 0; r < m; ++r)
+            for (int c = 0; c < m; ++c) A[r * m + c] = 0.0;
+        for (int r = 0; r < K; ++r) {
+            for (int c = 0; c < K; ++c) {
+                const double rr = std::hypot(xs[r] - xs[c], ys[r] - ys[c]);
+                A[r * m + c] = rr * rr * rr;
+            }
+            double p[NPOLY];
+            poly2(xs[r], ys[r], p);
+            for (int t = 0; t < NPOLY; ++t) {
+                A[r * m + K + t] = p[t];
+                A[(K + t) * m + r] = p[t];
+            }
+        }
+        bool factored = false;
+        const double xi = g->xy[2 * i], yi = g->xy[2 * i + 1];
+        *bbits = 0;
+        for (int k = 1; k <= 8; ++k) {
+            // departure point and source population (Sec. 2.2 Eq. 12, Sec. 3.2 Eq. 22)
+            double ox = -dx * EX[k], oy = -dx * EY[k];
+            if (inside_solid(xi + ox, yi + oy)) {
+                *bbits |= (uint8_t)(1u << (k - 1));
+                if (!inside_solid(xi - ox, yi - oy)) {
+                    ox = -ox;
+                    oy = -oy;
+                } else {
+                    ox = 0.0;
+                    oy = 0.0;
+                }
+            }
+            const double px = ox / R, py = oy / R;
+            double *wk = w + (int64_t)(k - 1) * K;
+            int jn = 0;
+            double dn = std::numeric_limits<double>::infinity();
+            double rp[MAXK];
+            for (int j = 0; j < K; ++j) {
+                rp[j] = std::hypot(xs[j] - px, ys[j] - py);
+                if (rp[j] < dn) { dn = rp[j]; jn = j; }
+            }
+            if (dn < 1e-12) {  // evaluation point on a node: the value there
+                for (int j = 0; j < K; ++j) wk[j] = 0.0;
+                wk[jn] = 1.0;
+                continue;
+            }
+            if (!factored) {
+                if (!lu(A, piv, m)) {
+                    err = "singular interpolation system at node " + std::to_string(i);
+                    return MLBM_ERR_SINGULAR;
+                }
+                factored = true;
+            }
+            double b[MAXK + NPOLY];
+            for (int j = 0; j < K; ++j) b[j] = rp[j] * rp[j] * rp[j];
+            poly2(px, py, b + K);
+            lu_solve(A, piv, m, b);
+            for (int j = 0; j < K; ++j) wk[j] = b[j];
+            // reproduction of the quadratics at the evaluation point
+            double pe[NPOLY], acc[NPOLY] = {0, 0, 0, 0, 0, 0};
+            poly2(px, py, pe);
+            for (int j = 0; j < K; ++j) {
+                double pj[NPOLY];
+                poly2(xs[j], ys[j], pj);
+                for (int t = 0; t < NPOLY; ++t) acc[t] += wk[j] * pj[t];
+            }
+            for (int t = 0; t < NPOLY; ++t) {
+                if (!(std::fabs(acc[t] - pe[t]) <= 1e-9)) {
+                    err = "interpolation at node " + std::to_string(i) + ", k=" + std::to_string(k) +
+                          " does not reproduce quadratics";
+                    return MLBM_ERR_SINGULAR;
+                }
+            }
+        }
+        return MLBM_OK;
+    }
+};
+
+uint64_t spread_bits(uint32_t v) {
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+}  // namespace
+
+extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_params *p,
+                                   mlbm_stencils *out) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (!g || !p || !out || !g->xy || !g->kind || !out->perm || !out->idx || !out->w || !out->bb ||
+        !out->area)
+        return fail(MLBM_ERR_ARG, "null pointer argument");
+    if (g->n_disks < 0 || (g->n_disks > 0 && !g->disks)) return fail(MLBM_ERR_ARG, "bad disk list");
+    if (p->K < 7 || p->K > MAXK) return fail(MLBM_ERR_ARG, "K=%d outside [7, %d]", p->K, MAXK);
+    if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(MLBM_ERR_ARG, "dx must be positive");
+    if (p->reorder != 0 && p->reorder != 1) return fail(MLBM_ERR_ARG, "reorder must be 0 or 1");
+    const int64_t n = g->n;
+    if (n < p->K) return fail(MLBM_ERR_GEOMETRY, "K=%d exceeds the node count %lld", p->K, (long long)n);
+
+    Builder B;
+    B.g = g;
+    B.K = p->K;
+    B.dx = p->dx;
+    for (int a = 0; a < 2; ++a) {
+        B.box.lo[a] = g->lo[a];
+        B.box.hi[a] = g->hi[a];
+        B.box.len[a] = g->hi[a] - g->lo[a];
+        B.box.per[a] = g->periodic[a] != 0;
+        if (!(B.box.len[a] > 0.0)) return fail(MLBM_ERR_GEOMETRY, "empty box");
+    }
+    B.box.wall_lo = g->wall_lo_y != 0;
+    B.box.wall_hi = g->wall_hi_y != 0;
+    B.box.tol = 1e-12 * std::max(B.box.len[0], B.box.len[1]);
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = g->xy[2 * i], y = g->xy[2 * i + 1];
+        if (!std::isfinite(x) || !std::isfinite(y) || x < g->lo[0] - B.box.tol ||
+            x > g->hi[0] + B.box.tol || y < g->lo[1] - B.box.tol || y > g->hi[1] + B.box.tol)
+            return fail(MLBM_ERR_GEOMETRY, "node %lld outside the box", (long long)i);
+        if (g->kind[i] > MLBM_DIRICHLET) return fail(MLBM_ERR_ARG, "node %lld has kind %d", (long long)i, g->kind[i]);
+    }
+    for (int64_t d = 0; d < g->n_disks; ++d) {
+        if (!(g->disks[3 * d + 2] > 0.0)) return fail(MLBM_ERR_GEOMETRY, "disk %lld has no radius", (long long)d);
+        B.rmax = std::max(B.rmax, g->disks[3 * d + 2]);
+    }
+    const double cell = std::sqrt(B.box.len[0] * B.box.len[1] / (double)n) * 1.5;
+    B.nodes.build(B.box, g->xy, 2, n, cell);
+    if (g->n_disks > 0) B.disks.build(B.box, g->disks, 3, g->n_disks, B.rmax);
+    for (int64_t i = 0; i < n; ++i)
+        if (B.inside_solid(g->xy[2 * i], g->xy[2 * i + 1]))
+            return fail(MLBM_ERR_GEOMETRY, "node %lld lies inside a solid", (long long)i);
+
+    // node order: Morton (Z) order of the coordinates quantised to 2^20 cells
+    std::vector<int64_t> perm(n), inv(n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    if (p->reorder == 1) {
+        std::vector<uint64_t> key(n);
+        const double q = (double)(1u << 20);
+        for (int64_t i = 0; i < n; ++i) {
+            double fx = (g->xy[2 * i] - g->lo[0]) / B.box.len[0];
+            double fy = (g->xy[2 * i + 1] - g->lo[1]) / B.box.len[1];
+            uint32_t ix = (uint32_t)std::min(std::max(fx * q, 0.0), q - 1);
+            uint32_t iy = (uint32_t)std::min(std::max(fy * q, 0.0), q - 1);
+            key[i] = spread_bits(ix) | (spread_bits(iy) << 1);
+        }
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+    }
+    for (int64_t i = 0; i < n; ++i) inv[perm[i]] = i;
+
+    int nthreads = p->n_threads > 0 ? p->n_threads : (int)std::thread::hardware_concurrency();
+    nthreads = std::max(1, std::min(nthreads, 256));
+    std::atomic<int64_t> next(0);
+    std::mutex emu;
+    int64_t err_node = n;
+    int err_code = MLBM_OK;
+    std::string err_msg;
+    const int K = p->K;
+    const int64_t chunk = 512;
+    auto work = [&]() {
+        std::vector<Cand> cand;
+        cand.reserve(256);
+        Cand st[MAXK];
+        for (;;) {
+            const int64_t a = next.fetch_add(chunk);
+            if (a >= n) break;
+            const int64_t b = std::min(n, a + chunk);
+            for (int64_t inew = a; inew < b; ++inew) {
+                const int64_t i = perm[inew];
+                std::string msg;
+                double area = 0;
+                uint8_t bits = 0;
+                const int rc = B.node(i, cand, st, out->w + inew * 8 * K, &bits, &area, msg);
+                if (rc != MLBM_OK) {
+                    std::lock_guard<std::mutex> lk(emu);
+                    if (i < err_node) { err_node = i; err_code = rc; err_msg = msg; }
+                    continue;
+                }
+                for (int j = 0; j < K; ++j) out->idx[inew * K + j] = (int32_t)inv[st[j].j];
+                out->bb[inew] = bits;
+                out->area[inew] = area;
+                out->perm[inew] = i;
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    if (err_code != MLBM_OK) return fail(err_code, "%s", err_msg.c_str());
+
+    double fluid = g->fluid_area;
+    if (!(fluid > 0.0)) {
+        fluid = B.box.len[0] * B.box.len[1];
+        for (int64_t d = 0; d < g->n_disks; ++d) fluid -= M_PI * g->disks[3 * d + 2] * g->disks[3 * d + 2];
+    }
+    // normalisation sums in the caller's node order
+    double total = 0;
+    for (int64_t i = 0; i < n; ++i) total += out->area[inv[i]];
+    const double scale = fluid / total;
+    for (int64_t i = 0; i < n; ++i) out->area[i] *= scale;
+    return MLBM_OK;
+}
+
+extern "C" int mlbm_packed_sizes(int64_t n, int32_t K, int32_t variant, int32_t storage, mlbm_sizes *out) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (!out) return fail(MLBM_ERR_ARG, "null output");
+    if (n < 1 || K < 1 || K > MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
+    if (storage < MLBM_F64 || storage > MLBM_BF16) return fail(MLBM_ERR_ARG, "bad storage %d", storage);
+    if (variant != MLBM_POPULATIONS && variant != MLBM_FIELDS) return fail(MLBM_ERR_ARG, "bad variant %d", variant);
+    const int kp = (K + 3) / 4 * 4;
+    const int64_t ts = storage == MLBM_F64 ? 8 : storage == MLBM_F32 ? 4 : 2;
+    out->k_padded = kp;
+    out->idx_bytes = (int64_t)kp * n * 4;
+    out->w_bytes = (int64_t)8 * kp * n * (storage == MLBM_F64 ? 8 : 4);
+    out->flags_bytes = n * 2;
+    out->state_bytes = variant == MLBM_POPULATIONS ? 9 * n * ts : 4 * n * ts;
+    return MLBM_OK;
+}
+
+extern "C" int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx, const double *w,
+                                  const uint8_t *bb, const uint8_t *kind, void *idx_packed, void *w_packed,
+                                  uint16_t *flags) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (!idx || !w || !bb || !kind || !idx_packed || !w_packed || !flags) return fail(MLBM_ERR_ARG, "null pointer argument");
+    if (n < 1 || K < 1 || K > MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
+    if (storage < MLBM_F64 || storage > MLBM_BF16) return fail(MLBM_ERR_ARG, "bad storage %d", storage);
+    const int kp = (K + 3) / 4 * 4;
+    int32_t *ip = (int32_t *)idx_packed;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int j = 0; j < kp; ++j) {
+            const int32_t v = j < K ? idx[i * K + j] : (int32_t)i;
+            if (v < 0 || v >= n) return fail(MLBM_ERR_ARG, "stencil index out of range at node %lld", (long long)i);
+            ip[((int64_t)(j / 4) * n + i) * 4 + (j % 4)] = v;
+        }
+        flags[i] = (uint16_t)(bb[i] | ((uint16_t)(kind[i] & 3) << 8));
+    }
+    if (storage == MLBM_F64) {
+        double *wp = (double *)w_packed;
+        const int kh = kp / 2;
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 8; ++k)
+                for (int j = 0; j < kp; ++j)
+                    wp[(((int64_t)k * kh + j / 2) * n + i) * 2 + (j % 2)] = j < K ? w[(i * 8 + k) * K + j] : 0.0;
+    } else {
+        float *wp = (float *)w_packed;
+        const int kq = kp / 4;
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 8; ++k)
+                for (int j = 0; j < kp; ++j)
+                    wp[(((int64_t)k * kq + j / 4) * n + i) * 4 + (j % 4)] =
+                        j < K ? (float)w[(i * 8 + k) * K + j] : 0.0f;
+    }
+    return MLBM_OK;
+}

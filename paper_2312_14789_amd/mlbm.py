@@ -1,0 +1,172 @@
+"""Python binding of libmlbm.so with the names of the C ABI (include/mlbm.h).
+
+Only argument marshalling lives here: numpy arrays for the host builder,
+PyTorch tensors for device memory and streams.  Every step of the method runs
+in the library (host C++ builder, HIP kernels).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BF16, F16S, F32, F64, FIELDS, POPULATIONS, RED_COUNT, DeviceState, Geometry,
+                   MlbmError, Sizes, StencilParams, Stencils, StepParams, check, lib)
+
+__all__ = ["build_stencils", "packed_sizes", "pack_stencils", "Simulation", "MlbmError",
+           "POPULATIONS", "FIELDS", "F64", "F32", "F16S", "BF16"]
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def geometry_struct(xy, kind, lo, hi, periodic, walls_y=(False, False), disks=None, fluid_area=0.0):
+    """Builds the mlbm_geometry struct; returns (struct, keep-alive arrays)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    disks = np.ascontiguousarray(np.zeros((0, 3)) if disks is None else disks, dtype=np.float64)
+    g = Geometry()
+    g.n = xy.shape[0]
+    g.xy = _ptr(xy)
+    g.kind = _ptr(kind)
+    g.lo[0], g.lo[1] = float(lo[0]), float(lo[1])
+    g.hi[0], g.hi[1] = float(hi[0]), float(hi[1])
+    g.periodic[0], g.periodic[1] = int(bool(periodic[0])), int(bool(periodic[1]))
+    g.wall_lo_y, g.wall_hi_y = int(bool(walls_y[0])), int(bool(walls_y[1]))
+    g.n_disks = disks.shape[0]
+    g.disks = _ptr(disks) if disks.shape[0] else None
+    g.fluid_area = float(fluid_area)
+    return g, (xy, kind, disks)
+
+
+def build_stencils(xy, kind, lo, hi, periodic, K, dx, walls_y=(False, False), disks=None,
+                   fluid_area=0.0, reorder=1, n_threads=0) -> dict:
+    """mlbm_build_stencils: returns perm (n,), idx (n, K), w (n, 8, K), bb (n,), area (n,)."""
+    g, keep = geometry_struct(xy, kind, lo, hi, periodic, walls_y, disks, fluid_area)
+    n = g.n
+    out = {"perm": np.zeros(n, np.int64), "idx": np.zeros((n, K), np.int32),
+           "w": np.zeros((n, 8, K), np.float64), "bb": np.zeros(n, np.uint8),
+           "area": np.zeros(n, np.float64)}
+    st = Stencils(_ptr(out["perm"]), _ptr(out["idx"]), _ptr(out["w"]), _ptr(out["bb"]), _ptr(out["area"]))
+    p = StencilParams(K=K, reorder=reorder, dx=float(dx), n_threads=n_threads)
+    check(lib.mlbm_build_stencils(ctypes.byref(g), ctypes.byref(p), ctypes.byref(st)))
+    del keep
+    return out
+
+
+def build_stencils_for(ns, K, dx, reorder=1, n_threads=0) -> dict:
+    """build_stencils for an object carrying xy, kind, lo, hi, periodic,
+    walls_y, disks and fluid_area()."""
+    return build_stencils(ns.xy, ns.kind, ns.lo, ns.hi, ns.periodic, K, dx, walls_y=ns.walls_y,
+                          disks=ns.disks, fluid_area=ns.fluid_area(), reorder=reorder,
+                          n_threads=n_threads)
+
+
+def packed_sizes(n, K, variant, storage) -> Sizes:
+    s = Sizes()
+    check(lib.mlbm_packed_sizes(n, K, variant, storage, ctypes.byref(s)))
+    return s
+
+
+def pack_stencils(idx, w, bb, kind, storage):
+    """mlbm_pack_stencils: host arrays in the device layout (idx, w, flags)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    bb = np.ascontiguousarray(bb, dtype=np.uint8)
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    n, K = idx.shape
+    s = packed_sizes(n, K, POPULATIONS, storage)
+    ip = np.zeros(s.idx_bytes, np.uint8)
+    wp = np.zeros(s.w_bytes, np.uint8)
+    fl = np.zeros(n, np.uint16)
+    check(lib.mlbm_pack_stencils(n, K, storage, _ptr(idx), _ptr(w), _ptr(bb), _ptr(kind), _ptr(ip),
+                                 _ptr(wp), _ptr(fl)))
+    return ip, wp, fl
+
+
+class Simulation:
+    """Device buffers (PyTorch) and parameters of one node set.
+
+    idx, w, bb, area are the builder's arrays in its node order; kind and bc
+    (n, 3) must be given in that same order."""
+
+    def __init__(self, idx, w, bb, kind, area, *, variant=POPULATIONS, storage=F32, tau_plus=0.8,
+                 tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
+                 device="cuda"):
+        import torch
+
+        self.torch = torch
+        n, K = np.asarray(idx).shape
+        self.n, self.K = n, K
+        ip, wp, fl = pack_stencils(idx, w, bb, kind, storage)
+        self.sizes = packed_sizes(n, K, variant, storage)
+        dev = torch.device(device)
+        self.idx_d = torch.from_numpy(ip).to(dev)
+        self.w_d = torch.from_numpy(wp).to(dev)
+        self.flags_d = torch.from_numpy(fl.view(np.int16)).to(dev)
+        if bc is None:
+            bc = np.zeros((n, 3))
+            bc[:, 0] = 1.0
+        self.bc_d = torch.from_numpy(np.ascontiguousarray(bc, dtype=np.float64)).to(dev)
+        self.area_d = torch.from_numpy(np.ascontiguousarray(area, dtype=np.float64)).to(dev)
+        self.state_d = [torch.zeros(self.sizes.state_bytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+        ws = lib.mlbm_reduction_workspace_bytes(n)
+        self.ws_d = torch.zeros(max(ws, 8), dtype=torch.uint8, device=dev)
+        self.red_d = torch.zeros(RED_COUNT, dtype=torch.float64, device=dev)
+        self.params = StepParams()
+        self.params.variant = variant
+        self.params.storage = storage
+        self.params.tau_plus = float(tau_plus)
+        self.params.tau_minus = float(tau_plus if tau_minus is None else tau_minus)
+        self.params.g[0], self.params.g[1] = float(g[0]), float(g[1])
+        self.params.scale_exp = int(scale_exp)
+        self.params.block = int(block)
+        self.params.xcd_remap = int(xcd_remap)
+        self.ds = DeviceState()
+        self.ds.n = n
+        self.ds.K = K
+        self.ds.idx = self.idx_d.data_ptr()
+        self.ds.w = self.w_d.data_ptr()
+        self.ds.flags = self.flags_d.data_ptr()
+        self.ds.bc = self.bc_d.data_ptr()
+        self.ds.state[0] = self.state_d[0].data_ptr()
+        self.ds.state[1] = self.state_d[1].data_ptr()
+        self.ds.cur = 0
+
+    def _stream(self, stream=None):
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def init_state(self, rho, u, stream=None):
+        """mlbm_init_state from host or device FP64 fields rho (n,), u (n, 2)."""
+        t = self.torch
+        r = t.as_tensor(np.ascontiguousarray(rho, dtype=np.float64) if isinstance(rho, np.ndarray) else rho,
+                        dtype=t.float64, device=self.state_d[0].device).contiguous()
+        v = t.as_tensor(np.ascontiguousarray(u, dtype=np.float64) if isinstance(u, np.ndarray) else u,
+                        dtype=t.float64, device=self.state_d[0].device).contiguous()
+        self._keep = (r, v)
+        check(lib.mlbm_init_state(ctypes.byref(self.params), ctypes.byref(self.ds), r.data_ptr(),
+                                  v.data_ptr(), self._stream(stream)))
+
+    def step(self, nsteps=1, stream=None):
+        """mlbm_step."""
+        check(lib.mlbm_step(ctypes.byref(self.params), ctypes.byref(self.ds), int(nsteps), self._stream(stream)))
+
+    def macroscopic(self, dx, u_prev=None, want_fields=True, stream=None):
+        """mlbm_macroscopic: returns (rho, u, reductions) as device tensors."""
+        t = self.torch
+        dev = self.state_d[0].device
+        rho = t.empty(self.n, dtype=t.float64, device=dev) if want_fields else None
+        u = t.empty((self.n, 2), dtype=t.float64, device=dev) if want_fields else None
+        check(lib.mlbm_macroscopic(ctypes.byref(self.params), ctypes.byref(self.ds), self.area_d.data_ptr(),
+                                   float(dx), rho.data_ptr() if rho is not None else None,
+                                   u.data_ptr() if u is not None else None,
+                                   u_prev.data_ptr() if u_prev is not None else None,
+                                   self.ws_d.data_ptr(), self.red_d.data_ptr(), self._stream(stream)))
+        return rho, u, self.red_d
+
+    def state_bytes(self):
+        """Current state buffer as a host numpy uint8 array (synchronises)."""
+        return self.state_d[self.ds.cur].cpu().numpy()

@@ -20,3 +20,12 @@ _CACHE = {}
 def oracle_cache():
     """Session cache for oracle stencils (building them is the slow part)."""
     return _CACHE
+
+
+def pytest_sessionstart(session):
+    # build the library only when nothing is built yet
+    lib = os.path.join(ROOT, "paper_2312_14789_amd", "libmlbm.so")
+    if not os.path.exists(lib):
+        from paper_2312_14789_amd.build import build
+
+        build()
