@@ -78,10 +78,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--s", type=float, default=1.0, help="streaming-distance scale (dx = h/s)")
+    ap.add_argument("--s", type=float, default=1.0, help="streaming-distance scale (dx = h_min/s)")
+    ap.add_argument("--K", type=int, default=16)
+    ap.add_argument("--trt", type=int, default=0, help="TRT with Lambda = 3/16 instead of BGK")
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16"])
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--xcd", type=int, default=1)
+    ap.add_argument("--fp32-arith", type=int, default=0, help="FP32 register arithmetic for f32 storage")
+    ap.add_argument("--sweeps", type=int, default=1, help="alternate the tile sweep direction")
+    ap.add_argument("--cached", type=int, default=0, help="ordinary (not non-temporal) weight loads")
+    ap.add_argument("--nodes", type=int, default=500_000, help="target node count of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -98,18 +104,22 @@ def main():
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]
     t0 = time.time()
-    ns = nodesets.karman()
-    dx = units.delta_x(ns.h, args.s)
+    ns = nodesets.karman(n_target=args.nodes)
+    # streaming distance from the finest spacing (refined ring around the
+    # cylinder): s = 1 keeps dx <= h everywhere
+    dx = units.delta_x(ns.h_min, args.s)
     re = 100.0 * args.s
     tau = units.tau_for_reynolds(0.05, 1.0, dx, re)
-    K = 16
+    tau_m = 0.5 + (3.0 / 16.0) / (tau - 0.5) if args.trt else tau
+    K = args.K
     b = M.build_stencils_for(ns, K, dx)
     perm = b["perm"]
     print(f"# built {ns.n} nodes, K={K}, dx={dx:.4g}, tau={tau:.4f} in {time.time() - t0:.1f} s",
           file=sys.stderr, flush=True)
     sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
-                       storage=storage, tau_plus=tau, tau_minus=tau, bc=ns.boundary_values()[perm],
-                       block=args.block, xcd_remap=args.xcd, scale_exp=12)
+                       storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
+                       block=args.block, xcd_remap=args.xcd, scale_exp=12, fp32_arith=args.fp32_arith,
+                       alternate_sweeps=args.sweeps, cached_weights=args.cached)
     n = ns.n
     sim.init_state(np.ones(n), np.zeros((n, 2)))
     sim.step(args.warmup)
@@ -146,13 +156,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "f16s": "f16(scaled offsets)/f32", "bf16": "bf16/f32"}[args.storage],
+        "dtype": {"f64": "f64", "f32": "f32" if args.fp32_arith else "f32 state+weights, f64 registers",
+                  "f16s": "f16 state (scaled offsets), f32 weights+registers",
+                  "bf16": "bf16 state, f32 weights+registers"}[args.storage],
         "data": "synthetic",
         "config": {"workload": "Karman street channel 22Dx4.1D, cylinder D at (2D,2D), "
                                f"{n} scattered nodes (4x denser within 1D of the cylinder), "
-                               f"K={K}, s={args.s:g} (Re={re:g}), BGK tau={tau:.4f}, "
+                               f"K={K}, s={args.s:g} (Re={re:g}), " + (f"TRT tau+={tau:.4f} tau-={tau_m:.4f}, " if args.trt else f"BGK tau={tau:.4f}, ") + 
                                f"{args.storage} populations",
                    "nodes": n, "K": K, "s": args.s, "block": args.block, "xcd_remap": args.xcd,
+                   "fp32_arith": args.fp32_arith, "alternate_sweeps": args.sweeps,
+                   "cached_weights": args.cached,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -38,6 +38,7 @@ class NodeSet:
     bc: np.ndarray | None = None      # (n, 3) (rho_b, ux_b, uy_b), used on kind-2 nodes
     h: float = 0.0            # reference (bulk) node spacing
     name: str = ""
+    h_min: float = 0.0        # finest node spacing (refined regions); 0 means h
 
     @property
     def n(self) -> int:
@@ -257,7 +258,7 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     y = xy[:, 1]
     bc[inout, 1] = 4.0 * u_max * y[inout] * (Ly - y[inout]) / Ly ** 2
     return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(False, False),
-                   disks=np.array([[cx, cy, r]]), bc=bc, h=hb, name="karman")
+                   disks=np.array([[cx, cy, r]]), bc=bc, h=hb, name="karman", h_min=hf)
 
 
 def random_disks(phi_target: float, r_min: float, r_max: float, gap: float,

@@ -176,8 +176,12 @@ def bounce_back_force(f, ns, st, tau_plus, tau_minus, g, dx, area=None):
     towards the solid is lost to the fluid and the population k that arrives
     instead is gained, so the solid receives e_k' (f_k'^post + f_k^new); each
     node counts with A_i / dx^2 lattice cells (area defaults to the stencil
-    quadrature weights).  The paper reports no forces on scattered nodes; the
-    formula is pinned by the steady momentum balance of a channel."""
+    quadrature weights).  Populations are taken relative to the rest state
+    (f - omega): a uniform pressure exerts no net force on a closed surface,
+    but its discretised surface sum on scattered nodes does not vanish, so
+    the reference pressure is removed before summing.  The paper reports no
+    forces on scattered nodes; the formula is pinned by the steady momentum
+    balance of a channel."""
     area = st.area if area is None else area
     fpost = post_collision(f, ns, tau_plus, tau_minus, g)
     fnew = stream(fpost, st)
@@ -186,7 +190,7 @@ def bounce_back_force(f, ns, st, tau_plus, tau_minus, g, dx, area=None):
         for k in range(1, 9):
             kp = int(lt.OPP[k])
             if st.src[i, k - 1] == kp:
-                F += (area[i] / dx ** 2) * lt.E[kp] * (fpost[kp, i] + fnew[k, i])
+                F += (area[i] / dx ** 2) * lt.E[kp] * ((fpost[kp, i] - lt.W[kp]) + (fnew[k, i] - lt.W[k]))
     return F
 
 
@@ -222,6 +226,30 @@ def mlbm1_step(rho, u, ns, st, g=(0.0, 0.0)):
         rho_new[d] = bc[d, 0]
         u_new[d] = bc[d, 1:3]
     return rho_new, u_new
+
+
+def mlbm1_bounce_back_force(rho, u, ns, st, g, dx, area=None):
+    """Momentum-exchange force of MLBM1 (same bookkeeping as
+    bounce_back_force): the post-collision population k' at the node is its
+    equilibrium plus half the force term (tau = 1), the returning population
+    k the same at the interpolated fields of the mirrored point; both
+    relative to the rest state."""
+    area = st.area if area is None else area
+    g = np.asarray(g, dtype=np.float64)
+    own = lt.equilibrium(rho, u) + 0.5 * lt.guo_force(rho, u, g)
+    F = np.zeros(2)
+    for i in range(ns.n):
+        for k in range(1, 9):
+            kp = int(lt.OPP[k])
+            if st.src[i, k - 1] != kp:
+                continue
+            w = st.w[i, k - 1]
+            nb = st.idx[i]
+            rh = np.array([np.sum(w * rho[nb])])
+            uh = np.array([[np.sum(w * u[nb, 0]), np.sum(w * u[nb, 1])]])
+            back = lt.equilibrium(rh, uh) + 0.5 * lt.guo_force(rh, uh, g)
+            F += (area[i] / dx ** 2) * lt.E[kp] * ((own[kp, i] - lt.W[kp]) + (back[kp, 0] - lt.W[k]))
+    return F
 
 
 # --------------------------------------------------------------------------

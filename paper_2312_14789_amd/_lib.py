@@ -53,7 +53,9 @@ class StepParams(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("tau_plus", ctypes.c_double), ("tau_minus", ctypes.c_double),
                 ("g", ctypes.c_double * 2), ("scale_exp", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("fp32_arith", ctypes.c_int32), ("alternate_sweeps", ctypes.c_int32),
+                ("cached_weights", ctypes.c_int32)]
 
 
 class DeviceState(ctypes.Structure):
@@ -68,6 +70,13 @@ class MlbmError(RuntimeError):
 
 
 def _load():
+    # One HIP runtime per process: when PyTorch is present its runtime is the
+    # process's, and the library must bind to that same libamdhip64 (same
+    # soname) rather than load a second copy, so PyTorch is imported first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(python paper_2312_14789_amd/build.py)")

@@ -110,11 +110,11 @@ __device__ __forceinline__ void store8(void *base, int64_t j, const C *o, float 
     if constexpr (S == MLBM_F64) {
         d2 *p = (d2 *)base + 4 * j;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) p[t] = d2{o[2 * t], o[2 * t + 1]};
+        for (int t = 0; t < 4; ++t) p[t] = d2{(double)o[2 * t], (double)o[2 * t + 1]};
     } else if constexpr (S == MLBM_F32) {
         f4 *p = (f4 *)base + 2 * j;
-        p[0] = f4{o[0], o[1], o[2], o[3]};
-        p[1] = f4{o[4], o[5], o[6], o[7]};
+        p[0] = f4{(float)o[0], (float)o[1], (float)o[2], (float)o[3]};
+        p[1] = f4{(float)o[4], (float)o[5], (float)o[6], (float)o[7]};
     } else {
         unsigned w[4];
 #pragma unroll
@@ -159,10 +159,10 @@ template <int S, class C>
 __device__ __forceinline__ void store3(void *base, int64_t j, const C *o, float scale) {
     if constexpr (S == MLBM_F64) {
         d2 *p = (d2 *)base + 2 * j;
-        p[0] = d2{o[0], o[1]};
-        p[1] = d2{o[2], 0.0};
+        p[0] = d2{(double)o[0], (double)o[1]};
+        p[1] = d2{(double)o[2], 0.0};
     } else if constexpr (S == MLBM_F32) {
-        ((f4 *)base)[j] = f4{o[0], o[1], o[2], 0.0f};
+        ((f4 *)base)[j] = f4{(float)o[0], (float)o[1], (float)o[2], 0.0f};
     } else {
         unsigned a = (unsigned)enc16<S>((float)o[0], scale) | ((unsigned)enc16<S>((float)o[1], scale) << 16);
         unsigned b = (unsigned)enc16<S>((float)o[2], scale);
@@ -170,23 +170,30 @@ __device__ __forceinline__ void store3(void *base, int64_t j, const C *o, float 
     }
 }
 
+// streamed (read-once-per-step) data: non-temporal unless cached is set
+template <class T>
+__device__ __forceinline__ T stream_load(const T *p, int cached) {
+    return cached ? *p : __builtin_nontemporal_load(p);
+}
+
 // four weights (stencil members 4q..4q+3) of arriving population k+1
 template <int S, int KQ, class C>
-__device__ __forceinline__ void load_w4(const void *w, int64_t n, int64_t i, int k, int q, C *o) {
+__device__ __forceinline__ void load_w4(const void *w, int64_t n, int64_t i, int k, int q, C *o,
+                                        int cached = 0) {
     if constexpr (S == MLBM_F64) {
         const d2 *p = (const d2 *)w;
-        d2 a = __builtin_nontemporal_load(p + ((int64_t)(k * 2 * KQ + 2 * q) * n + i));
-        d2 b = __builtin_nontemporal_load(p + ((int64_t)(k * 2 * KQ + 2 * q + 1) * n + i));
+        d2 a = stream_load(p + ((int64_t)(k * 2 * KQ + 2 * q) * n + i), cached);
+        d2 b = stream_load(p + ((int64_t)(k * 2 * KQ + 2 * q + 1) * n + i), cached);
         o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
     } else {
         const f4 *p = (const f4 *)w;
-        f4 a = __builtin_nontemporal_load(p + ((int64_t)(k * KQ + q) * n + i));
+        f4 a = stream_load(p + ((int64_t)(k * KQ + q) * n + i), cached);
         o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
     }
 }
 
-__device__ __forceinline__ i4 load_idx4(const int *idx, int64_t n, int64_t i, int q) {
-    return __builtin_nontemporal_load((const i4 *)idx + ((int64_t)q * n + i));
+__device__ __forceinline__ i4 load_idx4(const int *idx, int64_t n, int64_t i, int q, int cached = 0) {
+    return stream_load((const i4 *)idx + ((int64_t)q * n + i), cached);
 }
 
 // ---- lattice arithmetic in offset form ---------------------------------------
@@ -254,22 +261,30 @@ struct StepArgs {
     float scale, inv_scale;
     int64_t grid8;
     int xcd;
+    int reverse;   // sweep the tiles in reverse order (alternating sweeps)
+    int cached;    // plain loads for weights and indices instead of non-temporal
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin; with xcd each XCD gets
+// a contiguous range of tiles.  With reverse the tiles are visited in the
+// opposite order, so alternating sweeps start where the previous one ended and
+// meet its most recently cached data first.
 __device__ __forceinline__ int64_t node_of(const StepArgs &a) {
     int64_t b = blockIdx.x;
     if (a.xcd) {
         const int64_t per = a.grid8 >> 3;
-        b = (b & 7) * per + (b >> 3);
+        const int64_t r = b >> 3;
+        b = (b & 7) * per + (a.reverse ? per - 1 - r : r);
+    } else if (a.reverse) {
+        b = a.grid8 - 1 - b;
     }
     return b * (int64_t)blockDim.x + threadIdx.x;
 }
 
 // ---- population MLBM step ------------------------------------------------------
 
-template <int S, int KQ>
+template <int S, class C, int KQ>
 __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
-    using C = typename Fmt<S>::C;
     const int64_t i = node_of(a);
     if (i >= a.n) return;
     const int64_t n = a.n;
@@ -281,12 +296,16 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) f[k] = feq_off<C>(k, C(1), rb - C(1), rb, ub, vb);
     } else {
-        C acc[8];
+        // FP64 keeps the weight sum: sum_j w_j f_j = sum_j w_j (f_j - omega) + omega sum_j w_j,
+        // exactly the interpolation of the populations; reduced precision drops
+        // the (sum_j w_j - 1) omega term, which is weight rounding there.
+        constexpr bool kWsum = S == MLBM_F64;
+        C acc[8], sw[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = C(0);
+        for (int k = 0; k < 8; ++k) acc[k] = sw[k] = C(0);
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
-            const i4 id = load_idx4(a.idx, n, i, q);
+            const i4 id = load_idx4(a.idx, n, i, q, a.cached);
             C s[4][8];
             load8<S>(a.in, id.x, s[0], a.inv_scale);
             load8<S>(a.in, id.y, s[1], a.inv_scale);
@@ -295,18 +314,19 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 C wv[4];
-                load_w4<S, KQ>(a.w, n, i, k, q, wv);
+                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
                 const bool flip = (bb >> k) & 1u;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const C v = flip ? s[j][OPP8[k]] : s[j][k];
                     acc[k] = fma(wv[j], v, acc[k]);
+                    if constexpr (kWsum) sw[k] += wv[j];
                 }
             }
         }
         f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) f[k + 1] = acc[k];
+        for (int k = 0; k < 8; ++k) f[k + 1] = kWsum ? acc[k] + omega<C>(k + 1) * (sw[k] - C(1)) : acc[k];
         collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
     }
     store8<S>(a.out, i, f + 1, a.scale);
@@ -315,9 +335,8 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
 
 // ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
 
-template <int S, int KQ>
+template <int S, class C, int KQ>
 __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
-    using C = typename Fmt<S>::C;
     const int64_t i = node_of(a);
     if (i >= a.n) return;
     const int64_t n = a.n;
@@ -329,12 +348,13 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
         out[1] = (C)a.bc[3 * i + 1];
         out[2] = (C)a.bc[3 * i + 2];
     } else {
-        C ar[8], au[8], av[8];
+        constexpr bool kWsum = S == MLBM_F64;  // interpolate rho itself, not rho - 1
+        C ar[8], au[8], av[8], sw[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) ar[k] = au[k] = av[k] = C(0);
+        for (int k = 0; k < 8; ++k) ar[k] = au[k] = av[k] = sw[k] = C(0);
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
-            const i4 id = load_idx4(a.idx, n, i, q);
+            const i4 id = load_idx4(a.idx, n, i, q, a.cached);
             C m[4][3];
             load3<S>(a.in, id.x, m[0], a.inv_scale);
             load3<S>(a.in, id.y, m[1], a.inv_scale);
@@ -343,14 +363,19 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 C wv[4];
-                load_w4<S, KQ>(a.w, n, i, k, q, wv);
+                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     ar[k] = fma(wv[j], m[j][0], ar[k]);
                     au[k] = fma(wv[j], m[j][1], au[k]);
                     av[k] = fma(wv[j], m[j][2], av[k]);
+                    if constexpr (kWsum) sw[k] += wv[j];
                 }
             }
+        }
+        if constexpr (kWsum) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) ar[k] += sw[k] - C(1);
         }
         const C gx = (C)a.gx, gy = (C)a.gy;
         C own[3];
@@ -392,7 +417,7 @@ struct InitArgs {
 
 template <int S>
 __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
-    using C = typename Fmt<S>::C;
+    using C = double;  // one-off: computed in FP64 and rounded once on store
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const bool dir = (a.flags[i] >> 8) == MLBM_DIRICHLET;
@@ -517,7 +542,8 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
             v[MLBM_RED_FIRST_BAD] = (double)i;
         }
         if (bb && !dir) {
-            // momentum exchange of every bounced pair (i, k): e_k' (f_k'^post + f_k^new) A / dx^2
+            // momentum exchange of every bounced pair (i, k): e_k' (f_k'^post + f_k^new) A / dx^2,
+            // populations relative to the rest state (a uniform pressure exerts no net force)
             double Fx = 0, Fy = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -525,7 +551,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                 const int kp = OPP8[k];  // stored index of k'
                 double fout, fback = 0;
                 if constexpr (V == MLBM_POPULATIONS) {
-                    fout = (double)f[kp + 1] + (double)omega<double>(kp + 1);
+                    fout = (double)f[kp + 1];
                     double s = 0, sw = 0;
                     for (int q = 0; q < KQ; ++q) {
                         const i4 id = load_idx4(a.idx, n, i, q);
@@ -539,13 +565,12 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                             sw += (double)wv[j];
                         }
                     }
-                    fback = s + sw * (double)omega<double>(kp + 1);
+                    fback = s + (sw - 1.0) * (double)omega<double>(kp + 1);
                 } else {
                     const double r0 = 1.0 + (double)m[0];
-                    fout = omega<double>(kp + 1) +
-                           feq_off<double>(kp + 1, 1.0, (double)m[0], r0, (double)m[1], (double)m[2]) +
+                    fout = feq_off<double>(kp + 1, 1.0, (double)m[0], r0, (double)m[1], (double)m[2]) +
                            0.5 * force_k<double>(kp + 1, 1.0, r0, (double)m[1], (double)m[2], a.gx, a.gy);
-                    double ir = 0, iu = 0, iv = 0;
+                    double ir = 0, iu = 0, iv = 0, sw = 0;
                     for (int q = 0; q < KQ; ++q) {
                         const i4 id = load_idx4(a.idx, n, i, q);
                         C wv[4];
@@ -557,10 +582,11 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                             ir += (double)wv[j] * (double)mj[0];
                             iu += (double)wv[j] * (double)mj[1];
                             iv += (double)wv[j] * (double)mj[2];
+                            sw += (double)wv[j];
                         }
                     }
-                    const double rh = 1.0 + ir;
-                    fback = omega<double>(kp + 1) + feq_off<double>(kp + 1, 1.0, ir, rh, iu, iv) +
+                    const double rh = 1.0 + ir + (sw - 1.0);
+                    fback = feq_off<double>(kp + 1, 1.0, rh - 1.0, rh, iu, iv) +
                             0.5 * force_k<double>(kp + 1, 1.0, rh, iu, iv, a.gx, a.gy);
                 }
                 Fx += EX[kp + 1] * (fout + fback);
@@ -618,11 +644,11 @@ int block_of(const mlbm_step_params *p) {
 
 using StepFn = void (*)(const StepArgs);
 
-template <int S>
+template <int S, class C>
 StepFn pick_step(int variant, int kq) {
 #define MLBM_CASE(Q)                                                        \
     case Q:                                                                 \
-        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, Q> : (StepFn)k_step_fields<S, Q>;
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, C, Q> : (StepFn)k_step_fields<S, C, Q>;
     switch (kq) {
         MLBM_CASE(2)
         MLBM_CASE(3)
@@ -637,12 +663,16 @@ StepFn pick_step(int variant, int kq) {
 #undef MLBM_CASE
 }
 
-StepFn pick_step_any(int storage, int variant, int kq) {
+// FP32 state is updated with FP64 register arithmetic unless fp32_arith is set
+// (the kernel is bound by memory traffic, so the wider arithmetic is nearly
+// free and removes the FP32 rounding drift); 16-bit states use FP32.
+StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith) {
     switch (storage) {
-        case MLBM_F64: return pick_step<MLBM_F64>(variant, kq);
-        case MLBM_F32: return pick_step<MLBM_F32>(variant, kq);
-        case MLBM_F16S: return pick_step<MLBM_F16S>(variant, kq);
-        case MLBM_BF16: return pick_step<MLBM_BF16>(variant, kq);
+        case MLBM_F64: return pick_step<MLBM_F64, double>(variant, kq);
+        case MLBM_F32:
+            return fp32_arith ? pick_step<MLBM_F32, float>(variant, kq) : pick_step<MLBM_F32, double>(variant, kq);
+        case MLBM_F16S: return pick_step<MLBM_F16S, float>(variant, kq);
+        case MLBM_BF16: return pick_step<MLBM_BF16, float>(variant, kq);
     }
     return nullptr;
 }
@@ -728,7 +758,7 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     const int blk = block_of(p);
     if (blk != 64 && blk != 128 && blk != 256) return fail(MLBM_ERR_ARG, "block must be 64, 128 or 256");
     const int kq = (st->K + 3) / 4;
-    StepFn fn = pick_step_any(p->storage, p->variant, kq);
+    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith);
     if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
         return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
@@ -745,12 +775,14 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     a.scale = std::ldexp(1.0f, p->scale_exp);
     a.inv_scale = std::ldexp(1.0f, -p->scale_exp);
     a.xcd = p->xcd_remap ? 1 : 0;
+    a.cached = p->cached_weights ? 1 : 0;
     const int64_t nb = (st->n + blk - 1) / blk;
     a.grid8 = a.xcd ? (nb + 7) / 8 * 8 : nb;
     hipStream_t s = (hipStream_t)stream;
     for (int t = 0; t < nsteps; ++t) {
         a.in = st->state[st->cur];
         a.out = st->state[st->cur ^ 1];
+        a.reverse = p->alternate_sweeps && st->cur == 1;
         hipLaunchKernelGGL(fn, dim3((unsigned)a.grid8), dim3(blk), 0, s, a);
         rc = hip_check("mlbm_step launch");
         if (rc) return rc;

@@ -94,7 +94,7 @@ class Simulation:
 
     def __init__(self, idx, w, bb, kind, area, *, variant=POPULATIONS, storage=F32, tau_plus=0.8,
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
-                 device="cuda"):
+                 fp32_arith=0, alternate_sweeps=1, cached_weights=0, device="cuda"):
         import torch
 
         self.torch = torch
@@ -124,6 +124,9 @@ class Simulation:
         self.params.scale_exp = int(scale_exp)
         self.params.block = int(block)
         self.params.xcd_remap = int(xcd_remap)
+        self.params.fp32_arith = int(fp32_arith)
+        self.params.alternate_sweeps = int(alternate_sweeps)
+        self.params.cached_weights = int(cached_weights)
         self.ds = DeviceState()
         self.ds.n = n
         self.ds.K = K

@@ -128,7 +128,9 @@ def test_reductions_match_oracle(M, name):
     assert red[8] == 0 and red[9] == ns.n
     if var == 0:
         F = omlbm.bounce_back_force(f_ref, ns, st, tp, tm, g, dx)
-        np.testing.assert_allclose(red[6:8], F, rtol=1e-9, atol=1e-12 * np.abs(F).max())
+    else:
+        F = omlbm.mlbm1_bounce_back_force(r_ref, u_ref, ns, st, g, dx)
+    np.testing.assert_allclose(red[6:8], F, rtol=1e-9, atol=1e-9 * np.abs(F).max())
     # residual against a previous velocity field
     import torch
 
@@ -144,8 +146,10 @@ def test_launch_shape_and_determinism(M):
     # every node's update is independent of the launch shape: block size and
     # XCD remapping give bitwise-identical states, and reruns are identical
     outs = []
-    for blk, xcd in ((256, 1), (256, 0), (64, 1), (128, 0), (256, 1)):
-        sim, rho, u, red = _run_gpu(M, "channel_trt", 1, block=blk, xcd_remap=xcd)
+    for blk, xcd, sweeps, cached in ((256, 1, 1, 0), (256, 0, 0, 0), (64, 1, 0, 1), (128, 0, 1, 1),
+                                     (256, 1, 1, 0)):
+        sim, rho, u, red = _run_gpu(M, "channel_trt", 1, block=blk, xcd_remap=xcd,
+                                    alternate_sweeps=sweeps, cached_weights=cached)
         outs.append((sim.state_bytes(), red))
     for s, r in outs[1:]:
         np.testing.assert_array_equal(s, outs[0][0])
