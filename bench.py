@@ -73,6 +73,29 @@ def cpu_baseline(ns_perm, b, tau, budget_s=15.0):
                       f"({dt:.1f} s, numpy single thread)"}
 
 
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy: the reference that scales the HBM
+    byte counters and the practical bandwidth of the box."""
+    import torch
+
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
+                      "GBps_read_plus_write": 2 * 4 * n / ms / 1e6}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,7 +112,12 @@ def main():
     ap.add_argument("--cached", type=int, default=0, help="ordinary (not non-temporal) weight loads")
     ap.add_argument("--nodes", type=int, default=500_000, help="target node count of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a 1 GiB device copy (reference for byte counters and bandwidth)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "halo-exchange design is described but not built.", file=sys.stderr)
