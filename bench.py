@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--trt", type=int, default=0, help="TRT with Lambda = 3/16 instead of BGK")
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16"])
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--tile", type=int, default=256, help="LDS-staged tile size (0 = global gathers)")
     ap.add_argument("--xcd", type=int, default=1)
     ap.add_argument("--fp32-arith", type=int, default=0, help="FP32 register arithmetic for f32 storage")
     ap.add_argument("--sweeps", type=int, default=1, help="alternate the tile sweep direction")
@@ -147,7 +148,8 @@ def main():
     sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
                        storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
                        block=args.block, xcd_remap=args.xcd, scale_exp=12, fp32_arith=args.fp32_arith,
-                       alternate_sweeps=args.sweeps, cached_weights=args.cached)
+                       alternate_sweeps=args.sweeps, cached_weights=args.cached,
+                       tile=args.tile)
     n = ns.n
     sim.init_state(np.ones(n), np.zeros((n, 2)))
     sim.step(args.warmup)
@@ -171,7 +173,7 @@ def main():
     bpn = units.algorithmic_bytes_per_node(M.POPULATIONS, storage, kp)
     achieved = bpn * n / per_launch_s / 1e9
     workload = f"karman-n{n}-K{K}-s{args.s:g}"
-    kernel = "k_step_pop"
+    kernel = "k_step_pop" + ("_lds" if args.tile else "")
     traffic = measured_traffic(kernel, workload)
     out = {
         "metric": METRIC,
@@ -194,7 +196,7 @@ def main():
                                f"{args.storage} populations",
                    "nodes": n, "K": K, "s": args.s, "block": args.block, "xcd_remap": args.xcd,
                    "fp32_arith": args.fp32_arith, "alternate_sweeps": args.sweeps,
-                   "cached_weights": args.cached,
+                   "cached_weights": args.cached, "tile": args.tile,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -144,6 +144,24 @@ int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx
                        const uint8_t *bb, const uint8_t *kind, void *idx_packed, void *w_packed,
                        uint16_t *flags);
 
+/*
+ * Tile-local indices for LDS staging.  A tile is `tile` (64, 128 or 256)
+ * consecutive nodes, processed by one workgroup of that size.  Its halo is the
+ * sorted list of distinct nodes referenced by its stencils (its own nodes
+ * included).  Outputs (host, caller-allocated):
+ *   halo_off int32 [ntiles + 1]   CSR offsets into halo, ntiles = ceil(n / tile)
+ *   halo     int32 [total_halo]   node indices
+ *   lidx     uint16 [K8/8][n][8]  position of stencil member j of node i in its
+ *                                 tile's halo (K8 = K rounded up to 8; padding
+ *                                 members point at the node itself)
+ * mlbm_tile_sizes returns total_halo and the largest halo.  idx is the
+ * builder's [n][K] array.  Errors: MLBM_ERR_ARG.
+ */
+int mlbm_tile_sizes(int64_t n, int32_t K, int32_t tile, const int32_t *idx, int64_t *total_halo,
+                    int32_t *max_halo);
+int mlbm_pack_tiles(int64_t n, int32_t K, int32_t tile, const int32_t *idx, int32_t *halo_off,
+                    int32_t *halo, uint16_t *lidx);
+
 /* ---- time stepping (device) ------------------------------------------------ */
 typedef struct mlbm_step_params {
     int32_t variant;         /* MLBM_POPULATIONS or MLBM_FIELDS                    */
@@ -174,6 +192,13 @@ typedef struct mlbm_device_state {
     void *state[2];          /* device ping-pong state buffers (state_bytes each)  */
     int32_t cur;             /* index (0/1) of the buffer holding the current state;
                                 mlbm_step updates it                                */
+    int32_t tile;            /* 0: gather stencil members from global memory; 64, 128
+                                or 256: stage each tile's halo in LDS (workgroup =
+                                tile nodes) using the three arrays below            */
+    int32_t max_halo;        /* largest halo (from mlbm_tile_sizes)                 */
+    const int32_t *halo_off; /* device copies of mlbm_pack_tiles' outputs           */
+    const int32_t *halo;
+    const uint16_t *lidx;
 } mlbm_device_state;
 
 /*

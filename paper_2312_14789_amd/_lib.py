@@ -60,7 +60,9 @@ class StepParams(ctypes.Structure):
 
 class DeviceState(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("K", ctypes.c_int32), ("idx", _p), ("w", _p),
-                ("flags", _p), ("bc", _p), ("state", _p * 2), ("cur", ctypes.c_int32)]
+                ("flags", _p), ("bc", _p), ("state", _p * 2), ("cur", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("max_halo", ctypes.c_int32), ("halo_off", _p),
+                ("halo", _p), ("lidx", _p)]
 
 
 class MlbmError(RuntimeError):
@@ -88,6 +90,9 @@ def _load():
                                              ctypes.c_int32, P(Sizes)]),
         "mlbm_pack_stencils": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _p, _p,
                                               _p, _p, _p, _p, _p]),
+        "mlbm_tile_sizes": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _p,
+                                           P(ctypes.c_int64), P(ctypes.c_int32)]),
+        "mlbm_pack_tiles": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p]),
         "mlbm_init_state": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, _p, _p]),
         "mlbm_step": (ctypes.c_int, [P(StepParams), P(DeviceState), ctypes.c_int32, _p]),
         "mlbm_reduction_workspace_bytes": (ctypes.c_int64, [ctypes.c_int64]),
@@ -106,7 +111,8 @@ def _load():
 lib = _load()
 
 # every symbol the header declares (checked by the tests)
-EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_init_state",
+EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_tile_sizes",
+           "mlbm_pack_tiles", "mlbm_init_state",
            "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
            "mlbm_version"]
 

@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "mlbm.h"
 #include "mlbm_internal.h"
@@ -263,6 +264,9 @@ struct StepArgs {
     int xcd;
     int reverse;   // sweep the tiles in reverse order (alternating sweeps)
     int cached;    // plain loads for weights and indices instead of non-temporal
+    const int *halo_off;       // LDS staging: per-tile CSR offsets into halo
+    const int *halo;           // LDS staging: halo node lists
+    const unsigned short *lidx;  // LDS staging: tile-local member positions [K8/8][n][8]
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin; with xcd each XCD gets
@@ -281,12 +285,87 @@ __device__ __forceinline__ int64_t node_of(const StepArgs &a) {
     return b * (int64_t)blockDim.x + threadIdx.x;
 }
 
+__device__ __forceinline__ int64_t tile_of(const StepArgs &a) {
+    int64_t b = blockIdx.x;
+    if (a.xcd) {
+        const int64_t per = a.grid8 >> 3;
+        const int64_t r = b >> 3;
+        b = (b & 7) * per + (a.reverse ? per - 1 - r : r);
+    } else if (a.reverse) {
+        b = a.grid8 - 1 - b;
+    }
+    return b;
+}
+
+// Copies the state of every halo node of `tile` into LDS (NB bytes per node,
+// same layout as the global state), coalesced over 16-byte (or 8-byte) units.
+template <int NB>
+__device__ __forceinline__ void stage_halo(const StepArgs &a, int64_t tile, void *smem) {
+    const int h0 = a.halo_off[tile], hn = a.halo_off[tile + 1] - h0;
+    if constexpr (NB >= 16) {
+        constexpr int U = NB / 16;
+        const u4 *src = (const u4 *)a.in;
+        u4 *dst = (u4 *)smem;
+        for (int e = threadIdx.x; e < hn * U; e += blockDim.x) {
+            const int h = e / U, c = e - h * U;
+            dst[e] = src[(int64_t)a.halo[h0 + h] * U + c];
+        }
+    } else {
+        const u2 *src = (const u2 *)a.in;
+        u2 *dst = (u2 *)smem;
+        for (int h = threadIdx.x; h < hn; h += blockDim.x) dst[h] = src[a.halo[h0 + h]];
+    }
+    __syncthreads();
+}
+
+// bytes per node of the [n][8] population block / the [n][4] field block
+template <int S> constexpr int pop_bytes() { return 8 * Fmt<S>::TB; }
+template <int S> constexpr int field_bytes() { return 4 * Fmt<S>::TB; }
+
+// four stencil members of quad q: global node indices, or halo positions when staged
+template <bool LDS, int Q>
+__device__ __forceinline__ void members(const StepArgs &a, int64_t n, int64_t i, u4 &lv, int *m) {
+    if constexpr (LDS) {
+        if constexpr ((Q & 1) == 0) lv = stream_load((const u4 *)a.lidx + ((int64_t)(Q >> 1) * n + i), a.cached);
+        const unsigned lo = (Q & 1) ? lv.z : lv.x, hi = (Q & 1) ? lv.w : lv.y;
+        m[0] = (int)(lo & 0xffffu);
+        m[1] = (int)(lo >> 16);
+        m[2] = (int)(hi & 0xffffu);
+        m[3] = (int)(hi >> 16);
+    } else {
+        const i4 id = load_idx4(a.idx, n, i, Q, a.cached);
+        m[0] = id.x;
+        m[1] = id.y;
+        m[2] = id.z;
+        m[3] = id.w;
+    }
+}
+
+// compile-time loop over the stencil quads
+template <int Q, int KQ, class F>
+__device__ __forceinline__ void for_quads(F &&f) {
+    if constexpr (Q < KQ) {
+        f(std::integral_constant<int, Q>{});
+        for_quads<Q + 1, KQ>(f);
+    }
+}
+
 // ---- population MLBM step ------------------------------------------------------
 
-template <int S, class C, int KQ>
+template <int S, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
-    const int64_t i = node_of(a);
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t i;
+    if constexpr (LDS) {
+        const int64_t tile = tile_of(a);
+        if (tile * blockDim.x >= a.n) return;  // whole workgroup past the end
+        stage_halo<pop_bytes<S>()>(a, tile, smem);
+        i = tile * blockDim.x + threadIdx.x;
+    } else {
+        i = node_of(a);
+    }
     if (i >= a.n) return;
+    const void *src = LDS ? (const void *)smem : a.in;
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
@@ -303,14 +382,14 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
         C acc[8], sw[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[k] = sw[k] = C(0);
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            const i4 id = load_idx4(a.idx, n, i, q, a.cached);
+        u4 lv;
+        for_quads<0, KQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            int m[4];
+            members<LDS, q>(a, n, i, lv, m);
             C s[4][8];
-            load8<S>(a.in, id.x, s[0], a.inv_scale);
-            load8<S>(a.in, id.y, s[1], a.inv_scale);
-            load8<S>(a.in, id.z, s[2], a.inv_scale);
-            load8<S>(a.in, id.w, s[3], a.inv_scale);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) load8<S>(src, m[j], s[j], a.inv_scale);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 C wv[4];
@@ -323,7 +402,7 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
                     if constexpr (kWsum) sw[k] += wv[j];
                 }
             }
-        }
+        });
         f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
 #pragma unroll
         for (int k = 0; k < 8; ++k) f[k + 1] = kWsum ? acc[k] + omega<C>(k + 1) * (sw[k] - C(1)) : acc[k];
@@ -335,10 +414,20 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
 
 // ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
 
-template <int S, class C, int KQ>
+template <int S, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
-    const int64_t i = node_of(a);
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t i;
+    if constexpr (LDS) {
+        const int64_t tile = tile_of(a);
+        if (tile * blockDim.x >= a.n) return;
+        stage_halo<field_bytes<S>()>(a, tile, smem);
+        i = tile * blockDim.x + threadIdx.x;
+    } else {
+        i = node_of(a);
+    }
     if (i >= a.n) return;
+    const void *src = LDS ? (const void *)smem : a.in;
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
@@ -352,14 +441,14 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
         C ar[8], au[8], av[8], sw[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) ar[k] = au[k] = av[k] = sw[k] = C(0);
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            const i4 id = load_idx4(a.idx, n, i, q, a.cached);
+        u4 lv;
+        for_quads<0, KQ>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            int mi[4];
+            members<LDS, q>(a, n, i, lv, mi);
             C m[4][3];
-            load3<S>(a.in, id.x, m[0], a.inv_scale);
-            load3<S>(a.in, id.y, m[1], a.inv_scale);
-            load3<S>(a.in, id.z, m[2], a.inv_scale);
-            load3<S>(a.in, id.w, m[3], a.inv_scale);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) load3<S>(src, mi[j], m[j], a.inv_scale);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 C wv[4];
@@ -372,7 +461,7 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
                     if constexpr (kWsum) sw[k] += wv[j];
                 }
             }
-        }
+        });
         if constexpr (kWsum) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) ar[k] += sw[k] - C(1);
@@ -637,6 +726,8 @@ int check_common(const mlbm_step_params *p, const mlbm_device_state *st) {
     return MLBM_OK;
 }
 
+int storage_bytes(int storage) { return storage == MLBM_F64 ? 8 : storage == MLBM_F32 ? 4 : 2; }
+
 int block_of(const mlbm_step_params *p) {
     const int b = p->block == 0 ? 256 : p->block;
     return b;
@@ -645,10 +736,14 @@ int block_of(const mlbm_step_params *p) {
 using StepFn = void (*)(const StepArgs);
 
 template <int S, class C>
-StepFn pick_step(int variant, int kq) {
-#define MLBM_CASE(Q)                                                        \
-    case Q:                                                                 \
-        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, C, Q> : (StepFn)k_step_fields<S, C, Q>;
+StepFn pick_step(int variant, int kq, bool lds) {
+#define MLBM_CASE(Q)                                                                            \
+    case Q:                                                                                     \
+        if (lds)                                                                                \
+            return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, C, Q, true>              \
+                                               : (StepFn)k_step_fields<S, C, Q, true>;          \
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, C, Q, false>                 \
+                                           : (StepFn)k_step_fields<S, C, Q, false>;
     switch (kq) {
         MLBM_CASE(2)
         MLBM_CASE(3)
@@ -666,13 +761,14 @@ StepFn pick_step(int variant, int kq) {
 // FP32 state is updated with FP64 register arithmetic unless fp32_arith is set
 // (the kernel is bound by memory traffic, so the wider arithmetic is nearly
 // free and removes the FP32 rounding drift); 16-bit states use FP32.
-StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith) {
+StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith, bool lds) {
     switch (storage) {
-        case MLBM_F64: return pick_step<MLBM_F64, double>(variant, kq);
+        case MLBM_F64: return pick_step<MLBM_F64, double>(variant, kq, lds);
         case MLBM_F32:
-            return fp32_arith ? pick_step<MLBM_F32, float>(variant, kq) : pick_step<MLBM_F32, double>(variant, kq);
-        case MLBM_F16S: return pick_step<MLBM_F16S, float>(variant, kq);
-        case MLBM_BF16: return pick_step<MLBM_BF16, float>(variant, kq);
+            return fp32_arith ? pick_step<MLBM_F32, float>(variant, kq, lds)
+                              : pick_step<MLBM_F32, double>(variant, kq, lds);
+        case MLBM_F16S: return pick_step<MLBM_F16S, float>(variant, kq, lds);
+        case MLBM_BF16: return pick_step<MLBM_BF16, float>(variant, kq, lds);
     }
     return nullptr;
 }
@@ -755,10 +851,22 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     if (rc) return rc;
     if (nsteps < 0) return fail(MLBM_ERR_ARG, "nsteps must be >= 0");
     if (!st->idx || !st->w) return fail(MLBM_ERR_ARG, "null stencil buffer");
-    const int blk = block_of(p);
-    if (blk != 64 && blk != 128 && blk != 256) return fail(MLBM_ERR_ARG, "block must be 64, 128 or 256");
+    const bool lds = st->tile != 0;
+    const int blk = lds ? st->tile : block_of(p);
+    if (blk != 64 && blk != 128 && blk != 256) return fail(MLBM_ERR_ARG, "block / tile must be 64, 128 or 256");
     const int kq = (st->K + 3) / 4;
-    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith);
+    size_t shmem = 0;
+    if (lds) {
+        if (!st->halo_off || !st->halo || !st->lidx) return fail(MLBM_ERR_ARG, "null tile buffer");
+        const int ts = storage_bytes(p->storage);
+        const int nb = p->variant == MLBM_POPULATIONS ? 8 * ts : 4 * ts;
+        if (st->max_halo < 1) return fail(MLBM_ERR_ARG, "max_halo must be positive");
+        shmem = (size_t)st->max_halo * nb;
+        if (shmem > 65536)
+            return fail(MLBM_ERR_UNSUPPORTED, "halo of %d nodes needs %zu bytes of LDS (> 64 KiB); use tile 0 or a smaller tile",
+                        st->max_halo, shmem);
+    }
+    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith, lds);
     if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
         return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
@@ -776,6 +884,9 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     a.inv_scale = std::ldexp(1.0f, -p->scale_exp);
     a.xcd = p->xcd_remap ? 1 : 0;
     a.cached = p->cached_weights ? 1 : 0;
+    a.halo_off = st->halo_off;
+    a.halo = st->halo;
+    a.lidx = st->lidx;
     const int64_t nb = (st->n + blk - 1) / blk;
     a.grid8 = a.xcd ? (nb + 7) / 8 * 8 : nb;
     hipStream_t s = (hipStream_t)stream;
@@ -783,7 +894,7 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
         a.in = st->state[st->cur];
         a.out = st->state[st->cur ^ 1];
         a.reverse = p->alternate_sweeps && st->cur == 1;
-        hipLaunchKernelGGL(fn, dim3((unsigned)a.grid8), dim3(blk), 0, s, a);
+        hipLaunchKernelGGL(fn, dim3((unsigned)a.grid8), dim3(blk), shmem, s, a);
         rc = hip_check("mlbm_step launch");
         if (rc) return rc;
         st->cur ^= 1;

@@ -515,3 +515,73 @@ extern "C" int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const i
     }
     return MLBM_OK;
 }
+
+// ---- tile-local stencil indices (LDS staging) --------------------------------
+//
+// A tile is `tile` consecutive nodes (one workgroup).  Its halo is the sorted
+// set of distinct nodes its stencils reference (the tile's own nodes
+// included); each stencil member is re-addressed as a 16-bit position in that
+// halo, so a workgroup can stage the halo state in LDS once and gather from it.
+
+namespace {
+
+int tile_halo(const int32_t *idx, int64_t n, int K, int64_t tile, int64_t t, std::vector<int32_t> &h) {
+    const int64_t a = t * tile, b = std::min(n, a + tile);
+    h.assign(idx + a * K, idx + b * K);
+    std::sort(h.begin(), h.end());
+    h.erase(std::unique(h.begin(), h.end()), h.end());
+    return (int)h.size();
+}
+
+}  // namespace
+
+extern "C" int mlbm_tile_sizes(int64_t n, int32_t K, int32_t tile, const int32_t *idx, int64_t *total_halo,
+                               int32_t *max_halo) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (!idx || !total_halo || !max_halo) return fail(MLBM_ERR_ARG, "null pointer argument");
+    if (n < 1 || K < 1 || K > MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
+    if (tile != 64 && tile != 128 && tile != 256) return fail(MLBM_ERR_ARG, "tile must be 64, 128 or 256");
+    const int64_t nt = (n + tile - 1) / tile;
+    int64_t tot = 0;
+    int32_t mx = 0;
+    std::vector<int32_t> h;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int c = tile_halo(idx, n, K, tile, t, h);
+        tot += c;
+        mx = std::max(mx, c);
+    }
+    *total_halo = tot;
+    *max_halo = mx;
+    return MLBM_OK;
+}
+
+extern "C" int mlbm_pack_tiles(int64_t n, int32_t K, int32_t tile, const int32_t *idx, int32_t *halo_off,
+                               int32_t *halo, uint16_t *lidx) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (!idx || !halo_off || !halo || !lidx) return fail(MLBM_ERR_ARG, "null pointer argument");
+    if (n < 1 || K < 1 || K > MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
+    if (tile != 64 && tile != 128 && tile != 256) return fail(MLBM_ERR_ARG, "tile must be 64, 128 or 256");
+    const int64_t nt = (n + tile - 1) / tile;
+    const int k8 = (K + 7) / 8 * 8;
+    std::vector<int32_t> h;
+    int64_t off = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int c = tile_halo(idx, n, K, tile, t, h);
+        if (off > INT32_MAX - c) return fail(MLBM_ERR_ARG, "halo lists exceed 2^31 entries");
+        halo_off[t] = (int32_t)off;
+        std::copy(h.begin(), h.end(), halo + off);
+        const int64_t a = t * tile, b = std::min(n, a + tile);
+        for (int64_t i = a; i < b; ++i) {
+            for (int j = 0; j < k8; ++j) {
+                int32_t g = j < K ? idx[i * K + j] : (int32_t)i;
+                const int32_t pos = (int32_t)(std::lower_bound(h.begin(), h.end(), g) - h.begin());
+                lidx[((int64_t)(j / 8) * n + i) * 8 + (j % 8)] = (uint16_t)pos;
+            }
+        }
+        off += c;
+    }
+    halo_off[nt] = (int32_t)off;
+    return MLBM_OK;
+}

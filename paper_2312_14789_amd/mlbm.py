@@ -86,6 +86,22 @@ def pack_stencils(idx, w, bb, kind, storage):
     return ip, wp, fl
 
 
+def pack_tiles(idx, tile):
+    """mlbm_tile_sizes + mlbm_pack_tiles: (halo_off, halo, lidx, max_halo)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    n, K = idx.shape
+    total = ctypes.c_int64()
+    mx = ctypes.c_int32()
+    check(lib.mlbm_tile_sizes(n, K, tile, _ptr(idx), ctypes.byref(total), ctypes.byref(mx)))
+    nt = (n + tile - 1) // tile
+    halo_off = np.zeros(nt + 1, np.int32)
+    halo = np.zeros(max(total.value, 1), np.int32)
+    k8 = (K + 7) // 8 * 8
+    lidx = np.zeros(k8 * n, np.uint16)
+    check(lib.mlbm_pack_tiles(n, K, tile, _ptr(idx), _ptr(halo_off), _ptr(halo), _ptr(lidx)))
+    return halo_off, halo, lidx, mx.value
+
+
 class Simulation:
     """Device buffers (PyTorch) and parameters of one node set.
 
@@ -94,7 +110,7 @@ class Simulation:
 
     def __init__(self, idx, w, bb, kind, area, *, variant=POPULATIONS, storage=F32, tau_plus=0.8,
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
-                 fp32_arith=0, alternate_sweeps=1, cached_weights=0, device="cuda"):
+                 fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda"):
         import torch
 
         self.torch = torch
@@ -137,6 +153,26 @@ class Simulation:
         self.ds.state[0] = self.state_d[0].data_ptr()
         self.ds.state[1] = self.state_d[1].data_ptr()
         self.ds.cur = 0
+        self.set_tile(tile, idx)
+
+    def set_tile(self, tile, idx=None):
+        """Selects global gathers (tile 0) or LDS-staged tiles of 64/128/256
+        nodes (packs the tile halos from the [n][K] stencil indices)."""
+        self.ds.tile = int(tile)
+        if tile:
+            if idx is None:
+                idx = self._idx_host
+            halo_off, halo, lidx, mx = pack_tiles(idx, tile)
+            t = self.torch
+            dev = self.state_d[0].device
+            self.halo_off_d = t.from_numpy(halo_off).to(dev)
+            self.halo_d = t.from_numpy(halo).to(dev)
+            self.lidx_d = t.from_numpy(lidx.view(np.int16)).to(dev)
+            self.ds.max_halo = mx
+            self.ds.halo_off = self.halo_off_d.data_ptr()
+            self.ds.halo = self.halo_d.data_ptr()
+            self.ds.lidx = self.lidx_d.data_ptr()
+        self._idx_host = np.ascontiguousarray(idx if idx is not None else self._idx_host, dtype=np.int32)
 
     def _stream(self, stream=None):
         s = stream if stream is not None else self.torch.cuda.current_stream()

@@ -96,13 +96,13 @@ def _run_gpu(M, name, storage, **kw):
 
 
 @pytest.mark.parametrize("name", ["tgv64", "channel_trt", "karman_small", "porous_fields", "k25_fields"])
-@pytest.mark.parametrize("storage", [0, 1])
-def test_step_parity(M, name, storage):
-    print(f"[parity] case={name} storage={storage}", flush=True)
+@pytest.mark.parametrize("storage,tile", [(0, 256), (1, 256), (0, 0), (1, 0)])
+def test_step_parity(M, name, storage, tile):
+    print(f"[parity] case={name} storage={storage} tile={tile}", flush=True)
     ns, st, var, tp, tm, g, steps, rho0, u0, dx, r_ref, u_ref, _ = _case(name)
-    _, rho, u, _ = _run_gpu(M, name, storage)
+    _, rho, u, _ = _run_gpu(M, name, storage, tile=tile)
     err = rel_l2(u, u_ref)
-    print(f"[parity] case={name} storage={storage} rel_l2_u={err:.3e}", flush=True)
+    print(f"[parity] case={name} storage={storage} tile={tile} rel_l2_u={err:.3e}", flush=True)
     assert err <= BAR[storage]
     assert rel_l2(rho - 1.0, r_ref - 1.0) <= 10 * BAR[storage] or np.abs(rho - r_ref).max() < BAR[storage]
 
@@ -146,10 +146,10 @@ def test_launch_shape_and_determinism(M):
     # every node's update is independent of the launch shape: block size and
     # XCD remapping give bitwise-identical states, and reruns are identical
     outs = []
-    for blk, xcd, sweeps, cached in ((256, 1, 1, 0), (256, 0, 0, 0), (64, 1, 0, 1), (128, 0, 1, 1),
-                                     (256, 1, 1, 0)):
+    for blk, xcd, sweeps, cached, tile in ((256, 1, 1, 0, 256), (256, 0, 0, 0, 0), (64, 1, 0, 1, 0),
+                                           (128, 0, 1, 1, 128), (256, 1, 1, 0, 64), (256, 1, 1, 0, 256)):
         sim, rho, u, red = _run_gpu(M, "channel_trt", 1, block=blk, xcd_remap=xcd,
-                                    alternate_sweeps=sweeps, cached_weights=cached)
+                                    alternate_sweeps=sweeps, cached_weights=cached, tile=tile)
         outs.append((sim.state_bytes(), red))
     for s, r in outs[1:]:
         np.testing.assert_array_equal(s, outs[0][0])
@@ -163,10 +163,20 @@ def test_zero_steps_and_errors(M):
     before = sim.state_bytes()
     sim.step(0)
     np.testing.assert_array_equal(sim.state_bytes(), before)
+    sim.ds.tile = 96
+    with pytest.raises(M.MlbmError):
+        sim.step(1)
+    sim.ds.tile = 0
     sim.params.block = 96
     with pytest.raises(M.MlbmError):
         sim.step(1)
     sim.params.block = 256
+    sim.ds.tile = 256
+    mh = sim.ds.max_halo
+    sim.ds.max_halo = 5000          # halo beyond the LDS budget is refused, not launched
+    with pytest.raises(M.MlbmError):
+        sim.step(1)
+    sim.ds.max_halo = mh
     sim.params.variant = 1
     with pytest.raises(M.MlbmError):   # the fields variant fixes tau = 1
         sim.step(1)

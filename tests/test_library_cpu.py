@@ -177,3 +177,24 @@ def test_unit_conversions_reproduce_paper_numbers():
     a = 0.5
     assert units.time_step(a * 1e-3, 1.0, 0.8) == pytest.approx(a * a * units.time_step(1e-3, 1.0, 0.8))
     assert units.delta_x(0.01, 4) == pytest.approx(0.0025)
+
+
+def test_tile_halo_packing():
+    # every stencil member is found at its 16-bit position in its tile's halo,
+    # halos are sorted and distinct, and contain the tile's own nodes
+    ns = nodesets.porous(6000, seed=12, r_range=(0.03, 0.06))
+    b = M.build_stencils_for(ns, 16, ns.h / 2)
+    n, K = b["idx"].shape
+    for tile in (64, 128, 256):
+        ho, h, l, mx = M.pack_tiles(b["idx"], tile)
+        assert len(ho) == (n + tile - 1) // tile + 1 and ho[0] == 0
+        assert mx == np.diff(ho).max()
+        l = l.reshape(2, n, 8).transpose(1, 0, 2).reshape(n, 16)
+        for t in range(len(ho) - 1):
+            hl = h[ho[t]:ho[t + 1]]
+            assert np.all(np.diff(hl) > 0)
+            nodes = np.arange(t * tile, min(n, (t + 1) * tile))
+            np.testing.assert_array_equal(hl[l[nodes]], b["idx"][nodes])
+            assert np.isin(nodes, hl).all()
+    with pytest.raises(M.MlbmError):
+        M.pack_tiles(b["idx"], 100)
