@@ -58,7 +58,7 @@ extern "C" {
 #define MLBM_FIELDS      1  /* MLBM1, tau = 1, fields only (Sec. 2.2, Eqs. 14-15) */
 
 #define MLBM_F64  0  /* FP64 state, FP64 weights, FP64 arithmetic                 */
-#define MLBM_F32  1  /* FP32 state, FP32 weights, FP64 (or FP32) register arithmetic */
+#define MLBM_F32  1  /* FP32 state and weights, FP32 interpolation, FP64 collision */
 #define MLBM_F16S 2  /* FP16 state scaled by 2^scale_exp, FP32 weights/arithmetic */
 #define MLBM_BF16 3  /* BF16 state, FP32 weights and arithmetic                   */
 
@@ -173,8 +173,8 @@ typedef struct mlbm_step_params {
     int32_t block;           /* threads per workgroup, multiple of 64 in [64, 1024];
                                 0 = 256                                             */
     int32_t xcd_remap;       /* 1 = give each XCD a contiguous range of node tiles */
-    int32_t fp32_arith;      /* MLBM_F32 only: 1 = FP32 register arithmetic; 0 (default)
-                                = FP64 register arithmetic on the FP32 state       */
+    int32_t fp32_arith;      /* MLBM_F32 only: 1 = FP32 collision arithmetic; 0 (default)
+                                = FP64 collision (interpolation sums are FP32 either way) */
     int32_t alternate_sweeps;/* 1 = visit the node tiles in reverse order on every
                                 other step (the step reading state[1])             */
     int32_t cached_weights;  /* 1 = ordinary loads for weights and indices; 0 =

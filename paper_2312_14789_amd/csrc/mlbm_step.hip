@@ -352,7 +352,8 @@ __device__ __forceinline__ void for_quads(F &&f) {
 
 // ---- population MLBM step ------------------------------------------------------
 
-template <int S, class C, int KQ, bool LDS>
+// CG: gather (interpolation) arithmetic; C: collision arithmetic
+template <int S, class CG, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t i;
@@ -379,25 +380,25 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
         // exactly the interpolation of the populations; reduced precision drops
         // the (sum_j w_j - 1) omega term, which is weight rounding there.
         constexpr bool kWsum = S == MLBM_F64;
-        C acc[8], sw[8];
+        CG acc[8], sw[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = sw[k] = C(0);
+        for (int k = 0; k < 8; ++k) acc[k] = sw[k] = CG(0);
         u4 lv;
         for_quads<0, KQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             int m[4];
             members<LDS, q>(a, n, i, lv, m);
-            C s[4][8];
+            CG s[4][8];
 #pragma unroll
             for (int j = 0; j < 4; ++j) load8<S>(src, m[j], s[j], a.inv_scale);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                C wv[4];
+                CG wv[4];
                 load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
                 const bool flip = (bb >> k) & 1u;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const C v = flip ? s[j][OPP8[k]] : s[j][k];
+                    const CG v = flip ? s[j][OPP8[k]] : s[j][k];
                     acc[k] = fma(wv[j], v, acc[k]);
                     if constexpr (kWsum) sw[k] += wv[j];
                 }
@@ -405,7 +406,8 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
         });
         f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) f[k + 1] = kWsum ? acc[k] + omega<C>(k + 1) * (sw[k] - C(1)) : acc[k];
+        for (int k = 0; k < 8; ++k)
+            f[k + 1] = kWsum ? (C)acc[k] + omega<C>(k + 1) * ((C)sw[k] - C(1)) : (C)acc[k];
         collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
     }
     store8<S>(a.out, i, f + 1, a.scale);
@@ -414,7 +416,7 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
 
 // ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
 
-template <int S, class C, int KQ, bool LDS>
+template <int S, class CG, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t i;
@@ -438,20 +440,20 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
         out[2] = (C)a.bc[3 * i + 2];
     } else {
         constexpr bool kWsum = S == MLBM_F64;  // interpolate rho itself, not rho - 1
-        C ar[8], au[8], av[8], sw[8];
+        CG ar[8], au[8], av[8], sw[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) ar[k] = au[k] = av[k] = sw[k] = C(0);
+        for (int k = 0; k < 8; ++k) ar[k] = au[k] = av[k] = sw[k] = CG(0);
         u4 lv;
         for_quads<0, KQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             int mi[4];
             members<LDS, q>(a, n, i, lv, mi);
-            C m[4][3];
+            CG m[4][3];
 #pragma unroll
             for (int j = 0; j < 4; ++j) load3<S>(src, mi[j], m[j], a.inv_scale);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                C wv[4];
+                CG wv[4];
                 load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -464,7 +466,7 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
         });
         if constexpr (kWsum) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) ar[k] += sw[k] - C(1);
+            for (int k = 0; k < 8; ++k) ar[k] += sw[k] - CG(1);
         }
         const C gx = (C)a.gx, gy = (C)a.gy;
         C own[3];
@@ -476,9 +478,10 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const C sg = ((bb >> k) & 1u) ? C(-1) : C(1);  // source k' on bounce-back
-            const C rho = C(1) + ar[k];
-            const C fk = feq_off<C>(k + 1, sg, ar[k], rho, au[k], av[k]) +
-                         C(0.5) * force_k<C>(k + 1, sg, rho, au[k], av[k], gx, gy);
+            const C dr = (C)ar[k], uk = (C)au[k], vk = (C)av[k];
+            const C rho = C(1) + dr;
+            const C fk = feq_off<C>(k + 1, sg, dr, rho, uk, vk) +
+                         C(0.5) * force_k<C>(k + 1, sg, rho, uk, vk, gx, gy);
             sum += fk;
             jx += C(EX[k + 1]) * fk;
             jy += C(EY[k + 1]) * fk;
@@ -735,15 +738,15 @@ int block_of(const mlbm_step_params *p) {
 
 using StepFn = void (*)(const StepArgs);
 
-template <int S, class C>
+template <int S, class CG, class C>
 StepFn pick_step(int variant, int kq, bool lds) {
 #define MLBM_CASE(Q)                                                                            \
     case Q:                                                                                     \
         if (lds)                                                                                \
-            return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, C, Q, true>              \
-                                               : (StepFn)k_step_fields<S, C, Q, true>;          \
-        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, C, Q, false>                 \
-                                           : (StepFn)k_step_fields<S, C, Q, false>;
+            return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, CG, C, Q, true>          \
+                                               : (StepFn)k_step_fields<S, CG, C, Q, true>;      \
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, CG, C, Q, false>             \
+                                           : (StepFn)k_step_fields<S, CG, C, Q, false>;
     switch (kq) {
         MLBM_CASE(2)
         MLBM_CASE(3)
@@ -758,17 +761,19 @@ StepFn pick_step(int variant, int kq, bool lds) {
 #undef MLBM_CASE
 }
 
-// FP32 state is updated with FP64 register arithmetic unless fp32_arith is set
-// (the kernel is bound by memory traffic, so the wider arithmetic is nearly
-// free and removes the FP32 rounding drift); 16-bit states use FP32.
+// FP32 state: the interpolation sums run in FP32 and the collision in FP64
+// unless fp32_arith is set.  The FP32 rounding drift of a long run comes from
+// the collision (the interpolation in FP32 adds nothing measurable), and the
+// FP64 collision costs little in a kernel bound by memory traffic.  16-bit
+// states use FP32 throughout.
 StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith, bool lds) {
     switch (storage) {
-        case MLBM_F64: return pick_step<MLBM_F64, double>(variant, kq, lds);
+        case MLBM_F64: return pick_step<MLBM_F64, double, double>(variant, kq, lds);
         case MLBM_F32:
-            return fp32_arith ? pick_step<MLBM_F32, float>(variant, kq, lds)
-                              : pick_step<MLBM_F32, double>(variant, kq, lds);
-        case MLBM_F16S: return pick_step<MLBM_F16S, float>(variant, kq, lds);
-        case MLBM_BF16: return pick_step<MLBM_BF16, float>(variant, kq, lds);
+            return fp32_arith ? pick_step<MLBM_F32, float, float>(variant, kq, lds)
+                              : pick_step<MLBM_F32, float, double>(variant, kq, lds);
+        case MLBM_F16S: return pick_step<MLBM_F16S, float, float>(variant, kq, lds);
+        case MLBM_BF16: return pick_step<MLBM_BF16, float, float>(variant, kq, lds);
     }
     return nullptr;
 }

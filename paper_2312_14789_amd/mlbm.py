@@ -209,3 +209,26 @@ class Simulation:
     def state_bytes(self):
         """Current state buffer as a host numpy uint8 array (synchronises)."""
         return self.state_d[self.ds.cur].cpu().numpy()
+
+    def run_to_steady(self, dx, tol=1e-6, check_every=100, max_steps=1_000_000, stream=None):
+        """Steps until ||u^n - u^(n - check_every)|| / ||u^n|| < tol (checked every
+        check_every steps with mlbm_macroscopic; one small device-to-host copy
+        per check).  Returns (steps, residual, reductions as numpy)."""
+        t = self.torch
+        dev = self.state_d[0].device
+        u_prev = t.zeros((self.n, 2), dtype=t.float64, device=dev)
+        self.macroscopic(dx, u_prev=u_prev, want_fields=False, stream=stream)
+        steps = 0
+        res = float("inf")
+        red = None
+        while steps < max_steps:
+            self.step(check_every, stream=stream)
+            steps += check_every
+            _, _, red_d = self.macroscopic(dx, u_prev=u_prev, want_fields=False, stream=stream)
+            red = red_d.cpu().numpy()
+            if red[_lib.RED_N_BAD] > 0:
+                raise MlbmError(-6, f"unstable: {int(red[_lib.RED_N_BAD])} bad nodes, first {int(red[_lib.RED_FIRST_BAD])}")
+            res = float(np.sqrt(red[_lib.RED_NORM_DU2] / red[_lib.RED_NORM_U2])) if red[_lib.RED_NORM_U2] > 0 else 0.0
+            if res < tol:
+                break
+        return steps, res, red

@@ -80,3 +80,14 @@ def algorithmic_bytes_per_node(variant: int, storage: int, k_padded: int) -> int
     wb = 8 if storage == 0 else 4
     state = (9 if variant == 0 else 4) * tb
     return 2 * state + 8 * k_padded * wb + 4 * k_padded + 2
+
+
+def f16_scale_exp(u_ref: float, target: float = 1024.0) -> int:
+    """Power-of-two scale for FP16 offset storage: the stored value is
+    offset * 2^sigma, chosen so that an offset of the size of the reference
+    velocity u_ref maps to about `target` (well inside FP16's normal range,
+    ~60x below its largest value).  Population offsets are at most ~u/3 and
+    field offsets ~u, so both stay representable with margin."""
+    import math
+
+    return int(math.floor(math.log2(target / abs(u_ref))))
