@@ -145,6 +145,15 @@ int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx
                        uint16_t *flags);
 
 /*
+ * The same for nodes [offset, offset + n) of packed arrays sized for n_total
+ * nodes (idx, w, bb, kind hold the n rows; idx already counts from 0 of the
+ * whole set), so several node sets can be packed into one (batched runs).
+ */
+int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t n, int32_t K, int32_t storage,
+                             const int32_t *idx, const double *w, const uint8_t *bb, const uint8_t *kind,
+                             void *idx_packed, void *w_packed, uint16_t *flags);
+
+/*
  * Tile-local indices for LDS staging.  A tile is `tile` (64, 128 or 256)
  * consecutive nodes, processed by one workgroup of that size.  Its halo is the
  * sorted list of distinct nodes referenced by its stencils (its own nodes
@@ -219,6 +228,56 @@ int mlbm_init_state(const mlbm_step_params *params, mlbm_device_state *state, co
  */
 int mlbm_step(const mlbm_step_params *params, mlbm_device_state *state, int32_t nsteps,
               void *hip_stream);
+
+/* ---- batched runs (device) ----------------------------------------------------- */
+/*
+ * Many independent samples (e.g. porous media of uneven size) run as one
+ * concatenated node set whose tiles never straddle two samples (pad each
+ * sample to a multiple of `tile` nodes with Dirichlet nodes of zero area and
+ * no stencil).  mlbm_device_state must use tiles.  Persistent workgroups walk
+ * a device list of active tiles; every check_every steps each sample's
+ * residual ||u - u_prev|| / ||u|| is formed, samples below tol retire and the
+ * list is rebuilt on the device, so a captured graph of one check can be
+ * replayed until no sample is left.
+ */
+typedef struct mlbm_batch {
+    int32_t n_samples;               /* 1 .. 4096                                     */
+    int32_t check_every;             /* steps per check, even, >= 2                   */
+    int32_t grid;                    /* persistent workgroups (rounded up to 8); 0 = 1024 */
+    const int32_t *sample_tile_off;  /* device [n_samples + 1] tiles of sample s are
+                                        [off[s], off[s+1]); off[n_samples] = tile count */
+    const int32_t *sample_tile_off_host; /* the same offsets on the host (validation)  */
+    const double *area;              /* device [n] quadrature weights (0 on padding)  */
+    double *u_prev;                  /* device [n][2] workspace                       */
+    double *tile_red;                /* device [tiles][4] workspace                   */
+    int32_t *queue;                  /* device [tiles] workspace: active tile list     */
+    int32_t *counters;               /* device [4]: active tiles, steps, active samples,
+                                        checks                                        */
+    int32_t *sample_steps;           /* device [n_samples] out: steps to convergence; 0 =
+                                        not converged; -steps = unstable (non-finite) */
+    double *sample_residual;         /* device [n_samples] out: last residual          */
+    double *sample_int_ux;           /* device [n_samples] out: sum A u_x at last check */
+} mlbm_batch;
+
+/*
+ * Resets the batch (every sample active) and records the current velocity as
+ * u_prev.  Asynchronous.  Errors: MLBM_ERR_ARG, MLBM_ERR_HIP.
+ */
+int mlbm_batch_init(const mlbm_step_params *params, mlbm_device_state *state, mlbm_batch *batch,
+                    void *hip_stream);
+
+/*
+ * Runs checks of check_every steps until every sample has retired (residual
+ * below tol, or non-finite fields) or max_steps is reached.  With use_graph
+ * one check is captured into a HIP graph on hip_stream (which must not be the
+ * default stream) and replayed.  Synchronous: waits on hip_stream after each
+ * check to read 16 bytes of counters.  state->cur is unchanged on return (an
+ * even number of steps per check).  *steps_done receives the steps run.
+ * Errors: MLBM_ERR_ARG, MLBM_ERR_UNSUPPORTED, MLBM_ERR_HIP.
+ */
+int mlbm_step_batched(const mlbm_step_params *params, mlbm_device_state *state, mlbm_batch *batch,
+                      int32_t max_steps, double tol, int32_t use_graph, int32_t *steps_done,
+                      void *hip_stream);
 
 /* ---- macroscopic fields and reductions (device) ------------------------------ */
 #define MLBM_RED_MASS      0   /* sum A rho                                         */

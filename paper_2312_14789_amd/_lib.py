@@ -65,6 +65,13 @@ class DeviceState(ctypes.Structure):
                 ("halo", _p), ("lidx", _p)]
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int32), ("check_every", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("sample_tile_off", _p), ("sample_tile_off_host", _p), ("area", _p), ("u_prev", _p),
+                ("tile_red", _p), ("queue", _p), ("counters", _p), ("sample_steps", _p),
+                ("sample_residual", _p), ("sample_int_ux", _p)]
+
+
 class MlbmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"mlbm error {code}: {msg}")
@@ -90,6 +97,12 @@ def _load():
                                              ctypes.c_int32, P(Sizes)]),
         "mlbm_pack_stencils": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _p, _p,
                                               _p, _p, _p, _p, _p]),
+        "mlbm_pack_stencils_range": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                                    ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p,
+                                                    _p, _p]),
+        "mlbm_batch_init": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), _p]),
+        "mlbm_step_batched": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), ctypes.c_int32,
+                                             ctypes.c_double, ctypes.c_int32, P(ctypes.c_int32), _p]),
         "mlbm_tile_sizes": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _p,
                                            P(ctypes.c_int64), P(ctypes.c_int32)]),
         "mlbm_pack_tiles": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p]),
@@ -111,8 +124,8 @@ def _load():
 lib = _load()
 
 # every symbol the header declares (checked by the tests)
-EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_tile_sizes",
-           "mlbm_pack_tiles", "mlbm_init_state",
+EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_pack_stencils_range",
+           "mlbm_tile_sizes", "mlbm_pack_tiles", "mlbm_init_state", "mlbm_batch_init", "mlbm_step_batched",
            "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
            "mlbm_version"]
 

@@ -267,24 +267,14 @@ struct StepArgs {
     const int *halo_off;       // LDS staging: per-tile CSR offsets into halo
     const int *halo;           // LDS staging: halo node lists
     const unsigned short *lidx;  // LDS staging: tile-local member positions [K8/8][n][8]
+    const int *queue;          // batched launches: list of active tiles (NULL: every tile)
+    const int *queue_count;    // batched launches: number of entries in queue (device)
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin; with xcd each XCD gets
 // a contiguous range of tiles.  With reverse the tiles are visited in the
 // opposite order, so alternating sweeps start where the previous one ended and
 // meet its most recently cached data first.
-__device__ __forceinline__ int64_t node_of(const StepArgs &a) {
-    int64_t b = blockIdx.x;
-    if (a.xcd) {
-        const int64_t per = a.grid8 >> 3;
-        const int64_t r = b >> 3;
-        b = (b & 7) * per + (a.reverse ? per - 1 - r : r);
-    } else if (a.reverse) {
-        b = a.grid8 - 1 - b;
-    }
-    return b * (int64_t)blockDim.x + threadIdx.x;
-}
-
 __device__ __forceinline__ int64_t tile_of(const StepArgs &a) {
     int64_t b = blockIdx.x;
     if (a.xcd) {
@@ -301,6 +291,7 @@ __device__ __forceinline__ int64_t tile_of(const StepArgs &a) {
 // same layout as the global state), coalesced over 16-byte (or 8-byte) units.
 template <int NB>
 __device__ __forceinline__ void stage_halo(const StepArgs &a, int64_t tile, void *smem) {
+    __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
     const int h0 = a.halo_off[tile], hn = a.halo_off[tile + 1] - h0;
     if constexpr (NB >= 16) {
         constexpr int U = NB / 16;
@@ -316,6 +307,25 @@ __device__ __forceinline__ void stage_halo(const StepArgs &a, int64_t tile, void
         for (int h = threadIdx.x; h < hn; h += blockDim.x) dst[h] = src[a.halo[h0 + h]];
     }
     __syncthreads();
+}
+
+// Calls f(tile) for the tiles of this workgroup: one tile per workgroup over
+// the whole node range, or (batched launches) a contiguous chunk of the active
+// tile list per persistent workgroup, chunks XCD-contiguous like the tiles.
+template <class F>
+__device__ __forceinline__ void for_tiles(const StepArgs &a, F &&f) {
+    if (a.queue) {
+        const int na = *a.queue_count;
+        const int G = gridDim.x;
+        int b = blockIdx.x;
+        if (a.xcd) b = (b & 7) * (G >> 3) + (b >> 3);
+        const int chunk = (na + G - 1) / G;
+        const int c1 = min(na, (b + 1) * chunk);
+        for (int c = b * chunk; c < c1; ++c) f((int64_t)a.queue[c]);
+    } else {
+        const int64_t tile = tile_of(a);
+        if (tile * blockDim.x < a.n) f(tile);
+    }
 }
 
 // bytes per node of the [n][8] population block / the [n][4] field block
@@ -354,19 +364,7 @@ __device__ __forceinline__ void for_quads(F &&f) {
 
 // CG: gather (interpolation) arithmetic; C: collision arithmetic
 template <int S, class CG, class C, int KQ, bool LDS>
-__global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    int64_t i;
-    if constexpr (LDS) {
-        const int64_t tile = tile_of(a);
-        if (tile * blockDim.x >= a.n) return;  // whole workgroup past the end
-        stage_halo<pop_bytes<S>()>(a, tile, smem);
-        i = tile * blockDim.x + threadIdx.x;
-    } else {
-        i = node_of(a);
-    }
-    if (i >= a.n) return;
-    const void *src = LDS ? (const void *)smem : a.in;
+__device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int64_t i) {
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
@@ -414,22 +412,20 @@ __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
     store1<S, C>(a.out, n, i, f[0], a.scale);
 }
 
+template <int S, class CG, class C, int KQ, bool LDS>
+__global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for_tiles(a, [&](int64_t tile) {
+        if constexpr (LDS) stage_halo<pop_bytes<S>()>(a, tile, smem);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) pop_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i);
+    });
+}
+
 // ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
 
 template <int S, class CG, class C, int KQ, bool LDS>
-__global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    int64_t i;
-    if constexpr (LDS) {
-        const int64_t tile = tile_of(a);
-        if (tile * blockDim.x >= a.n) return;
-        stage_halo<field_bytes<S>()>(a, tile, smem);
-        i = tile * blockDim.x + threadIdx.x;
-    } else {
-        i = node_of(a);
-    }
-    if (i >= a.n) return;
-    const void *src = LDS ? (const void *)smem : a.in;
+__device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, int64_t i) {
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
@@ -492,6 +488,16 @@ __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
         out[2] = (jy + C(0.5) * rho * gy) / rho;
     }
     store3<S>(a.out, i, out, a.scale);
+}
+
+template <int S, class CG, class C, int KQ, bool LDS>
+__global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for_tiles(a, [&](int64_t tile) {
+        if constexpr (LDS) stage_halo<field_bytes<S>()>(a, tile, smem);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) fields_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i);
+    });
 }
 
 // ---- initial state -----------------------------------------------------------------
@@ -892,6 +898,8 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     a.halo_off = st->halo_off;
     a.halo = st->halo;
     a.lidx = st->lidx;
+    a.queue = nullptr;
+    a.queue_count = nullptr;
     const int64_t nb = (st->n + blk - 1) / blk;
     a.grid8 = a.xcd ? (nb + 7) / 8 * 8 : nb;
     hipStream_t s = (hipStream_t)stream;
@@ -948,4 +956,331 @@ extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_sta
     if (rc) return rc;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_BLOCK), 0, s, (const double *)workspace, nb, red_out);
     return hip_check("mlbm_macroscopic reduction launch");
+}
+
+// ---- batched runs: many samples in one node range ------------------------------------
+//
+// Samples are concatenated so that every tile (workgroup of `tile` nodes) lies
+// in one sample.  A device list of active tiles drives persistent step
+// kernels; every check_every steps a per-tile pass accumulates the velocity
+// change since the last check, and one workgroup retires converged samples and
+// rebuilds the list.  check_every is even, so every check sees the same state
+// buffer and a retired sample's final state stays there.
+
+namespace {
+
+struct BatchArgs {
+    int64_t n;
+    const uint16_t *flags;
+    const double *bc;
+    const void *state;
+    const double *area;
+    double *u_prev;
+    double *tile_red;
+    const int *queue;
+    int *counters;
+    const int *tile_off;
+    int n_samples;
+    int *sample_steps;
+    double *sample_res;
+    double *sample_ux;
+    double gx, gy, tol;
+    float inv_scale;
+    int check_every;
+    int64_t ntiles;
+};
+
+constexpr int BATCH_RED = 4;  // du2, u2, sum A u_x, bad nodes
+
+template <int S, int V>
+__global__ void __launch_bounds__(256) k_batch_tile_red(const BatchArgs a) {
+    __shared__ double lds[256 / 64];
+    const int na = a.counters[0];
+    for (int c = blockIdx.x; c < na; c += gridDim.x) {
+        const int64_t tile = a.queue[c];
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        double v[BATCH_RED] = {0, 0, 0, 0};
+        if (i < a.n) {
+            double rho, ux, uy;
+            if constexpr (V == MLBM_POPULATIONS) {
+                double f[9];
+                load8<S>(a.state, i, f + 1, a.inv_scale);
+                f[0] = load1<S, double>(a.state, a.n, i, a.inv_scale);
+                double dr = 0, jx = 0, jy = 0;
+                for (int k = 0; k < 9; ++k) {
+                    dr += (double)f[k];
+                    jx += EX[k] * (double)f[k];
+                    jy += EY[k] * (double)f[k];
+                }
+                rho = 1.0 + dr;
+                ux = jx / rho - 0.5 * a.gx;
+                uy = jy / rho - 0.5 * a.gy;
+            } else {
+                double m[3];
+                load3<S>(a.state, i, m, a.inv_scale);
+                rho = 1.0 + m[0];
+                ux = m[1];
+                uy = m[2];
+            }
+            if ((a.flags[i] >> 8) == MLBM_DIRICHLET) {
+                rho = a.bc[3 * i];
+                ux = a.bc[3 * i + 1];
+                uy = a.bc[3 * i + 2];
+            }
+            const double dx = ux - a.u_prev[2 * i], dy = uy - a.u_prev[2 * i + 1];
+            a.u_prev[2 * i] = ux;
+            a.u_prev[2 * i + 1] = uy;
+            v[0] = dx * dx + dy * dy;
+            v[1] = ux * ux + uy * uy;
+            v[2] = a.area[i] * ux;
+            v[3] = (isfinite(rho) && isfinite(ux) && isfinite(uy) && rho > 0.0) ? 0.0 : 1.0;
+        }
+        for (int r = 0; r < BATCH_RED; ++r) {
+            const double s = block_sum(v[r], lds);
+            if (threadIdx.x == 0) a.tile_red[tile * BATCH_RED + r] = s;
+        }
+    }
+}
+
+constexpr int MAX_SAMPLES = 4096;
+
+// one workgroup: per-sample residual, retirement, new active tile list
+__global__ void __launch_bounds__(256) k_batch_retire(const BatchArgs a, int mark) {
+    __shared__ int start[MAX_SAMPLES];
+    __shared__ int total, active;
+    const int steps = a.counters[1] + a.check_every;
+    for (int s = threadIdx.x; s < a.n_samples; s += blockDim.x) {
+        if (a.sample_steps[s] != 0) continue;
+        double r[BATCH_RED] = {0, 0, 0, 0};
+        for (int t = a.tile_off[s]; t < a.tile_off[s + 1]; ++t)
+            for (int q = 0; q < BATCH_RED; ++q) r[q] += a.tile_red[(int64_t)t * BATCH_RED + q];
+        const double res = r[1] > 0.0 ? sqrt(r[0] / r[1]) : (r[0] > 0.0 ? INFINITY : 0.0);
+        a.sample_res[s] = res;
+        a.sample_ux[s] = r[2];
+        if (!mark) continue;
+        if (r[3] > 0.0 || !isfinite(res)) a.sample_steps[s] = -steps;
+        else if (res < a.tol) a.sample_steps[s] = steps;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int pos = 0, act = 0;
+        for (int s = 0; s < a.n_samples; ++s) {
+            if (a.sample_steps[s] == 0) {
+                start[s] = pos;
+                pos += a.tile_off[s + 1] - a.tile_off[s];
+                ++act;
+            } else {
+                start[s] = -1;
+            }
+        }
+        total = pos;
+        active = act;
+    }
+    __syncthreads();
+    for (int s = 0; s < a.n_samples; ++s) {
+        if (start[s] < 0) continue;
+        const int cnt = a.tile_off[s + 1] - a.tile_off[s];
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) ((int *)a.queue)[start[s] + t] = a.tile_off[s] + t;
+    }
+    if (threadIdx.x == 0) {
+        a.counters[0] = total;
+        a.counters[1] = mark ? steps : 0;
+        a.counters[2] = active;
+        a.counters[3] += mark;
+    }
+}
+
+__global__ void k_batch_reset(const BatchArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < a.ntiles) ((int *)a.queue)[t] = (int)t;
+    if (t < a.n_samples) {
+        a.sample_steps[t] = 0;
+        a.sample_res[t] = INFINITY;
+        a.sample_ux[t] = 0.0;
+    }
+    if (t == 0) {
+        a.counters[0] = (int)a.ntiles;
+        a.counters[1] = 0;
+        a.counters[2] = a.n_samples;
+        a.counters[3] = 0;
+    }
+}
+
+using RedFn = void (*)(const BatchArgs);
+
+RedFn pick_red(int storage, int variant) {
+#define MLBM_RED(S)                                                                          \
+    case S:                                                                                  \
+        return variant == MLBM_POPULATIONS ? (RedFn)k_batch_tile_red<S, MLBM_POPULATIONS>    \
+                                           : (RedFn)k_batch_tile_red<S, MLBM_FIELDS>;
+    switch (storage) {
+        MLBM_RED(MLBM_F64)
+        MLBM_RED(MLBM_F32)
+        MLBM_RED(MLBM_F16S)
+        MLBM_RED(MLBM_BF16)
+    }
+#undef MLBM_RED
+    return nullptr;
+}
+
+int batch_args(const mlbm_step_params *p, const mlbm_device_state *st, const mlbm_batch *b, BatchArgs &ba) {
+    using mlbm::fail;
+    int rc = check_common(p, st);
+    if (rc) return rc;
+    if (!b) return fail(MLBM_ERR_ARG, "null batch");
+    if (st->tile == 0) return fail(MLBM_ERR_ARG, "batched runs need tiles (state->tile = 64, 128 or 256)");
+    if (b->n_samples < 1 || b->n_samples > MAX_SAMPLES) return fail(MLBM_ERR_ARG, "n_samples outside [1, %d]", MAX_SAMPLES);
+    if (!b->sample_tile_off || !b->sample_tile_off_host || !b->area || !b->u_prev || !b->tile_red || !b->queue ||
+        !b->counters || !b->sample_steps || !b->sample_residual || !b->sample_int_ux)
+        return fail(MLBM_ERR_ARG, "null batch buffer");
+    const int64_t ntiles = (st->n + st->tile - 1) / st->tile;
+    const int32_t *off = b->sample_tile_off_host;
+    if (off[0] != 0 || off[b->n_samples] != ntiles)
+        return fail(MLBM_ERR_ARG, "sample tiles must cover [0, %lld)", (long long)ntiles);
+    for (int s = 0; s < b->n_samples; ++s)
+        if (off[s + 1] <= off[s]) return fail(MLBM_ERR_ARG, "sample %d has no tiles", s);
+    if (b->check_every < 2 || (b->check_every & 1)) return fail(MLBM_ERR_ARG, "check_every must be even and >= 2");
+    ba.n = st->n;
+    ba.flags = st->flags;
+    ba.bc = st->bc;
+    ba.state = st->state[st->cur];
+    ba.area = b->area;
+    ba.u_prev = b->u_prev;
+    ba.tile_red = b->tile_red;
+    ba.queue = b->queue;
+    ba.counters = b->counters;
+    ba.tile_off = b->sample_tile_off;
+    ba.n_samples = b->n_samples;
+    ba.sample_steps = b->sample_steps;
+    ba.sample_res = b->sample_residual;
+    ba.sample_ux = b->sample_int_ux;
+    ba.gx = p->g[0];
+    ba.gy = p->g[1];
+    ba.tol = 0.0;
+    ba.inv_scale = std::ldexp(1.0f, -p->scale_exp);
+    ba.check_every = b->check_every;
+    ba.ntiles = ntiles;
+    return MLBM_OK;
+}
+
+int batch_grid(const mlbm_batch *b) {
+    int g = b->grid > 0 ? b->grid : 1024;
+    return (g + 7) / 8 * 8;
+}
+
+}  // namespace
+
+extern "C" int mlbm_batch_init(const mlbm_step_params *p, mlbm_device_state *st, mlbm_batch *b, void *stream) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    BatchArgs ba;
+    int rc = batch_args(p, st, b, ba);
+    if (rc) return rc;
+    RedFn red = pick_red(p->storage, p->variant);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t cover = std::max<int64_t>(ba.ntiles, b->n_samples);
+    hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)((cover + 255) / 256)), dim3(256), 0, s, ba);
+    hipLaunchKernelGGL(red, dim3((unsigned)batch_grid(b)), dim3(st->tile), 0, s, ba);
+    hipLaunchKernelGGL(k_batch_retire, dim3(1), dim3(256), 0, s, ba, 0);
+    return hip_check("mlbm_batch_init launch");
+}
+
+extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *st, mlbm_batch *b,
+                                 int32_t max_steps, double tol, int32_t use_graph, int32_t *steps_done,
+                                 void *stream) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    BatchArgs ba;
+    int rc = batch_args(p, st, b, ba);
+    if (rc) return rc;
+    if (max_steps < 0) return fail(MLBM_ERR_ARG, "max_steps must be >= 0");
+    if (!(tol >= 0.0)) return fail(MLBM_ERR_ARG, "tol must be >= 0");
+    if (use_graph && !stream) return fail(MLBM_ERR_ARG, "graph capture needs a non-default stream");
+    const int kq = (st->K + 3) / 4;
+    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith, true);
+    RedFn red = pick_red(p->storage, p->variant);
+    if (!fn || !red) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
+    if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
+        return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
+    if (!st->halo_off || !st->halo || !st->lidx || st->max_halo < 1) return fail(MLBM_ERR_ARG, "null tile buffer");
+    const int ts = storage_bytes(p->storage);
+    const size_t shmem = (size_t)st->max_halo * (p->variant == MLBM_POPULATIONS ? 8 * ts : 4 * ts);
+    if (shmem > 65536) return fail(MLBM_ERR_UNSUPPORTED, "halo needs %zu bytes of LDS (> 64 KiB)", shmem);
+    ba.tol = tol;
+    StepArgs a;
+    a.n = st->n;
+    a.idx = (const int *)st->idx;
+    a.w = st->w;
+    a.flags = st->flags;
+    a.bc = st->bc;
+    a.omp = 1.0 / p->tau_plus;
+    a.omm = 1.0 / p->tau_minus;
+    a.gx = p->g[0];
+    a.gy = p->g[1];
+    a.scale = std::ldexp(1.0f, p->scale_exp);
+    a.inv_scale = std::ldexp(1.0f, -p->scale_exp);
+    a.xcd = p->xcd_remap ? 1 : 0;
+    a.cached = p->cached_weights ? 1 : 0;
+    a.reverse = 0;
+    a.halo_off = st->halo_off;
+    a.halo = st->halo;
+    a.lidx = st->lidx;
+    a.queue = b->queue;
+    a.queue_count = b->counters;
+    a.grid8 = batch_grid(b);
+    const int G = (int)a.grid8;
+    hipStream_t s = (hipStream_t)stream;
+    const int cur0 = st->cur;
+    // one check: check_every steps, the per-tile pass, retirement
+    auto enqueue = [&]() -> int {
+        int cur = cur0;
+        for (int t = 0; t < b->check_every; ++t) {
+            a.in = st->state[cur];
+            a.out = st->state[cur ^ 1];
+            hipLaunchKernelGGL(fn, dim3(G), dim3(st->tile), shmem, s, a);
+            cur ^= 1;
+        }
+        ba.state = st->state[cur];
+        hipLaunchKernelGGL(red, dim3(G), dim3(st->tile), 0, s, ba);
+        hipLaunchKernelGGL(k_batch_retire, dim3(1), dim3(256), 0, s, ba, 1);
+        return hip_check("mlbm_step_batched launch");
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (use_graph) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(MLBM_ERR_HIP, "hipStreamBeginCapture failed");
+        rc = enqueue();
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc) return rc;
+        if (e != hipSuccess) return fail(MLBM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(graph);
+            return fail(MLBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    int steps = 0;
+    int counters[4] = {1, 0, 1, 0};
+    rc = MLBM_OK;
+    while (steps < max_steps) {
+        if (use_graph) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { rc = fail(MLBM_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e)); break; }
+        } else {
+            rc = enqueue();
+            if (rc) break;
+        }
+        steps += b->check_every;
+        if (hipMemcpyAsync(counters, b->counters, sizeof(counters), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = fail(MLBM_ERR_HIP, "reading the batch counters failed");
+            break;
+        }
+        if (counters[2] == 0) break;
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (steps_done) *steps_done = steps;
+    return rc;
 }

@@ -479,41 +479,49 @@ extern "C" int mlbm_packed_sizes(int64_t n, int32_t K, int32_t variant, int32_t 
     return MLBM_OK;
 }
 
-extern "C" int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx, const double *w,
-                                  const uint8_t *bb, const uint8_t *kind, void *idx_packed, void *w_packed,
-                                  uint16_t *flags) {
+extern "C" int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t n, int32_t K, int32_t storage,
+                                        const int32_t *idx, const double *w, const uint8_t *bb, const uint8_t *kind,
+                                        void *idx_packed, void *w_packed, uint16_t *flags) {
     using mlbm::fail;
     mlbm::clear_error();
     if (!idx || !w || !bb || !kind || !idx_packed || !w_packed || !flags) return fail(MLBM_ERR_ARG, "null pointer argument");
-    if (n < 1 || K < 1 || K > MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
+    if (n < 1 || K < 1 || K > MAXK || offset < 0 || offset + n > n_total) return fail(MLBM_ERR_ARG, "bad n, offset or K");
     if (storage < MLBM_F64 || storage > MLBM_BF16) return fail(MLBM_ERR_ARG, "bad storage %d", storage);
     const int kp = (K + 3) / 4 * 4;
+    const int64_t N = n_total;
     int32_t *ip = (int32_t *)idx_packed;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t i = offset + r;
         for (int j = 0; j < kp; ++j) {
-            const int32_t v = j < K ? idx[i * K + j] : (int32_t)i;
-            if (v < 0 || v >= n) return fail(MLBM_ERR_ARG, "stencil index out of range at node %lld", (long long)i);
-            ip[((int64_t)(j / 4) * n + i) * 4 + (j % 4)] = v;
+            const int32_t v = j < K ? idx[r * K + j] : (int32_t)i;
+            if (v < 0 || v >= N) return fail(MLBM_ERR_ARG, "stencil index out of range at node %lld", (long long)i);
+            ip[((int64_t)(j / 4) * N + i) * 4 + (j % 4)] = v;
         }
-        flags[i] = (uint16_t)(bb[i] | ((uint16_t)(kind[i] & 3) << 8));
+        flags[i] = (uint16_t)(bb[r] | ((uint16_t)(kind[r] & 3) << 8));
     }
     if (storage == MLBM_F64) {
         double *wp = (double *)w_packed;
         const int kh = kp / 2;
-        for (int64_t i = 0; i < n; ++i)
+        for (int64_t r = 0; r < n; ++r)
             for (int k = 0; k < 8; ++k)
                 for (int j = 0; j < kp; ++j)
-                    wp[(((int64_t)k * kh + j / 2) * n + i) * 2 + (j % 2)] = j < K ? w[(i * 8 + k) * K + j] : 0.0;
+                    wp[(((int64_t)k * kh + j / 2) * N + offset + r) * 2 + (j % 2)] = j < K ? w[(r * 8 + k) * K + j] : 0.0;
     } else {
         float *wp = (float *)w_packed;
         const int kq = kp / 4;
-        for (int64_t i = 0; i < n; ++i)
+        for (int64_t r = 0; r < n; ++r)
             for (int k = 0; k < 8; ++k)
                 for (int j = 0; j < kp; ++j)
-                    wp[(((int64_t)k * kq + j / 4) * n + i) * 4 + (j % 4)] =
-                        j < K ? (float)w[(i * 8 + k) * K + j] : 0.0f;
+                    wp[(((int64_t)k * kq + j / 4) * N + offset + r) * 4 + (j % 4)] =
+                        j < K ? (float)w[(r * 8 + k) * K + j] : 0.0f;
     }
     return MLBM_OK;
+}
+
+extern "C" int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx, const double *w,
+                                  const uint8_t *bb, const uint8_t *kind, void *idx_packed, void *w_packed,
+                                  uint16_t *flags) {
+    return mlbm_pack_stencils_range(n, 0, n, K, storage, idx, w, bb, kind, idx_packed, w_packed, flags);
 }
 
 // ---- tile-local stencil indices (LDS staging) --------------------------------

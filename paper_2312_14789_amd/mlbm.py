@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (BF16, F16S, F32, F64, FIELDS, POPULATIONS, RED_COUNT, DeviceState, Geometry,
+from ._lib import (BF16, F16S, F32, F64, FIELDS, POPULATIONS, RED_COUNT, Batch, DeviceState, Geometry,
                    MlbmError, Sizes, StencilParams, Stencils, StepParams, check, lib)
 
 __all__ = ["build_stencils", "packed_sizes", "pack_stencils", "Simulation", "MlbmError",
@@ -110,13 +110,14 @@ class Simulation:
 
     def __init__(self, idx, w, bb, kind, area, *, variant=POPULATIONS, storage=F32, tau_plus=0.8,
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
-                 fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda"):
+                 fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda",
+                 packed=None):
         import torch
 
         self.torch = torch
         n, K = np.asarray(idx).shape
         self.n, self.K = n, K
-        ip, wp, fl = pack_stencils(idx, w, bb, kind, storage)
+        ip, wp, fl = pack_stencils(idx, w, bb, kind, storage) if packed is None else packed
         self.sizes = packed_sizes(n, K, variant, storage)
         dev = torch.device(device)
         self.idx_d = torch.from_numpy(ip).to(dev)
@@ -232,3 +233,115 @@ class Simulation:
             if res < tol:
                 break
         return steps, res, red
+
+
+class BatchSimulation:
+    """Many node sets in one concatenated launch (mlbm_batch_init,
+    mlbm_step_batched).  Each sample is padded to a multiple of `tile` nodes
+    with Dirichlet nodes at rest that have no stencil and zero area, so no tile
+    spans two samples.
+
+    samples: list of (stencils dict from build_stencils, kind, bc) with kind
+    and bc in the builder's node order."""
+
+    def __init__(self, samples, *, variant=FIELDS, storage=F32, tau_plus=1.0, tau_minus=None,
+                 g=(0.0, 0.0), tile=256, check_every=100, grid=0, scale_exp=0, xcd_remap=1,
+                 fp32_arith=0, device="cuda"):
+        import torch
+
+        self.torch = torch
+        K = samples[0][0]["idx"].shape[1]
+        sizes = [st["idx"].shape[0] for st, _, _ in samples]
+        padded = [(m + tile - 1) // tile * tile for m in sizes]
+        off = np.concatenate([[0], np.cumsum(padded)]).astype(np.int64)
+        N = int(off[-1])
+        self.sizes, self.node_off, self.K, self.N = sizes, off, K, N
+        ps = packed_sizes(N, K, variant, storage)
+        ip = np.zeros(ps.idx_bytes, np.uint8)
+        wp = np.zeros(ps.w_bytes, np.uint8)
+        fl = np.zeros(N, np.uint16)
+        idx_all = np.empty((N, K), np.int32)
+        area_all = np.zeros(N)
+        bc_all = np.zeros((N, 3))
+        bc_all[:, 0] = 1.0
+        for s_, (st, kind, bc) in enumerate(samples):
+            a, m, p = int(off[s_]), sizes[s_], padded[s_]
+            idx = np.ascontiguousarray(st["idx"], dtype=np.int32) + a
+            pad_idx = np.repeat(np.arange(a + m, a + p, dtype=np.int32)[:, None], K, axis=1)
+            idx_s = np.concatenate([idx, pad_idx])
+            w_s = np.concatenate([st["w"], np.zeros((p - m, 8, K))])
+            bb_s = np.concatenate([st["bb"], np.zeros(p - m, np.uint8)])
+            kind_s = np.concatenate([np.asarray(kind, np.uint8), np.full(p - m, 2, np.uint8)])
+            check(lib.mlbm_pack_stencils_range(N, a, p, K, storage, _ptr(idx_s), _ptr(np.ascontiguousarray(w_s)),
+                                               _ptr(bb_s), _ptr(kind_s), _ptr(ip), _ptr(wp), _ptr(fl)))
+            idx_all[a:a + p] = idx_s
+            area_all[a:a + m] = st["area"]
+            if bc is not None:
+                bc_all[a:a + m] = bc
+        self.sim = Simulation(idx_all, None, None, None, area_all, variant=variant, storage=storage,
+                              tau_plus=tau_plus, tau_minus=tau_minus, g=g, bc=bc_all, scale_exp=scale_exp,
+                              xcd_remap=xcd_remap, fp32_arith=fp32_arith, tile=tile, device=device,
+                              packed=(ip, wp, fl))
+        t = torch
+        dev = self.sim.state_d[0].device
+        ntiles = N // tile
+        tile_off = (off // tile).astype(np.int32)
+        self.tile_off_host = tile_off
+        self.tile_off_d = t.from_numpy(tile_off).to(dev)
+        ns = len(samples)
+        self.u_prev_d = t.zeros((N, 2), dtype=t.float64, device=dev)
+        self.tile_red_d = t.zeros((ntiles, 4), dtype=t.float64, device=dev)
+        self.queue_d = t.zeros(ntiles, dtype=t.int32, device=dev)
+        self.counters_d = t.zeros(4, dtype=t.int32, device=dev)
+        self.steps_d = t.zeros(ns, dtype=t.int32, device=dev)
+        self.res_d = t.zeros(ns, dtype=t.float64, device=dev)
+        self.ux_d = t.zeros(ns, dtype=t.float64, device=dev)
+        self.batch = Batch()
+        b = self.batch
+        b.n_samples = ns
+        b.check_every = int(check_every)
+        b.grid = int(grid)
+        b.sample_tile_off = self.tile_off_d.data_ptr()
+        b.sample_tile_off_host = self.tile_off_host.ctypes.data
+        b.area = self.sim.area_d.data_ptr()
+        b.u_prev = self.u_prev_d.data_ptr()
+        b.tile_red = self.tile_red_d.data_ptr()
+        b.queue = self.queue_d.data_ptr()
+        b.counters = self.counters_d.data_ptr()
+        b.sample_steps = self.steps_d.data_ptr()
+        b.sample_residual = self.res_d.data_ptr()
+        b.sample_int_ux = self.ux_d.data_ptr()
+        self.stream = torch.cuda.Stream(device=dev)
+
+    def init_state(self, rho_list, u_list):
+        """Initial fields per sample (builder order); padding nodes at rest."""
+        N = self.N
+        rho = np.ones(N)
+        u = np.zeros((N, 2))
+        for s_, (r, v) in enumerate(zip(rho_list, u_list)):
+            a, m = int(self.node_off[s_]), self.sizes[s_]
+            rho[a:a + m] = r
+            u[a:a + m] = v
+        with self.torch.cuda.stream(self.stream):
+            self.sim.init_state(rho, u, stream=self.stream)
+            check(lib.mlbm_batch_init(ctypes.byref(self.sim.params), ctypes.byref(self.sim.ds),
+                                      ctypes.byref(self.batch), ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def run(self, max_steps, tol=1e-6, use_graph=True):
+        """mlbm_step_batched; returns the steps run."""
+        done = ctypes.c_int32()
+        check(lib.mlbm_step_batched(ctypes.byref(self.sim.params), ctypes.byref(self.sim.ds),
+                                    ctypes.byref(self.batch), int(max_steps), float(tol), int(bool(use_graph)),
+                                    ctypes.byref(done), ctypes.c_void_p(self.stream.cuda_stream)))
+        return done.value
+
+    def results(self):
+        """(steps to convergence, last residual, sum A u_x) per sample."""
+        self.stream.synchronize()
+        return self.steps_d.cpu().numpy(), self.res_d.cpu().numpy(), self.ux_d.cpu().numpy()
+
+    def state_of(self, s_):
+        """Raw state bytes of sample s_ (its node rows of every state block)."""
+        self.stream.synchronize()
+        raw = self.sim.state_d[self.sim.ds.cur].cpu().numpy()
+        return raw, int(self.node_off[s_]), self.sizes[s_]
