@@ -96,6 +96,104 @@ def copy_calibration():
                       "GBps_read_plus_write": 2 * 4 * n / ms / 1e6}), flush=True)
 
 
+def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
+    """The porous workload (1e6 nodes, phi = 0.7, MLBM1, s = 1, Darcy regime
+    Re ~ 0.1) run from rest to a velocity residual of tol with FP32, FP16
+    (scaled offsets) and BF16 state: steps, seconds and permeability, the
+    16-bit permeabilities relative to the FP32 one."""
+    t0 = time.time()
+    ns = nodesets.porous()
+    dx = ns.h
+    b = M.build_stencils_for(ns, 16, dx)
+    perm = b["perm"]
+    nu = units.nu_lattice(1.0)
+    out = {"workload": f"porous unit box, {ns.n} nodes, phi={ns.fluid_area():.3f}, {len(ns.disks)} disks, "
+                       f"MLBM1 (tau=1), K=16, s=1, g_lb={g:g}", "tol": tol,
+           "setup_s": None, "runs": {}}
+    k_ref = None
+    sigma = 0
+    for name, storage in (("f32", M.F32), ("f16s", M.F16S), ("bf16", M.BF16)):
+        sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.FIELDS,
+                           storage=storage, tau_plus=1.0, g=(g, 0.0), scale_exp=sigma)
+        if out["setup_s"] is None:
+            out["setup_s"] = round(time.time() - t0, 2)
+        sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        steps, res, red = sim.run_to_steady(dx, tol=tol, check_every=100, max_steps=200_000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        k = nu * (red[M._lib.RED_INT_UX] / 1.0) / g * dx * dx
+        umean = red[M._lib.RED_INT_UX] / ns.fluid_area()
+        rec = {"steps": steps, "seconds": round(dt, 3), "residual": res, "permeability": k,
+               "Re": umean / dx / nu, "MNUPS": round(ns.n * steps / dt / 1e6, 1)}
+        if storage == M.F32:
+            k_ref = k
+            _, u, _ = sim.macroscopic(dx)
+            sigma = units.f16_scale_exp(float(u.abs().max()))
+        else:
+            rec["scale_exp"] = sigma if storage == M.F16S else None
+            rec["permeability_rel_err_vs_f32"] = abs(k / k_ref - 1.0)
+        out["runs"][name] = rec
+        del sim
+    return out
+
+
+def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.242e-8, sequential=True):
+    """64 porous samples (nodes U(5e4, 4e5), porosity U(0.55, 0.85)), MLBM1
+    FP32, s = 1, run from rest to a residual of tol in one batched launch
+    (persistent tile queue, graph replay, autotuned shape), against the same
+    samples run one after another."""
+    from paper_2312_14789_amd import autotune
+
+    t0 = time.time()
+    sets = nodesets.porous_batch(n_samples)
+    built = [M.build_stencils_for(ns, 16, ns.h) for ns in sets]
+    batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for b, ns in zip(built, sets)], variant=M.FIELDS,
+                              storage=M.F32, tau_plus=1.0, g=(g, 0.0), tile=256, check_every=100)
+    setup = time.time() - t0
+    print(f"# batched setup {setup:.1f} s, {batch.N} nodes incl. padding", file=sys.stderr, flush=True)
+    t1 = time.time()
+    best = autotune.tune(batch, steps=200)
+    tune_s = time.time() - t1
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ran = batch.run(400_000, tol=tol, use_graph=True)
+    dt = time.perf_counter() - t2
+    steps, res, ux = batch.results()
+    sizes = np.array(batch.sizes)
+    updates = float(np.sum(sizes * np.abs(steps)))
+    out = {"metric": "batched time to steady state", "workload": f"{n_samples} porous samples, "
+           f"{int(sizes.sum())} nodes (min {sizes.min()}, max {sizes.max()}), MLBM1 FP32, K=16, s=1, g_lb={g:g}, "
+           f"residual {tol:g}", "seconds": round(dt, 3), "steps_run": ran,
+           "sample_steps_min_max": [int(steps.min()), int(steps.max())], "unconverged": int(np.sum(steps <= 0)),
+           "MNUPS_effective": round(updates / dt / 1e6, 1), "setup_s": round(setup, 1),
+           "autotune": {k: best[k] for k in ("tile", "grid", "xcd", "ms_per_step", "cached")},
+           "autotune_s": round(tune_s, 1)}
+    if sequential:
+        # the same samples one after another, each in its own launches (time
+        # of the stepping loops only, no construction or upload)
+        tile = best["tile"]
+        del batch
+        seq_seconds = 0.0
+        seq_steps = []
+        for b, ns in zip(built, sets):
+            sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[b["perm"]], b["area"], variant=M.FIELDS,
+                               storage=M.F32, tau_plus=1.0, g=(g, 0.0), tile=tile)
+            sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st_, _, _ = sim.run_to_steady(ns.h, tol=tol, check_every=100, max_steps=400_000)
+            torch.cuda.synchronize()
+            seq_seconds += time.perf_counter() - ta
+            seq_steps.append(st_)
+            del sim
+        out["sequential"] = {"seconds": round(seq_seconds, 3),
+                             "speedup_batched": round(seq_seconds / dt, 3),
+                             "same_steps_per_sample": bool(np.array_equal(np.array(seq_steps), steps))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +211,9 @@ def main():
     ap.add_argument("--cached", type=int, default=0, help="ordinary (not non-temporal) weight loads")
     ap.add_argument("--nodes", type=int, default=500_000, help="target node count of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
+    ap.add_argument("--workload", default="karman", choices=["karman", "batched"],
+                    help="karman: the fused-step throughput line; batched: 64 porous samples to steady state")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a 1 GiB device copy (reference for byte counters and bandwidth)")
     args = ap.parse_args()
@@ -130,6 +231,10 @@ def main():
     import nodesets
     from paper_2312_14789_amd import mlbm as M
     from paper_2312_14789_amd import units
+
+    if args.workload == "batched":
+        print(json.dumps(batched_workload(M, units, nodesets, np, torch)), flush=True)
+        return
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]
     t0 = time.time()
@@ -203,6 +308,9 @@ def main():
                      "traffic": traffic, "kernel": kernel, "bytes_per_node": bpn,
                      "avg_launch_us": round(per_launch_s * 1e6, 2)},
     }
+    if not args.no_steady:
+        del sim
+        out["time_to_steady"] = porous_time_to_steady(M, units, nodesets, np, torch)
     if not args.no_cpu_baseline:
         import copy
 

@@ -1,0 +1,91 @@
+"""Launch-shape autotuner for batched runs.
+
+Times the batched step (mlbm_step_batched, graph replay, no retirement) for
+every candidate (tile size, persistent grid, XCD-contiguous chunks) on the
+actual batch and keeps the fastest.  Results are cached in a JSON file keyed
+by GPU architecture, stencil size, variant, storage and the node count
+rounded to a power of two, so a later run on a similar batch reuses them.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+TILES = (64, 128, 256)
+GRIDS = (512, 1024, 2048)
+XCD = (1, 0)
+
+
+def default_cache_path() -> str:
+    base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(base, "mlbm", "autotune.json")
+
+
+def cache_key(batch) -> str:
+    import torch
+
+    arch = torch.cuda.get_device_properties(batch.sim.state_d[0].device).gcnArchName.split(":")[0]
+    p = batch.sim.params
+    return f"{arch}|K{batch.K}|v{p.variant}|s{p.storage}|N2^{round(math.log2(batch.N))}"
+
+
+def _time(batch, steps):
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(batch.stream)
+    batch.run(steps, tol=0.0, use_graph=True)
+    e1.record(batch.stream)
+    batch.stream.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(batch, steps=200, cache_path=None, use_cache=True, rho_u=None):
+    """Picks the fastest launch shape for `batch` (a BatchSimulation) and
+    applies it.  Returns {"tile", "grid", "xcd", "ms_per_step", "timings",
+    "cached"}.  The batch state is re-initialised (at rest, or from rho_u =
+    (rho_list, u_list)) after timing."""
+    cache_path = cache_path or default_cache_path()
+    key = cache_key(batch)
+    cache = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    if use_cache and key in cache:
+        best = dict(cache[key], cached=True)
+    else:
+        sizes = batch.sizes
+        init = rho_u or ([None] * len(sizes), [None] * len(sizes))
+        timings = []
+        for tile in TILES:
+            batch.set_tile(tile)
+            for grid in GRIDS:
+                for xcd in XCD:
+                    batch.batch.grid = grid
+                    batch.sim.params.xcd_remap = xcd
+                    _reinit(batch, init)
+                    _time(batch, batch.batch.check_every)  # warm-up (graph build, caches)
+                    ms = _time(batch, steps)
+                    timings.append({"tile": tile, "grid": grid, "xcd": xcd, "ms_per_step": ms})
+        best = dict(min(timings, key=lambda r: r["ms_per_step"]))
+        best["timings"] = timings
+        cache[key] = {k: best[k] for k in ("tile", "grid", "xcd", "ms_per_step")}
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+        best["cached"] = False
+    batch.set_tile(best["tile"])
+    batch.batch.grid = best["grid"]
+    batch.sim.params.xcd_remap = best["xcd"]
+    _reinit(batch, rho_u or ([None] * len(batch.sizes), [None] * len(batch.sizes)))
+    return best
+
+
+def _reinit(batch, rho_u):
+    import numpy as np
+
+    rho_list = [np.ones(m) if r is None else r for m, r in zip(batch.sizes, rho_u[0])]
+    u_list = [np.zeros((m, 2)) if u is None else u for m, u in zip(batch.sizes, rho_u[1])]
+    batch.init_state(rho_list, u_list)

@@ -252,7 +252,8 @@ class BatchSimulation:
         self.torch = torch
         K = samples[0][0]["idx"].shape[1]
         sizes = [st["idx"].shape[0] for st, _, _ in samples]
-        padded = [(m + tile - 1) // tile * tile for m in sizes]
+        pad = self.PAD  # a multiple of every tile size, so any tile stays in one sample
+        padded = [(m + pad - 1) // pad * pad for m in sizes]
         off = np.concatenate([[0], np.cumsum(padded)]).astype(np.int64)
         N = int(off[-1])
         self.sizes, self.node_off, self.K, self.N = sizes, off, K, N
@@ -284,10 +285,7 @@ class BatchSimulation:
                               packed=(ip, wp, fl))
         t = torch
         dev = self.sim.state_d[0].device
-        ntiles = N // tile
-        tile_off = (off // tile).astype(np.int32)
-        self.tile_off_host = tile_off
-        self.tile_off_d = t.from_numpy(tile_off).to(dev)
+        ntiles = N // 64  # workspaces sized for the smallest tile
         ns = len(samples)
         self.u_prev_d = t.zeros((N, 2), dtype=t.float64, device=dev)
         self.tile_red_d = t.zeros((ntiles, 4), dtype=t.float64, device=dev)
@@ -301,8 +299,6 @@ class BatchSimulation:
         b.n_samples = ns
         b.check_every = int(check_every)
         b.grid = int(grid)
-        b.sample_tile_off = self.tile_off_d.data_ptr()
-        b.sample_tile_off_host = self.tile_off_host.ctypes.data
         b.area = self.sim.area_d.data_ptr()
         b.u_prev = self.u_prev_d.data_ptr()
         b.tile_red = self.tile_red_d.data_ptr()
@@ -312,6 +308,21 @@ class BatchSimulation:
         b.sample_residual = self.res_d.data_ptr()
         b.sample_int_ux = self.ux_d.data_ptr()
         self.stream = torch.cuda.Stream(device=dev)
+        self.set_tile(tile)
+
+    PAD = 256
+
+    def set_tile(self, tile):
+        """Tile size of the LDS-staged persistent kernels (64, 128 or 256)."""
+        if tile not in (64, 128, 256):
+            raise ValueError("tile must be 64, 128 or 256")
+        if self.sim.ds.tile != tile:
+            self.sim.set_tile(tile)
+        self.tile = tile
+        self.tile_off_host = (self.node_off // tile).astype(np.int32)
+        self.tile_off_d = self.torch.from_numpy(self.tile_off_host).to(self.sim.state_d[0].device)
+        self.batch.sample_tile_off = self.tile_off_d.data_ptr()
+        self.batch.sample_tile_off_host = self.tile_off_host.ctypes.data
 
     def init_state(self, rho_list, u_list):
         """Initial fields per sample (builder order); padding nodes at rest."""
