@@ -72,6 +72,13 @@ class Batch(ctypes.Structure):
                 ("sample_residual", _p), ("sample_int_ux", _p)]
 
 
+class ConvDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("c_in", ctypes.c_int32), ("c_out", ctypes.c_int32), ("ksize", ctypes.c_int32),
+                ("x_stride", ctypes.c_int32), ("x_offset", ctypes.c_int32),
+                ("y_stride", ctypes.c_int32), ("y_offset", ctypes.c_int32), ("c_store", ctypes.c_int32)]
+
+
 class MlbmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"mlbm error {code}: {msg}")
@@ -111,6 +118,26 @@ def _load():
         "mlbm_reduction_workspace_bytes": (ctypes.c_int64, [ctypes.c_int64]),
         "mlbm_macroscopic": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, ctypes.c_double, _p,
                                             _p, _p, _p, _p, _p]),
+        "mlbm_conv_forward": (ctypes.c_int, [P(ConvDesc), _p, _p, _p, _p, ctypes.c_int32, ctypes.c_int32, _p]),
+        "mlbm_conv_wgrad_workspace": (ctypes.c_int64, [P(ConvDesc), ctypes.c_int32]),
+        "mlbm_conv_wgrad": (ctypes.c_int, [P(ConvDesc), _p, _p, _p, _p, ctypes.c_int32, _p, _p]),
+        "mlbm_conv_weights": (ctypes.c_int, [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p, _p]),
+        "mlbm_relu_backward": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _p, ctypes.c_int32, ctypes.c_int32,
+                                              _p, ctypes.c_int32, ctypes.c_int32, _p]),
+        "mlbm_pool_forward": (ctypes.c_int, [ctypes.c_int32] * 4 + [_p, ctypes.c_int32, ctypes.c_int32, _p,
+                                                                     ctypes.c_int32, ctypes.c_int32, _p]),
+        "mlbm_pool_backward": (ctypes.c_int, [ctypes.c_int32] * 4 + [_p, ctypes.c_int32, ctypes.c_int32, _p,
+                                                                      ctypes.c_int32, ctypes.c_int32, _p,
+                                                                      ctypes.c_int32, ctypes.c_int32, _p]),
+        "mlbm_upsample_forward": (ctypes.c_int, [ctypes.c_int32] * 4 + [_p, ctypes.c_int32, ctypes.c_int32, _p,
+                                                                         ctypes.c_int32, ctypes.c_int32, _p]),
+        "mlbm_upsample_backward": (ctypes.c_int, [ctypes.c_int32] * 4 + [_p, ctypes.c_int32, ctypes.c_int32, _p,
+                                                                          ctypes.c_int32, ctypes.c_int32, _p]),
+        "mlbm_mse_workspace": (ctypes.c_int64, [ctypes.c_int64]),
+        "mlbm_masked_mse": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _p, ctypes.c_int32, _p, _p,
+                                           ctypes.c_float, _p, _p, _p, _p]),
+        "mlbm_adam": (ctypes.c_int, [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_int32, _p]),
         "mlbm_last_error": (ctypes.c_char_p, []),
         "mlbm_version": (ctypes.c_char_p, []),
     }
@@ -128,6 +155,11 @@ EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "ml
            "mlbm_tile_sizes", "mlbm_pack_tiles", "mlbm_init_state", "mlbm_batch_init", "mlbm_step_batched",
            "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
            "mlbm_version"]
+
+# every symbol include/mlbm_unet.h declares
+UNET_EXPORTS = ["mlbm_conv_forward", "mlbm_conv_wgrad_workspace", "mlbm_conv_wgrad", "mlbm_conv_weights",
+                "mlbm_relu_backward", "mlbm_pool_forward", "mlbm_pool_backward", "mlbm_upsample_forward",
+                "mlbm_upsample_backward", "mlbm_mse_workspace", "mlbm_masked_mse", "mlbm_adam"]
 
 
 def check(rc):

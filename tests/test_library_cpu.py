@@ -19,13 +19,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_library_exports_every_declared_symbol():
-    with open(os.path.join(ROOT, "include", "mlbm.h")) as f:
-        header = f.read()
-    declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mlbm_[a-z_0-9]+)\s*\(", header, re.M))
-    assert declared == set(_lib.EXPORTS)
     raw = ctypes.CDLL(_lib.LIB_PATH)
-    for name in declared:
-        assert hasattr(raw, name), name
+    for hdr, names in (("mlbm.h", _lib.EXPORTS), ("mlbm_unet.h", _lib.UNET_EXPORTS)):
+        with open(os.path.join(ROOT, "include", hdr)) as f:
+            header = f.read()
+        declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mlbm_[a-z_0-9]+)\s*\(", header, re.M))
+        assert declared == set(names), hdr
+        for name in declared:
+            assert hasattr(raw, name), name
     assert _lib.lib.mlbm_version().decode().startswith("mlbm")
 
 
