@@ -25,7 +25,7 @@ extern "C" {
 
 typedef struct mlbm_conv_desc {
     int32_t n, h, w;          /* images, height, width; n*h*w a multiple of 128     */
-    int32_t c_in, c_out;      /* multiples of 32; c_out <= 256                      */
+    int32_t c_in, c_out;      /* multiples of 32 (c_out <= 256 for a bias gradient) */
     int32_t ksize;            /* 1 or 3                                             */
     int32_t x_stride, x_offset; /* input view (channels, multiples of 8)           */
     int32_t y_stride, y_offset; /* output view, or the output-gradient view        */

@@ -289,19 +289,23 @@ def random_disks(phi_target: float, r_min: float, r_max: float, gap: float,
 
 def porous(n_target: int = 1_000_000, phi: float = 0.7, seed: int = 231214789,
            r_range=(0.01, 0.03), jitter: float = 0.25, L: float = 1.0,
-           disks: np.ndarray | None = None) -> NodeSet:
+           disks: np.ndarray | None = None, h: float | None = None) -> NodeSet:
     """Periodic box [0, L)^2 with random non-overlapping disks (porosity phi),
-    fluid nodes on a jittered grid of spacing h ~ sqrt(phi L^2 / n_target), and
-    nodes exactly on every disk surface (no-slip, Sec. 3.2).  Disks keep a gap
-    of at least 2h so every throat holds fluid nodes."""
+    fluid nodes on a jittered grid of spacing h ~ sqrt(phi L^2 / n_target) (or
+    the given h; with jitter 0 and h = L / res the fluid nodes are the centres
+    of the fluid pixels of a res^2 raster), and nodes exactly on every disk
+    surface (no-slip, Sec. 3.2).  Disks keep a gap of at least 2h so every
+    throat holds fluid nodes."""
     rng = np.random.default_rng(seed)
-    h = math.sqrt(phi * L * L / n_target)
+    if h is None:
+        h = math.sqrt(phi * L * L / n_target)
     if disks is None:
         disks = random_disks(phi, r_range[0], r_range[1], 2.0 * h, rng, L)
     lo, hi = np.zeros(2), np.full(2, L)
     pts = _grid(lo, hi, h)
-    pts = pts + rng.uniform(-jitter * h, jitter * h, size=pts.shape)
-    pts = _wrap(pts, lo, hi, (True, True))
+    if jitter > 0:
+        pts = pts + rng.uniform(-jitter * h, jitter * h, size=pts.shape)
+        pts = _wrap(pts, lo, hi, (True, True))
     # drop grid points inside a disk or closer than h/2 to its surface (periodic)
     from scipy.spatial import cKDTree
 

@@ -326,8 +326,8 @@ int check_desc(const mlbm_conv_desc *d) {
     if (!d) return fail(MLBM_ERR_ARG, "null descriptor");
     if (d->ksize != 1 && d->ksize != 3) return fail(MLBM_ERR_ARG, "ksize must be 1 or 3");
     if (d->n < 1 || d->h < 1 || d->w < 1) return fail(MLBM_ERR_ARG, "empty tensor");
-    if (d->c_in < 32 || d->c_in % 32 || d->c_out < 32 || d->c_out % 32 || d->c_out > 256)
-        return fail(MLBM_ERR_ARG, "channel counts must be multiples of 32 (c_out <= 256)");
+    if (d->c_in < 32 || d->c_in % 32 || d->c_out < 32 || d->c_out % 32)
+        return fail(MLBM_ERR_ARG, "channel counts must be multiples of 32");
     if (((int64_t)d->n * d->h * d->w) % 128) return fail(MLBM_ERR_ARG, "pixel count must be a multiple of 128");
     if (d->x_stride % 8 || d->x_offset % 8 || d->y_stride % 8 || d->y_offset % 8)
         return fail(MLBM_ERR_ARG, "strides and offsets must be multiples of 8 channels");
@@ -370,6 +370,7 @@ extern "C" int mlbm_conv_wgrad(const mlbm_conv_desc *d, const void *x, const voi
     int rc = check_desc(d);
     if (rc) return rc;
     if (!x || !dy || !dw || !workspace || splits < 1) return mlbm::fail(MLBM_ERR_ARG, "null pointer or splits < 1");
+    if (db && d->c_out > 256) return mlbm::fail(MLBM_ERR_ARG, "bias gradient needs c_out <= 256");
     if (d->y_offset + d->c_out > d->y_stride) return mlbm::fail(MLBM_ERR_ARG, "gradient view exceeds its stride");
     const int64_t P = (int64_t)d->n * d->h * d->w;
     const int taps = d->ksize * d->ksize;
