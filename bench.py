@@ -168,7 +168,8 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
            f"residual {tol:g}", "seconds": round(dt, 3), "steps_run": ran,
            "sample_steps_min_max": [int(steps.min()), int(steps.max())], "unconverged": int(np.sum(steps <= 0)),
            "MNUPS_effective": round(updates / dt / 1e6, 1), "setup_s": round(setup, 1),
-           "autotune": {k: best[k] for k in ("tile", "grid", "xcd", "ms_per_step", "cached")},
+           "groups": int(batch.batch.n_groups),
+           "autotune": {k: best[k] for k in ("tile", "grid", "xcd", "group_bytes", "ms_per_step", "cached")},
            "autotune_s": round(tune_s, 1)}
     if sequential:
         # the same samples one after another, each in its own launches (time
@@ -194,6 +195,70 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
     return out
 
 
+def warmstart_workload(args, np, torch):
+    """Learned warm start (network of 5 levels, 32-256 channels, 256^2 rasters):
+    train on steady states of random-disk media computed by batched library
+    runs, then compare steps and wall time to a residual of 1e-6 from rest and
+    from the network's prediction on held-out samples."""
+    from paper_2312_14789_amd import unet, warmstart
+
+    res, g = 256, 1e-5
+    t0 = time.time()
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
+    geoms = warmstart.make_geometries(args.ws_train + args.ws_test, res=res, workers=16, log=log)
+    t_geo = time.time() - t0
+    print(f"# {len(geoms)} geometries in {t_geo:.1f} s", file=sys.stderr, flush=True)
+    train_g, test_g = geoms[:args.ws_train], geoms[args.ws_train:]
+    t0 = time.time()
+    fields, steps = warmstart.steady_states(train_g, g, batch_size=64, log=log)
+    t_data = time.time() - t0
+    print(f"# steady states in {t_data:.1f} s, steps {min(steps)}..{max(steps)}", file=sys.stderr, flush=True)
+    data = warmstart.Dataset(train_g, fields, res)
+    del fields
+    net = unet.UNet((32, 64, 128, 256, 256), res=res, batch=16, seed=1)
+    t0 = time.time()
+    hist = warmstart.train(net, data, epochs=args.ws_epochs, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    iters = args.ws_epochs * (data.n // net.batch)
+    # inference time per sample (one batch of 16)
+    masks = [m for _, m in test_g]
+    warmstart.predict(net, data, masks[:16], data.u_scale, data.r_scale)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    preds = warmstart.predict(net, data, masks, data.u_scale, data.r_scale)
+    torch.cuda.synchronize()
+    infer = (time.perf_counter() - t0) / len(masks)
+    rows = []
+    for i, ((ns, _), f) in enumerate(zip(test_g, preds)):
+        rows.append(warmstart.compare_runs(ns, f, res, g, infer_s=infer))
+        if (i + 1) % 20 == 0:
+            log(f"{i + 1}/{len(test_g)} held-out comparisons")
+    rest_steps = np.array([r["rest"]["steps"] for r in rows])
+    warm_steps = np.array([r["warm"]["steps"] for r in rows])
+    rest_s = np.array([r["rest"]["seconds"] for r in rows])
+    warm_s = np.array([r["warm"]["seconds"] for r in rows])
+    kerr = np.array([abs(r["warm"]["permeability"] / r["rest"]["permeability"] - 1) for r in rows])
+    np.savez(os.path.join(ROOT, "gpurun_out", "warmstart_weights.npz"), **net.state_dict()) \
+        if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    fl = 0.0
+    for name, k, ci, co in net.shapes:
+        fl += 2.0 * k * k * ci * co * (res >> (int(name[3]) if name != "head" else 0)) ** 2
+    return {"metric": "time-to-steady-state plain vs warm-start",
+            "workload": f"{args.ws_train} training + {len(test_g)} held-out random-disk media, {res}^2 rasters, "
+                        f"MLBM1 FP32 K=16 s=1 g_lb={g:g}, residual 1e-6",
+            "steps_rest_mean": float(rest_steps.mean()), "steps_warm_mean": float(warm_steps.mean()),
+            "step_ratio_rest_over_warm": float((rest_steps / warm_steps).mean()),
+            "seconds_rest_mean": float(rest_s.mean()), "seconds_warm_mean_incl_inference": float(warm_s.mean()),
+            "inference_ms_per_sample": round(1e3 * infer, 3),
+            "permeability_rel_err_max": float(kerr.max()), "permeability_within_0.5pct": bool(kerr.max() <= 5e-3),
+            "train": {"epochs": args.ws_epochs, "loss_first": hist[0], "loss_last": hist[-1], "seconds": round(t_train, 1),
+                      "iters": iters, "ms_per_iter": round(1e3 * t_train / max(iters, 1), 2),
+                      "tflops_fwd_bwd": round(3 * fl * net.batch * iters / t_train / 1e12, 2)},
+            "data": {"geometry_s": round(t_geo, 1), "steady_states_s": round(t_data, 1),
+                     "steps_min_max": [int(min(steps)), int(max(steps))]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,8 +277,12 @@ def main():
     ap.add_argument("--nodes", type=int, default=500_000, help="target node count of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
-    ap.add_argument("--workload", default="karman", choices=["karman", "batched"],
-                    help="karman: the fused-step throughput line; batched: 64 porous samples to steady state")
+    ap.add_argument("--workload", default="karman", choices=["karman", "batched", "warmstart"],
+                    help="karman: the fused-step throughput line; batched: 64 porous samples to steady "
+                         "state; warmstart: train the warm-start network and compare time to steady state")
+    ap.add_argument("--ws-train", type=int, default=2000)
+    ap.add_argument("--ws-test", type=int, default=200)
+    ap.add_argument("--ws-epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a 1 GiB device copy (reference for byte counters and bandwidth)")
     args = ap.parse_args()
@@ -234,6 +303,9 @@ def main():
 
     if args.workload == "batched":
         print(json.dumps(batched_workload(M, units, nodesets, np, torch)), flush=True)
+        return
+    if args.workload == "warmstart":
+        print(json.dumps(warmstart_workload(args, np, torch)), flush=True)
         return
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]

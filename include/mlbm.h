@@ -257,6 +257,14 @@ typedef struct mlbm_batch {
                                         not converged; -steps = unstable (non-finite) */
     double *sample_residual;         /* device [n_samples] out: last residual          */
     double *sample_int_ux;           /* device [n_samples] out: sum A u_x at last check */
+    int32_t n_groups;                /* sample groups (>= 1): within a check each group
+                                        runs its check_every steps before the next one,
+                                        so a group sized to the memory-side cache stays
+                                        resident across its steps                      */
+    const int32_t *group_sample_off; /* device [n_groups + 1]: samples of group g are
+                                        [off[g], off[g+1]); off[n_groups] = n_samples  */
+    const int32_t *group_sample_off_host; /* the same on the host (validation)         */
+    int32_t *group_queue_off;        /* device [n_groups + 1] workspace                 */
 } mlbm_batch;
 
 /*
@@ -270,8 +278,10 @@ int mlbm_batch_init(const mlbm_step_params *params, mlbm_device_state *state, ml
  * Runs checks of check_every steps until every sample has retired (residual
  * below tol, or non-finite fields) or max_steps is reached.  With use_graph
  * one check is captured into a HIP graph on hip_stream (which must not be the
- * default stream) and replayed.  Synchronous: waits on hip_stream after each
- * check to read 16 bytes of counters.  state->cur is unchanged on return (an
+ * default stream) and replayed; a group whose samples have all retired is no
+ * longer launched (the graph is captured again without it).  Synchronous:
+ * waits on hip_stream after each check to read the counters and the group
+ * queue ranges.  state->cur is unchanged on return (an
  * even number of steps per check).  *steps_done receives the steps run.
  * Errors: MLBM_ERR_ARG, MLBM_ERR_UNSUPPORTED, MLBM_ERR_HIP.
  */

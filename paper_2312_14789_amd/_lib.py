@@ -69,7 +69,8 @@ class Batch(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int32), ("check_every", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("sample_tile_off", _p), ("sample_tile_off_host", _p), ("area", _p), ("u_prev", _p),
                 ("tile_red", _p), ("queue", _p), ("counters", _p), ("sample_steps", _p),
-                ("sample_residual", _p), ("sample_int_ux", _p)]
+                ("sample_residual", _p), ("sample_int_ux", _p), ("n_groups", ctypes.c_int32),
+                ("group_sample_off", _p), ("group_sample_off_host", _p), ("group_queue_off", _p)]
 
 
 class ConvDesc(ctypes.Structure):

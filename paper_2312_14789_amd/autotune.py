@@ -1,10 +1,15 @@
 """Launch-shape autotuner for batched runs.
 
-Times the batched step (mlbm_step_batched, graph replay, no retirement) for
-every candidate (tile size, persistent grid, XCD-contiguous chunks) on the
-actual batch and keeps the fastest.  Results are cached in a JSON file keyed
-by GPU architecture, stencil size, variant, storage and the node count
-rounded to a power of two, so a later run on a similar batch reuses them.
+Times the batched step (mlbm_step_batched, graph replay, no retirement) on
+the actual batch in two stages and keeps the fastest: first the tile size and
+the XCD-contiguous chunking, then, with those, the persistent grid together
+with the size of the sample groups that run their steps back to back (a group
+that fits the memory-side cache is read from it instead of HBM on all but its
+first step; a grid at least as large as a group's tile count gives every
+workgroup one tile of it).
+Results are cached in a JSON file keyed by GPU architecture, stencil size,
+variant, storage, and node and sample counts rounded to powers of two, so a
+later run on a similar batch reuses them.
 """
 from __future__ import annotations
 
@@ -13,8 +18,10 @@ import math
 import os
 
 TILES = (64, 128, 256)
-GRIDS = (512, 1024, 2048)
 XCD = (1, 0)
+GRIDS = (1024, 2048, 4096)
+GROUP_BYTES = (0.0, 96e6, 160e6, 240e6)
+GRID0 = 2048
 
 
 def default_cache_path() -> str:
@@ -27,7 +34,8 @@ def cache_key(batch) -> str:
 
     arch = torch.cuda.get_device_properties(batch.sim.state_d[0].device).gcnArchName.split(":")[0]
     p = batch.sim.params
-    return f"{arch}|K{batch.K}|v{p.variant}|s{p.storage}|N2^{round(math.log2(batch.N))}"
+    return (f"{arch}|K{batch.K}|v{p.variant}|s{p.storage}|N2^{round(math.log2(batch.N))}"
+            f"|S2^{round(math.log2(len(batch.sizes)))}")
 
 
 def _time(batch, steps):
@@ -44,8 +52,8 @@ def _time(batch, steps):
 
 def tune(batch, steps=200, cache_path=None, use_cache=True, rho_u=None):
     """Picks the fastest launch shape for `batch` (a BatchSimulation) and
-    applies it.  Returns {"tile", "grid", "xcd", "ms_per_step", "timings",
-    "cached"}.  The batch state is re-initialised (at rest, or from rho_u =
+    applies it.  Returns {"tile", "grid", "xcd", "group_bytes", "ms_per_step",
+    "timings", "cached"}.  The batch state is re-initialised (at rest, or from rho_u =
     (rho_list, u_list)) after timing."""
     cache_path = cache_path or default_cache_path()
     key = cache_key(batch)
@@ -59,19 +67,29 @@ def tune(batch, steps=200, cache_path=None, use_cache=True, rho_u=None):
         sizes = batch.sizes
         init = rho_u or ([None] * len(sizes), [None] * len(sizes))
         timings = []
-        for tile in TILES:
+        group0 = batch.group_bytes
+
+        def run(tile, xcd, grid, gb):
             batch.set_tile(tile)
-            for grid in GRIDS:
-                for xcd in XCD:
-                    batch.batch.grid = grid
-                    batch.sim.params.xcd_remap = xcd
-                    _reinit(batch, init)
-                    _time(batch, batch.batch.check_every)  # warm-up (graph build, caches)
-                    ms = _time(batch, steps)
-                    timings.append({"tile": tile, "grid": grid, "xcd": xcd, "ms_per_step": ms})
+            batch.sim.params.xcd_remap = xcd
+            batch.batch.grid = grid
+            batch.set_groups(gb)
+            _reinit(batch, init)
+            _time(batch, batch.batch.check_every)  # warm-up (graph build, caches)
+            timings.append({"tile": tile, "grid": grid, "xcd": xcd, "group_bytes": gb,
+                            "ms_per_step": _time(batch, steps)})
+
+        for tile in TILES:
+            for xcd in XCD:
+                run(tile, xcd, GRID0, group0)
+        first = min(timings, key=lambda r: r["ms_per_step"])
+        for grid in GRIDS:
+            for gb in GROUP_BYTES:
+                if grid != GRID0 or gb != group0:
+                    run(first["tile"], first["xcd"], grid, gb)
         best = dict(min(timings, key=lambda r: r["ms_per_step"]))
         best["timings"] = timings
-        cache[key] = {k: best[k] for k in ("tile", "grid", "xcd", "ms_per_step")}
+        cache[key] = {k: best[k] for k in ("tile", "grid", "xcd", "group_bytes", "ms_per_step")}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
@@ -79,6 +97,7 @@ def tune(batch, steps=200, cache_path=None, use_cache=True, rho_u=None):
     batch.set_tile(best["tile"])
     batch.batch.grid = best["grid"]
     batch.sim.params.xcd_remap = best["xcd"]
+    batch.set_groups(best["group_bytes"])
     _reinit(batch, rho_u or ([None] * len(batch.sizes), [None] * len(batch.sizes)))
     return best
 

@@ -16,6 +16,7 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <vector>
 
 #include <cmath>
 #include <cstdint>
@@ -268,7 +269,8 @@ struct StepArgs {
     const int *halo;           // LDS staging: halo node lists
     const unsigned short *lidx;  // LDS staging: tile-local member positions [K8/8][n][8]
     const int *queue;          // batched launches: list of active tiles (NULL: every tile)
-    const int *queue_count;    // batched launches: number of entries in queue (device)
+    const int *queue_range;    // batched launches: device offsets; this launch walks
+    int group;                 //   queue[queue_range[group] .. queue_range[group + 1])
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin; with xcd each XCD gets
@@ -315,13 +317,18 @@ __device__ __forceinline__ void stage_halo(const StepArgs &a, int64_t tile, void
 template <class F>
 __device__ __forceinline__ void for_tiles(const StepArgs &a, F &&f) {
     if (a.queue) {
-        const int na = *a.queue_count;
+        const int q0 = a.queue_range[a.group], na = a.queue_range[a.group + 1] - q0;
         const int G = gridDim.x;
         int b = blockIdx.x;
-        if (a.xcd) b = (b & 7) * (G >> 3) + (b >> 3);
+        if (a.xcd) {
+            const int r = b >> 3, per = G >> 3;
+            b = (b & 7) * per + (a.reverse ? per - 1 - r : r);
+        } else if (a.reverse) {
+            b = G - 1 - b;
+        }
         const int chunk = (na + G - 1) / G;
         const int c1 = min(na, (b + 1) * chunk);
-        for (int c = b * chunk; c < c1; ++c) f((int64_t)a.queue[c]);
+        for (int c = b * chunk; c < c1; ++c) f((int64_t)a.queue[q0 + c]);
     } else {
         const int64_t tile = tile_of(a);
         if (tile * blockDim.x < a.n) f(tile);
@@ -899,7 +906,8 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     a.halo = st->halo;
     a.lidx = st->lidx;
     a.queue = nullptr;
-    a.queue_count = nullptr;
+    a.queue_range = nullptr;
+    a.group = 0;
     const int64_t nb = (st->n + blk - 1) / blk;
     a.grid8 = a.xcd ? (nb + 7) / 8 * 8 : nb;
     hipStream_t s = (hipStream_t)stream;
@@ -981,6 +989,9 @@ struct BatchArgs {
     int *counters;
     const int *tile_off;
     int n_samples;
+    int n_groups;                // sample groups run one after another within a check
+    const int *group_sample_off; // [n_groups + 1] samples of each group
+    int *group_queue_off;        // [n_groups + 1] queue range of each group (device)
     int *sample_steps;
     double *sample_res;
     double *sample_ux;
@@ -1075,6 +1086,15 @@ __global__ void __launch_bounds__(256) k_batch_retire(const BatchArgs a, int mar
         }
         total = pos;
         active = act;
+        // queue range of every group: its samples are consecutive, so their
+        // active tiles are consecutive in the queue
+        int q = 0;
+        for (int gi = 0; gi < a.n_groups; ++gi) {
+            a.group_queue_off[gi] = q;
+            for (int s = a.group_sample_off[gi]; s < a.group_sample_off[gi + 1]; ++s)
+                if (start[s] >= 0) q += a.tile_off[s + 1] - a.tile_off[s];
+        }
+        a.group_queue_off[a.n_groups] = q;
     }
     __syncthreads();
     for (int s = 0; s < a.n_samples; ++s) {
@@ -1140,6 +1160,12 @@ int batch_args(const mlbm_step_params *p, const mlbm_device_state *st, const mlb
     for (int s = 0; s < b->n_samples; ++s)
         if (off[s + 1] <= off[s]) return fail(MLBM_ERR_ARG, "sample %d has no tiles", s);
     if (b->check_every < 2 || (b->check_every & 1)) return fail(MLBM_ERR_ARG, "check_every must be even and >= 2");
+    if (b->n_groups < 1 || !b->group_sample_off || !b->group_sample_off_host || !b->group_queue_off)
+        return fail(MLBM_ERR_ARG, "batch needs at least one sample group");
+    const int32_t *go = b->group_sample_off_host;
+    if (go[0] != 0 || go[b->n_groups] != b->n_samples) return fail(MLBM_ERR_ARG, "groups must cover the samples");
+    for (int gi = 0; gi < b->n_groups; ++gi)
+        if (go[gi + 1] <= go[gi]) return fail(MLBM_ERR_ARG, "group %d is empty", gi);
     ba.n = st->n;
     ba.flags = st->flags;
     ba.bc = st->bc;
@@ -1160,6 +1186,9 @@ int batch_args(const mlbm_step_params *p, const mlbm_device_state *st, const mlb
     ba.inv_scale = std::ldexp(1.0f, -p->scale_exp);
     ba.check_every = b->check_every;
     ba.ntiles = ntiles;
+    ba.n_groups = b->n_groups;
+    ba.group_sample_off = b->group_sample_off;
+    ba.group_queue_off = b->group_queue_off;
     return MLBM_OK;
 }
 
@@ -1226,39 +1255,63 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     a.halo = st->halo;
     a.lidx = st->lidx;
     a.queue = b->queue;
-    a.queue_count = b->counters;
+    a.queue_range = b->group_queue_off;
     a.grid8 = batch_grid(b);
     const int G = (int)a.grid8;
     hipStream_t s = (hipStream_t)stream;
     const int cur0 = st->cur;
-    // one check: check_every steps, the per-tile pass, retirement
+    // one check: check_every steps of every sample group in turn (a group's
+    // nodes stay cache-resident across its steps), the per-tile pass, retirement
+    // groups whose samples have all retired are left out of the launches
+    std::vector<int32_t> qoff(b->n_groups + 1);
+    std::vector<char> live(b->n_groups, 1);
     auto enqueue = [&]() -> int {
-        int cur = cur0;
-        for (int t = 0; t < b->check_every; ++t) {
-            a.in = st->state[cur];
-            a.out = st->state[cur ^ 1];
-            hipLaunchKernelGGL(fn, dim3(G), dim3(st->tile), shmem, s, a);
-            cur ^= 1;
+        for (int gi = 0; gi < b->n_groups; ++gi) {
+            if (!live[gi]) continue;
+            int cur = cur0;
+            a.group = gi;
+            for (int t = 0; t < b->check_every; ++t) {
+                a.in = st->state[cur];
+                a.out = st->state[cur ^ 1];
+                a.reverse = p->alternate_sweeps ? (t & 1) : 0;
+                hipLaunchKernelGGL(fn, dim3(G), dim3(st->tile), shmem, s, a);
+                cur ^= 1;
+            }
         }
-        ba.state = st->state[cur];
+        ba.state = st->state[cur0];
         hipLaunchKernelGGL(red, dim3(G), dim3(st->tile), 0, s, ba);
         hipLaunchKernelGGL(k_batch_retire, dim3(1), dim3(256), 0, s, ba, 1);
         return hip_check("mlbm_step_batched launch");
     };
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    if (use_graph) {
+    auto release = [&]() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    auto capture = [&]() -> int {
+        release();
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(MLBM_ERR_HIP, "hipStreamBeginCapture failed");
-        rc = enqueue();
+        int r = enqueue();
         hipError_t e = hipStreamEndCapture(s, &graph);
-        if (rc) return rc;
+        if (r) return r;
         if (e != hipSuccess) return fail(MLBM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            hipGraphDestroy(graph);
-            return fail(MLBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-        }
+        if (e != hipSuccess) return fail(MLBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        return MLBM_OK;
+    };
+    // the queue ranges left by the last retirement decide which groups run
+    if (hipMemcpyAsync(qoff.data(), b->group_queue_off, qoff.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MLBM_ERR_HIP, "reading the group queue ranges failed");
+    for (int gi = 0; gi < b->n_groups; ++gi) live[gi] = qoff[gi + 1] > qoff[gi];
+    if (use_graph && (rc = capture())) {
+        release();
+        return rc;
     }
     int steps = 0;
     int counters[4] = {1, 0, 1, 0};
@@ -1273,14 +1326,22 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
         }
         steps += b->check_every;
         if (hipMemcpyAsync(counters, b->counters, sizeof(counters), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(qoff.data(), b->group_queue_off, qoff.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             rc = fail(MLBM_ERR_HIP, "reading the batch counters failed");
             break;
         }
         if (counters[2] == 0) break;
+        bool changed = false;
+        for (int gi = 0; gi < b->n_groups; ++gi) {
+            const char l = qoff[gi + 1] > qoff[gi];
+            changed |= l != live[gi];
+            live[gi] = l;
+        }
+        if (changed && use_graph && steps < max_steps && (rc = capture())) break;
     }
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    release();
     if (steps_done) *steps_done = steps;
     return rc;
 }

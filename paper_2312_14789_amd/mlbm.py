@@ -246,7 +246,7 @@ class BatchSimulation:
 
     def __init__(self, samples, *, variant=FIELDS, storage=F32, tau_plus=1.0, tau_minus=None,
                  g=(0.0, 0.0), tile=256, check_every=100, grid=0, scale_exp=0, xcd_remap=1,
-                 fp32_arith=0, device="cuda"):
+                 fp32_arith=0, group_bytes=160e6, alternate_sweeps=1, device="cuda"):
         import torch
 
         self.torch = torch
@@ -307,8 +307,33 @@ class BatchSimulation:
         b.sample_steps = self.steps_d.data_ptr()
         b.sample_residual = self.res_d.data_ptr()
         b.sample_int_ux = self.ux_d.data_ptr()
+        self.sim.params.alternate_sweeps = int(alternate_sweeps)
+        self.set_groups(group_bytes)
         self.stream = torch.cuda.Stream(device=dev)
         self.set_tile(tile)
+
+    def set_groups(self, group_bytes):
+        """Consecutive samples grouped so each group's stepping data (state,
+        weights, indices) stays under group_bytes (0 = one group)."""
+        per_node = packed_sizes(1 << 10, self.K, self.sim.params.variant, self.sim.params.storage)
+        bpn = (per_node.w_bytes + per_node.idx_bytes + 2 * per_node.state_bytes) / (1 << 10)
+        off = [0]
+        acc = 0.0
+        for s_, m in enumerate(self.sizes):
+            if group_bytes and acc > 0 and acc + m * bpn > group_bytes:
+                off.append(s_)
+                acc = 0.0
+            acc += m * bpn
+        off.append(len(self.sizes))
+        self.group_bytes = float(group_bytes)
+        self.group_off_host = np.asarray(off, np.int32)
+        dev = self.sim.state_d[0].device
+        self.group_off_d = self.torch.from_numpy(self.group_off_host).to(dev)
+        self.group_q_d = self.torch.zeros(len(off), dtype=self.torch.int32, device=dev)
+        self.batch.n_groups = len(off) - 1
+        self.batch.group_sample_off = self.group_off_d.data_ptr()
+        self.batch.group_sample_off_host = self.group_off_host.ctypes.data
+        self.batch.group_queue_off = self.group_q_d.data_ptr()
 
     PAD = 256
 

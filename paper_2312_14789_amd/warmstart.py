@@ -31,15 +31,23 @@ def _make_sample(args):
     return ns, mask
 
 
-def make_geometries(n, res=256, seed=231214789, phi_range=(0.6, 0.8), r_range=(0.01, 0.03), workers=8):
+def make_geometries(n, res=256, seed=231214789, phi_range=(0.6, 0.8), r_range=(0.01, 0.03), workers=8, log=None):
     """n periodic random-disk samples (porosity drawn uniformly from phi_range,
     radii uniform in r_range)."""
     rng = np.random.default_rng(seed)
     jobs = [(int(seed + 1000 + i), res, float(rng.uniform(*phi_range)), tuple(r_range)) for i in range(n)]
-    if workers > 1:
-        with ProcessPoolExecutor(max_workers=workers) as ex:
-            return list(ex.map(_make_sample, jobs, chunksize=4))
-    return [_make_sample(j) for j in jobs]
+    out = []
+    ex = ProcessPoolExecutor(max_workers=workers) if workers > 1 else None
+    try:
+        it = ex.map(_make_sample, jobs, chunksize=4) if ex else map(_make_sample, jobs)
+        for i, r in enumerate(it):
+            out.append(r)
+            if log and (i + 1) % 128 == 0:
+                log(f"{i + 1}/{n} geometries")
+    finally:
+        if ex:
+            ex.shutdown()
+    return out
 
 
 def pixel_of_nodes(ns, res):
@@ -50,7 +58,7 @@ def pixel_of_nodes(ns, res):
     return np.where(grid, iy, -1), np.where(grid, ix, -1)
 
 
-def steady_states(samples, g, K=16, tol=1e-6, batch_size=64, max_steps=200_000, check_every=100):
+def steady_states(samples, g, K=16, tol=1e-6, batch_size=64, max_steps=200_000, check_every=100, log=None):
     """Steady MLBM1 (FP32) fields of every sample, computed in batched runs.
     Returns per sample (rho, u) in the node set's order, and the steps each
     sample needed."""
@@ -74,6 +82,8 @@ def steady_states(samples, g, K=16, tol=1e-6, batch_size=64, max_steps=200_000, 
             out.append((rho[o:o + m][inv], u[o:o + m][inv]))
         steps_all.extend(steps.tolist())
         del batch
+        if log:
+            log(f"{len(out)}/{len(samples)} steady states")
     return out, steps_all
 
 

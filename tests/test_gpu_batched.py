@@ -40,13 +40,16 @@ def _rows(raw, n_total, a, m, variant, tb):
     return main[a:a + m].tobytes() + rest[a:a + m].tobytes()
 
 
-@pytest.mark.parametrize("variant,storage", [(1, 1), (0, 1), (1, 2)])
-def test_batched_state_equals_single_runs(M, variant, storage):
+@pytest.mark.parametrize("variant,storage,group_bytes", [(1, 1, 160e6), (0, 1, 160e6), (1, 2, 160e6), (1, 1, 1),
+                                                         (0, 1, 1)])
+def test_batched_state_equals_single_runs(M, variant, storage, group_bytes):
     samples = _samples(M)
     g = (3e-6, 0.0)
     tau = 1.0 if variant == 1 else 0.8
     batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for ns, b in samples], variant=variant,
-                              storage=storage, tau_plus=tau, g=g, tile=256, check_every=100, scale_exp=16)
+                              storage=storage, tau_plus=tau, g=g, tile=256, check_every=100, scale_exp=16,
+                              group_bytes=group_bytes)
+    assert batch.batch.n_groups == (1 if group_bytes > 1 else len(samples))
     steps_ = 600
     for use_graph in (True, False):
         batch.init_state([np.ones(b["idx"].shape[0]) for _, b in samples],
@@ -65,11 +68,12 @@ def test_batched_state_equals_single_runs(M, variant, storage):
             assert _rows(raw, batch.N, a, m, variant, tb) == _rows(single, m, 0, m, variant, tb), (s_, use_graph)
 
 
-def test_batched_retirement(M):
+@pytest.mark.parametrize("group_bytes", [160e6, 2e6])
+def test_batched_retirement(M, group_bytes):
     samples = _samples(M, sizes=(1200, 2000, 3200, 900), seed=50)
     g = (2e-6, 0.0)
     batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for ns, b in samples], variant=1, storage=1,
-                              g=g, tile=128, check_every=100)
+                              g=g, tile=128, check_every=100, group_bytes=group_bytes)
     batch.init_state([np.ones(b["idx"].shape[0]) for _, b in samples],
                      [np.zeros((b["idx"].shape[0], 2)) for _, b in samples])
     ran = batch.run(200000, tol=1e-6, use_graph=True)
