@@ -119,6 +119,23 @@ def jittered_grid(n: int, jitter: float = 0.3, seed: int = 231214789, L: float =
     return ns
 
 
+def patch_jittered_grid(n: int, radius: float, centre=(0.5, 0.5), jitter: float = 0.3,
+                        seed: int = 231214789, L: float = 1.0) -> NodeSet:
+    """Hybrid periodic set: the cell-centred n x n grid with only the nodes
+    within `radius` (minimum image) of `centre` jittered as in jittered_grid;
+    the rest stay on the lattice."""
+    ns = regular_grid(n, L)
+    rng = np.random.default_rng(seed)
+    h = L / n
+    d = _min_image(ns.xy - np.asarray(centre, dtype=np.float64), ns.hi - ns.lo, ns.periodic)
+    sel = np.hypot(d[:, 0], d[:, 1]) < radius
+    off = rng.uniform(-jitter * h, jitter * h, size=ns.xy.shape)
+    xy = ns.xy + np.where(sel[:, None], off, 0.0)
+    ns.xy = _wrap(xy, ns.lo, ns.hi, ns.periodic)
+    ns.name = f"patch{n}"
+    return ns
+
+
 def channel(nx: int, ny: int, jitter: float = 0.0, seed: int = 231214789,
             Lx: float = 1.0, H: float = 1.0) -> NodeSet:
     """Plane channel [0, Lx) x [0, H], periodic along x, no-slip walls at y=0

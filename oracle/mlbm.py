@@ -22,13 +22,18 @@ of a Dirichlet node is overwritten by the equilibrium of the prescribed
 density and velocity.
 
 Stencils: one stencil of the K nearest nodes per Eulerian node, shared by its
-eight departure points, with separate weights per departure point.
+eight departure points, with separate weights per departure point.  In a
+hybrid node set (Sec. 2.2) a fluid node whose nine nearest nodes form a square
+block of the lattice spacing h, and none of whose departure points needs the
+bounce-back rule, uses the block (nine members) with biquadratic Lagrange
+weights instead (oracle.lagrange).
 """
 import dataclasses
 
 import numpy as np
 
 from . import lattice as lt
+from .lagrange import biquadratic_weights, lattice_block
 from .rbf import interpolation_weights, min_image, nearest
 
 FLUID, WALL, DIRICHLET = 0, 1, 2
@@ -41,6 +46,7 @@ class Stencils:
     src: np.ndarray     # (n, 8) source population of each arriving k (k or k')
     point: np.ndarray   # (n, 8, 2) departure point offsets from the node
     area: np.ndarray    # (n,) quadrature weight of each node
+    lagrange: np.ndarray = None  # (n,) True where the biquadratic Lagrange block is used
 
 
 def inside_solid(p, ns, eps=1e-12):
@@ -83,32 +89,44 @@ def node_area(ns, i, m=4):
     return 0.5 * a if ns.kind[i] != FLUID else a
 
 
-def stencil_at(ns, i, K, dx):
-    """Stencil indices (K,), weights (8, K), sources (8,) and departure offsets
-    (8, 2) of node i."""
-    idx, X = nearest(ns.xy, i, K, ns.hi - ns.lo, ns.periodic)
+def stencil_at(ns, i, K, dx, lattice_h=None):
+    """Stencil indices (K,), weights (8, K), sources (8,), departure offsets
+    (8, 2) of node i, and whether the Lagrange block was used (lattice_h: the
+    spacing of the regular part of a hybrid set, None for RBF-FD everywhere)."""
     src = np.zeros(8, dtype=np.int64)
     pts = np.zeros((8, 2))
     for k in range(1, 9):
         pts[k - 1], src[k - 1] = departure(ns, i, k, dx)
+    if lattice_h is not None and ns.kind[i] == FLUID and dx <= lattice_h and np.all(src == np.arange(1, 9)):
+        block = lattice_block(ns, i, lattice_h)
+        if block is not None:
+            idx = np.full(K, i, dtype=np.int64)
+            idx[:9] = block
+            w = np.zeros((8, K))
+            w[:, :9] = biquadratic_weights(pts, lattice_h)
+            return idx, w, src, pts, True
+    idx, X = nearest(ns.xy, i, K, ns.hi - ns.lo, ns.periodic)
     w = interpolation_weights(X, pts)
-    return idx, w, src, pts
+    return idx, w, src, pts, False
 
 
-def build_stencils(ns, K, dx):
+def build_stencils(ns, K, dx, lattice_h=None):
     """Stencils of every node, plus quadrature weights normalised so that they
     sum to the analytic fluid area."""
     n = ns.n
+    if lattice_h is not None and K < 10:
+        raise ValueError("hybrid stencils need K >= 10")
     idx = np.zeros((n, K), dtype=np.int64)
     w = np.zeros((n, 8, K))
     src = np.zeros((n, 8), dtype=np.int64)
     pts = np.zeros((n, 8, 2))
     area = np.zeros(n)
+    lag = np.zeros(n, dtype=bool)
     for i in range(n):
-        idx[i], w[i], src[i], pts[i] = stencil_at(ns, i, K, dx)
+        idx[i], w[i], src[i], pts[i], lag[i] = stencil_at(ns, i, K, dx, lattice_h)
         area[i] = node_area(ns, i)
     area *= ns.fluid_area() / area.sum()
-    return Stencils(idx=idx, w=w, src=src, point=pts, area=area)
+    return Stencils(idx=idx, w=w, src=src, point=pts, area=area, lagrange=lag)
 
 
 # --------------------------------------------------------------------------

@@ -49,7 +49,7 @@ def sim_from_oracle(M, ns, st, variant, storage, tau_plus, tau_minus, g, **kw):
                         g=g, bc=ns.boundary_values(), **kw)
 
 
-def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus, g):
+def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus, g, lattice_h=None):
     """Fields after one step at the listed nodes only, computed node by node
     with the oracle's own stencil of each node (for node sets too large for a
     whole oracle run).  rho0, u0: initial fields of all nodes."""
@@ -57,7 +57,7 @@ def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus,
     d_all = ns.kind == nodesets.DIRICHLET
     bc = ns.boundary_values()
     for i in nodes:
-        idx, w, src, _ = omlbm.stencil_at(ns, i, K, dx)
+        idx, w, src, _, _ = omlbm.stencil_at(ns, i, K, dx, lattice_h)
         if d_all[i]:
             out_r.append(bc[i, 0])
             out_u.append(bc[i, 1:3])
