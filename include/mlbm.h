@@ -82,6 +82,9 @@ typedef struct mlbm_stencil_params {
     int32_t reorder;         /* 0 keep the caller's order, 1 Morton (Z) order     */
     double dx;               /* streaming distance dx > 0, units of xy             */
     int32_t n_threads;       /* host threads; 0 = all hardware threads            */
+    double lattice_h;        /* > 0: hybrid set whose regular part is a square
+                                lattice of this spacing (K >= 10); 0: RBF-FD at
+                                every node                                         */
 } mlbm_stencil_params;
 
 /* Caller-allocated host outputs of mlbm_build_stencils. */
@@ -92,6 +95,10 @@ typedef struct mlbm_stencils {
     uint8_t *bb;             /* [n]       bit k-1 set: population k is rebuilt from
                                           source population k' (bounce-back)      */
     double *area;            /* [n]       quadrature weight of each node           */
+    uint8_t *lagrange;       /* [n] or NULL: 1 where the block weights are used    */
+    double *w_lagrange;      /* [8][9] or NULL: the block weights of arriving
+                                populations k = 1..8 over members 0..8           */
+    int64_t n_lagrange;      /* written: number of block centres                  */
 } mlbm_stencils;
 
 /*
@@ -107,6 +114,15 @@ typedef struct mlbm_stencils {
  * its own weights).  Quadrature weights: squared mean distance to the four
  * nearest other nodes, halved for MLBM_WALL / MLBM_DIRICHLET nodes, scaled to
  * sum to geometry->fluid_area.
+ * Hybrid sets (lattice_h > 0, Sec. 2.2): a fluid node whose nine nearest nodes
+ * are the 3 x 3 lattice block x + lattice_h e_j around it (the tenth lies
+ * farther than the block corners), whose departure points all lie in the
+ * fluid and with dx <= lattice_h, is a block centre: its members 0..7 are the
+ * lattice neighbours x + lattice_h e_1 .. e_8, member 8 is the node itself,
+ * any further members the node itself with weight 0, and its weights are the
+ * tensor-product quadratic Lagrange weights through the block, the same for
+ * every block centre (w_lagrange).  With reorder = 1 the block centres follow
+ * every other node.
  * Errors: MLBM_ERR_ARG (null pointers, K out of range, dx <= 0),
  * MLBM_ERR_GEOMETRY (K > n, node inside a solid, empty box, node outside the
  * box), MLBM_ERR_SINGULAR (a local system is singular or fails to reproduce
@@ -121,7 +137,7 @@ int mlbm_build_stencils(const mlbm_geometry *geometry, const mlbm_stencil_params
  * itself with weight 0).  Packed arrays (all little-endian, node index i fast):
  *   idx    int32  [Kp/4][n][4]
  *   w      F64 storage: double [8][Kp/2][n][2]; otherwise float [8][Kp/4][n][4]
- *   flags  uint16 [n]: bits 0-7 = bb, bits 8-9 = kind
+ *   flags  uint16 [n]: bits 0-7 = bb, bits 8-9 = kind, bit 10 = MLBM_FLAG_LAGRANGE
  *   state  (MLBM_POPULATIONS) offsets f_k - omega_k of the post-collision
  *          populations: T [n][8] for k = 1..8, then T [n] for k = 0;
  *          (MLBM_FIELDS) T [n][4] = (rho - 1, u_x, u_y, 0);
@@ -152,6 +168,14 @@ int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx
 int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t n, int32_t K, int32_t storage,
                              const int32_t *idx, const double *w, const uint8_t *bb, const uint8_t *kind,
                              void *idx_packed, void *w_packed, uint16_t *flags);
+
+/*
+ * Sets MLBM_FLAG_LAGRANGE in packed flags[i] where lagrange[i] != 0 (the
+ * builder's lagrange output), so that mlbm_step takes those nodes' weights
+ * from mlbm_device_state.w_lagrange.  Errors: MLBM_ERR_ARG.
+ */
+#define MLBM_FLAG_LAGRANGE 0x400u  /* flags bit 10: node interpolated on its lattice block */
+int mlbm_mark_lagrange(int64_t n, const uint8_t *lagrange, uint16_t *flags);
 
 /*
  * Tile-local indices for LDS staging.  A tile is `tile` (64, 128 or 256)
@@ -208,6 +232,17 @@ typedef struct mlbm_device_state {
     const int32_t *halo_off; /* device copies of mlbm_pack_tiles' outputs           */
     const int32_t *halo;
     const uint16_t *lidx;
+    const void *w_lagrange;  /* device [8][9] block weights (double for MLBM_F64
+                                storage, float otherwise) or NULL                 */
+    int64_t lagrange_begin;  /* with w_lagrange: nodes [lagrange_begin, n) are all
+                                block centres flagged MLBM_FLAG_LAGRANGE (the
+                                builder's order puts them last); the tiles made
+                                only of them run a kernel that reads the shared
+                                weights and eight neighbour indices per node, every
+                                other node its own packed weights (which the
+                                builder also fills for block centres).  A node of
+                                that range without the flag gets a NaN state.
+                                Batched runs use the packed weights throughout.   */
 } mlbm_device_state;
 
 /*

@@ -215,7 +215,8 @@ def _circle_nodes(cx, cy, r, h):
 
 
 def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
-           u_max: float = 0.05, jitter: float = 0.35) -> NodeSet:
+           u_max: float = 0.05, jitter: float = 0.35, hybrid: bool = False,
+           wake: float = 6.0) -> NodeSet:
     """Channel 22D x 4.1D with a cylinder of diameter D centred at (2D, 2D).
 
     Scattered nodes: stratified (jittered) samples at spacing h_b in the bulk
@@ -224,7 +225,13 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     no-slip); Dirichlet nodes on the four straight boundaries (spacing h_b):
     parabolic inflow/outflow profile with maximum u_max on x=0 and x=22D,
     zero velocity on y=0 and y=4.1D, unit density (the boundary treatment of
-    Sec. 3.1).  h_b is chosen so that the set holds about n_target nodes."""
+    Sec. 3.1).  h_b is chosen so that the set holds about n_target nodes.
+
+    hybrid: the arrangement of Sec. 3.1 (scattered near the cylinder and in
+    its wake, a square lattice elsewhere): bulk nodes are jittered only within
+    2D of the cylinder centre and in the wake box [2D, 2D + wake D] x
+    [0.5D, 3.5D]; elsewhere they stay on the lattice of spacing h_b, which is
+    then D/(10 m) for an integer m so that it divides both channel sides."""
     rng = np.random.default_rng(seed)
     Lx, Ly = 22.0 * D, 4.1 * D
     cx, cy, r = 2.0 * D, 2.0 * D, 0.5 * D
@@ -232,12 +239,19 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     a_fine = np.pi * ((r + ring) ** 2 - r ** 2)
     a_bulk = Lx * Ly - np.pi * (r + ring) ** 2
     hb = math.sqrt((a_bulk + 4.0 * a_fine) / n_target)
+    if hybrid:
+        hb = 0.1 * D / max(1, round(0.1 * D / hb))
     hf = 0.5 * hb
     lo, hi = np.zeros(2), np.array([Lx, Ly])
 
     # Bulk: jittered grid away from the boundaries.
     bulk = _grid(lo, hi, hb)
-    bulk = bulk + rng.uniform(-jitter * hb, jitter * hb, size=bulk.shape)
+    off = rng.uniform(-jitter * hb, jitter * hb, size=bulk.shape)
+    if hybrid:
+        near = np.hypot(bulk[:, 0] - cx, bulk[:, 1] - cy) < 2.0 * D
+        in_wake = (bulk[:, 0] >= cx) & (bulk[:, 0] <= cx + wake * D) & (np.abs(bulk[:, 1] - cy) <= 1.5 * D)
+        off[~(near | in_wake)] = 0.0
+    bulk = bulk + off
     rb = np.hypot(bulk[:, 0] - cx, bulk[:, 1] - cy)
     inside = (bulk[:, 0] > 0.5 * hb) & (bulk[:, 0] < Lx - 0.5 * hb) & \
              (bulk[:, 1] > 0.5 * hb) & (bulk[:, 1] < Ly - 0.5 * hb)
@@ -275,7 +289,8 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     y = xy[:, 1]
     bc[inout, 1] = 4.0 * u_max * y[inout] * (Ly - y[inout]) / Ly ** 2
     return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(False, False),
-                   disks=np.array([[cx, cy, r]]), bc=bc, h=hb, name="karman", h_min=hf)
+                   disks=np.array([[cx, cy, r]]), bc=bc, h=hb, name="karman-hybrid" if hybrid else "karman",
+                   h_min=hf)
 
 
 def random_disks(phi_target: float, r_min: float, r_max: float, gap: float,

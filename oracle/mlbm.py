@@ -100,10 +100,12 @@ def stencil_at(ns, i, K, dx, lattice_h=None):
     if lattice_h is not None and ns.kind[i] == FLUID and dx <= lattice_h and np.all(src == np.arange(1, 9)):
         block = lattice_block(ns, i, lattice_h)
         if block is not None:
+            # members: the eight lattice neighbours, then the node itself
+            order = [1, 2, 3, 4, 5, 6, 7, 8, 0]
             idx = np.full(K, i, dtype=np.int64)
-            idx[:9] = block
+            idx[:9] = block[order]
             w = np.zeros((8, K))
-            w[:, :9] = biquadratic_weights(pts, lattice_h)
+            w[:, :9] = biquadratic_weights(pts, lattice_h)[:, order]
             return idx, w, src, pts, True
     idx, X = nearest(ns.xy, i, K, ns.hi - ns.lo, ns.periodic)
     w = interpolation_weights(X, pts)

@@ -17,6 +17,7 @@ MLBM_ERR_HIP = -4
 MLBM_ERR_UNSUPPORTED = -5
 
 FLUID, WALL, DIRICHLET = 0, 1, 2
+FLAG_LAGRANGE = 0x400
 POPULATIONS, FIELDS = 0, 1
 F64, F32, F16S, BF16 = 0, 1, 2, 3
 
@@ -36,11 +37,12 @@ class Geometry(ctypes.Structure):
 
 class StencilParams(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("reorder", ctypes.c_int32), ("dx", ctypes.c_double),
-                ("n_threads", ctypes.c_int32)]
+                ("n_threads", ctypes.c_int32), ("lattice_h", ctypes.c_double)]
 
 
 class Stencils(ctypes.Structure):
-    _fields_ = [("perm", _p), ("idx", _p), ("w", _p), ("bb", _p), ("area", _p)]
+    _fields_ = [("perm", _p), ("idx", _p), ("w", _p), ("bb", _p), ("area", _p), ("lagrange", _p),
+                ("w_lagrange", _p), ("n_lagrange", ctypes.c_int64)]
 
 
 class Sizes(ctypes.Structure):
@@ -62,7 +64,7 @@ class DeviceState(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("K", ctypes.c_int32), ("idx", _p), ("w", _p),
                 ("flags", _p), ("bc", _p), ("state", _p * 2), ("cur", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("max_halo", ctypes.c_int32), ("halo_off", _p),
-                ("halo", _p), ("lidx", _p)]
+                ("halo", _p), ("lidx", _p), ("w_lagrange", _p), ("lagrange_begin", ctypes.c_int64)]
 
 
 class Batch(ctypes.Structure):
@@ -108,6 +110,7 @@ def _load():
         "mlbm_pack_stencils_range": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                                     ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p,
                                                     _p, _p]),
+        "mlbm_mark_lagrange": (ctypes.c_int, [ctypes.c_int64, _p, _p]),
         "mlbm_batch_init": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), _p]),
         "mlbm_step_batched": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), ctypes.c_int32,
                                              ctypes.c_double, ctypes.c_int32, P(ctypes.c_int32), _p]),
@@ -153,6 +156,7 @@ lib = _load()
 
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_pack_stencils_range",
+           "mlbm_mark_lagrange",
            "mlbm_tile_sizes", "mlbm_pack_tiles", "mlbm_init_state", "mlbm_batch_init", "mlbm_step_batched",
            "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
            "mlbm_version"]

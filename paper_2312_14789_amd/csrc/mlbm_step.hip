@@ -44,6 +44,9 @@ __device__ __forceinline__ C omega(int k) {
     return k == 0 ? C(4) / C(9) : (k < 5 ? C(1) / C(9) : C(1) / C(36));
 }
 
+// node kind from the packed flags (bits 8-9)
+__device__ __forceinline__ unsigned kind_of(unsigned fl) { return (fl >> 8) & 3u; }
+
 // ---- storage formats -------------------------------------------------------
 
 __device__ __forceinline__ float half_to_float(unsigned short h) {
@@ -268,6 +271,8 @@ struct StepArgs {
     const int *halo_off;       // LDS staging: per-tile CSR offsets into halo
     const int *halo;           // LDS staging: halo node lists
     const unsigned short *lidx;  // LDS staging: tile-local member positions [K8/8][n][8]
+    const void *wl;            // block weights [8][9] (FP64 storage: double, else float)
+    int64_t tile0, tile1;      // tiles [tile0, tile1) of this launch (non-batched)
     const int *queue;          // batched launches: list of active tiles (NULL: every tile)
     const int *queue_range;    // batched launches: device offsets; this launch walks
     int group;                 //   queue[queue_range[group] .. queue_range[group + 1])
@@ -291,22 +296,31 @@ __device__ __forceinline__ int64_t tile_of(const StepArgs &a) {
 
 // Copies the state of every halo node of `tile` into LDS (NB bytes per node,
 // same layout as the global state), coalesced over 16-byte (or 8-byte) units.
-template <int NB>
-__device__ __forceinline__ void stage_halo(const StepArgs &a, int64_t tile, void *smem) {
+// The halo is sorted and holds every node of the tile, so the tile's own nodes
+// sit at consecutive positions; *self0 receives the first of them.
+template <int NB, bool SELF>
+__device__ __forceinline__ void stage_halo(const StepArgs &a, int64_t tile, void *smem, int *self0) {
     __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
     const int h0 = a.halo_off[tile], hn = a.halo_off[tile + 1] - h0;
+    const int64_t first = tile * blockDim.x;
     if constexpr (NB >= 16) {
         constexpr int U = NB / 16;
         const u4 *src = (const u4 *)a.in;
         u4 *dst = (u4 *)smem;
         for (int e = threadIdx.x; e < hn * U; e += blockDim.x) {
             const int h = e / U, c = e - h * U;
-            dst[e] = src[(int64_t)a.halo[h0 + h] * U + c];
+            const int node = a.halo[h0 + h];
+            if (SELF && c == 0 && node == first) *self0 = h;
+            dst[e] = src[(int64_t)node * U + c];
         }
     } else {
         const u2 *src = (const u2 *)a.in;
         u2 *dst = (u2 *)smem;
-        for (int h = threadIdx.x; h < hn; h += blockDim.x) dst[h] = src[a.halo[h0 + h]];
+        for (int h = threadIdx.x; h < hn; h += blockDim.x) {
+            const int node = a.halo[h0 + h];
+            if (SELF && node == first) *self0 = h;
+            dst[h] = src[node];
+        }
     }
     __syncthreads();
 }
@@ -330,8 +344,8 @@ __device__ __forceinline__ void for_tiles(const StepArgs &a, F &&f) {
         const int c1 = min(na, (b + 1) * chunk);
         for (int c = b * chunk; c < c1; ++c) f((int64_t)a.queue[q0 + c]);
     } else {
-        const int64_t tile = tile_of(a);
-        if (tile * blockDim.x < a.n) f(tile);
+        const int64_t tile = a.tile0 + tile_of(a);
+        if (tile < a.tile1) f(tile);
     }
 }
 
@@ -358,6 +372,34 @@ __device__ __forceinline__ void members(const StepArgs &a, int64_t n, int64_t i,
     }
 }
 
+// Block centres of a hybrid set: members 0..7 are the lattice neighbours
+// x + h e_1 .. x + h e_8 (first index plane), member 8 the node itself, at
+// position self (its halo position, or i).
+template <bool LDS>
+__device__ __forceinline__ void block_members(const StepArgs &a, int64_t n, int64_t i, int self, int *m) {
+    if constexpr (LDS) {
+        const u4 lv = stream_load((const u4 *)a.lidx + i, a.cached);
+        const unsigned v[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            m[2 * t] = (int)(v[t] & 0xffffu);
+            m[2 * t + 1] = (int)(v[t] >> 16);
+        }
+    } else {
+        const i4 q0 = load_idx4(a.idx, n, i, 0, a.cached), q1 = load_idx4(a.idx, n, i, 1, a.cached);
+        m[0] = q0.x; m[1] = q0.y; m[2] = q0.z; m[3] = q0.w;
+        m[4] = q1.x; m[5] = q1.y; m[6] = q1.z; m[7] = q1.w;
+    }
+    m[8] = self;
+}
+
+// one block weight; the address is the same for every lane (a scalar load)
+template <int S, class CG>
+__device__ __forceinline__ CG block_weight(const StepArgs &a, int t) {
+    if constexpr (S == MLBM_F64) return (CG)((const double *)a.wl)[t];
+    else return (CG)((const float *)a.wl)[t];
+}
+
 // compile-time loop over the stencil quads
 template <int Q, int KQ, class F>
 __device__ __forceinline__ void for_quads(F &&f) {
@@ -369,25 +411,55 @@ __device__ __forceinline__ void for_quads(F &&f) {
 
 // ---- population MLBM step ------------------------------------------------------
 
-// CG: gather (interpolation) arithmetic; C: collision arithmetic
+// CG: gather (interpolation) arithmetic; C: collision arithmetic.  KQ = 0
+// instantiates the block-centre kernel of a hybrid set: every node it visits
+// is a block centre with the shared weights (a node without the flag gets a
+// NaN state, so a wrong node range shows up at once).
 template <int S, class CG, class C, int KQ, bool LDS>
-__device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int64_t i) {
+__device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int64_t i, int self) {
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
     C f[9];
-    if ((fl >> 8) == MLBM_DIRICHLET) {
+    // FP64 keeps the weight sum: sum_j w_j f_j = sum_j w_j (f_j - omega) + omega sum_j w_j,
+    // exactly the interpolation of the populations; reduced precision drops
+    // the (sum_j w_j - 1) omega term, which is weight rounding there.
+    constexpr bool kWsum = S == MLBM_F64;
+    CG acc[8], sw[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = sw[k] = CG(0);
+    if (kind_of(fl) == MLBM_DIRICHLET) {
         const C rb = (C)a.bc[3 * i], ub = (C)a.bc[3 * i + 1], vb = (C)a.bc[3 * i + 2];
 #pragma unroll
         for (int k = 0; k < 9; ++k) f[k] = feq_off<C>(k, C(1), rb - C(1), rb, ub, vb);
-    } else {
-        // FP64 keeps the weight sum: sum_j w_j f_j = sum_j w_j (f_j - omega) + omega sum_j w_j,
-        // exactly the interpolation of the populations; reduced precision drops
-        // the (sum_j w_j - 1) omega term, which is weight rounding there.
-        constexpr bool kWsum = S == MLBM_F64;
-        CG acc[8], sw[8];
+        store8<S>(a.out, i, f + 1, a.scale);
+        store1<S, C>(a.out, n, i, f[0], a.scale);
+        return;
+    }
+    if constexpr (KQ == 0) {
+        // block centre: the shared biquadratic weights (no bounce-back here)
+        if (!(fl & MLBM_FLAG_LAGRANGE)) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = sw[k] = CG(0);
+            for (int k = 0; k < 8; ++k) acc[k] = CG(NAN);
+        }
+        int m[9];
+        block_members<LDS>(a, n, i, self, m);
+        for_quads<0, 3>([&](auto gc) {
+            constexpr int j0 = 4 * decltype(gc)::value, nj = j0 < 8 ? 4 : 1;
+            CG v[4][8];
+#pragma unroll
+            for (int j = 0; j < nj; ++j) load8<S>(src, m[j0 + j], v[j], a.inv_scale);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+#pragma unroll
+                for (int j = 0; j < nj; ++j) {
+                    const CG wv = block_weight<S, CG>(a, k * 9 + j0 + j);
+                    acc[k] = fma(wv, v[j][k], acc[k]);
+                    if constexpr (kWsum) sw[k] += wv;
+                }
+            }
+        });
+    } else {
         u4 lv;
         for_quads<0, KQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
@@ -409,12 +481,12 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
                 }
             }
         });
-        f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            f[k + 1] = kWsum ? (C)acc[k] + omega<C>(k + 1) * ((C)sw[k] - C(1)) : (C)acc[k];
-        collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
     }
+    f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        f[k + 1] = kWsum ? (C)acc[k] + omega<C>(k + 1) * ((C)sw[k] - C(1)) : (C)acc[k];
+    collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
     store8<S>(a.out, i, f + 1, a.scale);
     store1<S, C>(a.out, n, i, f[0], a.scale);
 }
@@ -422,22 +494,25 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
 template <int S, class CG, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int self0;
     for_tiles(a, [&](int64_t tile) {
-        if constexpr (LDS) stage_halo<pop_bytes<S>()>(a, tile, smem);
+        if constexpr (LDS) stage_halo<pop_bytes<S>(), KQ == 0>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
-        if (i < a.n) pop_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i);
+        if (i < a.n)
+            pop_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i,
+                                        KQ == 0 && LDS ? self0 + (int)threadIdx.x : (int)i);
     });
 }
 
 // ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
 
 template <int S, class CG, class C, int KQ, bool LDS>
-__device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, int64_t i) {
+__device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, int64_t i, int self) {
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
     C out[3];
-    if ((fl >> 8) == MLBM_DIRICHLET) {
+    if (kind_of(fl) == MLBM_DIRICHLET) {
         out[0] = (C)a.bc[3 * i] - C(1);
         out[1] = (C)a.bc[3 * i + 1];
         out[2] = (C)a.bc[3 * i + 2];
@@ -446,6 +521,32 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
         CG ar[8], au[8], av[8], sw[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) ar[k] = au[k] = av[k] = sw[k] = CG(0);
+        if constexpr (KQ == 0) {
+            // block centre: the shared biquadratic weights (no bounce-back here)
+            if (!(fl & MLBM_FLAG_LAGRANGE)) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) ar[k] = CG(NAN);
+            }
+            int mi[9];
+            block_members<LDS>(a, n, i, self, mi);
+            for_quads<0, 3>([&](auto gc) {
+                constexpr int j0 = 4 * decltype(gc)::value, nj = j0 < 8 ? 4 : 1;
+                CG m[4][3];
+#pragma unroll
+                for (int j = 0; j < nj; ++j) load3<S>(src, mi[j0 + j], m[j], a.inv_scale);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+#pragma unroll
+                    for (int j = 0; j < nj; ++j) {
+                        const CG wv = block_weight<S, CG>(a, k * 9 + j0 + j);
+                        ar[k] = fma(wv, m[j][0], ar[k]);
+                        au[k] = fma(wv, m[j][1], au[k]);
+                        av[k] = fma(wv, m[j][2], av[k]);
+                        if constexpr (kWsum) sw[k] += wv;
+                    }
+                }
+            });
+        } else {
         u4 lv;
         for_quads<0, KQ>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
@@ -467,6 +568,7 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
                 }
             }
         });
+        }
         if constexpr (kWsum) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) ar[k] += sw[k] - CG(1);
@@ -500,10 +602,13 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
 template <int S, class CG, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int self0;
     for_tiles(a, [&](int64_t tile) {
-        if constexpr (LDS) stage_halo<field_bytes<S>()>(a, tile, smem);
+        if constexpr (LDS) stage_halo<field_bytes<S>(), KQ == 0>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
-        if (i < a.n) fields_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i);
+        if (i < a.n)
+            fields_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i,
+                                           KQ == 0 && LDS ? self0 + (int)threadIdx.x : (int)i);
     });
 }
 
@@ -525,7 +630,7 @@ __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
     using C = double;  // one-off: computed in FP64 and rounded once on store
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    const bool dir = (a.flags[i] >> 8) == MLBM_DIRICHLET;
+    const bool dir = kind_of(a.flags[i]) == MLBM_DIRICHLET;
     const double r = dir ? a.bc[3 * i] : a.rho[i];
     const double ux = dir ? a.bc[3 * i + 1] : a.u[2 * i];
     const double uy = dir ? a.bc[3 * i + 2] : a.u[2 * i + 1];
@@ -596,7 +701,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
         const int64_t n = a.n;
         const unsigned fl = a.flags[i];
         const unsigned bb = fl & 0xffu;
-        const bool dir = (fl >> 8) == MLBM_DIRICHLET;
+        const bool dir = kind_of(fl) == MLBM_DIRICHLET;
         double rho, ux, uy;
         C f[9];
         C m[3];
@@ -739,6 +844,7 @@ int check_common(const mlbm_step_params *p, const mlbm_device_state *st) {
     if (p->variant == MLBM_POPULATIONS && !(p->tau_plus > 0.5 && p->tau_minus > 0.5))
         return fail(MLBM_ERR_ARG, "relaxation times must exceed 1/2");
     if (p->storage == MLBM_F16S && (p->scale_exp < -30 || p->scale_exp > 30)) return fail(MLBM_ERR_ARG, "scale_exp out of range");
+    if (st->w_lagrange && st->K < 10) return fail(MLBM_ERR_ARG, "block weights need stencils of K >= 10");
     return MLBM_OK;
 }
 
@@ -761,6 +867,7 @@ StepFn pick_step(int variant, int kq, bool lds) {
         return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, CG, C, Q, false>             \
                                            : (StepFn)k_step_fields<S, CG, C, Q, false>;
     switch (kq) {
+        MLBM_CASE(0)
         MLBM_CASE(2)
         MLBM_CASE(3)
         MLBM_CASE(4)
@@ -905,17 +1012,36 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     a.halo_off = st->halo_off;
     a.halo = st->halo;
     a.lidx = st->lidx;
+    a.wl = st->w_lagrange;
     a.queue = nullptr;
     a.queue_range = nullptr;
     a.group = 0;
+    // tiles [0, split) run the per-node weights; in a hybrid set the tiles
+    // made only of block centres, [split, nb), run the block-centre kernel
     const int64_t nb = (st->n + blk - 1) / blk;
-    a.grid8 = a.xcd ? (nb + 7) / 8 * 8 : nb;
+    int64_t split = nb;
+    StepFn fb = nullptr;
+    if (st->w_lagrange && st->lagrange_begin < st->n) {
+        if (st->lagrange_begin < 0) return fail(MLBM_ERR_ARG, "lagrange_begin must be >= 0");
+        split = (st->lagrange_begin + blk - 1) / blk;
+        fb = pick_step_any(p->storage, p->variant, 0, p->fp32_arith, lds);
+        if (!fb) return fail(MLBM_ERR_UNSUPPORTED, "no block-centre kernel for storage %d", p->storage);
+    }
+    const int64_t ranges[2][2] = {{0, split}, {split, nb}};
+    const StepFn fns[2] = {fn, fb};
     hipStream_t s = (hipStream_t)stream;
     for (int t = 0; t < nsteps; ++t) {
         a.in = st->state[st->cur];
         a.out = st->state[st->cur ^ 1];
         a.reverse = p->alternate_sweeps && st->cur == 1;
-        hipLaunchKernelGGL(fn, dim3((unsigned)a.grid8), dim3(blk), shmem, s, a);
+        for (int r = 0; r < 2; ++r) {
+            const int64_t cnt = ranges[r][1] - ranges[r][0];
+            if (cnt <= 0) continue;
+            a.tile0 = ranges[r][0];
+            a.tile1 = ranges[r][1];
+            a.grid8 = a.xcd ? (cnt + 7) / 8 * 8 : cnt;
+            hipLaunchKernelGGL(fns[r], dim3((unsigned)a.grid8), dim3(blk), shmem, s, a);
+        }
         rc = hip_check("mlbm_step launch");
         if (rc) return rc;
         st->cur ^= 1;
@@ -1033,7 +1159,7 @@ __global__ void __launch_bounds__(256) k_batch_tile_red(const BatchArgs a) {
                 ux = m[1];
                 uy = m[2];
             }
-            if ((a.flags[i] >> 8) == MLBM_DIRICHLET) {
+            if (kind_of(a.flags[i]) == MLBM_DIRICHLET) {
                 rho = a.bc[3 * i];
                 ux = a.bc[3 * i + 1];
                 uy = a.bc[3 * i + 2];
@@ -1254,6 +1380,7 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     a.halo_off = st->halo_off;
     a.halo = st->halo;
     a.lidx = st->lidx;
+    a.wl = st->w_lagrange;
     a.queue = b->queue;
     a.queue_range = b->group_queue_off;
     a.grid8 = batch_grid(b);

@@ -15,6 +15,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <mutex>
 #include <string>
@@ -104,9 +105,67 @@ struct Builder {
     double dx;
     CellGrid nodes, disks;
     double rmax = 0;
+    double lat_h = 0;          // lattice spacing of the regular part (0: none)
+    double wlag[8][9] = {};    // biquadratic Lagrange weights shared by block centres
+
+    // ---- regular blocks of a hybrid set (Sec. 2.2) -------------------------
+    // quadratic Lagrange basis through -1, 0, 1, the one that is 1 at a
+    static double lag1(int a, double t) {
+        switch (a) {
+            case -1: return 0.5 * t * (t - 1.0);
+            case 0: return (1.0 - t) * (1.0 + t);
+            default: return 0.5 * t * (t + 1.0);
+        }
+    }
+
+    // member slot of the lattice node x + h e_d: the neighbours d = 1..8 take
+    // slots 0..7 (one index plane on the device), the node itself slot 8
+    static int slot_of(int d) { return d == 0 ? 8 : d - 1; }
+
+    void lagrange_table() {
+        for (int k = 1; k <= 8; ++k) {
+            const double tx = -dx * EX[k] / lat_h, ty = -dx * EY[k] / lat_h;
+            for (int d = 0; d < 9; ++d) wlag[k - 1][slot_of(d)] = lag1(EX[d], tx) * lag1(EY[d], ty);
+        }
+    }
+
+    // True if the nine nearest nodes of i are x_i + h e_d (d = 0..8, each within
+    // 1e-9 h) and the tenth lies beyond the block corners; mem[slot_of(d)]
+    // receives the node at x_i + h e_d.
+    bool lattice_block(int64_t i, std::vector<Cand> &cand, int64_t *mem) const {
+        Cand st[10];
+        nearest_n(i, 10, cand, st);
+        const double h = lat_h, tol = 1e-9 * h;
+        const double corner = std::sqrt(2.0) * h * (1.0 + 1e-9);
+        if (!(st[9].r2 > corner * corner)) return false;
+        unsigned seen = 0;
+        for (int t = 0; t < 9; ++t) {
+            const long a = std::lround(st[t].dx / h), b = std::lround(st[t].dy / h);
+            if (a < -1 || a > 1 || b < -1 || b > 1) return false;
+            if (std::hypot(st[t].dx - (double)a * h, st[t].dy - (double)b * h) > tol) return false;
+            int d = 0;
+            while (EX[d] != a || EY[d] != b) ++d;
+            if (seen & (1u << d)) return false;
+            seen |= 1u << d;
+            mem[slot_of(d)] = st[t].j;
+        }
+        return seen == 0x1ffu;
+    }
+
+    // A fluid node is interpolated on its block when the streaming distance
+    // fits in the block and no departure point needs the bounce-back rule.
+    bool is_block_centre(int64_t i, std::vector<Cand> &cand, int64_t *mem) const {
+        if (!(lat_h > 0.0) || g->kind[i] != MLBM_FLUID || dx > lat_h) return false;
+        const double xi = g->xy[2 * i], yi = g->xy[2 * i + 1];
+        for (int k = 1; k <= 8; ++k)
+            if (inside_solid(xi - dx * EX[k], yi - dx * EY[k])) return false;
+        return lattice_block(i, cand, mem);
+    }
 
     // ---- K nearest neighbours --------------------------------------------
-    void nearest(int64_t i, std::vector<Cand> &cand, Cand *out) const {
+    void nearest(int64_t i, std::vector<Cand> &cand, Cand *out) const { nearest_n(i, K, cand, out); }
+
+    void nearest_n(int64_t i, int K, std::vector<Cand> &cand, Cand *out) const {
         const double xi = g->xy[2 * i], yi = g->xy[2 * i + 1];
         cand.clear();
         const int ci = nodes.cell_x(box, xi), cj = nodes.cell_y(box, yi);
@@ -234,7 +293,7 @@ struct Builder {
 
     // Stencil, weights, bounce-back bits and unnormalised area of node i.
     // Returns MLBM_OK or an error code with the message recorded in err.
-    int node(int64_t i, std::vector<Cand> &cand, Cand *st, double *w, uint8_t *bbits,
+    int node(int64_t i, bool lag, std::vector<Cand> &cand, Cand *st, double *w, uint8_t *bbits,
              double *area, std::string &err) const {
         nearest(i, cand, st);
         if (st[0].j != i || (K > 1 && st[1].r2 == 0.0)) {
@@ -246,6 +305,19 @@ struct Builder {
         for (int t = 1; t <= 4; ++t) s += std::hypot(st[t].dx, st[t].dy);
         const double mean = s / 4.0;
         *area = mean * mean * (g->kind[i] != MLBM_FLUID ? 0.5 : 1.0);
+        *bbits = 0;
+        if (lag) {
+            int64_t mem[9];
+            if (!is_block_centre(i, cand, mem)) {
+                err = "node " + std::to_string(i) + " lost its lattice block";
+                return MLBM_ERR_GEOMETRY;
+            }
+            for (int j = 0; j < K; ++j) {
+                st[j].j = j < 9 ? mem[j] : i;
+                for (int k = 0; k < 8; ++k) w[(int64_t)k * K + j] = j < 9 ? wlag[k][j] : 0.0;
+            }
+            return MLBM_OK;
+        }
 
         double R = 0;
         for (int j = 0; j < K; ++j) R = std::max(R, std::hypot(st[j].dx, st[j].dy));
@@ -356,6 +428,8 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
     if (p->K < 7 || p->K > MAXK) return fail(MLBM_ERR_ARG, "K=%d outside [7, %d]", p->K, MAXK);
     if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(MLBM_ERR_ARG, "dx must be positive");
     if (p->reorder != 0 && p->reorder != 1) return fail(MLBM_ERR_ARG, "reorder must be 0 or 1");
+    if (!(p->lattice_h >= 0.0) || !std::isfinite(p->lattice_h)) return fail(MLBM_ERR_ARG, "lattice_h must be >= 0");
+    if (p->lattice_h > 0.0 && p->K < 10) return fail(MLBM_ERR_ARG, "hybrid stencils need K >= 10");
     const int64_t n = g->n;
     if (n < p->K) return fail(MLBM_ERR_GEOMETRY, "K=%d exceeds the node count %lld", p->K, (long long)n);
 
@@ -363,6 +437,8 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
     B.g = g;
     B.K = p->K;
     B.dx = p->dx;
+    B.lat_h = p->lattice_h;
+    if (B.lat_h > 0.0) B.lagrange_table();
     for (int a = 0; a < 2; ++a) {
         B.box.lo[a] = g->lo[a];
         B.box.hi[a] = g->hi[a];
@@ -391,7 +467,36 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
         if (B.inside_solid(g->xy[2 * i], g->xy[2 * i + 1]))
             return fail(MLBM_ERR_GEOMETRY, "node %lld lies inside a solid", (long long)i);
 
-    // node order: Morton (Z) order of the coordinates quantised to 2^20 cells
+    int nthreads = p->n_threads > 0 ? p->n_threads : (int)std::thread::hardware_concurrency();
+    nthreads = std::max(1, std::min(nthreads, 256));
+    auto parallel = [&](const std::function<void(int64_t, int64_t, std::vector<Cand> &)> &body) {
+        std::atomic<int64_t> next(0);
+        const int64_t chunk = 512;
+        auto run = [&]() {
+            std::vector<Cand> cand;
+            cand.reserve(256);
+            for (;;) {
+                const int64_t a = next.fetch_add(chunk);
+                if (a >= n) break;
+                body(a, std::min(n, a + chunk), cand);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthreads; ++t) pool.emplace_back(run);
+        run();
+        for (auto &t : pool) t.join();
+    };
+
+    // block centres of the regular part (caller's order)
+    std::vector<uint8_t> lag(n, 0);
+    if (B.lat_h > 0.0)
+        parallel([&](int64_t a, int64_t b, std::vector<Cand> &cand) {
+            int64_t mem[9];
+            for (int64_t i = a; i < b; ++i) lag[i] = B.is_block_centre(i, cand, mem) ? 1 : 0;
+        });
+
+    // node order: Morton (Z) order of the coordinates quantised to 2^20 cells;
+    // in a hybrid set the block centres come after every other node
     std::vector<int64_t> perm(n), inv(n);
     for (int64_t i = 0; i < n; ++i) perm[i] = i;
     if (p->reorder == 1) {
@@ -404,50 +509,43 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
             uint32_t iy = (uint32_t)std::min(std::max(fy * q, 0.0), q - 1);
             key[i] = spread_bits(ix) | (spread_bits(iy) << 1);
         }
-        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
+            return lag[a] != lag[b] ? lag[a] < lag[b] : key[a] < key[b];
+        });
     }
     for (int64_t i = 0; i < n; ++i) inv[perm[i]] = i;
 
-    int nthreads = p->n_threads > 0 ? p->n_threads : (int)std::thread::hardware_concurrency();
-    nthreads = std::max(1, std::min(nthreads, 256));
-    std::atomic<int64_t> next(0);
     std::mutex emu;
     int64_t err_node = n;
     int err_code = MLBM_OK;
     std::string err_msg;
     const int K = p->K;
-    const int64_t chunk = 512;
-    auto work = [&]() {
-        std::vector<Cand> cand;
-        cand.reserve(256);
+    parallel([&](int64_t a, int64_t b, std::vector<Cand> &cand) {
         Cand st[MAXK];
-        for (;;) {
-            const int64_t a = next.fetch_add(chunk);
-            if (a >= n) break;
-            const int64_t b = std::min(n, a + chunk);
-            for (int64_t inew = a; inew < b; ++inew) {
-                const int64_t i = perm[inew];
-                std::string msg;
-                double area = 0;
-                uint8_t bits = 0;
-                const int rc = B.node(i, cand, st, out->w + inew * 8 * K, &bits, &area, msg);
-                if (rc != MLBM_OK) {
-                    std::lock_guard<std::mutex> lk(emu);
-                    if (i < err_node) { err_node = i; err_code = rc; err_msg = msg; }
-                    continue;
-                }
-                for (int j = 0; j < K; ++j) out->idx[inew * K + j] = (int32_t)inv[st[j].j];
-                out->bb[inew] = bits;
-                out->area[inew] = area;
-                out->perm[inew] = i;
+        for (int64_t inew = a; inew < b; ++inew) {
+            const int64_t i = perm[inew];
+            std::string msg;
+            double area = 0;
+            uint8_t bits = 0;
+            const int rc = B.node(i, lag[i] != 0, cand, st, out->w + inew * 8 * K, &bits, &area, msg);
+            if (rc != MLBM_OK) {
+                std::lock_guard<std::mutex> lk(emu);
+                if (i < err_node) { err_node = i; err_code = rc; err_msg = msg; }
+                continue;
             }
+            for (int j = 0; j < K; ++j) out->idx[inew * K + j] = (int32_t)inv[st[j].j];
+            out->bb[inew] = bits;
+            out->area[inew] = area;
+            out->perm[inew] = i;
+            if (out->lagrange) out->lagrange[inew] = lag[i];
         }
-    };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
-    work();
-    for (auto &t : pool) t.join();
+    });
     if (err_code != MLBM_OK) return fail(err_code, "%s", err_msg.c_str());
+    out->n_lagrange = 0;
+    for (int64_t i = 0; i < n; ++i) out->n_lagrange += lag[i];
+    if (out->w_lagrange)
+        for (int k = 0; k < 8; ++k)
+            for (int j = 0; j < 9; ++j) out->w_lagrange[k * 9 + j] = B.lat_h > 0.0 ? B.wlag[k][j] : 0.0;
 
     double fluid = g->fluid_area;
     if (!(fluid > 0.0)) {
@@ -522,6 +620,15 @@ extern "C" int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const i
                                   const uint8_t *bb, const uint8_t *kind, void *idx_packed, void *w_packed,
                                   uint16_t *flags) {
     return mlbm_pack_stencils_range(n, 0, n, K, storage, idx, w, bb, kind, idx_packed, w_packed, flags);
+}
+
+extern "C" int mlbm_mark_lagrange(int64_t n, const uint8_t *lagrange, uint16_t *flags) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (n < 0 || (n > 0 && (!lagrange || !flags))) return fail(MLBM_ERR_ARG, "null pointer or negative n");
+    for (int64_t i = 0; i < n; ++i)
+        if (lagrange[i]) flags[i] = (uint16_t)(flags[i] | MLBM_FLAG_LAGRANGE);
+    return MLBM_OK;
 }
 
 // ---- tile-local stencil indices (LDS staging) --------------------------------

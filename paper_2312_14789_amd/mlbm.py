@@ -42,26 +42,38 @@ def geometry_struct(xy, kind, lo, hi, periodic, walls_y=(False, False), disks=No
 
 
 def build_stencils(xy, kind, lo, hi, periodic, K, dx, walls_y=(False, False), disks=None,
-                   fluid_area=0.0, reorder=1, n_threads=0) -> dict:
-    """mlbm_build_stencils: returns perm (n,), idx (n, K), w (n, 8, K), bb (n,), area (n,)."""
+                   fluid_area=0.0, reorder=1, n_threads=0, lattice_h=0.0) -> dict:
+    """mlbm_build_stencils: returns perm (n,), idx (n, K), w (n, 8, K), bb (n,),
+    area (n,), lagrange (n,) uint8, w_lagrange (8, 9) and n_lagrange
+    (lattice_h > 0: hybrid set, block centres use the shared weights)."""
     g, keep = geometry_struct(xy, kind, lo, hi, periodic, walls_y, disks, fluid_area)
     n = g.n
     out = {"perm": np.zeros(n, np.int64), "idx": np.zeros((n, K), np.int32),
            "w": np.zeros((n, 8, K), np.float64), "bb": np.zeros(n, np.uint8),
-           "area": np.zeros(n, np.float64)}
-    st = Stencils(_ptr(out["perm"]), _ptr(out["idx"]), _ptr(out["w"]), _ptr(out["bb"]), _ptr(out["area"]))
-    p = StencilParams(K=K, reorder=reorder, dx=float(dx), n_threads=n_threads)
+           "area": np.zeros(n, np.float64), "lagrange": np.zeros(n, np.uint8),
+           "w_lagrange": np.zeros((8, 9), np.float64)}
+    st = Stencils(_ptr(out["perm"]), _ptr(out["idx"]), _ptr(out["w"]), _ptr(out["bb"]), _ptr(out["area"]),
+                  _ptr(out["lagrange"]), _ptr(out["w_lagrange"]), 0)
+    p = StencilParams(K=K, reorder=reorder, dx=float(dx), n_threads=n_threads, lattice_h=float(lattice_h))
     check(lib.mlbm_build_stencils(ctypes.byref(g), ctypes.byref(p), ctypes.byref(st)))
+    out["n_lagrange"] = int(st.n_lagrange)
     del keep
     return out
 
 
-def build_stencils_for(ns, K, dx, reorder=1, n_threads=0) -> dict:
+def build_stencils_for(ns, K, dx, reorder=1, n_threads=0, lattice_h=0.0) -> dict:
     """build_stencils for an object carrying xy, kind, lo, hi, periodic,
     walls_y, disks and fluid_area()."""
     return build_stencils(ns.xy, ns.kind, ns.lo, ns.hi, ns.periodic, K, dx, walls_y=ns.walls_y,
                           disks=ns.disks, fluid_area=ns.fluid_area(), reorder=reorder,
-                          n_threads=n_threads)
+                          n_threads=n_threads, lattice_h=lattice_h)
+
+
+def mark_lagrange(lagrange, flags):
+    """mlbm_mark_lagrange on host packed flags (in place)."""
+    lagrange = np.ascontiguousarray(lagrange, dtype=np.uint8)
+    check(lib.mlbm_mark_lagrange(lagrange.shape[0], _ptr(lagrange), _ptr(flags)))
+    return flags
 
 
 def packed_sizes(n, K, variant, storage) -> Sizes:
@@ -111,7 +123,7 @@ class Simulation:
     def __init__(self, idx, w, bb, kind, area, *, variant=POPULATIONS, storage=F32, tau_plus=0.8,
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
                  fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda",
-                 packed=None):
+                 packed=None, lagrange=None, w_lagrange=None):
         import torch
 
         self.torch = torch
@@ -120,6 +132,15 @@ class Simulation:
         ip, wp, fl = pack_stencils(idx, w, bb, kind, storage) if packed is None else packed
         self.sizes = packed_sizes(n, K, variant, storage)
         dev = torch.device(device)
+        self.wl_d = None
+        self.lagrange_begin = n
+        if lagrange is not None and w_lagrange is not None and np.any(lagrange):
+            lag = np.asarray(lagrange).astype(bool)
+            fl = mark_lagrange(lag, fl.copy())
+            # the block-centre kernel takes the trailing run of block centres
+            self.lagrange_begin = n - int(np.argmin(lag[::-1])) if not lag.all() else 0
+            wt = np.float64 if storage == F64 else np.float32
+            self.wl_d = torch.from_numpy(np.ascontiguousarray(w_lagrange, dtype=wt)).to(dev)
         self.idx_d = torch.from_numpy(ip).to(dev)
         self.w_d = torch.from_numpy(wp).to(dev)
         self.flags_d = torch.from_numpy(fl.view(np.int16)).to(dev)
@@ -154,6 +175,8 @@ class Simulation:
         self.ds.state[0] = self.state_d[0].data_ptr()
         self.ds.state[1] = self.state_d[1].data_ptr()
         self.ds.cur = 0
+        self.ds.w_lagrange = self.wl_d.data_ptr() if self.wl_d is not None else None
+        self.ds.lagrange_begin = self.lagrange_begin
         self.set_tile(tile, idx)
 
     def set_tile(self, tile, idx=None):

@@ -82,6 +82,15 @@ def algorithmic_bytes_per_node(variant: int, storage: int, k_padded: int) -> int
     return 2 * state + 8 * k_padded * wb + 4 * k_padded + 2
 
 
+def block_centre_bytes_per_node(variant: int, storage: int) -> int:
+    """The same for a block centre of a hybrid set: its eight neighbour
+    indices replace the stencil indices, and its weights are shared by all
+    block centres (read once per launch, not per node)."""
+    tb = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
+    state = (9 if variant == 0 else 4) * tb
+    return 2 * state + 8 * 4 + 2
+
+
 def f16_scale_exp(u_ref: float, target: float = 1024.0) -> int:
     """Power-of-two scale for FP16 offset storage: the stored value is
     offset * 2^sigma, chosen so that an offset of the size of the reference

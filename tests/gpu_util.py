@@ -29,6 +29,25 @@ def initial_fields(ns, seed, amp_u, amp_rho):
     return rho, u
 
 
+def lagrange_last(ns, st):
+    """The node set and the oracle's stencils renumbered so that the block
+    centres come after every other node (the order the library's block-centre
+    kernel needs); returns (ns, st) in the new order."""
+    import copy
+
+    p = np.argsort(st.lagrange, kind="stable")
+    inv = np.empty_like(p)
+    inv[p] = np.arange(len(p))
+    ns2 = copy.copy(ns)
+    ns2.xy = ns.xy[p]
+    ns2.kind = ns.kind[p]
+    if ns.bc is not None:
+        ns2.bc = ns.bc[p]
+    st2 = omlbm.Stencils(idx=inv[st.idx[p]], w=st.w[p], src=st.src[p], point=st.point[p],
+                         area=st.area[p], lagrange=st.lagrange[p])
+    return ns2, st2
+
+
 def run_oracle(ns, st, variant, steps, rho0, u0, tau_plus, tau_minus, g):
     """Oracle fields after `steps` steps: (rho, u)."""
     if variant == 0:
@@ -44,9 +63,11 @@ def run_oracle(ns, st, variant, steps, rho0, u0, tau_plus, tau_minus, g):
 
 def sim_from_oracle(M, ns, st, variant, storage, tau_plus, tau_minus, g, **kw):
     """Simulation fed with the oracle's own stencil arrays (oracle node order)."""
+    lag = st.lagrange if st.lagrange is not None and st.lagrange.any() else None
+    wl = st.w[int(np.argmax(st.lagrange))][:, :9] if lag is not None else None
     return M.Simulation(st.idx.astype(np.int32), st.w, oracle_bb(st), ns.kind, st.area,
                         variant=variant, storage=storage, tau_plus=tau_plus, tau_minus=tau_minus,
-                        g=g, bc=ns.boundary_values(), **kw)
+                        g=g, bc=ns.boundary_values(), lagrange=lag, w_lagrange=wl, **kw)
 
 
 def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus, g, lattice_h=None):

@@ -15,7 +15,7 @@ import nodesets
 from oracle import lattice as lt
 from oracle import mlbm as omlbm
 
-from gpu_util import (initial_fields, oracle_bb, oracle_one_step_at, rel_l2, run_oracle,
+from gpu_util import (initial_fields, lagrange_last, oracle_bb, oracle_one_step_at, rel_l2, run_oracle,
                       sim_from_oracle)
 
 pytestmark = pytest.mark.gpu
@@ -78,6 +78,21 @@ def _case(name):
         st = omlbm.build_stencils(ns, 25, dx)
         rho0, u0 = initial_fields(ns, 15, 0.02, 0.005)
         c = (ns, st, 1, 1.0, 1.0, (0.0, 0.0), 100, rho0, u0, dx)
+    elif name == "hybrid_tgv":     # regular lattice with a jittered patch: block centres + RBF-FD
+        ns = nodesets.patch_jittered_grid(64, radius=0.3, seed=16)
+        dx = 1.0 / 64 / 1.5
+        ns, st = lagrange_last(ns, omlbm.build_stencils(ns, 12, dx, lattice_h=1.0 / 64))
+        k = 2 * np.pi
+        x, y = ns.xy[:, 0], ns.xy[:, 1]
+        u0 = np.stack([0.01 * np.sin(k * x) * np.cos(k * y), -0.01 * np.cos(k * x) * np.sin(k * y)], 1)
+        rho0 = 1 - (0.01 ** 2 / (4 * lt.CS2)) * (np.cos(2 * k * x) + np.cos(2 * k * y))
+        c = (ns, st, 0, 0.8, 0.8, (0.0, 0.0), 300, rho0, u0, dx)
+    elif name == "hybrid_pixels_fields":  # pixel-centre porous set: MLBM1, grains, body force
+        ns = nodesets.porous(0, phi=0.75, seed=17, h=1.0 / 56, jitter=0.0, r_range=(0.05, 0.09))
+        dx = ns.h / 2.0
+        ns, st = lagrange_last(ns, omlbm.build_stencils(ns, 16, dx, lattice_h=ns.h))
+        rho0, u0 = initial_fields(ns, 18, 0.01, 0.002)
+        c = (ns, st, 1, 1.0, 1.0, (1e-5, 2e-6), 300, rho0, u0, dx)
     else:
         raise KeyError(name)
     ns, st, var, tp, tm, g, steps, rho0, u0, dx = c
@@ -95,7 +110,8 @@ def _run_gpu(M, name, storage, **kw):
     return sim, rho.cpu().numpy(), u.cpu().numpy(), red.cpu().numpy()
 
 
-@pytest.mark.parametrize("name", ["tgv64", "channel_trt", "karman_small", "porous_fields", "k25_fields"])
+@pytest.mark.parametrize("name", ["tgv64", "channel_trt", "karman_small", "porous_fields", "k25_fields",
+                                  "hybrid_tgv", "hybrid_pixels_fields"])
 @pytest.mark.parametrize("storage,tile", [(0, 256), (1, 256), (0, 0), (1, 0)])
 def test_step_parity(M, name, storage, tile):
     print(f"[parity] case={name} storage={storage} tile={tile}", flush=True)
@@ -105,6 +121,32 @@ def test_step_parity(M, name, storage, tile):
     print(f"[parity] case={name} storage={storage} tile={tile} rel_l2_u={err:.3e}", flush=True)
     assert err <= BAR[storage]
     assert rel_l2(rho - 1.0, r_ref - 1.0) <= 10 * BAR[storage] or np.abs(rho - r_ref).max() < BAR[storage]
+
+
+@pytest.mark.parametrize("name", ["hybrid_tgv", "hybrid_pixels_fields"])
+@pytest.mark.parametrize("storage,tile", [(0, 256), (1, 256), (1, 0), (2, 256)])
+def test_block_centre_kernel_equals_per_node_weights(M, name, storage, tile):
+    # the block-centre kernel reads the shared table and eight neighbour
+    # indices; the per-node path reads the same weights from each node's row
+    # (zeros past member 8) and sums in the same order.  The two kernels may
+    # still fuse multiply-adds of the collision differently, so the states
+    # agree to rounding (FP64, FP32) or to a storage ulp (16-bit).
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case(name)
+    out = []
+    for use_block in (True, False):
+        sim = sim_from_oracle(M, ns, st, var, storage, tp, tm, g, tile=tile, scale_exp=14)
+        if not use_block:
+            sim.ds.w_lagrange = None
+        else:
+            assert sim.ds.lagrange_begin < ns.n - 256
+        sim.init_state(rho0, u0)
+        sim.step(50)
+        _, u, _ = sim.macroscopic(dx)
+        out.append(u.cpu().numpy())
+    err = rel_l2(out[0], out[1])
+    print(f"[block] case={name} storage={storage} tile={tile} block centres from {sim.lagrange_begin} "
+          f"rel_l2_u={err:.3e}", flush=True)
+    assert err <= {0: 1e-13, 1: 1e-6, 2: 1e-3}[storage]
 
 
 def test_tgv_amplitude_matches_closed_form(M):
@@ -190,12 +232,13 @@ def test_zero_steps_and_errors(M):
 # Full-size workloads: library-built stencils, sampled oracle nodes
 # ---------------------------------------------------------------------------
 
-def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed):
-    b = M.build_stencils_for(ns, K, dx)
+def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed, lattice_h=None):
+    b = M.build_stencils_for(ns, K, dx, lattice_h=lattice_h or 0.0)
     perm = b["perm"]
     rho0, u0 = initial_fields(ns, seed, amp_u, 0.002)
     sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=variant,
-                       storage=storage, tau_plus=tp, tau_minus=tm, g=g, bc=ns.boundary_values()[perm])
+                       storage=storage, tau_plus=tp, tau_minus=tm, g=g, bc=ns.boundary_values()[perm],
+                       lagrange=b["lagrange"], w_lagrange=b["w_lagrange"])
     sim.init_state(rho0[perm], u0[perm])
     sim.step(1)
     rho, u, red = sim.macroscopic(dx)
@@ -206,7 +249,10 @@ def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed):
     rng = np.random.default_rng(seed)
     pick = np.concatenate([rng.choice(ns.n, nsample, replace=False),
                            np.nonzero(ns.kind == nodesets.WALL)[0][:8]])
-    r_ref, u_ref = oracle_one_step_at(ns, pick, K, dx, variant, rho0, u0, tp, tm, g)
+    if lattice_h:  # block centres and scattered nodes both sampled
+        lag_old = perm[b["lagrange"].astype(bool)]
+        pick = np.concatenate([pick, rng.choice(lag_old, 16, replace=False)])
+    r_ref, u_ref = oracle_one_step_at(ns, pick, K, dx, variant, rho0, u0, tp, tm, g, lattice_h)
     return rho[inv[pick]], u[inv[pick]], r_ref, u_ref, red.cpu().numpy(), sim, b
 
 
@@ -218,6 +264,21 @@ def test_karman_full_size_sampled(M):
     dx = units.delta_x(ns.h, 2.0)
     tau = units.tau_for_reynolds(0.05, 1.0, dx, 200.0)
     r, u, r_ref, u_ref, red, sim, b = _sampled(M, ns, 16, dx, 0, 1, tau, tau, (0.0, 0.0), 0.05, 48, 21)
+    assert rel_l2(u, u_ref) < 1e-5
+    assert np.abs(r - r_ref).max() < 1e-6
+    assert red[8] == 0
+
+
+def test_hybrid_karman_full_size_sampled(M):
+    ns = nodesets.karman(hybrid=True)   # ~5e5 nodes, lattice away from the cylinder and wake
+    print(f"[full] karman-hybrid n={ns.n}", flush=True)
+    from paper_2312_14789_amd import units
+
+    dx = units.delta_x(ns.h_min, 1.0)
+    tau = units.tau_for_reynolds(0.05, 1.0, dx, 100.0)
+    r, u, r_ref, u_ref, red, sim, b = _sampled(M, ns, 16, dx, 0, 1, tau, tau, (0.0, 0.0), 0.05, 48, 23,
+                                               lattice_h=ns.h)
+    assert b["n_lagrange"] > ns.n // 2
     assert rel_l2(u, u_ref) < 1e-5
     assert np.abs(r - r_ref).max() < 1e-6
     assert red[8] == 0

@@ -41,17 +41,29 @@ CASES = {
     "porous": lambda: (nodesets.porous(1500, phi=0.75, seed=4, r_range=(0.05, 0.1)), 16, None),
     "karman": lambda: (nodesets.karman(n_target=1500, seed=5), 16, None),
     "k25": lambda: (nodesets.jittered_grid(20, seed=8), 25, 1.0 / 20 / 3.0),
+    # hybrid sets (fourth entry: lattice spacing of the regular part)
+    "hybrid_patch": lambda: (nodesets.patch_jittered_grid(24, radius=0.25, seed=4), 12, 1.0 / 24 / 1.5, 1.0 / 24),
+    "hybrid_pixels": lambda: (nodesets.porous(0, phi=0.8, seed=3, h=1.0 / 40, jitter=0.0, r_range=(0.05, 0.1)),
+                              16, 1.0 / 40, 1.0 / 40),
+    "hybrid_s1": lambda: (nodesets.regular_grid(12), 10, 1.0 / 12, 1.0 / 12),
 }
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_builder_matches_oracle(case):
-    ns, K, dx = CASES[case]()
+    ns, K, dx, *lat = CASES[case]()
+    lat = lat[0] if lat else None
     dx = ns.h / 2.0 if dx is None else dx
-    b = M.build_stencils_for(ns, K, dx, reorder=1, n_threads=4)
-    st = omlbm.build_stencils(ns, K, dx)
+    b = M.build_stencils_for(ns, K, dx, reorder=1, n_threads=4, lattice_h=lat or 0.0)
+    st = omlbm.build_stencils(ns, K, dx, lattice_h=lat)
     perm = b["perm"]
     assert sorted(perm.tolist()) == list(range(ns.n))
+    lag = b["lagrange"].astype(bool)
+    np.testing.assert_array_equal(lag, st.lagrange[perm])
+    assert b["n_lagrange"] == lag.sum()
+    if lat:
+        assert 0 < lag.sum() and np.all(lag[np.argmax(lag):])  # block centres come last
+        np.testing.assert_allclose(b["w_lagrange"], st.w[perm][lag][0][:, :9], atol=1e-15, rtol=0)
     np.testing.assert_array_equal(perm[b["idx"]], st.idx[perm])
     np.testing.assert_array_equal(b["bb"], _oracle_bb(st)[perm])
     np.testing.assert_allclose(b["w"], st.w[perm], atol=1e-10, rtol=0)
