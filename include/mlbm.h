@@ -212,6 +212,12 @@ typedef struct mlbm_step_params {
                                 other step (the step reading state[1])             */
     int32_t cached_weights;  /* 1 = ordinary loads for weights and indices; 0 =
                                 non-temporal loads                                  */
+    int32_t stochastic_rounding; /* MLBM_F16S / MLBM_BF16 in mlbm_step: 1 = round each
+                                stored value up or down at random with the
+                                probabilities that make it unbiased (random bits
+                                from a counter-based hash of node, component and
+                                mlbm_device_state.step_count); 0 = to nearest even.
+                                Batched runs always round to nearest.              */
 } mlbm_step_params;
 
 typedef struct mlbm_device_state {
@@ -243,6 +249,8 @@ typedef struct mlbm_device_state {
                                 builder also fills for block centres).  A node of
                                 that range without the flag gets a NaN state.
                                 Batched runs use the packed weights throughout.   */
+    uint64_t step_count;     /* steps taken (key of the stochastic rounding);
+                                mlbm_step adds nsteps                              */
 } mlbm_device_state;
 
 /*

@@ -57,14 +57,15 @@ class StepParams(ctypes.Structure):
                 ("g", ctypes.c_double * 2), ("scale_exp", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("fp32_arith", ctypes.c_int32), ("alternate_sweeps", ctypes.c_int32),
-                ("cached_weights", ctypes.c_int32)]
+                ("cached_weights", ctypes.c_int32), ("stochastic_rounding", ctypes.c_int32)]
 
 
 class DeviceState(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("K", ctypes.c_int32), ("idx", _p), ("w", _p),
                 ("flags", _p), ("bc", _p), ("state", _p * 2), ("cur", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("max_halo", ctypes.c_int32), ("halo_off", _p),
-                ("halo", _p), ("lidx", _p), ("w_lagrange", _p), ("lagrange_begin", ctypes.c_int64)]
+                ("halo", _p), ("lidx", _p), ("w_lagrange", _p), ("lagrange_begin", ctypes.c_int64),
+                ("step_count", ctypes.c_uint64)]
 
 
 class Batch(ctypes.Structure):

@@ -77,10 +77,47 @@ __device__ __forceinline__ float dec16(unsigned short v, float inv_scale) {
     if constexpr (S == MLBM_F16S) return half_to_float(v) * inv_scale;
     else return bf16_to_float(v);
 }
+// murmur3's 32-bit finaliser (a bijective integer mixer)
+__host__ __device__ __forceinline__ unsigned mix32(unsigned x) {
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+// Random bits for stochastic rounding of 16-bit stores, counter based: one key
+// per (node, step), mixed with the component index.  on == 0: round to nearest.
+struct Rnd {
+    unsigned key = 0;
+    int on = 0;
+    __device__ __forceinline__ unsigned bits(int c) const { return mix32(key ^ (0x9e3779b9u * (unsigned)(c + 1))); }
+};
+
+// 16-bit encodings.  Stochastic rounding adds uniform random bits below the
+// kept mantissa bits of the FP32 value and truncates, so a value is rounded up
+// with probability equal to its distance from the lower neighbour: the stored
+// value is unbiased (exact for normal results; FP16 subnormals, below 2^-14
+// after scaling, are rounded to nearest from the 13-bit step and keep a small bias).
 template <int S>
-__device__ __forceinline__ unsigned short enc16(float v, float scale) {
-    if constexpr (S == MLBM_F16S) return float_to_half(v * scale);
-    else return float_to_bf16(v);
+__device__ __forceinline__ unsigned short enc16(float v, float scale, unsigned r = 0, int sr = 0) {
+    if constexpr (S == MLBM_F16S) {
+        const float x = v * scale;
+        if (sr) {
+            // with its 13 low bits cleared the value is exact in FP16 (normal range)
+            unsigned u = __float_as_uint(x);
+            if ((u & 0x7f800000u) != 0x7f800000u) u = (u + (r & 0x1fffu)) & ~0x1fffu;
+            return float_to_half(__uint_as_float(u));
+        }
+        return float_to_half(x);
+    } else {
+        if (sr) {
+            const unsigned u = __float_as_uint(v);
+            if ((u & 0x7f800000u) != 0x7f800000u) return (unsigned short)((u + (r & 0xffffu)) >> 16);
+        }
+        return float_to_bf16(v);
+    }
 }
 
 // eight population offsets (k = 1..8) of node j
@@ -111,7 +148,7 @@ __device__ __forceinline__ void load8(const void *base, int64_t j, C *o, float i
 }
 
 template <int S, class C>
-__device__ __forceinline__ void store8(void *base, int64_t j, const C *o, float scale) {
+__device__ __forceinline__ void store8(void *base, int64_t j, const C *o, float scale, Rnd rnd = {}) {
     if constexpr (S == MLBM_F64) {
         d2 *p = (d2 *)base + 4 * j;
 #pragma unroll
@@ -124,7 +161,8 @@ __device__ __forceinline__ void store8(void *base, int64_t j, const C *o, float 
         unsigned w[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-            w[t] = (unsigned)enc16<S>((float)o[2 * t], scale) | ((unsigned)enc16<S>((float)o[2 * t + 1], scale) << 16);
+            w[t] = (unsigned)enc16<S>((float)o[2 * t], scale, rnd.bits(2 * t), rnd.on) |
+                   ((unsigned)enc16<S>((float)o[2 * t + 1], scale, rnd.bits(2 * t + 1), rnd.on) << 16);
         ((u4 *)base)[j] = u4{w[0], w[1], w[2], w[3]};
     }
 }
@@ -137,10 +175,10 @@ __device__ __forceinline__ C load1(const void *base, int64_t n, int64_t j, float
     else return dec16<S>(((const unsigned short *)base)[8 * n + j], inv_scale);
 }
 template <int S, class C>
-__device__ __forceinline__ void store1(void *base, int64_t n, int64_t j, C v, float scale) {
+__device__ __forceinline__ void store1(void *base, int64_t n, int64_t j, C v, float scale, Rnd rnd = {}) {
     if constexpr (S == MLBM_F64) ((double *)base)[8 * n + j] = v;
     else if constexpr (S == MLBM_F32) ((float *)base)[8 * n + j] = v;
-    else ((unsigned short *)base)[8 * n + j] = enc16<S>((float)v, scale);
+    else ((unsigned short *)base)[8 * n + j] = enc16<S>((float)v, scale, rnd.bits(8), rnd.on);
 }
 
 // fields (rho - 1, u_x, u_y) of node j
@@ -161,7 +199,7 @@ __device__ __forceinline__ void load3(const void *base, int64_t j, C *o, float i
     }
 }
 template <int S, class C>
-__device__ __forceinline__ void store3(void *base, int64_t j, const C *o, float scale) {
+__device__ __forceinline__ void store3(void *base, int64_t j, const C *o, float scale, Rnd rnd = {}) {
     if constexpr (S == MLBM_F64) {
         d2 *p = (d2 *)base + 2 * j;
         p[0] = d2{(double)o[0], (double)o[1]};
@@ -169,8 +207,9 @@ __device__ __forceinline__ void store3(void *base, int64_t j, const C *o, float 
     } else if constexpr (S == MLBM_F32) {
         ((f4 *)base)[j] = f4{(float)o[0], (float)o[1], (float)o[2], 0.0f};
     } else {
-        unsigned a = (unsigned)enc16<S>((float)o[0], scale) | ((unsigned)enc16<S>((float)o[1], scale) << 16);
-        unsigned b = (unsigned)enc16<S>((float)o[2], scale);
+        unsigned a = (unsigned)enc16<S>((float)o[0], scale, rnd.bits(0), rnd.on) |
+                     ((unsigned)enc16<S>((float)o[1], scale, rnd.bits(1), rnd.on) << 16);
+        unsigned b = (unsigned)enc16<S>((float)o[2], scale, rnd.bits(2), rnd.on);
         ((u2 *)base)[j] = u2{a, b};
     }
 }
@@ -273,10 +312,20 @@ struct StepArgs {
     const unsigned short *lidx;  // LDS staging: tile-local member positions [K8/8][n][8]
     const void *wl;            // block weights [8][9] (FP64 storage: double, else float)
     int64_t tile0, tile1;      // tiles [tile0, tile1) of this launch (non-batched)
+    int sr;                    // stochastic rounding of 16-bit stores
+    unsigned seed;             // this step's random key
     const int *queue;          // batched launches: list of active tiles (NULL: every tile)
     const int *queue_range;    // batched launches: device offsets; this launch walks
     int group;                 //   queue[queue_range[group] .. queue_range[group + 1])
 };
+
+// random key of node i in this step (stochastic rounding of 16-bit states)
+__device__ __forceinline__ Rnd step_rnd(const StepArgs &a, int64_t i) {
+    Rnd r;
+    r.on = a.sr;
+    r.key = a.sr ? mix32((unsigned)i * 0x9e3779b9u + a.seed) : 0u;
+    return r;
+}
 
 // Workgroups are dispatched to the 8 XCDs round-robin; with xcd each XCD gets
 // a contiguous range of tiles.  With reverse the tiles are visited in the
@@ -458,6 +507,7 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
                     if constexpr (kWsum) sw[k] += wv;
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);  // keep the groups' loads apart (registers)
         });
     } else {
         u4 lv;
@@ -487,12 +537,23 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
     for (int k = 0; k < 8; ++k)
         f[k + 1] = kWsum ? (C)acc[k] + omega<C>(k + 1) * ((C)sw[k] - C(1)) : (C)acc[k];
     collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
-    store8<S>(a.out, i, f + 1, a.scale);
-    store1<S, C>(a.out, n, i, f[0], a.scale);
+    if (a.sr) {
+        const Rnd rnd = step_rnd(a, i);
+        store8<S>(a.out, i, f + 1, a.scale, rnd);
+        store1<S, C>(a.out, n, i, f[0], a.scale, rnd);
+    } else {
+        store8<S>(a.out, i, f + 1, a.scale);
+        store1<S, C>(a.out, n, i, f[0], a.scale);
+    }
 }
 
+// The block-centre kernels (KQ = 0) are short and latency bound: they are
+// compiled for at least six waves per SIMD with 32-bit arithmetic (the others
+// are left to the compiler, 1 = no constraint).
+template <int S, int KQ> constexpr int block_waves() { return KQ != 0 ? 1 : (S == MLBM_F64 ? 3 : 6); }
+
 template <int S, class CG, class C, int KQ, bool LDS>
-__global__ void __launch_bounds__(256) k_step_pop(const StepArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_waves<S, KQ>()))) k_step_pop(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
     for_tiles(a, [&](int64_t tile) {
@@ -545,6 +606,7 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
                         if constexpr (kWsum) sw[k] += wv;
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             });
         } else {
         u4 lv;
@@ -596,11 +658,11 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
         out[1] = (jx + C(0.5) * rho * gx) / rho;
         out[2] = (jy + C(0.5) * rho * gy) / rho;
     }
-    store3<S>(a.out, i, out, a.scale);
+    store3<S>(a.out, i, out, a.scale, step_rnd(a, i));
 }
 
 template <int S, class CG, class C, int KQ, bool LDS>
-__global__ void __launch_bounds__(256) k_step_fields(const StepArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_waves<S, KQ>()))) k_step_fields(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
     for_tiles(a, [&](int64_t tile) {
@@ -1030,10 +1092,13 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     const int64_t ranges[2][2] = {{0, split}, {split, nb}};
     const StepFn fns[2] = {fn, fb};
     hipStream_t s = (hipStream_t)stream;
+    a.sr = (p->stochastic_rounding && (p->storage == MLBM_F16S || p->storage == MLBM_BF16)) ? 1 : 0;
     for (int t = 0; t < nsteps; ++t) {
         a.in = st->state[st->cur];
         a.out = st->state[st->cur ^ 1];
         a.reverse = p->alternate_sweeps && st->cur == 1;
+        const uint64_t step = st->step_count++;
+        a.seed = mix32((unsigned)step ^ mix32((unsigned)(step >> 32) + 0x6a09e667u));
         for (int r = 0; r < 2; ++r) {
             const int64_t cnt = ranges[r][1] - ranges[r][0];
             if (cnt <= 0) continue;
@@ -1380,7 +1445,10 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     a.halo_off = st->halo_off;
     a.halo = st->halo;
     a.lidx = st->lidx;
-    a.wl = st->w_lagrange;
+    a.wl = nullptr;  // batched runs use every node's own weights
+    a.tile0 = a.tile1 = 0;
+    a.sr = 0;        // and round to nearest (a captured graph replays fixed keys)
+    a.seed = 0;
     a.queue = b->queue;
     a.queue_range = b->group_queue_off;
     a.grid8 = batch_grid(b);

@@ -5,11 +5,15 @@ seeded inputs, over long runs towards a steady state.
 Bars: FP32 state 1e-5 (relative L2 of velocity); 16-bit storage 2e-3 on the
 velocity field and 0.5 % on permeability.  Met: FP32 everywhere; FP16 fields
 (MLBM1, the porous workload's variant) on velocity and permeability; BF16
-fields on permeability.  Not met, asserted at the measured level as
-regression guards: BF16 fields velocity (5e-3), FP16 populations (3e-3) and
-BF16 populations (9e-2: the per-step forcing increment of a slow
-body-force-driven channel is below half a BF16 ulp of the stored offsets, so
-round-to-nearest stagnates)."""
+fields on permeability.  Not met with rounding to nearest, asserted at the
+measured level as regression guards: BF16 fields velocity (5e-3), FP16
+populations (3e-3) and BF16 populations (9e-2: the per-step forcing increment
+of a slow body-force-driven channel is below half a BF16 ulp of the stored
+offsets, so round-to-nearest stagnates).  Stochastic rounding of the stores
+keeps the expected value of every stored quantity: FP16 meets the 2e-3 bar
+and both formats keep the permeability within 5e-4; a BF16 snapshot of the
+velocity field keeps rounding noise of the order of its 8-bit mantissa
+(2^-8 = 3.9e-3 relative), asserted at 5e-3."""
 import numpy as np
 import pytest
 
@@ -69,10 +73,11 @@ def _sigma(M, u):
     return units.f16_scale_exp(float(np.abs(u).max()))
 
 
-@pytest.mark.parametrize("storage,bar", [(1, 1e-5), (2, 2e-3), (3, 1e-2)])
-def test_fields_reduced_storage(M, storage, bar):
+@pytest.mark.parametrize("storage,sr,bar", [(1, 0, 1e-5), (2, 0, 2e-3), (3, 0, 1e-2), (2, 1, 2e-3), (3, 1, 5e-3)])
+def test_fields_reduced_storage(M, storage, sr, bar):
     ns, st, dx, g, steps, r_ref, u_ref = _porous_case()
-    sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, g, scale_exp=_sigma(M, u_ref))
+    sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, g, scale_exp=_sigma(M, u_ref),
+                          stochastic_rounding=sr)
     sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
     sim.step(steps)
     rho, u, red = sim.macroscopic(dx)
@@ -81,18 +86,47 @@ def test_fields_reduced_storage(M, storage, bar):
     err = rel_l2(u, u_ref)
     k_ref = omlbm.permeability(omlbm.reductions(r_ref, u_ref, st.area), 1.0, 1.0 / 6.0, g[0], dx)
     k = 1.0 / 6.0 * (red[1] / 1.0) / g[0] * dx * dx
-    print(f"[reduced] fields storage={storage} rel_l2_u={err:.3e} k_err={abs(k / k_ref - 1):.3e}", flush=True)
+    print(f"[reduced] fields storage={storage} sr={sr} rel_l2_u={err:.3e} k_err={abs(k / k_ref - 1):.3e}",
+          flush=True)
     assert err <= bar
-    assert abs(k / k_ref - 1) <= 5e-3
+    assert abs(k / k_ref - 1) <= (5e-4 if sr else 5e-3)
 
 
-@pytest.mark.parametrize("storage,bar", [(1, 1e-5), (2, 5e-3), (3, 0.15)])
-def test_populations_reduced_storage(M, storage, bar):
+@pytest.mark.parametrize("storage,sr,bar", [(1, 0, 1e-5), (2, 0, 5e-3), (3, 0, 0.15), (2, 1, 2e-3), (3, 1, 5e-3)])
+def test_populations_reduced_storage(M, storage, sr, bar):
     ns, st, dx, g, steps, r_ref, u_ref, tp, tm = _channel_case()
-    sim = sim_from_oracle(M, ns, st, 0, storage, tp, tm, g, scale_exp=_sigma(M, u_ref))
+    sim = sim_from_oracle(M, ns, st, 0, storage, tp, tm, g, scale_exp=_sigma(M, u_ref),
+                          stochastic_rounding=sr)
     sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
     sim.step(steps)
     rho, u, red = sim.macroscopic(dx)
     err = rel_l2(u.cpu().numpy(), u_ref)
-    print(f"[reduced] populations storage={storage} rel_l2_u={err:.3e}", flush=True)
+    print(f"[reduced] populations storage={storage} sr={sr} rel_l2_u={err:.3e}", flush=True)
     assert err <= bar
+
+
+@pytest.mark.parametrize("storage", [2, 3])
+def test_stochastic_rounding_accumulates_small_increments(M, storage):
+    # Uniform body force on a periodic lattice with dx = h (MLBM1 = LBM1): the
+    # velocity grows by exactly g per step.  Once g is below half a storage
+    # ulp of u, rounding to nearest returns the old value and u stalls;
+    # stochastic rounding keeps the expected value, so the mean velocity
+    # follows n g.
+    ns = nodesets.regular_grid(64)
+    st = omlbm.build_stencils(ns, 12, ns.h)
+    g, steps = 2e-7, 3000
+    sigma = 19 if storage == 2 else 0
+    means = {}
+    for sr in (0, 1):
+        sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, (g, 0.0), scale_exp=sigma, stochastic_rounding=sr)
+        sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+        sim.step(steps)
+        _, u, _ = sim.macroscopic(ns.h)
+        means[sr] = float(u[:, 0].mean())
+    exact = g * steps
+    e_near, e_sr = abs(means[0] / exact - 1), abs(means[1] / exact - 1)
+    print(f"[sr] storage={storage} nearest err {e_near:.3e} stochastic err {e_sr:.3e}", flush=True)
+    # rounding noise of the mean after n steps: about half an ulp of u times
+    # sqrt(n / nodes), 2e-4 (FP16) and 3e-3 (BF16) of n g here
+    assert e_near > 0.05
+    assert e_sr < 1e-2
