@@ -102,8 +102,8 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
     and BF16 state: steps, seconds and permeability, the 16-bit permeabilities
     relative to the FP32 one.  Criteria: the field residual below tol (FP32;
     16-bit rounding keeps the field residual near the storage ulp, so 16-bit
-    runs stop at the step cap) and the mean-velocity change below tol (all
-    storages; 16-bit with stochastic rounding)."""
+    runs stop at the step cap) and the mean-velocity change below tol at three
+    consecutive checks (all storages; 16-bit with stochastic rounding)."""
     t0 = time.time()
     ns = nodesets.porous()
     dx = ns.h
@@ -126,7 +126,8 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
         sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        steps, res, red = sim.run_to_steady(dx, tol=tol, check_every=100, max_steps=cap, criterion=crit)
+        steps, res, red = sim.run_to_steady(dx, tol=tol, check_every=100, max_steps=cap, criterion=crit,
+                                            hold=3 if crit == "mean" else 1)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         k = nu * (red[M._lib.RED_INT_UX] / 1.0) / g * dx * dx

@@ -16,6 +16,7 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <vector>
 
 #include <cmath>
@@ -493,7 +494,7 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
         }
         int m[9];
         block_members<LDS>(a, n, i, self, m);
-        for_quads<0, 3>([&](auto gc) {
+        for_quads<0, 3>([&](auto gc) __attribute__((always_inline)) {
             constexpr int j0 = 4 * decltype(gc)::value, nj = j0 < 8 ? 4 : 1;
             CG v[4][8];
 #pragma unroll
@@ -511,7 +512,7 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
         });
     } else {
         u4 lv;
-        for_quads<0, KQ>([&](auto qc) {
+        for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value;
             int m[4];
             members<LDS, q>(a, n, i, lv, m);
@@ -556,7 +557,7 @@ template <int S, class CG, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_waves<S, KQ>()))) k_step_pop(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
-    for_tiles(a, [&](int64_t tile) {
+    for_tiles(a, [&](int64_t tile) __attribute__((always_inline)) {
         if constexpr (LDS) stage_halo<pop_bytes<S>(), KQ == 0>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
         if (i < a.n)
@@ -590,7 +591,7 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
             }
             int mi[9];
             block_members<LDS>(a, n, i, self, mi);
-            for_quads<0, 3>([&](auto gc) {
+            for_quads<0, 3>([&](auto gc) __attribute__((always_inline)) {
                 constexpr int j0 = 4 * decltype(gc)::value, nj = j0 < 8 ? 4 : 1;
                 CG m[4][3];
 #pragma unroll
@@ -610,7 +611,7 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
             });
         } else {
         u4 lv;
-        for_quads<0, KQ>([&](auto qc) {
+        for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value;
             int mi[4];
             members<LDS, q>(a, n, i, lv, mi);
@@ -665,7 +666,7 @@ template <int S, class CG, class C, int KQ, bool LDS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_waves<S, KQ>()))) k_step_fields(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
-    for_tiles(a, [&](int64_t tile) {
+    for_tiles(a, [&](int64_t tile) __attribute__((always_inline)) {
         if constexpr (LDS) stage_halo<field_bytes<S>(), KQ == 0>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
         if (i < a.n)
@@ -1460,6 +1461,13 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     // groups whose samples have all retired are left out of the launches
     std::vector<int32_t> qoff(b->n_groups + 1);
     std::vector<char> live(b->n_groups, 1);
+    // a group's launches need no more workgroups than it has tiles
+    std::vector<int> group_grid(b->n_groups);
+    for (int gi = 0; gi < b->n_groups; ++gi) {
+        const int32_t *so = b->sample_tile_off_host, *go = b->group_sample_off_host;
+        const int tiles = so[go[gi + 1]] - so[go[gi]];
+        group_grid[gi] = std::min(G, (tiles + 7) / 8 * 8);
+    }
     auto enqueue = [&]() -> int {
         for (int gi = 0; gi < b->n_groups; ++gi) {
             if (!live[gi]) continue;
@@ -1469,7 +1477,7 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
                 a.in = st->state[cur];
                 a.out = st->state[cur ^ 1];
                 a.reverse = p->alternate_sweeps ? (t & 1) : 0;
-                hipLaunchKernelGGL(fn, dim3(G), dim3(st->tile), shmem, s, a);
+                hipLaunchKernelGGL(fn, dim3(group_grid[gi]), dim3(st->tile), shmem, s, a);
                 cur ^= 1;
             }
         }

@@ -235,13 +235,15 @@ class Simulation:
         """Current state buffer as a host numpy uint8 array (synchronises)."""
         return self.state_d[self.ds.cur].cpu().numpy()
 
-    def run_to_steady(self, dx, tol=1e-6, check_every=100, max_steps=1_000_000, stream=None, criterion="field"):
+    def run_to_steady(self, dx, tol=1e-6, check_every=100, max_steps=1_000_000, stream=None, criterion="field",
+                      hold=1):
         """Steps until the residual is below tol, checked every check_every
         steps with mlbm_macroscopic (one small device-to-host copy per check).
         criterion "field": ||u^n - u^(n - check_every)|| / ||u^n|| over the
         nodes; "mean": the relative change of the mean velocity (the integral
         of u_x), the paper's steady criterion (Sec. 3.2), which stays
-        meaningful when 16-bit storage keeps rounding noise in every node.
+        meaningful when 16-bit storage keeps rounding noise in every node.  The
+        residual must stay below tol for `hold` consecutive checks.
         Returns (steps, residual, reductions as numpy)."""
         t = self.torch
         dev = self.state_d[0].device
@@ -253,6 +255,7 @@ class Simulation:
         res = float("inf")
         red = None
         prev_ux = None
+        below = 0
         while steps < max_steps:
             self.step(check_every, stream=stream)
             steps += check_every
@@ -266,7 +269,8 @@ class Simulation:
                 ux = float(red[_lib.RED_INT_UX])
                 res = abs(ux - prev_ux) / abs(ux) if prev_ux is not None and ux != 0.0 else float("inf")
                 prev_ux = ux
-            if res < tol:
+            below = below + 1 if res < tol else 0
+            if below >= hold:
                 break
         return steps, res, red
 
