@@ -148,15 +148,17 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
     return out
 
 
-def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.242e-8, sequential=True):
+def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.242e-8, sequential=True,
+                     n_range=(50_000, 400_000)):
     """64 porous samples (nodes U(5e4, 4e5), porosity U(0.55, 0.85)), MLBM1
     FP32, s = 1, run from rest to a residual of tol in one batched launch
     (persistent tile queue, graph replay, autotuned shape), against the same
-    samples run one after another."""
+    samples run one after another.  A second call with many small samples
+    (each too small to fill the GPU alone) shows what batching buys there."""
     from paper_2312_14789_amd import autotune
 
     t0 = time.time()
-    sets = nodesets.porous_batch(n_samples)
+    sets = nodesets.porous_batch(n_samples, n_range=n_range)
     built = [M.build_stencils_for(ns, 16, ns.h) for ns in sets]
     batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for b, ns in zip(built, sets)], variant=M.FIELDS,
                               storage=M.F32, tau_plus=1.0, g=(g, 0.0), tile=256, check_every=100)
@@ -202,6 +204,58 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
                              "speedup_batched": round(seq_seconds / dt, 3),
                              "same_steps_per_sample": bool(np.array_equal(np.array(seq_steps), steps))}
     return out
+
+
+def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=400_000, tol=1e-6):
+    """Onset of inertia in the porous sample of Sec. 3.2: MLBM1 (tau = 1) on
+    the hybrid porous channel at a fixed lattice forcing g_lb for a sweep of
+    streaming distances dx, all of them in one batched launch (one sample per
+    dx).  With the physical viscosity 1 (dt = nu_lb dx^2), each dx gives the
+    physical acceleration g = g_lb dx / dt^2, the mean velocity <u> (Eq. 23),
+    Re = <u> (unit length and viscosity) and the tortuosity
+    T_V = <|u|> / <u> (Eq. 25), at steady state or at the step cap."""
+    t0 = time.time()
+    ns = nodesets.porous_channel()
+    dxs = [2e-3, 1.5e-3, 1e-3, 7e-4, 5e-4, 3e-4, 2e-4, 1.5e-4]
+    built = [M.build_stencils_for(ns, 16, dx, lattice_h=ns.h) for dx in dxs]
+    batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for b in built], variant=M.FIELDS, storage=M.F32,
+                              tau_plus=1.0, g=(g_lb, 0.0), tile=256, check_every=100)
+    batch.init_state([np.ones(ns.n)] * len(dxs), [np.zeros((ns.n, 2))] * len(dxs))
+    setup = time.time() - t0
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ran = batch.run(max_steps, tol=tol, use_graph=True)
+    torch.cuda.synchronize()
+    dt_run = time.perf_counter() - t1
+    steps, res, _ = batch.results()
+    _, u, _ = batch.sim.macroscopic(1.0)
+    u = u.cpu().numpy()
+    phi = ns.fluid_area()
+    nu_lb = units.nu_lattice(1.0)
+    rows = []
+    for s_, (dx, b) in enumerate(zip(dxs, built)):
+        o, m = int(batch.node_off[s_]), batch.sizes[s_]
+        us = u[o:o + m]
+        area = b["area"]
+        int_ux = float(np.sum(area * us[:, 0]))
+        int_speed = float(np.sum(area * np.hypot(us[:, 0], us[:, 1])))
+        dt = units.time_step(dx, 1.0, 1.0)
+        u_mean = int_ux / phi * dx / dt
+        rows.append({"dx": dx, "s_bulk": round(ns.h / dx, 3), "g": units.acceleration_phys(g_lb, dx, dt),
+                     "u_mean": u_mean, "Re": u_mean, "T_V": int_speed / int_ux if int_ux else None,
+                     "steps": int(abs(steps[s_])) if steps[s_] else ran, "converged": bool(steps[s_] > 0),
+                     "unstable": bool(steps[s_] < 0), "residual": float(res[s_])})
+    # Darcy: <u> proportional to g; the deviation is <u>/g relative to the smallest g
+    base = rows[0]["u_mean"] / rows[0]["g"]
+    for r in rows:
+        r["darcy_ratio"] = r["u_mean"] / r["g"] / base
+    return {"metric": "Darcy deviation and tortuosity versus Re (MLBM1, batched sweep over dx)",
+            "workload": f"porous channel (Sec. 3.2 arrangement): {ns.n} nodes, phi={phi:.3f}, {len(ns.disks)} disks, "
+                        f"periodic x, no-slip walls y, hybrid lattice h={ns.h:g} / band nodes to h={ns.h_min:g}; "
+                        f"g_lb={g_lb:g}, K=16, residual {tol:g} or {max_steps} steps",
+            "seconds": round(dt_run, 2), "steps_run": ran, "setup_s": round(setup, 1),
+            "MNUPS_effective": round(float(np.sum(np.abs(steps) * ns.n)) / dt_run / 1e6, 1) if dt_run else None,
+            "rows": rows}
 
 
 def warmstart_workload(args, np, torch):
@@ -289,9 +343,10 @@ def main():
                          "Lagrange weights at the block centres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
-    ap.add_argument("--workload", default="karman", choices=["karman", "batched", "warmstart"],
+    ap.add_argument("--workload", default="karman", choices=["karman", "batched", "warmstart", "darcy"],
                     help="karman: the fused-step throughput line; batched: 64 porous samples to steady "
-                         "state; warmstart: train the warm-start network and compare time to steady state")
+                         "state; warmstart: train the warm-start network and compare time to steady state; "
+                         "darcy: mean velocity and tortuosity of the porous channel over a sweep of dx")
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-test", type=int, default=200)
     ap.add_argument("--ws-epochs", type=int, default=20)
@@ -314,10 +369,16 @@ def main():
     from paper_2312_14789_amd import units
 
     if args.workload == "batched":
-        print(json.dumps(batched_workload(M, units, nodesets, np, torch)), flush=True)
+        out = batched_workload(M, units, nodesets, np, torch)
+        out["small_samples"] = batched_workload(M, units, nodesets, np, torch, n_samples=256,
+                                                n_range=(2_000, 20_000))
+        print(json.dumps(out), flush=True)
         return
     if args.workload == "warmstart":
         print(json.dumps(warmstart_workload(args, np, torch)), flush=True)
+        return
+    if args.workload == "darcy":
+        print(json.dumps(darcy_workload(M, units, nodesets, np, torch)), flush=True)
         return
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]

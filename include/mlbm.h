@@ -277,11 +277,14 @@ int mlbm_step(const mlbm_step_params *params, mlbm_device_state *state, int32_t 
  * Many independent samples (e.g. porous media of uneven size) run as one
  * concatenated node set whose tiles never straddle two samples (pad each
  * sample to a multiple of `tile` nodes with Dirichlet nodes of zero area and
- * no stencil).  mlbm_device_state must use tiles.  Persistent workgroups walk
- * a device list of active tiles; every check_every steps each sample's
- * residual ||u - u_prev|| / ||u|| is formed, samples below tol retire and the
- * list is rebuilt on the device, so a captured graph of one check can be
- * replayed until no sample is left.
+ * no stencil).  mlbm_device_state must use tiles.  Samples are taken in
+ * groups (see n_groups): a group whose samples are all active is stepped with
+ * one workgroup per tile; once some of its samples have retired, persistent
+ * workgroups (at most `grid`) walk the group's part of a device list of active
+ * tiles.  Every check_every steps each sample's residual
+ * ||u - u_prev|| / ||u|| is formed, samples below tol retire and the list is
+ * rebuilt on the device, so captured graphs can be replayed: one per group
+ * (captured again when the group loses a sample) and one for the check.
  */
 typedef struct mlbm_batch {
     int32_t n_samples;               /* 1 .. 4096                                     */
@@ -320,9 +323,9 @@ int mlbm_batch_init(const mlbm_step_params *params, mlbm_device_state *state, ml
 /*
  * Runs checks of check_every steps until every sample has retired (residual
  * below tol, or non-finite fields) or max_steps is reached.  With use_graph
- * one check is captured into a HIP graph on hip_stream (which must not be the
- * default stream) and replayed; a group whose samples have all retired is no
- * longer launched (the graph is captured again without it).  Synchronous:
+ * the steps of each group and the check are captured into HIP graphs on
+ * hip_stream (which must not be the default stream) and replayed; a group
+ * whose samples have all retired is no longer launched.  Synchronous:
  * waits on hip_stream after each check to read the counters and the group
  * queue ranges.  state->cur is unchanged on return (an
  * even number of steps per check).  *steps_done receives the steps run.

@@ -358,6 +358,80 @@ def porous(n_target: int = 1_000_000, phi: float = 0.7, seed: int = 231214789,
                    disks=disks, h=h, name="porous")
 
 
+def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, band: float = 0.04,
+                   r_range=(0.06, 0.1), seed: int = 231214789, L: float = 1.0) -> NodeSet:
+    """The porous sample of Sec. 3.2: the box [0, L]^2, periodic along x,
+    no-slip walls on y = 0 and y = L (nodes on them), random non-overlapping
+    disks (radii uniform in r_range, porosity phi, clear of the walls), and a
+    hybrid node set: a square lattice of spacing h farther than `band` from
+    every disk, scattered nodes within the band whose spacing grows linearly
+    from h_surf on the disk surfaces to h at the band's edge (jittered samples
+    thinned to that density, close pairs removed), and nodes on every disk
+    surface at spacing h_surf."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    # disks: random sequential addition, periodic along x only
+    disks = []
+    solid, target, tries = 0.0, (1.0 - phi) * L * L, 0
+    gap = 2.0 * h_surf
+    while solid < target and tries < 200_000:
+        tries += 1
+        rr = rng.uniform(*r_range)
+        c = np.array([rng.uniform(0.0, L), rng.uniform(rr + gap, L - rr - gap)])
+        if disks:
+            D = np.asarray(disks)
+            d = D[:, :2] - c
+            d[:, 0] -= L * np.round(d[:, 0] / L)
+            if not np.all(np.hypot(d[:, 0], d[:, 1]) >= D[:, 2] + rr + gap):
+                continue
+        disks.append((c[0], c[1], rr))
+        solid += np.pi * rr * rr
+    disks = np.asarray(disks, dtype=np.float64).reshape(-1, 3)
+    lo, hi = np.zeros(2), np.full(2, L)
+
+    def surface_distance(pts):
+        d = np.full(len(pts), np.inf)
+        for cx, cy, r in disks:
+            dx = pts[:, 0] - cx
+            dx -= L * np.round(dx / L)
+            d = np.minimum(d, np.hypot(dx, pts[:, 1] - cy) - r)
+        return d
+
+    # lattice: x = i h (periodic), y = j h (rows on both walls)
+    nx, ny = int(round(L / h)), int(round(L / h))
+    X, Y = np.meshgrid(np.arange(nx) * (L / nx), np.arange(ny + 1) * (L / ny), indexing="xy")
+    lat = np.stack([X.ravel(), Y.ravel()], axis=1)
+    dl = surface_distance(lat)
+    lat = lat[dl > band]
+    # band: jittered candidates at h_surf, kept with probability (h_surf / h(d))^2
+    cand = _grid(lo, hi, h_surf)
+    cand = cand + rng.uniform(-0.35 * h_surf, 0.35 * h_surf, size=cand.shape)
+    cand[:, 0] = np.mod(cand[:, 0], L)
+    cand = cand[(cand[:, 1] > 0.5 * h_surf) & (cand[:, 1] < L - 0.5 * h_surf)]
+    dc = surface_distance(cand)
+    sel = (dc > 0.5 * h_surf) & (dc <= band)
+    cand, dc = cand[sel], dc[sel]
+    hloc_c = h_surf + (h - h_surf) * np.clip(dc / band, 0.0, 1.0)
+    cand = cand[rng.uniform(size=len(cand)) < (h_surf / hloc_c) ** 2]
+    hloc_c = h_surf + (h - h_surf) * np.clip(surface_distance(cand) / band, 0.0, 1.0)
+    surf = np.concatenate([_circle_nodes(c[0], c[1], c[2], h_surf) for c in disks]) if len(disks) else np.zeros((0, 2))
+    surf[:, 0] = np.mod(surf[:, 0], L)
+    walls = np.concatenate([np.stack([np.arange(nx) * (L / nx), np.zeros(nx)], 1),
+                            np.stack([np.arange(nx) * (L / nx), np.full(nx, L)], 1)])
+    on_wall_lat = (np.isclose(lat[:, 1], 0.0)) | (np.isclose(lat[:, 1], L))
+    lat_in = lat[~on_wall_lat]
+    xy = np.concatenate([lat_in, cand, surf, walls])
+    kind = np.concatenate([np.zeros(len(lat_in) + len(cand), np.uint8), np.full(len(surf) + len(walls), WALL, np.uint8)])
+    hloc = np.concatenate([np.full(len(lat_in), h), hloc_c, np.full(len(surf), h_surf), np.full(len(walls), h)])
+    # lattice nodes are fixed too, so the clean-up removes band nodes only
+    fixed = np.concatenate([np.ones(len(lat_in), bool), np.zeros(len(cand), bool), np.ones(len(surf) + len(walls), bool)])
+    keep = _cleanup(xy, hloc, fixed, lo, hi, (True, False), frac=0.45)
+    xy, kind = xy[keep], kind[keep]
+    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(True, False), walls_y=(True, True),
+                   disks=disks, h=h, name="porous-channel", h_min=h_surf)
+
+
 def porous_batch(n_samples: int = 64, seed: int = 231214789, n_range=(50_000, 400_000),
                  phi_range=(0.55, 0.85)) -> list:
     """n_samples porous media with node counts and porosities drawn uniformly

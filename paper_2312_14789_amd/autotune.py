@@ -1,4 +1,5 @@
-"""Launch-shape autotuner for batched runs.
+"""Launch-shape autotuners: batched runs (tune) and single node sets
+(tune_simulation).
 
 Times the batched step (mlbm_step_batched, graph replay, no retirement) on
 the actual batch in two stages and keeps the fastest: first the tile size and
@@ -108,3 +109,62 @@ def _reinit(batch, rho_u):
     rho_list = [np.ones(m) if r is None else r for m, r in zip(batch.sizes, rho_u[0])]
     u_list = [np.zeros((m, 2)) if u is None else u for m, u in zip(batch.sizes, rho_u[1])]
     batch.init_state(rho_list, u_list)
+
+
+SIM_TILES = (0, 64, 128, 256)
+SIM_SWEEPS = (1, 0)
+
+
+def sim_cache_key(sim) -> str:
+    import torch
+
+    arch = torch.cuda.get_device_properties(sim.state_d[0].device).gcnArchName.split(":")[0]
+    p = sim.params
+    return f"sim|{arch}|K{sim.K}|v{p.variant}|s{p.storage}|N2^{round(math.log2(sim.n))}"
+
+
+def tune_simulation(sim, steps=200, cache_path=None, use_cache=True):
+    """Picks tile size (0 = gathers from global memory, else LDS-staged tiles
+    of that many nodes), XCD-contiguous tiles and alternating sweeps for a
+    Simulation by timing mlbm_step on its own node set, and applies them.
+    The state is advanced by the timing runs; re-initialise it afterwards.
+    Returns {"tile", "xcd", "sweeps", "ms_per_step", "timings", "cached"}."""
+    import torch
+
+    cache_path = cache_path or default_cache_path()
+    key = sim_cache_key(sim)
+    cache = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    if use_cache and key in cache:
+        best = dict(cache[key], cached=True)
+    else:
+        timings = []
+        stream = torch.cuda.current_stream()
+        for tile in SIM_TILES:
+            sim.set_tile(tile)
+            for xcd in XCD:
+                for sweeps in SIM_SWEEPS:
+                    sim.params.xcd_remap = xcd
+                    sim.params.alternate_sweeps = sweeps
+                    sim.step(steps // 4)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    sim.step(steps)
+                    e1.record(stream)
+                    e1.synchronize()
+                    timings.append({"tile": tile, "xcd": xcd, "sweeps": sweeps,
+                                    "ms_per_step": e0.elapsed_time(e1) / steps})
+        best = dict(min(timings, key=lambda r: r["ms_per_step"]))
+        best["timings"] = timings
+        cache[key] = {k: best[k] for k in ("tile", "xcd", "sweeps", "ms_per_step")}
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+        best["cached"] = False
+    sim.set_tile(best["tile"])
+    sim.params.xcd_remap = best["xcd"]
+    sim.params.alternate_sweeps = best["sweeps"]
+    return best

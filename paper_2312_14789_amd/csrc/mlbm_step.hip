@@ -1248,23 +1248,39 @@ __global__ void __launch_bounds__(256) k_batch_tile_red(const BatchArgs a) {
 constexpr int MAX_SAMPLES = 4096;
 
 // one workgroup: per-sample residual, retirement, new active tile list
+// One workgroup per sample: the sample's residual from its tiles' partial
+// sums, added in a fixed order (strided per thread, then a tree), and its
+// retirement.
+__global__ void __launch_bounds__(256) k_batch_sample_red(const BatchArgs a, int mark) {
+    __shared__ double part[BATCH_RED][256];
+    const int s = blockIdx.x;
+    if (a.sample_steps[s] != 0) return;  // uniform over the workgroup
+    double r[BATCH_RED] = {0, 0, 0, 0};
+    for (int t = a.tile_off[s] + (int)threadIdx.x; t < a.tile_off[s + 1]; t += blockDim.x)
+        for (int q = 0; q < BATCH_RED; ++q) r[q] += a.tile_red[(int64_t)t * BATCH_RED + q];
+    for (int q = 0; q < BATCH_RED; ++q) part[q][threadIdx.x] = r[q];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < BATCH_RED; ++q) part[q][threadIdx.x] += part[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double du2 = part[0][0], u2 = part[1][0];
+    const double res = u2 > 0.0 ? sqrt(du2 / u2) : (du2 > 0.0 ? INFINITY : 0.0);
+    a.sample_res[s] = res;
+    a.sample_ux[s] = part[2][0];
+    if (!mark) return;
+    const int steps = a.counters[1] + a.check_every;
+    if (part[3][0] > 0.0 || !isfinite(res)) a.sample_steps[s] = -steps;
+    else if (res < a.tol) a.sample_steps[s] = steps;
+}
+
+// Rebuilds the list of active tiles and the groups' queue ranges.
 __global__ void __launch_bounds__(256) k_batch_retire(const BatchArgs a, int mark) {
     __shared__ int start[MAX_SAMPLES];
     __shared__ int total, active;
     const int steps = a.counters[1] + a.check_every;
-    for (int s = threadIdx.x; s < a.n_samples; s += blockDim.x) {
-        if (a.sample_steps[s] != 0) continue;
-        double r[BATCH_RED] = {0, 0, 0, 0};
-        for (int t = a.tile_off[s]; t < a.tile_off[s + 1]; ++t)
-            for (int q = 0; q < BATCH_RED; ++q) r[q] += a.tile_red[(int64_t)t * BATCH_RED + q];
-        const double res = r[1] > 0.0 ? sqrt(r[0] / r[1]) : (r[0] > 0.0 ? INFINITY : 0.0);
-        a.sample_res[s] = res;
-        a.sample_ux[s] = r[2];
-        if (!mark) continue;
-        if (r[3] > 0.0 || !isfinite(res)) a.sample_steps[s] = -steps;
-        else if (res < a.tol) a.sample_steps[s] = steps;
-    }
-    __syncthreads();
     if (threadIdx.x == 0) {
         int pos = 0, act = 0;
         for (int s = 0; s < a.n_samples; ++s) {
@@ -1402,6 +1418,7 @@ extern "C" int mlbm_batch_init(const mlbm_step_params *p, mlbm_device_state *st,
     const int64_t cover = std::max<int64_t>(ba.ntiles, b->n_samples);
     hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)((cover + 255) / 256)), dim3(256), 0, s, ba);
     hipLaunchKernelGGL(red, dim3((unsigned)batch_grid(b)), dim3(st->tile), 0, s, ba);
+    hipLaunchKernelGGL(k_batch_sample_red, dim3(b->n_samples), dim3(256), 0, s, ba, 0);
     hipLaunchKernelGGL(k_batch_retire, dim3(1), dim3(256), 0, s, ba, 0);
     return hip_check("mlbm_batch_init launch");
 }
@@ -1461,49 +1478,95 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     // groups whose samples have all retired are left out of the launches
     std::vector<int32_t> qoff(b->n_groups + 1);
     std::vector<char> live(b->n_groups, 1);
-    // a group's launches need no more workgroups than it has tiles
-    std::vector<int> group_grid(b->n_groups);
+    // a group's launches need no more workgroups than it has tiles; while all
+    // of its samples are active its tiles are one contiguous range, walked
+    // directly (one workgroup per tile, no queue lookup on the critical path)
+    std::vector<int> group_grid(b->n_groups), group_tiles(b->n_groups), group_tile0(b->n_groups);
+    std::vector<char> full(b->n_groups, 0);
     for (int gi = 0; gi < b->n_groups; ++gi) {
         const int32_t *so = b->sample_tile_off_host, *go = b->group_sample_off_host;
-        const int tiles = so[go[gi + 1]] - so[go[gi]];
-        group_grid[gi] = std::min(G, (tiles + 7) / 8 * 8);
+        group_tile0[gi] = so[go[gi]];
+        group_tiles[gi] = so[go[gi + 1]] - so[go[gi]];
+        group_grid[gi] = std::min(G, (group_tiles[gi] + 7) / 8 * 8);
     }
-    auto enqueue = [&]() -> int {
-        for (int gi = 0; gi < b->n_groups; ++gi) {
-            if (!live[gi]) continue;
-            int cur = cur0;
-            a.group = gi;
-            for (int t = 0; t < b->check_every; ++t) {
-                a.in = st->state[cur];
-                a.out = st->state[cur ^ 1];
-                a.reverse = p->alternate_sweeps ? (t & 1) : 0;
-                hipLaunchKernelGGL(fn, dim3(group_grid[gi]), dim3(st->tile), shmem, s, a);
-                cur ^= 1;
-            }
+    // the check_every steps of one group
+    auto enqueue_group = [&](int gi) {
+        int cur = cur0;
+        a.group = gi;
+        int grid = group_grid[gi];
+        if (full[gi]) {
+            a.queue = nullptr;
+            a.tile0 = group_tile0[gi];
+            a.tile1 = group_tile0[gi] + group_tiles[gi];
+            grid = a.xcd ? (group_tiles[gi] + 7) / 8 * 8 : group_tiles[gi];
+            a.grid8 = grid;
+        } else {
+            a.queue = b->queue;
+            a.grid8 = G;
         }
+        for (int t = 0; t < b->check_every; ++t) {
+            a.in = st->state[cur];
+            a.out = st->state[cur ^ 1];
+            a.reverse = p->alternate_sweeps ? (t & 1) : 0;
+            hipLaunchKernelGGL(fn, dim3(grid), dim3(st->tile), shmem, s, a);
+            cur ^= 1;
+        }
+    };
+    // the per-tile sums, the per-sample residuals, retirement
+    auto enqueue_check = [&]() {
         ba.state = st->state[cur0];
         hipLaunchKernelGGL(red, dim3(G), dim3(st->tile), 0, s, ba);
+        hipLaunchKernelGGL(k_batch_sample_red, dim3(b->n_samples), dim3(256), 0, s, ba, 1);
         hipLaunchKernelGGL(k_batch_retire, dim3(1), dim3(256), 0, s, ba, 1);
-        return hip_check("mlbm_step_batched launch");
     };
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    auto release = [&]() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
+    // With graphs, each group's steps are one graph and the check another, so
+    // a group that retires or loses a sample costs one small capture.
+    std::vector<hipGraph_t> graphs(b->n_groups + 1, nullptr);
+    std::vector<hipGraphExec_t> execs(b->n_groups + 1, nullptr);
+    std::vector<char> graph_full(b->n_groups, 0);
+    auto release = [&](int k) {
+        if (execs[k]) hipGraphExecDestroy(execs[k]);
+        if (graphs[k]) hipGraphDestroy(graphs[k]);
+        execs[k] = nullptr;
+        graphs[k] = nullptr;
     };
-    auto capture = [&]() -> int {
-        release();
+    auto capture = [&](int k) -> int {  // k < n_groups: group k; k == n_groups: the check
+        release(k);
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(MLBM_ERR_HIP, "hipStreamBeginCapture failed");
-        int r = enqueue();
-        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (k < b->n_groups) enqueue_group(k);
+        else enqueue_check();
+        const int r = hip_check("mlbm_step_batched launch");
+        hipError_t e = hipStreamEndCapture(s, &graphs[k]);
         if (r) return r;
         if (e != hipSuccess) return fail(MLBM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&execs[k], graphs[k], nullptr, nullptr, 0);
         if (e != hipSuccess) return fail(MLBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        if (k < b->n_groups) graph_full[k] = full[k];
+        return MLBM_OK;
+    };
+    auto run_check = [&]() -> int {
+        for (int gi = 0; gi < b->n_groups; ++gi) {
+            if (!live[gi]) continue;
+            if (!use_graph) {
+                enqueue_group(gi);
+                continue;
+            }
+            if (!execs[gi] || graph_full[gi] != full[gi]) {
+                const int r = capture(gi);
+                if (r) return r;
+            }
+            if (hipGraphLaunch(execs[gi], s) != hipSuccess) return fail(MLBM_ERR_HIP, "hipGraphLaunch failed");
+        }
+        if (!use_graph) {
+            enqueue_check();
+            return hip_check("mlbm_step_batched launch");
+        }
+        if (!execs[b->n_groups]) {
+            const int r = capture(b->n_groups);
+            if (r) return r;
+        }
+        if (hipGraphLaunch(execs[b->n_groups], s) != hipSuccess) return fail(MLBM_ERR_HIP, "hipGraphLaunch failed");
         return MLBM_OK;
     };
     // the queue ranges left by the last retirement decide which groups run
@@ -1511,22 +1574,16 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return fail(MLBM_ERR_HIP, "reading the group queue ranges failed");
-    for (int gi = 0; gi < b->n_groups; ++gi) live[gi] = qoff[gi + 1] > qoff[gi];
-    if (use_graph && (rc = capture())) {
-        release();
-        return rc;
+    for (int gi = 0; gi < b->n_groups; ++gi) {
+        live[gi] = qoff[gi + 1] > qoff[gi];
+        full[gi] = qoff[gi + 1] - qoff[gi] == group_tiles[gi];
     }
     int steps = 0;
     int counters[4] = {1, 0, 1, 0};
     rc = MLBM_OK;
     while (steps < max_steps) {
-        if (use_graph) {
-            hipError_t e = hipGraphLaunch(exec, s);
-            if (e != hipSuccess) { rc = fail(MLBM_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e)); break; }
-        } else {
-            rc = enqueue();
-            if (rc) break;
-        }
+        rc = run_check();
+        if (rc) break;
         steps += b->check_every;
         if (hipMemcpyAsync(counters, b->counters, sizeof(counters), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(qoff.data(), b->group_queue_off, qoff.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -1536,15 +1593,12 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
             break;
         }
         if (counters[2] == 0) break;
-        bool changed = false;
         for (int gi = 0; gi < b->n_groups; ++gi) {
-            const char l = qoff[gi + 1] > qoff[gi];
-            changed |= l != live[gi];
-            live[gi] = l;
+            live[gi] = qoff[gi + 1] > qoff[gi];
+            full[gi] = qoff[gi + 1] - qoff[gi] == group_tiles[gi];
         }
-        if (changed && use_graph && steps < max_steps && (rc = capture())) break;
     }
-    release();
+    for (int k = 0; k <= b->n_groups; ++k) release(k);
     if (steps_done) *steps_done = steps;
     return rc;
 }

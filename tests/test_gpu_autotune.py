@@ -1,0 +1,54 @@
+"""Autotuner for single node sets: it times every launch shape on the node set
+itself and applies the fastest; the shapes it chooses among compute the same
+sums in the same order (only the data movement differs), so the tuned run
+agrees with the default shape to rounding (kernels built for different shapes
+may fuse multiply-adds differently)."""
+import numpy as np
+import pytest
+
+import nodesets
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_14789_amd import mlbm
+
+    return mlbm
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_tuned_simulation_matches_default_shape(M, variant, tmp_path):
+    from paper_2312_14789_amd import autotune
+
+    ns = nodesets.karman(n_target=20000, seed=9)
+    b = M.build_stencils_for(ns, 16, ns.h_min)
+    perm = b["perm"]
+    tau = 1.0 if variant == 1 else 0.7
+
+    def make():
+        return M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=variant, storage=M.F32,
+                            tau_plus=tau, bc=ns.boundary_values()[perm])
+
+    ref = make()
+    ref.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+    ref.step(100)
+    sim = make()
+    best = autotune.tune_simulation(sim, steps=40, cache_path=str(tmp_path / "tune.json"))
+    print(f"[autotune] variant={variant} best tile={best['tile']} xcd={best['xcd']} sweeps={best['sweeps']} "
+          f"{best['ms_per_step'] * 1e3:.1f} us/step over {len(best['timings'])} shapes", flush=True)
+    assert len(best["timings"]) == len(autotune.SIM_TILES) * len(autotune.XCD) * len(autotune.SIM_SWEEPS)
+    assert sim.ds.tile == best["tile"]
+    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+    sim.step(100)
+    _, u, _ = sim.macroscopic(ns.h_min)
+    _, u_ref, _ = ref.macroscopic(ns.h_min)
+    u, u_ref = u.cpu().numpy(), u_ref.cpu().numpy()
+    assert np.linalg.norm(u - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+    again = autotune.tune_simulation(make(), steps=40, cache_path=str(tmp_path / "tune.json"))
+    assert again["cached"] and again["tile"] == best["tile"]
