@@ -22,7 +22,11 @@ of a Dirichlet node is overwritten by the equilibrium of the prescribed
 density and velocity.
 
 Stencils: one stencil of the K nearest nodes per Eulerian node, shared by its
-eight departure points, with separate weights per departure point.  In a
+eight departure points, with separate weights per departure point; or, as in
+the paper (Sec. 2.2), one stencil per departure point: the K nearest Eulerian
+nodes of that point.  No-slip: the mirrored departure point described above,
+or the simple bounce-back f_k = f_k'^post at the node itself, which the paper
+uses on its cylinder (Sec. 3.1).  In a
 hybrid node set (Sec. 2.2) a fluid node whose nine nearest nodes form a square
 block of the lattice spacing h, and none of whose departure points needs the
 bounce-back rule, uses the block (nine members) with biquadratic Lagrange
@@ -34,14 +38,14 @@ import numpy as np
 
 from . import lattice as lt
 from .lagrange import biquadratic_weights, lattice_block
-from .rbf import interpolation_weights, min_image, nearest
+from .rbf import interpolation_weights, min_image, nearest, nearest_to_point
 
 FLUID, WALL, DIRICHLET = 0, 1, 2
 
 
 @dataclasses.dataclass
 class Stencils:
-    idx: np.ndarray     # (n, K) stencil node indices
+    idx: np.ndarray     # (n, K) stencil node indices, or (n, 8, K) one stencil per departure point
     w: np.ndarray       # (n, 8, K) weights for k = 1..8
     src: np.ndarray     # (n, 8) source population of each arriving k (k or k')
     point: np.ndarray   # (n, 8, 2) departure point offsets from the node
@@ -65,18 +69,24 @@ def inside_solid(p, ns, eps=1e-12):
     return False
 
 
-def departure(ns, i, k, dx):
+def departure(ns, i, k, dx, simple_bb=False):
     """Departure point (offset from x_i) and source population of the
-    population k arriving at node i (Sec. 2.2, Eq. 12; Sec. 3.2, Eq. 22)."""
+    population k arriving at node i (Sec. 2.2, Eq. 12; Sec. 3.2, Eq. 22;
+    simple_bb: the node itself, Sec. 3.1)."""
     x = ns.xy[i]
     e = lt.E[k]
     p = x - dx * e
     if not inside_solid(p, ns):
         return -dx * e, k
     q = x + dx * e
-    if not inside_solid(q, ns):
+    if not simple_bb and not inside_solid(q, ns):
         return dx * e, int(lt.OPP[k])
     return np.zeros(2), int(lt.OPP[k])
+
+
+def members(st, k):
+    """Stencil indices (n, K) used for the arriving population k (1..8)."""
+    return st.idx if st.idx.ndim == 2 else st.idx[:, k - 1, :]
 
 
 def node_area(ns, i, m=4):
@@ -89,14 +99,15 @@ def node_area(ns, i, m=4):
     return 0.5 * a if ns.kind[i] != FLUID else a
 
 
-def stencil_at(ns, i, K, dx, lattice_h=None):
-    """Stencil indices (K,), weights (8, K), sources (8,), departure offsets
-    (8, 2) of node i, and whether the Lagrange block was used (lattice_h: the
-    spacing of the regular part of a hybrid set, None for RBF-FD everywhere)."""
+def stencil_at(ns, i, K, dx, lattice_h=None, per_departure=False, simple_bb=False):
+    """Stencil indices (K,) (per_departure: (8, K)), weights (8, K), sources
+    (8,), departure offsets (8, 2) of node i, and whether the Lagrange block
+    was used (lattice_h: the spacing of the regular part of a hybrid set, None
+    for RBF-FD everywhere)."""
     src = np.zeros(8, dtype=np.int64)
     pts = np.zeros((8, 2))
     for k in range(1, 9):
-        pts[k - 1], src[k - 1] = departure(ns, i, k, dx)
+        pts[k - 1], src[k - 1] = departure(ns, i, k, dx, simple_bb)
     if lattice_h is not None and ns.kind[i] == FLUID and dx <= lattice_h and np.all(src == np.arange(1, 9)):
         block = lattice_block(ns, i, lattice_h)
         if block is not None:
@@ -106,26 +117,36 @@ def stencil_at(ns, i, K, dx, lattice_h=None):
             idx[:9] = block[order]
             w = np.zeros((8, K))
             w[:, :9] = biquadratic_weights(pts, lattice_h)[:, order]
+            if per_departure:
+                idx = np.tile(idx, (8, 1))
             return idx, w, src, pts, True
+    if per_departure:
+        # the K nearest nodes of each departure point, weights at that point
+        idx = np.zeros((8, K), dtype=np.int64)
+        w = np.zeros((8, K))
+        for k in range(8):
+            idx[k], X = nearest_to_point(ns.xy, i, pts[k], K, ns.hi - ns.lo, ns.periodic)
+            w[k] = interpolation_weights(X, np.zeros((1, 2)))[0]
+        return idx, w, src, pts, False
     idx, X = nearest(ns.xy, i, K, ns.hi - ns.lo, ns.periodic)
     w = interpolation_weights(X, pts)
     return idx, w, src, pts, False
 
 
-def build_stencils(ns, K, dx, lattice_h=None):
+def build_stencils(ns, K, dx, lattice_h=None, per_departure=False, simple_bb=False):
     """Stencils of every node, plus quadrature weights normalised so that they
     sum to the analytic fluid area."""
     n = ns.n
     if lattice_h is not None and K < 10:
         raise ValueError("hybrid stencils need K >= 10")
-    idx = np.zeros((n, K), dtype=np.int64)
+    idx = np.zeros((n, 8, K) if per_departure else (n, K), dtype=np.int64)
     w = np.zeros((n, 8, K))
     src = np.zeros((n, 8), dtype=np.int64)
     pts = np.zeros((n, 8, 2))
     area = np.zeros(n)
     lag = np.zeros(n, dtype=bool)
     for i in range(n):
-        idx[i], w[i], src[i], pts[i], lag[i] = stencil_at(ns, i, K, dx, lattice_h)
+        idx[i], w[i], src[i], pts[i], lag[i] = stencil_at(ns, i, K, dx, lattice_h, per_departure, simple_bb)
         area[i] = node_area(ns, i)
     area *= ns.fluid_area() / area.sum()
     return Stencils(idx=idx, w=w, src=src, point=pts, area=area, lagrange=lag)
@@ -159,7 +180,7 @@ def stream(fpost, st):
     rows = np.arange(n)[:, None]
     for k in range(1, 9):
         s = st.src[:, k - 1][:, None] + 0 * rows
-        vals = fpost[s, st.idx]
+        vals = fpost[s, members(st, k)]
         fnew[k] = np.sum(st.w[:, k - 1, :] * vals, axis=1)
     return fnew
 
@@ -233,9 +254,10 @@ def mlbm1_step(rho, u, ns, st, g=(0.0, 0.0)):
     fhat[0] = own[0]
     for k in range(1, 9):
         wk = st.w[:, k - 1, :]
-        rho_h = np.sum(wk * rho[st.idx], axis=1)
-        u_h = np.stack([np.sum(wk * u[st.idx, 0], axis=1),
-                        np.sum(wk * u[st.idx, 1], axis=1)], axis=1)
+        mk = members(st, k)
+        rho_h = np.sum(wk * rho[mk], axis=1)
+        u_h = np.stack([np.sum(wk * u[mk, 0], axis=1),
+                        np.sum(wk * u[mk, 1], axis=1)], axis=1)
         at_p = lt.equilibrium(rho_h, u_h) + 0.5 * lt.guo_force(rho_h, u_h, g)
         fhat[k] = at_p[st.src[:, k - 1], cols]
     rho_new = lt.density(fhat)
@@ -264,7 +286,7 @@ def mlbm1_bounce_back_force(rho, u, ns, st, g, dx, area=None):
             if st.src[i, k - 1] != kp:
                 continue
             w = st.w[i, k - 1]
-            nb = st.idx[i]
+            nb = members(st, k)[i]
             rh = np.array([np.sum(w * rho[nb])])
             uh = np.array([[np.sum(w * u[nb, 0]), np.sum(w * u[nb, 1])]])
             back = lt.equilibrium(rh, uh) + 0.5 * lt.guo_force(rh, uh, g)

@@ -45,6 +45,21 @@ def nearest(xy, i, K, box, periodic):
     return sel, d[sel]
 
 
+def nearest_to_point(xy, i, o, K, box, periodic):
+    """The K nearest nodes of the point p = x_i + o, ordered like nearest():
+    squared distance, then the offset x_j - p (dx, then dy).  The offsets are
+    formed as (x_j - x_i) - o, so on a lattice every node's point sees the
+    same offsets (and the same ties) whatever the rounding of x_i + o.
+    Returns (indices (K,), offsets x_j - p (K, 2))."""
+    d = min_image(xy - xy[i], box, periodic) - np.asarray(o, dtype=np.float64)
+    r2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]
+    cut = np.partition(r2, K - 1)[K - 1]
+    cand = np.nonzero(r2 <= cut)[0]
+    order = cand[np.lexsort((d[cand, 1], d[cand, 0], r2[cand]))]
+    sel = order[:K]
+    return sel, d[sel]
+
+
 def poly2(p):
     """Monomials of total degree <= 2 at points p (..., 2) -> (..., 6)."""
     x, y = p[..., 0], p[..., 1]

@@ -70,7 +70,8 @@ def sim_from_oracle(M, ns, st, variant, storage, tau_plus, tau_minus, g, **kw):
                         g=g, bc=ns.boundary_values(), lagrange=lag, w_lagrange=wl, **kw)
 
 
-def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus, g, lattice_h=None):
+def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus, g, lattice_h=None,
+                       per_departure=False, simple_bb=False):
     """Fields after one step at the listed nodes only, computed node by node
     with the oracle's own stencil of each node (for node sets too large for a
     whole oracle run).  rho0, u0: initial fields of all nodes."""
@@ -78,22 +79,23 @@ def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus,
     d_all = ns.kind == nodesets.DIRICHLET
     bc = ns.boundary_values()
     for i in nodes:
-        idx, w, src, _, _ = omlbm.stencil_at(ns, i, K, dx, lattice_h)
+        idx, w, src, _, _ = omlbm.stencil_at(ns, i, K, dx, lattice_h, per_departure, simple_bb)
+        if idx.ndim == 1:
+            idx = np.tile(idx, (8, 1))
         if d_all[i]:
             out_r.append(bc[i, 0])
             out_u.append(bc[i, 1:3])
             continue
         if variant == 0:
-            cols = np.concatenate([[i], idx])
-            f0 = omlbm.init_populations(rho0[cols], u0[cols])
-            fpost = lt.collide(f0, tau_plus, tau_minus, g)
-            dd = d_all[cols]
-            if np.any(dd):
-                fpost[:, dd] = lt.equilibrium(bc[cols[dd], 0], bc[cols[dd], 1:3])
             f = np.empty(9)
-            f[0] = fpost[0, 0]
-            for k in range(1, 9):
-                f[k] = np.sum(w[k - 1] * fpost[src[k - 1], 1:])
+            for k in range(0, 9):
+                cols = np.concatenate([[i], idx[max(k, 1) - 1]])
+                f0 = omlbm.init_populations(rho0[cols], u0[cols])
+                fpost = lt.collide(f0, tau_plus, tau_minus, g)
+                dd = d_all[cols]
+                if np.any(dd):
+                    fpost[:, dd] = lt.equilibrium(bc[cols[dd], 0], bc[cols[dd], 1:3])
+                f[k] = fpost[0, 0] if k == 0 else np.sum(w[k - 1] * fpost[src[k - 1], 1:])
             r = f.sum()
             u = (lt.E.T @ f + 0.5 * r * np.asarray(g)) / r
         else:
@@ -102,8 +104,9 @@ def oracle_one_step_at(ns, nodes, K, dx, variant, rho0, u0, tau_plus, tau_minus,
             f = np.empty(9)
             f[0] = own[0, 0]
             for k in range(1, 9):
-                rh = np.sum(w[k - 1] * rho0[idx])
-                uh = np.array([[np.sum(w[k - 1] * u0[idx, 0]), np.sum(w[k - 1] * u0[idx, 1])]])
+                mk = idx[k - 1]
+                rh = np.sum(w[k - 1] * rho0[mk])
+                uh = np.array([[np.sum(w[k - 1] * u0[mk, 0]), np.sum(w[k - 1] * u0[mk, 1])]])
                 at = lt.equilibrium(np.array([rh]), uh) + 0.5 * lt.guo_force(np.array([rh]), uh, g_)
                 f[k] = at[src[k - 1], 0]
             r = f.sum()
