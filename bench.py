@@ -167,6 +167,8 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
     t1 = time.time()
     best = autotune.tune(batch, steps=200)
     tune_s = time.time() - t1
+    print(f"# autotuned in {tune_s:.1f} s: {best['tile']} {best['grid']} {best['xcd']} {best['group_bytes']}",
+          file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ran = batch.run(400_000, tol=tol, use_graph=True)
@@ -189,7 +191,10 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
         del batch
         seq_seconds = 0.0
         seq_steps = []
-        for b, ns in zip(built, sets):
+        print(f"# batched run {dt:.2f} s; sequential runs follow", file=sys.stderr, flush=True)
+        for si, (b, ns) in enumerate(zip(built, sets)):
+            if si % 16 == 15:
+                print(f"# sequential {si + 1}/{len(sets)}", file=sys.stderr, flush=True)
             sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[b["perm"]], b["area"], variant=M.FIELDS,
                                storage=M.F32, tau_plus=1.0, g=(g, 0.0), tile=tile)
             sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
@@ -206,7 +211,7 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
     return out
 
 
-def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=400_000, tol=1e-6):
+def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_000_000, tol=1e-6, K=25):
     """Onset of inertia in the porous sample of Sec. 3.2: MLBM1 (tau = 1) on
     the hybrid porous channel at a fixed lattice forcing g_lb for a sweep of
     streaming distances dx, all of them in one batched launch (one sample per
@@ -217,14 +222,21 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=400_000, 
     t0 = time.time()
     ns = nodesets.porous_channel()
     dxs = [2e-3, 1.5e-3, 1e-3, 7e-4, 5e-4, 3e-4, 2e-4, 1.5e-4]
-    built = [M.build_stencils_for(ns, 16, dx, lattice_h=ns.h) for dx in dxs]
+    built = [M.build_stencils_for(ns, K, dx, lattice_h=ns.h) for dx in dxs]
     batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for b in built], variant=M.FIELDS, storage=M.F32,
                               tau_plus=1.0, g=(g_lb, 0.0), tile=256, check_every=100)
     batch.init_state([np.ones(ns.n)] * len(dxs), [np.zeros((ns.n, 2))] * len(dxs))
     setup = time.time() - t0
+    print(f"# darcy sweep: {len(dxs)} samples of {ns.n} nodes, setup {setup:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ran = batch.run(max_steps, tol=tol, use_graph=True)
+    ran = 0
+    while ran < max_steps:  # in slices, so progress shows
+        ran += batch.run(min(100_000, max_steps - ran), tol=tol, use_graph=True)
+        steps_now, _, _ = batch.results()
+        print(f"# {ran} steps, {int(np.sum(steps_now == 0))} samples running", file=sys.stderr, flush=True)
+        if not np.any(steps_now == 0):
+            break
     torch.cuda.synchronize()
     dt_run = time.perf_counter() - t1
     steps, res, _ = batch.results()
@@ -252,7 +264,7 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=400_000, 
     return {"metric": "Darcy deviation and tortuosity versus Re (MLBM1, batched sweep over dx)",
             "workload": f"porous channel (Sec. 3.2 arrangement): {ns.n} nodes, phi={phi:.3f}, {len(ns.disks)} disks, "
                         f"periodic x, no-slip walls y, hybrid lattice h={ns.h:g} / band nodes to h={ns.h_min:g}; "
-                        f"g_lb={g_lb:g}, K=16, residual {tol:g} or {max_steps} steps",
+                        f"g_lb={g_lb:g}, K={K}, residual {tol:g} or {max_steps} steps",
             "seconds": round(dt_run, 2), "steps_run": ran, "setup_s": round(setup, 1),
             "MNUPS_effective": round(float(np.sum(np.abs(steps) * ns.n)) / dt_run / 1e6, 1) if dt_run else None,
             "rows": rows}

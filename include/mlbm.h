@@ -85,12 +85,20 @@ typedef struct mlbm_stencil_params {
     double lattice_h;        /* > 0: hybrid set whose regular part is a square
                                 lattice of this spacing (K >= 10); 0: RBF-FD at
                                 every node                                         */
+    int32_t per_departure;   /* 1: one stencil per departure point, its K nearest
+                                nodes (the paper's stencils, Sec. 2.2); idx is then
+                                [n][8][K].  0: one stencil per node               */
+    int32_t simple_bounce_back; /* 1: a departure point inside a solid is replaced
+                                by the node itself (simple bounce-back, Sec. 3.1);
+                                0: by the mirrored point x + dx e_k              */
 } mlbm_stencil_params;
 
 /* Caller-allocated host outputs of mlbm_build_stencils. */
 typedef struct mlbm_stencils {
     int64_t *perm;           /* [n]       perm[new] = old                          */
-    int32_t *idx;            /* [n][K]    stencil members (new order), idx[i][0] = i */
+    int32_t *idx;            /* [n][K]    stencil members (new order), idx[i][0] = i;
+                                [n][8][K] with per_departure (the K nearest nodes of
+                                each departure point, nearest first)              */
     double *w;               /* [n][8][K] weights of arriving populations k = 1..8 */
     uint8_t *bb;             /* [n]       bit k-1 set: population k is rebuilt from
                                           source population k' (bounce-back)      */
@@ -188,7 +196,11 @@ int mlbm_mark_lagrange(int64_t n, const uint8_t *lagrange, uint16_t *flags);
  *                                 tile's halo (K8 = K rounded up to 8; padding
  *                                 members point at the node itself)
  * mlbm_tile_sizes returns total_halo and the largest halo.  idx is the
- * builder's [n][K] array.  Errors: MLBM_ERR_ARG.
+ * builder's [n][K] array (K <= 256 members per row).  For per-departure
+ * stencils pass the rows [n][8][K8] (each departure point's K members padded
+ * to K8 with the node itself) as K = 8 * K8: the planes of departure point k
+ * are then k * K8/8 .. (k + 1) * K8/8 - 1, the layout mlbm_step reads.
+ * Errors: MLBM_ERR_ARG.
  */
 int mlbm_tile_sizes(int64_t n, int32_t K, int32_t tile, const int32_t *idx, int64_t *total_halo,
                     int32_t *max_halo);
@@ -251,6 +263,12 @@ typedef struct mlbm_device_state {
                                 Batched runs use the packed weights throughout.   */
     uint64_t step_count;     /* steps taken (key of the stochastic rounding);
                                 mlbm_step adds nsteps                              */
+    int32_t per_departure;   /* 1: one stencil per departure point (builder's
+                                per_departure); needs tiles, lidx as described at
+                                mlbm_pack_tiles, weights packed as usual, idx the
+                                eight packed stencils one after another
+                                ([8][Kp/4][n][4], read by mlbm_macroscopic's
+                                wall force); not with w_lagrange or batched runs  */
 } mlbm_device_state;
 
 /*

@@ -37,7 +37,8 @@ class Geometry(ctypes.Structure):
 
 class StencilParams(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("reorder", ctypes.c_int32), ("dx", ctypes.c_double),
-                ("n_threads", ctypes.c_int32), ("lattice_h", ctypes.c_double)]
+                ("n_threads", ctypes.c_int32), ("lattice_h", ctypes.c_double),
+                ("per_departure", ctypes.c_int32), ("simple_bounce_back", ctypes.c_int32)]
 
 
 class Stencils(ctypes.Structure):
@@ -65,7 +66,7 @@ class DeviceState(ctypes.Structure):
                 ("flags", _p), ("bc", _p), ("state", _p * 2), ("cur", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("max_halo", ctypes.c_int32), ("halo_off", _p),
                 ("halo", _p), ("lidx", _p), ("w_lagrange", _p), ("lagrange_begin", ctypes.c_int64),
-                ("step_count", ctypes.c_uint64)]
+                ("step_count", ctypes.c_uint64), ("per_departure", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):

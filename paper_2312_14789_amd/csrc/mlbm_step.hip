@@ -675,6 +675,155 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_
     });
 }
 
+// ---- one stencil per departure point (the paper's stencils) ----------------------------
+//
+// Arriving population k has its own K members (its departure point's nearest
+// nodes), in index planes k * K8/8 .. (k + 1) * K8/8 - 1 of the tile-local
+// indices; from each member only one population (k, or k' on bounce-back) or
+// the fields are read.  LDS-staged tiles only.
+
+// population c of the staged node m
+template <int S, class CG>
+__device__ __forceinline__ CG load_comp(const void *src, int m, int c, float inv_scale) {
+    if constexpr (S == MLBM_F64) return ((const double *)src)[8 * m + c];
+    else if constexpr (S == MLBM_F32) return ((const float *)src)[8 * m + c];
+    else return dec16<S>(((const unsigned short *)src)[8 * m + c], inv_scale);
+}
+
+// four members of quad q of departure point k (plane k * k8q + q / 2)
+__device__ __forceinline__ void members_pd(const StepArgs &a, int64_t n, int64_t i, int plane, int half, u4 &lv,
+                                           int *m) {
+    if (half == 0) lv = stream_load((const u4 *)a.lidx + ((int64_t)plane * n + i), a.cached);
+    const unsigned lo = half ? lv.z : lv.x, hi = half ? lv.w : lv.y;
+    m[0] = (int)(lo & 0xffffu);
+    m[1] = (int)(lo >> 16);
+    m[2] = (int)(hi & 0xffffu);
+    m[3] = (int)(hi >> 16);
+}
+
+template <int S, class CG, class C, int KQ>
+__device__ __forceinline__ void pop_node_pd(const StepArgs &a, const void *src, int64_t i) {
+    constexpr int K8Q = (KQ + 1) / 2;  // index planes per departure point
+    const int64_t n = a.n;
+    const unsigned fl = a.flags[i];
+    const unsigned bb = fl & 0xffu;
+    C f[9];
+    if (kind_of(fl) == MLBM_DIRICHLET) {
+        const C rb = (C)a.bc[3 * i], ub = (C)a.bc[3 * i + 1], vb = (C)a.bc[3 * i + 2];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k] = feq_off<C>(k, C(1), rb - C(1), rb, ub, vb);
+    } else {
+        constexpr bool kWsum = S == MLBM_F64;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = ((bb >> k) & 1u) ? OPP8[k] : k;
+            CG acc = CG(0), sw = CG(0);
+            u4 lv;
+            for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = decltype(qc)::value;
+                int m[4];
+                members_pd(a, n, i, k * K8Q + (q >> 1), q & 1, lv, m);
+                CG wv[4];
+                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc = fma(wv[j], load_comp<S, CG>(src, m[j], c, a.inv_scale), acc);
+                    if constexpr (kWsum) sw += wv[j];
+                }
+            });
+            f[k + 1] = kWsum ? (C)acc + omega<C>(k + 1) * ((C)sw - C(1)) : (C)acc;
+        }
+        f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
+        collide<C>(f, (C)a.omp, (C)a.omm, (C)a.gx, (C)a.gy);
+    }
+    if (a.sr) {
+        const Rnd rnd = step_rnd(a, i);
+        store8<S>(a.out, i, f + 1, a.scale, rnd);
+        store1<S, C>(a.out, n, i, f[0], a.scale, rnd);
+    } else {
+        store8<S>(a.out, i, f + 1, a.scale);
+        store1<S, C>(a.out, n, i, f[0], a.scale);
+    }
+}
+
+template <int S, class CG, class C, int KQ>
+__global__ void __launch_bounds__(256) k_step_pop_pd(const StepArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int self0;
+    for_tiles(a, [&](int64_t tile) __attribute__((always_inline)) {
+        stage_halo<pop_bytes<S>(), false>(a, tile, smem, &self0);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) pop_node_pd<S, CG, C, KQ>(a, (const void *)smem, i);
+    });
+}
+
+template <int S, class CG, class C, int KQ>
+__device__ __forceinline__ void fields_node_pd(const StepArgs &a, const void *src, int64_t i) {
+    constexpr int K8Q = (KQ + 1) / 2;
+    const int64_t n = a.n;
+    const unsigned fl = a.flags[i];
+    const unsigned bb = fl & 0xffu;
+    C out[3];
+    if (kind_of(fl) == MLBM_DIRICHLET) {
+        out[0] = (C)a.bc[3 * i] - C(1);
+        out[1] = (C)a.bc[3 * i + 1];
+        out[2] = (C)a.bc[3 * i + 2];
+    } else {
+        constexpr bool kWsum = S == MLBM_F64;
+        const C gx = (C)a.gx, gy = (C)a.gy;
+        C own[3];
+        load3<S>(a.in, i, own, a.inv_scale);
+        C sum = feq_off<C>(0, C(1), own[0], C(1) + own[0], own[1], own[2]) +
+                C(0.5) * force_k<C>(0, C(1), C(1) + own[0], own[1], own[2], gx, gy);
+        C jx = C(0), jy = C(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            CG ar = CG(0), au = CG(0), av = CG(0), sw = CG(0);
+            u4 lv;
+            for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = decltype(qc)::value;
+                int mi[4];
+                members_pd(a, n, i, k * K8Q + (q >> 1), q & 1, lv, mi);
+                CG wv[4];
+                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    CG m[3];
+                    load3<S>(src, mi[j], m, a.inv_scale);
+                    ar = fma(wv[j], m[0], ar);
+                    au = fma(wv[j], m[1], au);
+                    av = fma(wv[j], m[2], av);
+                    if constexpr (kWsum) sw += wv[j];
+                }
+            });
+            if constexpr (kWsum) ar += sw - CG(1);
+            const C sg = ((bb >> k) & 1u) ? C(-1) : C(1);
+            const C dr = (C)ar, uk = (C)au, vk = (C)av;
+            const C rho = C(1) + dr;
+            const C fk = feq_off<C>(k + 1, sg, dr, rho, uk, vk) + C(0.5) * force_k<C>(k + 1, sg, rho, uk, vk, gx, gy);
+            sum += fk;
+            jx += C(EX[k + 1]) * fk;
+            jy += C(EY[k + 1]) * fk;
+        }
+        const C rho = C(1) + sum;
+        out[0] = sum;
+        out[1] = (jx + C(0.5) * rho * gx) / rho;
+        out[2] = (jy + C(0.5) * rho * gy) / rho;
+    }
+    store3<S>(a.out, i, out, a.scale, step_rnd(a, i));
+}
+
+template <int S, class CG, class C, int KQ>
+__global__ void __launch_bounds__(256) k_step_fields_pd(const StepArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int self0;
+    for_tiles(a, [&](int64_t tile) __attribute__((always_inline)) {
+        stage_halo<field_bytes<S>(), false>(a, tile, smem, &self0);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) fields_node_pd<S, CG, C, KQ>(a, (const void *)smem, i);
+    });
+}
+
 // ---- initial state -----------------------------------------------------------------
 
 struct InitArgs {
@@ -726,6 +875,7 @@ struct MacroArgs {
     double *ws;
     double gx, gy, inv_dx2;
     float inv_scale;
+    int pd;  // idx holds one stencil per departure point: [8][Kp/4][n][4]
 };
 
 // wave64 then workgroup tree sum in a fixed order; lane 0 of wave 0 holds the result
@@ -827,7 +977,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                     fout = (double)f[kp + 1];
                     double s = 0, sw = 0;
                     for (int q = 0; q < KQ; ++q) {
-                        const i4 id = load_idx4(a.idx, n, i, q);
+                        const i4 id = load_idx4(a.idx, n, i, a.pd ? k * KQ + q : q);
                         C wv[4];
                         load_w4<S, KQ>(a.w, n, i, k, q, wv);
                         const int ids[4] = {id.x, id.y, id.z, id.w};
@@ -845,7 +995,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                            0.5 * force_k<double>(kp + 1, 1.0, r0, (double)m[1], (double)m[2], a.gx, a.gy);
                     double ir = 0, iu = 0, iv = 0, sw = 0;
                     for (int q = 0; q < KQ; ++q) {
-                        const i4 id = load_idx4(a.idx, n, i, q);
+                        const i4 id = load_idx4(a.idx, n, i, a.pd ? k * KQ + q : q);
                         C wv[4];
                         load_w4<S, KQ>(a.w, n, i, k, q, wv);
                         const int ids[4] = {id.x, id.y, id.z, id.w};
@@ -949,6 +1099,38 @@ StepFn pick_step(int variant, int kq, bool lds) {
 // the collision (the interpolation in FP32 adds nothing measurable), and the
 // FP64 collision costs little in a kernel bound by memory traffic.  16-bit
 // states use FP32 throughout.
+template <int S, class CG, class C>
+StepFn pick_step_pd(int variant, int kq) {
+#define MLBM_CASE(Q)                                                                              \
+    case Q:                                                                                       \
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop_pd<S, CG, C, Q> : (StepFn)k_step_fields_pd<S, CG, C, Q>;
+    switch (kq) {
+        MLBM_CASE(2)
+        MLBM_CASE(3)
+        MLBM_CASE(4)
+        MLBM_CASE(5)
+        MLBM_CASE(6)
+        MLBM_CASE(7)
+        MLBM_CASE(8)
+        default:
+            return nullptr;
+    }
+#undef MLBM_CASE
+}
+
+// per-departure stencils: the same arithmetic choices as pick_step_any
+StepFn pick_step_pd_any(int storage, int variant, int kq, int fp32_arith) {
+    switch (storage) {
+        case MLBM_F64: return pick_step_pd<MLBM_F64, double, double>(variant, kq);
+        case MLBM_F32:
+            return fp32_arith ? pick_step_pd<MLBM_F32, float, float>(variant, kq)
+                              : pick_step_pd<MLBM_F32, float, double>(variant, kq);
+        case MLBM_F16S: return pick_step_pd<MLBM_F16S, float, float>(variant, kq);
+        case MLBM_BF16: return pick_step_pd<MLBM_BF16, float, float>(variant, kq);
+    }
+    return nullptr;
+}
+
 StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith, bool lds) {
     switch (storage) {
         case MLBM_F64: return pick_step<MLBM_F64, double, double>(variant, kq, lds);
@@ -1054,7 +1236,10 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
             return fail(MLBM_ERR_UNSUPPORTED, "halo of %d nodes needs %zu bytes of LDS (> 64 KiB); use tile 0 or a smaller tile",
                         st->max_halo, shmem);
     }
-    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith, lds);
+    if (st->per_departure && !lds) return fail(MLBM_ERR_UNSUPPORTED, "per-departure stencils need tiles");
+    if (st->per_departure && st->w_lagrange) return fail(MLBM_ERR_ARG, "per-departure stencils take no block weights");
+    StepFn fn = st->per_departure ? pick_step_pd_any(p->storage, p->variant, kq, p->fp32_arith)
+                                  : pick_step_any(p->storage, p->variant, kq, p->fp32_arith, lds);
     if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
         return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
@@ -1136,6 +1321,7 @@ extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_sta
     MacroArgs a;
     a.n = st->n;
     a.idx = (const int *)st->idx;
+    a.pd = st->per_departure ? 1 : 0;
     a.w = st->w;
     a.flags = st->flags;
     a.bc = st->bc;
@@ -1435,6 +1621,7 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     if (!(tol >= 0.0)) return fail(MLBM_ERR_ARG, "tol must be >= 0");
     if (use_graph && !stream) return fail(MLBM_ERR_ARG, "graph capture needs a non-default stream");
     const int kq = (st->K + 3) / 4;
+    if (st->per_departure) return fail(MLBM_ERR_UNSUPPORTED, "batched runs take one stencil per node");
     StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith, true);
     RedFn red = pick_red(p->storage, p->variant);
     if (!fn || !red) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);

@@ -106,6 +106,8 @@ struct Builder {
     CellGrid nodes, disks;
     double rmax = 0;
     double lat_h = 0;          // lattice spacing of the regular part (0: none)
+    bool per_departure = false;  // one stencil per departure point (else one per node)
+    bool simple_bb = false;      // bounce-back at the node itself (else the mirrored point)
     double wlag[8][9] = {};    // biquadratic Lagrange weights shared by block centres
 
     // ---- regular blocks of a hybrid set (Sec. 2.2) -------------------------
@@ -165,10 +167,27 @@ struct Builder {
     // ---- K nearest neighbours --------------------------------------------
     void nearest(int64_t i, std::vector<Cand> &cand, Cand *out) const { nearest_n(i, K, cand, out); }
 
-    void nearest_n(int64_t i, int K, std::vector<Cand> &cand, Cand *out) const {
+    // The K nearest nodes of the point x_i + (ox, oy); offsets are formed as
+    // (x_j - x_i) - o, so on a lattice every node's point sees the same
+    // offsets and ties.
+    void nearest_n(int64_t i, int K, std::vector<Cand> &cand, Cand *out, double ox = 0.0, double oy = 0.0) const {
         const double xi = g->xy[2 * i], yi = g->xy[2 * i + 1];
         cand.clear();
-        const int ci = nodes.cell_x(box, xi), cj = nodes.cell_y(box, yi);
+        double px = xi + ox, py = yi + oy, slack2 = 0.0;
+        for (int a = 0; a < 2; ++a) {
+            double &v = a ? py : px;
+            if (box.per[a]) {
+                v = box.lo[a] + std::fmod(v - box.lo[a], box.len[a]);
+                if (v < box.lo[a]) v += box.len[a];
+            } else {
+                // a point outside a non-periodic box: the ring search counts
+                // its radius from the box edge
+                const double out_d = std::max({box.lo[a] - v, 0.0, v - box.hi[a]});
+                slack2 += out_d * out_d;
+            }
+        }
+        const double slack = std::sqrt(slack2);
+        const int ci = nodes.cell_x(box, px), cj = nodes.cell_y(box, py);
         const double cmin = std::min(nodes.cx, nodes.cy);
         const int rmax_ring = std::max(nodes.nx, nodes.ny);
         bool brute = false;
@@ -191,6 +210,8 @@ struct Builder {
                         const int64_t j = nodes.items[q];
                         double ddx = g->xy[2 * j] - xi, ddy = g->xy[2 * j + 1] - yi;
                         min_image(box, ddx, ddy);
+                        ddx -= ox;
+                        ddy -= oy;
                         cand.push_back({ddx * ddx + ddy * ddy, ddx, ddy, j});
                     }
                 }
@@ -198,8 +219,8 @@ struct Builder {
             if ((int)cand.size() >= K) {
                 std::nth_element(cand.begin(), cand.begin() + (K - 1), cand.end(), cand_less);
                 const double kth = cand[K - 1].r2;
-                const double reach = r * cmin;
-                if (kth < reach * reach) break;
+                const double reach = r * cmin - slack;
+                if (reach > 0.0 && kth < reach * reach) break;
             }
         }
         if (brute) {
@@ -207,6 +228,8 @@ struct Builder {
             for (int64_t j = 0; j < g->n; ++j) {
                 double ddx = g->xy[2 * j] - xi, ddy = g->xy[2 * j + 1] - yi;
                 min_image(box, ddx, ddy);
+                ddx -= ox;
+                ddy -= oy;
                 cand.push_back({ddx * ddx + ddy * ddy, ddx, ddy, j});
             }
         }
@@ -291,8 +314,87 @@ struct Builder {
         }
     }
 
-    // Stencil, weights, bounce-back bits and unnormalised area of node i.
-    // Returns MLBM_OK or an error code with the message recorded in err.
+    // Local PHS3 + P2 fit (Sec. 2.2, Eq. 13) through K stencil members whose
+    // offsets from a common origin are given: coordinates scaled by the stencil
+    // radius, the saddle-point matrix factored on first use, then the weights
+    // of any evaluation point.
+    struct Fit {
+        int K = 0, m = 0;
+        double R = 0;
+        double A[(MAXK + NPOLY) * (MAXK + NPOLY)];
+        int piv[MAXK + NPOLY];
+        double xs[MAXK], ys[MAXK];
+        bool factored = false;
+
+        void setup(const Cand *st, int k_members) {
+            K = k_members;
+            m = K + NPOLY;
+            R = 0;
+            for (int j = 0; j < K; ++j) R = std::max(R, std::hypot(st[j].dx, st[j].dy));
+            for (int j = 0; j < K; ++j) {
+                xs[j] = st[j].dx / R;
+                ys[j] = st[j].dy / R;
+            }
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < m; ++c) A[r * m + c] = 0.0;
+            for (int r = 0; r < K; ++r) {
+                for (int c = 0; c < K; ++c) {
+                    const double rr = std::hypot(xs[r] - xs[c], ys[r] - ys[c]);
+                    A[r * m + c] = rr * rr * rr;
+                }
+                double p[NPOLY];
+                poly2(xs[r], ys[r], p);
+                for (int t = 0; t < NPOLY; ++t) {
+                    A[r * m + K + t] = p[t];
+                    A[(K + t) * m + r] = p[t];
+                }
+            }
+            factored = false;
+        }
+
+        // weights wk[K] of the point (ox, oy) (offset from the origin); returns
+        // MLBM_OK, MLBM_ERR_SINGULAR (system singular) or -100 (the quadratics
+        // are not reproduced)
+        int weights(double ox, double oy, double *wk) {
+            const double px = ox / R, py = oy / R;
+            int jn = 0;
+            double dn = std::numeric_limits<double>::infinity();
+            double rp[MAXK];
+            for (int j = 0; j < K; ++j) {
+                rp[j] = std::hypot(xs[j] - px, ys[j] - py);
+                if (rp[j] < dn) { dn = rp[j]; jn = j; }
+            }
+            if (dn < 1e-12) {  // evaluation point on a node: the value there
+                for (int j = 0; j < K; ++j) wk[j] = 0.0;
+                wk[jn] = 1.0;
+                return MLBM_OK;
+            }
+            if (!factored) {
+                if (!lu(A, piv, m)) return MLBM_ERR_SINGULAR;
+                factored = true;
+            }
+            double b[MAXK + NPOLY];
+            for (int j = 0; j < K; ++j) b[j] = rp[j] * rp[j] * rp[j];
+            poly2(px, py, b + K);
+            lu_solve(A, piv, m, b);
+            for (int j = 0; j < K; ++j) wk[j] = b[j];
+            double pe[NPOLY], acc[NPOLY] = {0, 0, 0, 0, 0, 0};
+            poly2(px, py, pe);
+            for (int j = 0; j < K; ++j) {
+                double pj[NPOLY];
+                poly2(xs[j], ys[j], pj);
+                for (int t = 0; t < NPOLY; ++t) acc[t] += wk[j] * pj[t];
+            }
+            for (int t = 0; t < NPOLY; ++t)
+                if (!(std::fabs(acc[t] - pe[t]) <= 1e-9)) return -100;
+            return MLBM_OK;
+        }
+    };
+
+    // Stencil(s), weights, bounce-back bits and unnormalised area of node i.
+    // st receives the members: K of them (shared stencil), or 8 x MAXK (one
+    // stencil per departure point, k-th at st + k * MAXK).  Returns MLBM_OK
+    // or an error code with the message in err.
     int node(int64_t i, bool lag, std::vector<Cand> &cand, Cand *st, double *w, uint8_t *bbits,
              double *area, std::string &err) const {
         nearest(i, cand, st);
@@ -316,89 +418,51 @@ struct Builder {
                 st[j].j = j < 9 ? mem[j] : i;
                 for (int k = 0; k < 8; ++k) w[(int64_t)k * K + j] = j < 9 ? wlag[k][j] : 0.0;
             }
+            if (per_departure)
+                for (int k = 1; k < 8; ++k) std::copy(st, st + K, st + k * MAXK);
             return MLBM_OK;
         }
-
-        double R = 0;
-        for (int j = 0; j < K; ++j) R = std::max(R, std::hypot(st[j].dx, st[j].dy));
-        const int m = K + NPOLY;
-        double A[(MAXK + NPOLY) * (MAXK + NPOLY)];
-        int piv[MAXK + NPOLY];
-        double xs[MAXK], ys[MAXK];
-        for (int j = 0; j < K; ++j) {
-            xs[j] = st[j].dx / R;
-            ys[j] = st[j].dy / R;
-        }
-        for (int r = 0; r < m; ++r)
-            for (int c = 0; c < m; ++c) A[r * m + c] = 0.0;
-        for (int r = 0; r < K; ++r) {
-            for (int c = 0; c < K; ++c) {
-                const double rr = std::hypot(xs[r] - xs[c], ys[r] - ys[c]);
-                A[r * m + c] = rr * rr * rr;
-            }
-            double p[NPOLY];
-            poly2(xs[r], ys[r], p);
-            for (int t = 0; t < NPOLY; ++t) {
-                A[r * m + K + t] = p[t];
-                A[(K + t) * m + r] = p[t];
-            }
-        }
-        bool factored = false;
+        // departure points and source populations (Sec. 2.2 Eq. 12; Sec. 3.2
+        // Eq. 22, or simple bounce-back at the node, Sec. 3.1)
         const double xi = g->xy[2 * i], yi = g->xy[2 * i + 1];
-        *bbits = 0;
+        double ox[8], oy[8];
         for (int k = 1; k <= 8; ++k) {
-            // departure point and source population (Sec. 2.2 Eq. 12, Sec. 3.2 Eq. 22)
-            double ox = -dx * EX[k], oy = -dx * EY[k];
-            if (inside_solid(xi + ox, yi + oy)) {
+            double a = -dx * EX[k], b = -dx * EY[k];
+            if (inside_solid(xi + a, yi + b)) {
                 *bbits |= (uint8_t)(1u << (k - 1));
-                if (!inside_solid(xi - ox, yi - oy)) {
-                    ox = -ox;
-                    oy = -oy;
+                if (!simple_bb && !inside_solid(xi - a, yi - b)) {
+                    a = -a;
+                    b = -b;
                 } else {
-                    ox = 0.0;
-                    oy = 0.0;
+                    a = 0.0;
+                    b = 0.0;
                 }
             }
-            const double px = ox / R, py = oy / R;
+            ox[k - 1] = a;
+            oy[k - 1] = b;
+        }
+        Fit fit;
+        if (!per_departure) fit.setup(st, K);
+        for (int k = 1; k <= 8; ++k) {
             double *wk = w + (int64_t)(k - 1) * K;
-            int jn = 0;
-            double dn = std::numeric_limits<double>::infinity();
-            double rp[MAXK];
-            for (int j = 0; j < K; ++j) {
-                rp[j] = std::hypot(xs[j] - px, ys[j] - py);
-                if (rp[j] < dn) { dn = rp[j]; jn = j; }
+            int rc;
+            if (per_departure) {
+                // the K nearest nodes of the departure point, weights at that point
+                Cand *stk = st + (k - 1) * MAXK;
+                nearest_n(i, K, cand, stk, ox[k - 1], oy[k - 1]);
+                fit.setup(stk, K);
+                rc = fit.weights(0.0, 0.0, wk);
+            } else {
+                rc = fit.weights(ox[k - 1], oy[k - 1], wk);
             }
-            if (dn < 1e-12) {  // evaluation point on a node: the value there
-                for (int j = 0; j < K; ++j) wk[j] = 0.0;
-                wk[jn] = 1.0;
-                continue;
+            if (rc == MLBM_ERR_SINGULAR) {
+                err = "singular interpolation system at node " + std::to_string(i);
+                return MLBM_ERR_SINGULAR;
             }
-            if (!factored) {
-                if (!lu(A, piv, m)) {
-                    err = "singular interpolation system at node " + std::to_string(i);
-                    return MLBM_ERR_SINGULAR;
-                }
-                factored = true;
-            }
-            double b[MAXK + NPOLY];
-            for (int j = 0; j < K; ++j) b[j] = rp[j] * rp[j] * rp[j];
-            poly2(px, py, b + K);
-            lu_solve(A, piv, m, b);
-            for (int j = 0; j < K; ++j) wk[j] = b[j];
-            // reproduction of the quadratics at the evaluation point
-            double pe[NPOLY], acc[NPOLY] = {0, 0, 0, 0, 0, 0};
-            poly2(px, py, pe);
-            for (int j = 0; j < K; ++j) {
-                double pj[NPOLY];
-                poly2(xs[j], ys[j], pj);
-                for (int t = 0; t < NPOLY; ++t) acc[t] += wk[j] * pj[t];
-            }
-            for (int t = 0; t < NPOLY; ++t) {
-                if (!(std::fabs(acc[t] - pe[t]) <= 1e-9)) {
-                    err = "interpolation at node " + std::to_string(i) + ", k=" + std::to_string(k) +
-                          " does not reproduce quadratics";
-                    return MLBM_ERR_SINGULAR;
-                }
+            if (rc != MLBM_OK) {
+                err = "interpolation at node " + std::to_string(i) + ", k=" + std::to_string(k) +
+                      " does not reproduce quadratics";
+                return MLBM_ERR_SINGULAR;
             }
         }
         return MLBM_OK;
@@ -438,6 +502,8 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
     B.K = p->K;
     B.dx = p->dx;
     B.lat_h = p->lattice_h;
+    B.per_departure = p->per_departure != 0;
+    B.simple_bb = p->simple_bounce_back != 0;
     if (B.lat_h > 0.0) B.lagrange_table();
     for (int a = 0; a < 2; ++a) {
         B.box.lo[a] = g->lo[a];
@@ -520,8 +586,9 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
     int err_code = MLBM_OK;
     std::string err_msg;
     const int K = p->K;
+    const int P = B.per_departure ? 8 : 1;
     parallel([&](int64_t a, int64_t b, std::vector<Cand> &cand) {
-        Cand st[MAXK];
+        Cand st[8 * MAXK];
         for (int64_t inew = a; inew < b; ++inew) {
             const int64_t i = perm[inew];
             std::string msg;
@@ -533,7 +600,8 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
                 if (i < err_node) { err_node = i; err_code = rc; err_msg = msg; }
                 continue;
             }
-            for (int j = 0; j < K; ++j) out->idx[inew * K + j] = (int32_t)inv[st[j].j];
+            for (int k = 0; k < P; ++k)
+                for (int j = 0; j < K; ++j) out->idx[(inew * P + k) * K + j] = (int32_t)inv[st[k * MAXK + j].j];
             out->bb[inew] = bits;
             out->area[inew] = area;
             out->perm[inew] = i;
@@ -655,7 +723,7 @@ extern "C" int mlbm_tile_sizes(int64_t n, int32_t K, int32_t tile, const int32_t
     using mlbm::fail;
     mlbm::clear_error();
     if (!idx || !total_halo || !max_halo) return fail(MLBM_ERR_ARG, "null pointer argument");
-    if (n < 1 || K < 1 || K > MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
+    if (n < 1 || K < 1 || K > 8 * MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
     if (tile != 64 && tile != 128 && tile != 256) return fail(MLBM_ERR_ARG, "tile must be 64, 128 or 256");
     const int64_t nt = (n + tile - 1) / tile;
     int64_t tot = 0;
@@ -676,7 +744,7 @@ extern "C" int mlbm_pack_tiles(int64_t n, int32_t K, int32_t tile, const int32_t
     using mlbm::fail;
     mlbm::clear_error();
     if (!idx || !halo_off || !halo || !lidx) return fail(MLBM_ERR_ARG, "null pointer argument");
-    if (n < 1 || K < 1 || K > MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
+    if (n < 1 || K < 1 || K > 8 * MAXK) return fail(MLBM_ERR_ARG, "bad n or K");
     if (tile != 64 && tile != 128 && tile != 256) return fail(MLBM_ERR_ARG, "tile must be 64, 128 or 256");
     const int64_t nt = (n + tile - 1) / tile;
     const int k8 = (K + 7) / 8 * 8;

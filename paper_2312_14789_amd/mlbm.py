@@ -42,31 +42,36 @@ def geometry_struct(xy, kind, lo, hi, periodic, walls_y=(False, False), disks=No
 
 
 def build_stencils(xy, kind, lo, hi, periodic, K, dx, walls_y=(False, False), disks=None,
-                   fluid_area=0.0, reorder=1, n_threads=0, lattice_h=0.0) -> dict:
-    """mlbm_build_stencils: returns perm (n,), idx (n, K), w (n, 8, K), bb (n,),
-    area (n,), lagrange (n,) uint8, w_lagrange (8, 9) and n_lagrange
-    (lattice_h > 0: hybrid set, block centres use the shared weights)."""
+                   fluid_area=0.0, reorder=1, n_threads=0, lattice_h=0.0, per_departure=False,
+                   simple_bounce_back=False) -> dict:
+    """mlbm_build_stencils: returns perm (n,), idx (n, K) (per_departure:
+    (n, 8, K)), w (n, 8, K), bb (n,), area (n,), lagrange (n,) uint8,
+    w_lagrange (8, 9) and n_lagrange (lattice_h > 0: hybrid set, block
+    centres use the shared weights)."""
     g, keep = geometry_struct(xy, kind, lo, hi, periodic, walls_y, disks, fluid_area)
     n = g.n
-    out = {"perm": np.zeros(n, np.int64), "idx": np.zeros((n, K), np.int32),
+    out = {"perm": np.zeros(n, np.int64), "idx": np.zeros((n, 8, K) if per_departure else (n, K), np.int32),
            "w": np.zeros((n, 8, K), np.float64), "bb": np.zeros(n, np.uint8),
            "area": np.zeros(n, np.float64), "lagrange": np.zeros(n, np.uint8),
            "w_lagrange": np.zeros((8, 9), np.float64)}
     st = Stencils(_ptr(out["perm"]), _ptr(out["idx"]), _ptr(out["w"]), _ptr(out["bb"]), _ptr(out["area"]),
                   _ptr(out["lagrange"]), _ptr(out["w_lagrange"]), 0)
-    p = StencilParams(K=K, reorder=reorder, dx=float(dx), n_threads=n_threads, lattice_h=float(lattice_h))
+    p = StencilParams(K=K, reorder=reorder, dx=float(dx), n_threads=n_threads, lattice_h=float(lattice_h),
+                      per_departure=int(bool(per_departure)), simple_bounce_back=int(bool(simple_bounce_back)))
     check(lib.mlbm_build_stencils(ctypes.byref(g), ctypes.byref(p), ctypes.byref(st)))
     out["n_lagrange"] = int(st.n_lagrange)
     del keep
     return out
 
 
-def build_stencils_for(ns, K, dx, reorder=1, n_threads=0, lattice_h=0.0) -> dict:
+def build_stencils_for(ns, K, dx, reorder=1, n_threads=0, lattice_h=0.0, per_departure=False,
+                       simple_bounce_back=False) -> dict:
     """build_stencils for an object carrying xy, kind, lo, hi, periodic,
     walls_y, disks and fluid_area()."""
     return build_stencils(ns.xy, ns.kind, ns.lo, ns.hi, ns.periodic, K, dx, walls_y=ns.walls_y,
                           disks=ns.disks, fluid_area=ns.fluid_area(), reorder=reorder,
-                          n_threads=n_threads, lattice_h=lattice_h)
+                          n_threads=n_threads, lattice_h=lattice_h, per_departure=per_departure,
+                          simple_bounce_back=simple_bounce_back)
 
 
 def mark_lagrange(lagrange, flags):
@@ -99,8 +104,15 @@ def pack_stencils(idx, w, bb, kind, storage):
 
 
 def pack_tiles(idx, tile):
-    """mlbm_tile_sizes + mlbm_pack_tiles: (halo_off, halo, lidx, max_halo)."""
+    """mlbm_tile_sizes + mlbm_pack_tiles: (halo_off, halo, lidx, max_halo).
+    idx (n, K), or (n, 8, K) for per-departure stencils (each departure
+    point's members padded to a multiple of 8 with the node itself)."""
     idx = np.ascontiguousarray(idx, dtype=np.int32)
+    if idx.ndim == 3:
+        n, _, K = idx.shape
+        k8 = (K + 7) // 8 * 8
+        pad = np.repeat(np.arange(n, dtype=np.int32)[:, None, None], 8, axis=1)
+        idx = np.concatenate([idx, np.repeat(pad, k8 - K, axis=2)], axis=2).reshape(n, 8 * k8)
     n, K = idx.shape
     total = ctypes.c_int64()
     mx = ctypes.c_int32()
@@ -127,9 +139,19 @@ class Simulation:
         import torch
 
         self.torch = torch
-        n, K = np.asarray(idx).shape
+        idx = np.asarray(idx)
+        self.per_departure = idx.ndim == 3
+        n, K = idx.shape[0], idx.shape[-1]
         self.n, self.K = n, K
-        ip, wp, fl = pack_stencils(idx, w, bb, kind, storage) if packed is None else packed
+        if packed is not None:
+            ip, wp, fl = packed
+        elif self.per_departure:
+            # the eight stencils' packed indices one after another, weights as usual
+            parts = [pack_stencils(idx[:, k, :], w, bb, kind, storage) for k in range(8)]
+            ip = np.concatenate([p_[0] for p_ in parts])
+            wp, fl = parts[0][1], parts[0][2]
+        else:
+            ip, wp, fl = pack_stencils(idx, w, bb, kind, storage)
         self.sizes = packed_sizes(n, K, variant, storage)
         dev = torch.device(device)
         self.wl_d = None
@@ -178,6 +200,7 @@ class Simulation:
         self.ds.cur = 0
         self.ds.w_lagrange = self.wl_d.data_ptr() if self.wl_d is not None else None
         self.ds.lagrange_begin = self.lagrange_begin
+        self.ds.per_departure = int(self.per_departure)
         self.set_tile(tile, idx)
 
     def set_tile(self, tile, idx=None):
@@ -290,6 +313,8 @@ class BatchSimulation:
         import torch
 
         self.torch = torch
+        if any(np.asarray(st["idx"]).ndim != 2 for st, _, _ in samples):
+            raise ValueError("batched runs take one stencil per node (no per-departure stencils)")
         K = samples[0][0]["idx"].shape[1]
         sizes = [st["idx"].shape[0] for st, _, _ in samples]
         pad = self.PAD  # a multiple of every tile size, so any tile stays in one sample

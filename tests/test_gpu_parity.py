@@ -93,6 +93,30 @@ def _case(name):
         ns, st = lagrange_last(ns, omlbm.build_stencils(ns, 16, dx, lattice_h=ns.h))
         rho0, u0 = initial_fields(ns, 18, 0.01, 0.002)
         c = (ns, st, 1, 1.0, 1.0, (1e-5, 2e-6), 300, rho0, u0, dx)
+    elif name == "pd_tgv":           # the paper's stencils: 25 nearest nodes of each departure point
+        ns = nodesets.jittered_grid(48, seed=19)
+        dx = 1.0 / 48 / 1.5
+        st = omlbm.build_stencils(ns, 25, dx, per_departure=True)
+        k = 2 * np.pi
+        x, y = ns.xy[:, 0], ns.xy[:, 1]
+        u0 = np.stack([0.01 * np.sin(k * x) * np.cos(k * y), -0.01 * np.cos(k * x) * np.sin(k * y)], 1)
+        rho0 = 1 - (0.01 ** 2 / (4 * lt.CS2)) * (np.cos(2 * k * x) + np.cos(2 * k * y))
+        c = (ns, st, 0, 0.8, 0.8, (0.0, 0.0), 300, rho0, u0, dx)
+    elif name == "pd_karman_trt":    # per-departure stencils, TRT Lambda = 3/16, simple bounce-back
+        ns = nodesets.karman(n_target=3000, seed=20)
+        dx = ns.h / 2
+        st = omlbm.build_stencils(ns, 25, dx, per_departure=True, simple_bb=True)
+        rho0, u0 = initial_fields(ns, 21, 0.02, 0.0)
+        rho0[:] = 1.0
+        u0[ns.kind != nodesets.DIRICHLET] = 0.0
+        tp = 0.6
+        c = (ns, st, 0, tp, lt.tau_minus_from_lambda(tp, 3 / 16), (0.0, 0.0), 200, rho0, u0, dx)
+    elif name == "pd_porous_fields":  # MLBM1 with per-departure stencils, grains, force
+        ns = nodesets.porous(2500, phi=0.7, seed=22, r_range=(0.05, 0.09))
+        dx = ns.h / 1.5
+        st = omlbm.build_stencils(ns, 16, dx, per_departure=True)
+        rho0, u0 = initial_fields(ns, 23, 0.01, 0.002)
+        c = (ns, st, 1, 1.0, 1.0, (1e-5, 2e-6), 200, rho0, u0, dx)
     else:
         raise KeyError(name)
     ns, st, var, tp, tm, g, steps, rho0, u0, dx = c
@@ -147,6 +171,26 @@ def test_block_centre_kernel_equals_per_node_weights(M, name, storage, tile):
     print(f"[block] case={name} storage={storage} tile={tile} block centres from {sim.lagrange_begin} "
           f"rel_l2_u={err:.3e}", flush=True)
     assert err <= {0: 1e-13, 1: 1e-6, 2: 1e-3}[storage]
+
+
+@pytest.mark.parametrize("name", ["pd_tgv", "pd_karman_trt", "pd_porous_fields"])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_per_departure_step_parity(M, name, storage):
+    print(f"[parity-pd] case={name} storage={storage}", flush=True)
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, r_ref, u_ref, _ = _case(name)
+    _, rho, u, red = _run_gpu(M, name, storage, tile=256)
+    err = rel_l2(u, u_ref)
+    print(f"[parity-pd] case={name} storage={storage} rel_l2_u={err:.3e}", flush=True)
+    assert err <= BAR[storage]
+    assert red[8] == 0
+
+
+def test_per_departure_needs_tiles(M):
+    ns, st, var, tp, tm, g, *_ = _case("pd_tgv")
+    with pytest.raises(M.MlbmError):
+        sim = sim_from_oracle(M, ns, st, var, 1, tp, tm, g, tile=0)
+        sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+        sim.step(1)
 
 
 def test_tgv_amplitude_matches_closed_form(M):

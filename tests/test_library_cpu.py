@@ -71,6 +71,21 @@ def test_builder_matches_oracle(case):
     assert abs(b["area"].sum() - ns.fluid_area()) < 1e-12 * ns.fluid_area()
 
 
+@pytest.mark.parametrize("case,simple_bb", [("jittered", False), ("channel", False), ("karman", True),
+                                            ("porous", False)])
+def test_builder_matches_oracle_per_departure(case, simple_bb):
+    # one stencil per departure point (the paper's), mirrored or simple bounce-back
+    ns, K, dx, *_ = CASES[case]()
+    dx = ns.h / 2.0 if dx is None else dx
+    b = M.build_stencils_for(ns, K, dx, per_departure=True, simple_bounce_back=simple_bb, n_threads=4)
+    st = omlbm.build_stencils(ns, K, dx, per_departure=True, simple_bb=simple_bb)
+    perm = b["perm"]
+    assert b["idx"].shape == (ns.n, 8, K)
+    np.testing.assert_array_equal(perm[b["idx"]], st.idx[perm])
+    np.testing.assert_array_equal(b["bb"], _oracle_bb(st)[perm])
+    np.testing.assert_allclose(b["w"], st.w[perm], atol=1e-10, rtol=0)
+
+
 def test_builder_is_deterministic_across_thread_counts():
     ns = nodesets.porous(3000, seed=9, r_range=(0.04, 0.08))
     a = M.build_stencils_for(ns, 16, ns.h / 3, n_threads=1)
