@@ -270,6 +270,72 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_000_000
             "rows": rows}
 
 
+def strouhal_workload(M, units, nodesets, np, torch, reynolds=(105, 126, 147, 168), periods=10, transient=10,
+                      every=50):
+    """The paper's cylinder flow (Sec. 3.1) in its own configuration: 3 x 1
+    channel, d = 0.14, U0 = 0.01, TRT with tau+ = 0.53 and Lambda = 3/16,
+    one 25-node stencil per departure point, biquadratic Lagrange on the
+    lattice part, simple bounce-back on the cylinder; Re = U0 d / nu raised by
+    shrinking dx (Sec. 2.3).  The lift (momentum exchange on the cylinder) is
+    sampled every `every` steps; after `transient` shedding periods its
+    dominant frequency over `periods` periods gives St = f d / U0 (lattice
+    units: f in cycles per step, d in streaming distances)."""
+    ns = nodesets.karman_paper()
+    d, u0, tau = 0.14, 1e-2, 0.53
+    tau_m = 0.5 + (3.0 / 16.0) / (tau - 0.5)
+    nu_lb = units.nu_lattice(tau)
+    rows = []
+    total_updates, total_s = 0, 0.0
+    for re in reynolds:
+        dx = u0 * d / (re * nu_lb)
+        b = M.build_stencils_for(ns, 25, dx, lattice_h=ns.h, per_departure=True, simple_bounce_back=True)
+        perm = b["perm"]
+        sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
+                           storage=M.F32, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm], tile=256)
+        # at rest, boundary values on the Dirichlet nodes, and a small transverse
+        # kick behind the cylinder so the shedding does not wait for round-off
+        xy = ns.xy[perm]
+        u = np.zeros((ns.n, 2))
+        wake = (xy[:, 0] > 0.6) & (xy[:, 0] < 1.0) & (np.abs(xy[:, 1] - 0.5) < 0.1)
+        u[wake, 1] = 0.1 * u0
+        dmask = ns.kind[perm] == nodesets.DIRICHLET
+        u[dmask] = ns.boundary_values()[perm][dmask, 1:3]
+        sim.init_state(np.ones(ns.n), u)
+        t_shed = (d / dx) / (0.2 * u0)  # steps per period for St ~ 0.2
+        n_samples = int((transient + periods) * t_shed / every)
+        lift = np.zeros(n_samples)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(n_samples):
+            sim.step(every)
+            _, _, red = sim.macroscopic(dx, want_fields=False)
+            lift[s_] = float(red[M._lib.RED_FORCE_Y].item())
+            if s_ % 2000 == 1999:
+                print(f"# Re {re}: {s_ + 1}/{n_samples} lift samples", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, _, red = sim.macroscopic(dx, want_fields=False)
+        bad = int(red[M._lib.RED_N_BAD].item())
+        tail = lift[int(transient * t_shed / every):]
+        tail = tail - tail.mean()
+        spec = np.abs(np.fft.rfft(tail * np.hanning(len(tail)), n=8 * len(tail)))
+        freqs = np.fft.rfftfreq(8 * len(tail), d=every)
+        f = freqs[int(np.argmax(spec[1:]) + 1)]
+        st = f * (d / dx) / u0
+        n_steps = n_samples * every
+        total_updates += n_steps * ns.n
+        total_s += dt
+        rows.append({"Re": re, "dx": dx, "s_min": round(ns.h_min / dx, 3), "s_max": round(ns.h / dx, 3),
+                     "steps": n_steps, "St": round(float(st), 4), "lift_amplitude": float(np.abs(tail).max()),
+                     "unstable_nodes": bad, "seconds": round(dt, 2), "MNUPS": round(ns.n * n_steps / dt / 1e6, 1)})
+        print(f"# Re {re}: St {st:.4f}, {dt:.1f} s", file=sys.stderr, flush=True)
+        del sim
+    return {"metric": "Strouhal number of the cylinder wake vs Re (the paper's configuration)",
+            "workload": f"3x1 channel, d=0.14, {ns.n} hybrid nodes (h {ns.h_min:g}..{ns.h:g}, symmetric), "
+                        f"TRT tau+=0.53 Lambda=3/16, per-departure K=25 stencils, simple bounce-back, FP32",
+            "rows": rows, "MNUPS_mean": round(total_updates / total_s / 1e6, 1) if total_s else None}
+
+
 def warmstart_workload(args, np, torch):
     """Learned warm start (network of 5 levels, 32-256 channels, 256^2 rasters):
     train on steady states of random-disk media computed by batched library
@@ -355,10 +421,11 @@ def main():
                          "Lagrange weights at the block centres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
-    ap.add_argument("--workload", default="karman", choices=["karman", "batched", "warmstart", "darcy"],
+    ap.add_argument("--workload", default="karman", choices=["karman", "batched", "warmstart", "darcy", "strouhal"],
                     help="karman: the fused-step throughput line; batched: 64 porous samples to steady "
                          "state; warmstart: train the warm-start network and compare time to steady state; "
-                         "darcy: mean velocity and tortuosity of the porous channel over a sweep of dx")
+                         "darcy: mean velocity and tortuosity of the porous channel over a sweep of dx; "
+                         "strouhal: the paper's cylinder channel, St from the lift over Re 105-168")
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-test", type=int, default=200)
     ap.add_argument("--ws-epochs", type=int, default=20)
@@ -391,6 +458,9 @@ def main():
         return
     if args.workload == "darcy":
         print(json.dumps(darcy_workload(M, units, nodesets, np, torch)), flush=True)
+        return
+    if args.workload == "strouhal":
+        print(json.dumps(strouhal_workload(M, units, nodesets, np, torch)), flush=True)
         return
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]

@@ -293,6 +293,80 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
                    h_min=hf)
 
 
+def karman_paper(h_min: float = 1.0 / 200, h_max: float = 1.0 / 25, grade: float = 0.3,
+                 wake_stretch: float = 0.1, d: float = 0.14, u0: float = 1e-2,
+                 seed: int = 231214789) -> NodeSet:
+    """The cylinder channel of Sec. 3.1: a 3 x 1 channel with a cylinder of
+    diameter d on the axis, 0.5 from the inlet; parabolic inflow/outflow with
+    maximum u0 and zero velocity on the top and bottom, all four sides by
+    equilibrium overwrite (Dirichlet nodes), the cylinder no-slip.  Hybrid
+    nodes, symmetric about the channel axis (built in the upper half and
+    mirrored): scattered around the cylinder and in its wake, their spacing
+    growing from h_min on the cylinder surface to h_max at a distance `grade`
+    (the wake distance counted wake_stretch times shorter), and a square
+    lattice of spacing h_max elsewhere (aligned with the channel sides, which
+    carry the Dirichlet nodes)."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly = 3.0, 1.0
+    cx, cy, R = 0.5, 0.5, 0.5 * d
+    lo, hi = np.zeros(2), np.array([Lx, Ly])
+
+    def reach(pts):
+        dxw = pts[:, 0] - cx
+        dxw = np.where(dxw > 0, dxw * wake_stretch, dxw)
+        return np.hypot(dxw, pts[:, 1] - cy) - R
+
+    def spacing(pts):
+        return h_min + (h_max - h_min) * np.clip(reach(pts) / grade, 0.0, 1.0)
+
+    # lattice at h_max (cell vertices, upper half including the axis row)
+    nx, ny = int(round(Lx / h_max)), int(round(Ly / h_max))
+    X, Y = np.meshgrid(np.arange(nx + 1) * (Lx / nx), np.arange(ny + 1) * (Ly / ny), indexing="xy")
+    lat = np.stack([X.ravel(), Y.ravel()], axis=1)
+    lat = lat[lat[:, 1] >= cy - 1e-12]
+    edge = (lat[:, 0] == 0.0) | (lat[:, 0] == Lx) | (lat[:, 1] == Ly)
+    bnd = lat[edge]
+    lat = lat[~edge]
+    lat = lat[reach(lat) > grade]
+    # graded zone: jittered candidates at h_min, thinned to density 1/h^2
+    zlo = np.array([cx - R - grade - h_max, cy])
+    zhi = np.array([min(Lx - h_max, cx + (R + grade) / wake_stretch + h_max), cy + R + grade + h_max])
+    cand = _grid(zlo, zhi, h_min)
+    cand = cand + rng.uniform(-0.3 * h_min, 0.3 * h_min, size=cand.shape)
+    inside = (cand[:, 0] > 0.5 * h_max) & (cand[:, 0] < Lx - 0.5 * h_max) & (cand[:, 1] < Ly - 0.5 * h_max)
+    cand = cand[inside & (reach(cand) <= grade) & (np.hypot(cand[:, 0] - cx, cand[:, 1] - cy) > R + 0.5 * h_min)]
+    cand = cand[rng.uniform(size=len(cand)) < (h_min / spacing(cand)) ** 2]
+    # keep clear of the axis (half the clean-up distance) so the mirror image does not collide
+    cand = cand[cand[:, 1] - cy > 0.25 * spacing(cand)]
+    ax_up = np.arange(max(cx - R - grade, 0.5 * h_max), cx - R - 0.5 * h_min, h_min)
+    ax_dn = np.arange(cx + R + h_min, min(Lx - h_max, cx + (R + grade) / wake_stretch), h_min)
+    axis = np.stack([np.concatenate([ax_up, ax_dn]), np.full(len(ax_up) + len(ax_dn), cy)], 1)
+    axis = axis[rng.uniform(size=len(axis)) < h_min / spacing(axis)]
+    m = int(np.ceil(np.pi * d / h_min / 2.0))
+    ang = np.linspace(0.0, np.pi, m + 1)
+    surf = np.stack([cx + R * np.cos(ang), cy + R * np.sin(ang)], 1)
+    xy = np.concatenate([lat, cand, axis, surf, bnd])
+    kind = np.concatenate([np.zeros(len(lat) + len(cand) + len(axis), np.uint8), np.full(len(surf), WALL, np.uint8),
+                           np.full(len(bnd), DIRICHLET, np.uint8)])
+    hloc = np.concatenate([np.full(len(lat), h_max), spacing(cand), spacing(axis), np.full(len(surf), h_min),
+                           np.full(len(bnd), h_max)])
+    fixed = np.concatenate([np.ones(len(lat), bool), np.zeros(len(cand) + len(axis), bool),
+                            np.ones(len(surf) + len(bnd), bool)])
+    keep = _cleanup(xy, hloc, fixed, lo, hi, (False, False), frac=0.45)
+    xy, kind = xy[keep], kind[keep]
+    # mirror everything off the axis
+    off = xy[:, 1] > cy + 1e-12
+    xy = np.concatenate([xy, xy[off] * [1.0, -1.0] + [0.0, 2.0 * cy]])
+    kind = np.concatenate([kind, kind[off]])
+    bc = np.zeros((len(xy), 3))
+    bc[:, 0] = 1.0
+    inout = (kind == DIRICHLET) & (np.isclose(xy[:, 0], 0.0) | np.isclose(xy[:, 0], Lx))
+    y = xy[:, 1]
+    bc[inout, 1] = 4.0 * u0 * y[inout] * (Ly - y[inout]) / Ly ** 2
+    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(False, False), disks=np.array([[cx, cy, R]]), bc=bc,
+                   h=h_max, name="karman-paper", h_min=h_min)
+
+
 def random_disks(phi_target: float, r_min: float, r_max: float, gap: float,
                  rng, L: float = 1.0, max_tries: int = 200_000) -> np.ndarray:
     """Random sequential addition of non-overlapping disks in the periodic box
