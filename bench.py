@@ -159,7 +159,12 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
 
     t0 = time.time()
     sets = nodesets.porous_batch(n_samples, n_range=n_range)
-    built = [M.build_stencils_for(ns, 16, ns.h) for ns in sets]
+    print(f"# {n_samples} porous samples generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    built = []
+    for si, ns in enumerate(sets):
+        built.append(M.build_stencils_for(ns, 16, ns.h))
+        if si % 32 == 31:
+            print(f"# stencils {si + 1}/{n_samples}", file=sys.stderr, flush=True)
     batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for b, ns in zip(built, sets)], variant=M.FIELDS,
                               storage=M.F32, tau_plus=1.0, g=(g, 0.0), tile=256, check_every=100)
     setup = time.time() - t0

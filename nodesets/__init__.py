@@ -293,6 +293,47 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
                    h_min=hf)
 
 
+def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_cand: int = 12) -> np.ndarray:
+    """Poisson-disk node placement by advancing fronts (after Slak & Kosec,
+    2019): every node of the current front proposes n_cand candidates on the
+    circle of radius h(p) around itself (random rotation); a candidate is kept
+    if admit() accepts it and no node, old or newly kept, lies closer than
+    0.99 h(p).  The kept candidates form the next front.  Returns the new
+    nodes only (fixed and seeds are taken as already placed)."""
+    from scipy.spatial import cKDTree
+
+    placed = np.concatenate([fixed, seeds])
+    front = seeds
+    out = []
+    ang0 = 2.0 * np.pi * np.arange(n_cand) / n_cand
+    while len(front):
+        hp = spacing(front)
+        rot = rng.uniform(0.0, 2.0 * np.pi, size=len(front))
+        a = rot[:, None] + ang0[None, :]
+        cand = (front[:, None, :] + hp[:, None, None] * np.stack([np.cos(a), np.sin(a)], -1)).reshape(-1, 2)
+        hc = np.repeat(hp, n_cand)
+        ok = admit(cand)
+        cand, hc = cand[ok], hc[ok]
+        if len(cand) == 0:
+            break
+        dist, _ = cKDTree(placed).query(cand)
+        ok = dist >= 0.99 * hc
+        cand, hc = cand[ok], hc[ok]
+        if len(cand) == 0:
+            break
+        # greedy among the candidates themselves, in proposal order
+        tree = cKDTree(cand)
+        nbrs = tree.query_ball_point(cand, r=0.99 * hc)
+        taken = np.zeros(len(cand), bool)
+        for i in range(len(cand)):
+            if not any(taken[j] for j in nbrs[i] if j != i):
+                taken[i] = True
+        front = cand[taken]
+        out.append(front)
+        placed = np.concatenate([placed, front])
+    return np.concatenate(out) if out else np.zeros((0, 2))
+
+
 def karman_paper(h_min: float = 1.0 / 200, h_max: float = 1.0 / 25, grade: float = 0.3,
                  wake_stretch: float = 0.1, d: float = 0.14, u0: float = 1e-2,
                  seed: int = 231214789) -> NodeSet:
@@ -328,23 +369,28 @@ def karman_paper(h_min: float = 1.0 / 200, h_max: float = 1.0 / 25, grade: float
     bnd = lat[edge]
     lat = lat[~edge]
     lat = lat[reach(lat) > grade]
-    # graded zone: jittered candidates at h_min, thinned to density 1/h^2
-    zlo = np.array([cx - R - grade - h_max, cy])
-    zhi = np.array([min(Lx - h_max, cx + (R + grade) / wake_stretch + h_max), cy + R + grade + h_max])
-    cand = _grid(zlo, zhi, h_min)
-    cand = cand + rng.uniform(-0.3 * h_min, 0.3 * h_min, size=cand.shape)
-    inside = (cand[:, 0] > 0.5 * h_max) & (cand[:, 0] < Lx - 0.5 * h_max) & (cand[:, 1] < Ly - 0.5 * h_max)
-    cand = cand[inside & (reach(cand) <= grade) & (np.hypot(cand[:, 0] - cx, cand[:, 1] - cy) > R + 0.5 * h_min)]
-    cand = cand[rng.uniform(size=len(cand)) < (h_min / spacing(cand)) ** 2]
-    # keep clear of the axis (half the clean-up distance) so the mirror image does not collide
-    cand = cand[cand[:, 1] - cy > 0.25 * spacing(cand)]
-    ax_up = np.arange(max(cx - R - grade, 0.5 * h_max), cx - R - 0.5 * h_min, h_min)
-    ax_dn = np.arange(cx + R + h_min, min(Lx - h_max, cx + (R + grade) / wake_stretch), h_min)
-    axis = np.stack([np.concatenate([ax_up, ax_dn]), np.full(len(ax_up) + len(ax_dn), cy)], 1)
-    axis = axis[rng.uniform(size=len(axis)) < h_min / spacing(axis)]
+    # the cylinder surface (upper half) and the axis, each at the local spacing
     m = int(np.ceil(np.pi * d / h_min / 2.0))
     ang = np.linspace(0.0, np.pi, m + 1)
     surf = np.stack([cx + R * np.cos(ang), cy + R * np.sin(ang)], 1)
+    axis = []
+    for x0, x1 in ((cx - R - grade, cx - R), (cx + R, min(Lx, cx + (R + grade) / wake_stretch))):
+        x = x0 if x0 < cx else x0 + h_min
+        while x < x1 - 0.5 * h_min:
+            if 0.5 * h_max < x < Lx - 0.5 * h_max and (x < cx - R - 0.5 * h_min or x > cx + R + 0.5 * h_min):
+                axis.append(x)
+            x += float(spacing(np.array([[x, cy]]))[0])
+    axis = np.stack([np.asarray(axis), np.full(len(axis), cy)], 1)
+    # graded zone: Poisson-disk fronts grown from the surface and the axis up
+    # to the lattice (half a lattice step beyond the zone, where the spacing
+    # test against the lattice nodes decides)
+
+    def admit(c):
+        return ((c[:, 0] > 0.5 * h_max) & (c[:, 0] < Lx - 0.5 * h_max) & (c[:, 1] < Ly - 0.5 * h_max)
+                & (c[:, 1] - cy > 0.4 * spacing(c)) & (reach(c) <= grade + 0.5 * h_max)
+                & (np.hypot(c[:, 0] - cx, c[:, 1] - cy) > R + 0.5 * h_min))
+
+    cand = _front_fill(np.concatenate([lat, bnd]), np.concatenate([surf, axis]), spacing, admit, rng)
     xy = np.concatenate([lat, cand, axis, surf, bnd])
     kind = np.concatenate([np.zeros(len(lat) + len(cand) + len(axis), np.uint8), np.full(len(surf), WALL, np.uint8),
                            np.full(len(bnd), DIRICHLET, np.uint8)])
