@@ -216,7 +216,7 @@ def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.
     return out
 
 
-def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_000_000, tol=1e-6, K=25):
+def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_560_000, tol=1e-6, K=25):
     """Onset of inertia in the porous sample of Sec. 3.2: MLBM1 (tau = 1) on
     the hybrid porous channel at a fixed lattice forcing g_lb for a sweep of
     streaming distances dx, all of them in one batched launch (one sample per
@@ -226,7 +226,7 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_000_000
     T_V = <|u|> / <u> (Eq. 25), at steady state or at the step cap."""
     t0 = time.time()
     ns = nodesets.porous_channel()
-    dxs = [2e-3, 1.5e-3, 1e-3, 7e-4, 5e-4, 3e-4, 2e-4, 1.5e-4]
+    dxs = [2e-3, 1.35e-3, 1.05e-3, 7.5e-4, 6e-4, 4.5e-4, 2.7e-4, 2.1e-4, 1.5e-4]  # Sec. 3.2's sweep
     built = [M.build_stencils_for(ns, K, dx, lattice_h=ns.h) for dx in dxs]
     batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for b in built], variant=M.FIELDS, storage=M.F32,
                               tau_plus=1.0, g=(g_lb, 0.0), tile=256, check_every=100)
@@ -271,74 +271,109 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_000_000
                         f"periodic x, no-slip walls y, hybrid lattice h={ns.h:g} / band nodes to h={ns.h_min:g}; "
                         f"g_lb={g_lb:g}, K={K}, residual {tol:g} or {max_steps} steps",
             "seconds": round(dt_run, 2), "steps_run": ran, "setup_s": round(setup, 1),
-            "MNUPS_effective": round(float(np.sum(np.abs(steps) * ns.n)) / dt_run / 1e6, 1) if dt_run else None,
+            "MNUPS_effective": round(sum(r["steps"] for r in rows) * ns.n / dt_run / 1e6, 1) if dt_run else None,
             "rows": rows}
 
 
-def strouhal_workload(M, units, nodesets, np, torch, reynolds=(105, 126, 147, 168), periods=10, transient=10,
-                      every=50):
-    """The paper's cylinder flow (Sec. 3.1) in its own configuration: 3 x 1
-    channel, d = 0.14, U0 = 0.01, TRT with tau+ = 0.53 and Lambda = 3/16,
-    one 25-node stencil per departure point, biquadratic Lagrange on the
-    lattice part, simple bounce-back on the cylinder; Re = U0 d / nu raised by
-    shrinking dx (Sec. 2.3).  The lift (momentum exchange on the cylinder) is
-    sampled every `every` steps; after `transient` shedding periods its
-    dominant frequency over `periods` periods gives St = f d / U0 (lattice
-    units: f in cycles per step, d in streaming distances)."""
-    ns = nodesets.karman_paper()
+ST_CASES = (("coarsened", "shared", (105, 126, 147, 168)),
+            ("uniform", "shared", (105, 126, 147, 168)),
+            ("coarsened", "per-departure", (105, 168)))
+
+
+def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10, transient=10, every=50,
+                      dump=None):
+    """The paper's cylinder flow (Sec. 3.1): 3 x 1 channel, d = 0.14,
+    U0 = 0.01, TRT with tau+ = 0.53 and Lambda = 3/16, K = 25 stencils,
+    biquadratic Lagrange on the lattice part, simple bounce-back on the
+    cylinder; Re = U0 d / nu raised by shrinking dx (Sec. 2.3).  The lift
+    (momentum exchange on the cylinder) is sampled every `every` steps; after
+    `transient` shedding periods (estimated with St = 0.2) the next `periods`
+    give St = f d / U0 (lattice units: f in cycles per step, d in streaming
+    distances), f from the mean spacing of upward zero crossings (the peak of
+    the zero-padded spectrum as a check).  Each case names the node set
+    ("coarsened": h 1/200 on the cylinder to 1/25, the set the paper measures
+    St on; "uniform": 1/200 everywhere), the stencil form ("per-departure":
+    the K nearest nodes of each departure point, as the paper states;
+    "shared": one stencil per node for its eight departure points) and the
+    Reynolds numbers."""
+    sets = {"coarsened": nodesets.karman_paper(),
+            "uniform": nodesets.karman_paper(h_max=1.0 / 200, grade=0.15, wake_stretch=0.3)}
     d, u0, tau = 0.14, 1e-2, 0.53
     tau_m = 0.5 + (3.0 / 16.0) / (tau - 0.5)
     nu_lb = units.nu_lattice(tau)
     rows = []
-    total_updates, total_s = 0, 0.0
-    for re in reynolds:
-        dx = u0 * d / (re * nu_lb)
-        b = M.build_stencils_for(ns, 25, dx, lattice_h=ns.h, per_departure=True, simple_bounce_back=True)
-        perm = b["perm"]
-        sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
-                           storage=M.F32, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm], tile=256)
-        # at rest, boundary values on the Dirichlet nodes, and a small transverse
-        # kick behind the cylinder so the shedding does not wait for round-off
-        xy = ns.xy[perm]
-        u = np.zeros((ns.n, 2))
-        wake = (xy[:, 0] > 0.6) & (xy[:, 0] < 1.0) & (np.abs(xy[:, 1] - 0.5) < 0.1)
-        u[wake, 1] = 0.1 * u0
-        dmask = ns.kind[perm] == nodesets.DIRICHLET
-        u[dmask] = ns.boundary_values()[perm][dmask, 1:3]
-        sim.init_state(np.ones(ns.n), u)
-        t_shed = (d / dx) / (0.2 * u0)  # steps per period for St ~ 0.2
-        n_samples = int((transient + periods) * t_shed / every)
-        lift = np.zeros(n_samples)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s_ in range(n_samples):
-            sim.step(every)
+    series = {}
+    for set_name, mode, reynolds in cases:
+        ns = sets[set_name]
+        for re in reynolds:
+            dx = u0 * d / (re * nu_lb)
+            b = M.build_stencils_for(ns, 25, dx, lattice_h=ns.h, per_departure=mode == "per-departure",
+                                     simple_bounce_back=True)
+            perm = b["perm"]
+            # per-departure rows of block centres carry their block weights
+            # themselves; shared stencils take the one block table
+            lag = dict(lagrange=b["lagrange"], w_lagrange=b["w_lagrange"]) if mode == "shared" else {}
+            sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
+                               storage=M.F32, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
+                               tile=256, **lag)
+            # at rest, boundary values on the Dirichlet nodes, and a small transverse
+            # kick behind the cylinder so the shedding does not wait for round-off
+            xy = ns.xy[perm]
+            u = np.zeros((ns.n, 2))
+            wake = (xy[:, 0] > 0.6) & (xy[:, 0] < 1.0) & (np.abs(xy[:, 1] - 0.5) < 0.1)
+            u[wake, 1] = 0.1 * u0
+            dmask = ns.kind[perm] == nodesets.DIRICHLET
+            u[dmask] = ns.boundary_values()[perm][dmask, 1:3]
+            sim.init_state(np.ones(ns.n), u)
+            t_shed = (d / dx) / (0.2 * u0)  # steps per period for St ~ 0.2
+            n_samples = int((transient + periods) * t_shed / every)
+            lift = np.zeros(n_samples)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s_ in range(n_samples):
+                sim.step(every)
+                _, _, red = sim.macroscopic(dx, want_fields=False)
+                lift[s_] = float(red[M._lib.RED_FORCE_Y].item())
+                if s_ % 4000 == 3999:
+                    print(f"# {set_name} {mode} Re {re}: {s_ + 1}/{n_samples} lift samples", file=sys.stderr,
+                          flush=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
             _, _, red = sim.macroscopic(dx, want_fields=False)
-            lift[s_] = float(red[M._lib.RED_FORCE_Y].item())
-            if s_ % 2000 == 1999:
-                print(f"# Re {re}: {s_ + 1}/{n_samples} lift samples", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        _, _, red = sim.macroscopic(dx, want_fields=False)
-        bad = int(red[M._lib.RED_N_BAD].item())
-        tail = lift[int(transient * t_shed / every):]
-        tail = tail - tail.mean()
-        spec = np.abs(np.fft.rfft(tail * np.hanning(len(tail)), n=8 * len(tail)))
-        freqs = np.fft.rfftfreq(8 * len(tail), d=every)
-        f = freqs[int(np.argmax(spec[1:]) + 1)]
-        st = f * (d / dx) / u0
-        n_steps = n_samples * every
-        total_updates += n_steps * ns.n
-        total_s += dt
-        rows.append({"Re": re, "dx": dx, "s_min": round(ns.h_min / dx, 3), "s_max": round(ns.h / dx, 3),
-                     "steps": n_steps, "St": round(float(st), 4), "lift_amplitude": float(np.abs(tail).max()),
-                     "unstable_nodes": bad, "seconds": round(dt, 2), "MNUPS": round(ns.n * n_steps / dt / 1e6, 1)})
-        print(f"# Re {re}: St {st:.4f}, {dt:.1f} s", file=sys.stderr, flush=True)
-        del sim
+            bad = int(red[M._lib.RED_N_BAD].item())
+            tail = lift[int(transient * t_shed / every):]
+            tail = tail - tail.mean()
+            spec = np.abs(np.fft.rfft(tail * np.hanning(len(tail)), n=8 * len(tail)))
+            freqs = np.fft.rfftfreq(8 * len(tail), d=every)
+            st_fft = freqs[int(np.argmax(spec[1:]) + 1)] * (d / dx) / u0
+            # mean period between the first and last upward zero crossings
+            # (linear interpolation between samples)
+            sg = np.sign(tail)
+            up = np.nonzero((sg[:-1] < 0) & (sg[1:] >= 0))[0]
+            if len(up) >= 3:
+                tc = up + (-tail[up]) / (tail[up + 1] - tail[up])
+                st = (d / dx) / ((tc[-1] - tc[0]) / (len(tc) - 1) * every * u0)
+            else:
+                st = float("nan")
+            n_steps = n_samples * every
+            series[f"{set_name}_{mode}_Re{re}"] = lift
+            rows.append({"nodes": set_name, "n": ns.n, "block_centres": int(b["n_lagrange"]), "stencils": mode,
+                         "Re": re, "dx": dx, "s_min": round(ns.h_min / dx, 3), "s_max": round(ns.h / dx, 3),
+                         "steps": n_steps, "St": round(float(st), 4), "St_fft": round(float(st_fft), 4),
+                         "lift_amplitude": float(np.abs(tail).max()), "lift_rms": float(np.sqrt(np.mean(tail ** 2))),
+                         "unstable_nodes": bad, "seconds": round(dt, 2),
+                         "MNUPS": round(ns.n * n_steps / dt / 1e6, 1)})
+            print(f"# {set_name} {mode} Re {re}: St {st:.4f}, {dt:.1f} s, unstable nodes {bad}", file=sys.stderr,
+                  flush=True)
+            del sim
+    if dump:
+        np.savez(dump, every=every, **series)
     return {"metric": "Strouhal number of the cylinder wake vs Re (the paper's configuration)",
-            "workload": f"3x1 channel, d=0.14, {ns.n} hybrid nodes (h {ns.h_min:g}..{ns.h:g}, symmetric), "
-                        f"TRT tau+=0.53 Lambda=3/16, per-departure K=25 stencils, simple bounce-back, FP32",
-            "rows": rows, "MNUPS_mean": round(total_updates / total_s / 1e6, 1) if total_s else None}
+            "workload": "3x1 channel, d=0.14, U0=0.01, hybrid symmetric node sets "
+                        + ", ".join(f"{k}: {v.n} nodes (h {v.h_min:g}..{v.h:g})" for k, v in sets.items())
+                        + ", TRT tau+=0.53 Lambda=3/16, K=25, simple bounce-back, FP32, lift every "
+                        + f"{every} steps, {transient} + {periods} periods",
+            "rows": rows}
 
 
 def warmstart_workload(args, np, torch):
@@ -426,6 +461,7 @@ def main():
                          "Lagrange weights at the block centres")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
+    ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
     ap.add_argument("--workload", default="karman", choices=["karman", "batched", "warmstart", "darcy", "strouhal"],
                     help="karman: the fused-step throughput line; batched: 64 porous samples to steady "
                          "state; warmstart: train the warm-start network and compare time to steady state; "
@@ -465,7 +501,7 @@ def main():
         print(json.dumps(darcy_workload(M, units, nodesets, np, torch)), flush=True)
         return
     if args.workload == "strouhal":
-        print(json.dumps(strouhal_workload(M, units, nodesets, np, torch)), flush=True)
+        print(json.dumps(strouhal_workload(M, units, nodesets, np, torch, dump=args.st_dump)), flush=True)
         return
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]

@@ -293,14 +293,22 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
                    h_min=hf)
 
 
-def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_cand: int = 12) -> np.ndarray:
+def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_cand: int = 12,
+                period_x: float = 0.0) -> np.ndarray:
     """Poisson-disk node placement by advancing fronts (after Slak & Kosec,
     2019): every node of the current front proposes n_cand candidates on the
     circle of radius h(p) around itself (random rotation); a candidate is kept
     if admit() accepts it and no node, old or newly kept, lies closer than
     0.99 h(p).  The kept candidates form the next front.  Returns the new
-    nodes only (fixed and seeds are taken as already placed)."""
+    nodes only (fixed and seeds are taken as already placed).  period_x > 0:
+    periodic along x on [0, period_x) (candidates wrapped, distances by
+    minimum image)."""
     from scipy.spatial import cKDTree
+
+    def tree(pts):
+        if period_x:
+            return cKDTree(pts, boxsize=[period_x, 1e30])
+        return cKDTree(pts)
 
     placed = np.concatenate([fixed, seeds])
     front = seeds
@@ -311,19 +319,21 @@ def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_can
         rot = rng.uniform(0.0, 2.0 * np.pi, size=len(front))
         a = rot[:, None] + ang0[None, :]
         cand = (front[:, None, :] + hp[:, None, None] * np.stack([np.cos(a), np.sin(a)], -1)).reshape(-1, 2)
+        if period_x:
+            cand[:, 0] = np.mod(cand[:, 0], period_x)
+            cand[cand[:, 0] >= period_x, 0] = 0.0
         hc = np.repeat(hp, n_cand)
         ok = admit(cand)
         cand, hc = cand[ok], hc[ok]
         if len(cand) == 0:
             break
-        dist, _ = cKDTree(placed).query(cand)
+        dist, _ = tree(placed).query(cand)
         ok = dist >= 0.99 * hc
         cand, hc = cand[ok], hc[ok]
         if len(cand) == 0:
             break
         # greedy among the candidates themselves, in proposal order
-        tree = cKDTree(cand)
-        nbrs = tree.query_ball_point(cand, r=0.99 * hc)
+        nbrs = tree(cand).query_ball_point(cand, r=0.99 * hc)
         taken = np.zeros(len(cand), bool)
         for i in range(len(cand)):
             if not any(taken[j] for j in nbrs[i] if j != i):
@@ -485,8 +495,8 @@ def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, b
     disks (radii uniform in r_range, porosity phi, clear of the walls), and a
     hybrid node set: a square lattice of spacing h farther than `band` from
     every disk, scattered nodes within the band whose spacing grows linearly
-    from h_surf on the disk surfaces to h at the band's edge (jittered samples
-    thinned to that density, close pairs removed), and nodes on every disk
+    from h_surf on the disk surfaces to h at the band's edge (placed by
+    advancing Poisson-disk fronts from the surfaces), and nodes on every disk
     surface at spacing h_surf."""
     from scipy.spatial import cKDTree
 
@@ -524,23 +534,25 @@ def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, b
     lat = np.stack([X.ravel(), Y.ravel()], axis=1)
     dl = surface_distance(lat)
     lat = lat[dl > band]
-    # band: jittered candidates at h_surf, kept with probability (h_surf / h(d))^2
-    cand = _grid(lo, hi, h_surf)
-    cand = cand + rng.uniform(-0.35 * h_surf, 0.35 * h_surf, size=cand.shape)
-    cand[:, 0] = np.mod(cand[:, 0], L)
-    cand = cand[(cand[:, 1] > 0.5 * h_surf) & (cand[:, 1] < L - 0.5 * h_surf)]
-    dc = surface_distance(cand)
-    sel = (dc > 0.5 * h_surf) & (dc <= band)
-    cand, dc = cand[sel], dc[sel]
-    hloc_c = h_surf + (h - h_surf) * np.clip(dc / band, 0.0, 1.0)
-    cand = cand[rng.uniform(size=len(cand)) < (h_surf / hloc_c) ** 2]
-    hloc_c = h_surf + (h - h_surf) * np.clip(surface_distance(cand) / band, 0.0, 1.0)
     surf = np.concatenate([_circle_nodes(c[0], c[1], c[2], h_surf) for c in disks]) if len(disks) else np.zeros((0, 2))
     surf[:, 0] = np.mod(surf[:, 0], L)
     walls = np.concatenate([np.stack([np.arange(nx) * (L / nx), np.zeros(nx)], 1),
                             np.stack([np.arange(nx) * (L / nx), np.full(nx, L)], 1)])
     on_wall_lat = (np.isclose(lat[:, 1], 0.0)) | (np.isclose(lat[:, 1], L))
     lat_in = lat[~on_wall_lat]
+
+    # band: Poisson-disk fronts grown from the disk surfaces up to the lattice
+    # (half a lattice step beyond the band, where the spacing test against the
+    # lattice nodes decides)
+    def spacing(pts):
+        return h_surf + (h - h_surf) * np.clip(surface_distance(pts) / band, 0.0, 1.0)
+
+    def admit(c):
+        dc = surface_distance(c)
+        return (c[:, 1] > 0.5 * h_surf) & (c[:, 1] < L - 0.5 * h_surf) & (dc > 0.5 * h_surf) & (dc <= band + 0.5 * h)
+
+    cand = _front_fill(np.concatenate([lat_in, walls]), surf, spacing, admit, rng, period_x=L)
+    hloc_c = spacing(cand)
     xy = np.concatenate([lat_in, cand, surf, walls])
     kind = np.concatenate([np.zeros(len(lat_in) + len(cand), np.uint8), np.full(len(surf) + len(walls), WALL, np.uint8)])
     hloc = np.concatenate([np.full(len(lat_in), h), hloc_c, np.full(len(surf), h_surf), np.full(len(walls), h)])

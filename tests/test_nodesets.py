@@ -48,15 +48,19 @@ def test_porous_channel():
     assert np.all(ns.disks[:, 1] - r > 0) and np.all(ns.disks[:, 1] + r < 1)
     wall_rows = np.isclose(ns.xy[:, 1], 0) | np.isclose(ns.xy[:, 1], 1)
     assert np.all(ns.kind[wall_rows] == nodesets.WALL)
-    # the lattice part: nodes farther than the band from every disk sit on the h lattice
+    # the lattice part: nodes farther than the band (plus the half lattice step
+    # the band's fronts may reach beyond it) from every disk sit on the h lattice
     far = np.ones(ns.n, bool)
     for cx, cy, rr in ns.disks:
         dx = ns.xy[:, 0] - cx
         dx -= np.round(dx)
-        far &= np.hypot(dx, ns.xy[:, 1] - cy) - rr > 0.04 + 1e-9
+        far &= np.hypot(dx, ns.xy[:, 1] - cy) - rr > 0.04 + 0.5 * ns.h + 1e-9
     grid = ns.xy[far] / ns.h
     np.testing.assert_allclose(grid, np.round(grid), atol=1e-9)
     assert far.sum() > 0.15 * ns.n
+    # band nodes keep their spacing: no pair closer than 0.99 of the finer spacing
+    d, _ = cKDTree(ns.xy, boxsize=[1.0, 1e30]).query(ns.xy, k=2)
+    assert d[:, 1].min() > 0.95 * ns.h_min
 
 
 def test_hybrid_karman_lattice():
