@@ -100,10 +100,13 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
     """The porous workload (1e6 nodes, phi = 0.7, MLBM1, s = 1, Darcy regime
     Re ~ 0.1) run from rest to steady state with FP32, FP16 (scaled offsets)
     and BF16 state: steps, seconds and permeability, the 16-bit permeabilities
-    relative to the FP32 one.  Criteria: the field residual below tol (FP32;
-    16-bit rounding keeps the field residual near the storage ulp, so 16-bit
-    runs stop at the step cap) and the mean-velocity change below tol at three
-    consecutive checks (all storages; 16-bit with stochastic rounding)."""
+    relative to the FP32 one.  Criteria: the field residual between checks
+    100 steps apart below tol (FP32; 16-bit rounding keeps the field residual
+    near the storage ulp, so 16-bit runs stop at the step cap), and the
+    relative change of the mean velocity between checks 1000 steps apart below
+    10 tol (all storages; 16-bit with stochastic rounding): the same rate per
+    step, measured over an interval long enough that the rounding noise of the
+    mean stays below it (the paper's criterion is a rate too, Sec. 3.2)."""
     t0 = time.time()
     ns = nodesets.porous()
     dx = ns.h
@@ -126,13 +129,14 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
         sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        steps, res, red = sim.run_to_steady(dx, tol=tol, check_every=100, max_steps=cap, criterion=crit,
-                                            hold=3 if crit == "mean" else 1)
+        every, tol_c = (1000, 10.0 * tol) if crit == "mean" else (100, tol)
+        steps, res, red = sim.run_to_steady(dx, tol=tol_c, check_every=every, max_steps=cap, criterion=crit)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         k = nu * (red[M._lib.RED_INT_UX] / 1.0) / g * dx * dx
         umean = red[M._lib.RED_INT_UX] / ns.fluid_area()
-        rec = {"criterion": crit, "stochastic_rounding": sr, "steps": steps, "converged": bool(res < tol),
+        rec = {"criterion": crit, "check_every": every, "tol": tol_c, "stochastic_rounding": sr, "steps": steps,
+               "converged": bool(res < tol_c),
                "seconds": round(dt, 3), "residual": res, "permeability": k,
                "Re": umean / dx / nu, "MNUPS": round(ns.n * steps / dt / 1e6, 1)}
         if name == "f32":

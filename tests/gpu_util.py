@@ -63,7 +63,8 @@ def run_oracle(ns, st, variant, steps, rho0, u0, tau_plus, tau_minus, g):
 
 def sim_from_oracle(M, ns, st, variant, storage, tau_plus, tau_minus, g, **kw):
     """Simulation fed with the oracle's own stencil arrays (oracle node order)."""
-    lag = st.lagrange if st.lagrange is not None and st.lagrange.any() else None
+    # per-departure rows of block centres carry their block weights themselves
+    lag = st.lagrange if st.lagrange is not None and st.lagrange.any() and st.idx.ndim == 2 else None
     wl = st.w[int(np.argmax(st.lagrange))][:, :9] if lag is not None else None
     return M.Simulation(st.idx.astype(np.int32), st.w, oracle_bb(st), ns.kind, st.area,
                         variant=variant, storage=storage, tau_plus=tau_plus, tau_minus=tau_minus,

@@ -117,6 +117,20 @@ def _case(name):
         st = omlbm.build_stencils(ns, 16, dx, per_departure=True)
         rho0, u0 = initial_fields(ns, 23, 0.01, 0.002)
         c = (ns, st, 1, 1.0, 1.0, (1e-5, 2e-6), 200, rho0, u0, dx)
+    elif name == "pd_hybrid_patch":  # per-departure stencils on a hybrid set: block rows stored densely
+        ns = nodesets.patch_jittered_grid(32, radius=0.25, seed=24)
+        dx = 1.0 / 32 / 1.5
+        st = omlbm.build_stencils(ns, 25, dx, lattice_h=1.0 / 32, per_departure=True)
+        assert 0 < st.lagrange.sum() < ns.n
+        rho0, u0 = initial_fields(ns, 25, 0.01, 0.002)
+        c = (ns, st, 0, 0.8, 0.8, (1e-5, 0.0), 200, rho0, u0, dx)
+    elif name == "pd_cylinder_channel":  # the Strouhal configuration, coarse: Dirichlet sides, TRT, simple BB
+        ns = nodesets.karman_paper(h_min=1.0 / 80, h_max=1.0 / 10)
+        dx = 0.14 / 42.0
+        st = omlbm.build_stencils(ns, 25, dx, lattice_h=ns.h, per_departure=True, simple_bb=True)
+        rho0, u0 = initial_fields(ns, 26, 0.01, 0.001)
+        tp = 0.53
+        c = (ns, st, 0, tp, lt.tau_minus_from_lambda(tp, 3 / 16), (0.0, 0.0), 100, rho0, u0, dx)
     else:
         raise KeyError(name)
     ns, st, var, tp, tm, g, steps, rho0, u0, dx = c
@@ -173,7 +187,8 @@ def test_block_centre_kernel_equals_per_node_weights(M, name, storage, tile):
     assert err <= {0: 1e-13, 1: 1e-6, 2: 1e-3}[storage]
 
 
-@pytest.mark.parametrize("name", ["pd_tgv", "pd_karman_trt", "pd_porous_fields"])
+@pytest.mark.parametrize("name", ["pd_tgv", "pd_karman_trt", "pd_porous_fields", "pd_hybrid_patch",
+                                  "pd_cylinder_channel"])
 @pytest.mark.parametrize("storage", [0, 1])
 def test_per_departure_step_parity(M, name, storage):
     print(f"[parity-pd] case={name} storage={storage}", flush=True)
@@ -182,8 +197,21 @@ def test_per_departure_step_parity(M, name, storage):
     # of a 256-node tile's halo can exceed the 64 KiB of LDS, 128-node tiles fit
     _, rho, u, red = _run_gpu(M, name, storage, tile=128 if storage == 0 else 256)
     err = rel_l2(u, u_ref)
+    bar = BAR[storage]
+    if name == "pd_cylinder_channel" and storage == 0:
+        # tau+ = 0.53 with tau- = 6.75 amplifies rounding: the oracle itself,
+        # started from its initial populations perturbed by 1e-16 (relative),
+        # moves by `sens` over the same steps; a different summation order
+        # perturbs every step, so the bar is ten times that response
+        f0 = omlbm.init_populations(rho0, u0)
+        f0 = f0 * (1.0 + 1e-16 * np.random.default_rng(0).standard_normal(f0.shape))
+        for _ in range(steps):
+            f0 = omlbm.step(f0, ns, st, tp, tm, g)
+        sens = rel_l2(omlbm.macroscopic(f0, ns, g)[1], u_ref)
+        bar = max(bar, 10.0 * sens)
+        print(f"[parity-pd] oracle sensitivity {sens:.3e}, bar {bar:.3e}", flush=True)
     print(f"[parity-pd] case={name} storage={storage} rel_l2_u={err:.3e}", flush=True)
-    assert err <= BAR[storage]
+    assert err <= bar
     assert red[8] == 0
 
 
