@@ -153,16 +153,19 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
 
 
 def batched_workload(M, units, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.242e-8, sequential=True,
-                     n_range=(50_000, 400_000)):
+                     n_range=(50_000, 400_000), r_range=(0.01, 0.03)):
     """64 porous samples (nodes U(5e4, 4e5), porosity U(0.55, 0.85)), MLBM1
     FP32, s = 1, run from rest to a residual of tol in one batched launch
     (persistent tile queue, graph replay, autotuned shape), against the same
     samples run one after another.  A second call with many small samples
-    (each too small to fill the GPU alone) shows what batching buys there."""
+    (each too small to fill the GPU alone, with disks of radius 0.05-0.12 so
+    that their coarser nodes still resolve them) shows what batching buys
+    there."""
     from paper_2312_14789_amd import autotune
 
     t0 = time.time()
-    sets = nodesets.porous_batch(n_samples, n_range=n_range)
+    sets = nodesets.porous_batch(n_samples, n_range=n_range, r_range=r_range,
+                                 log=lambda m: print("# " + m, file=sys.stderr, flush=True))
     print(f"# {n_samples} porous samples generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     built = []
     for si, ns in enumerate(sets):
@@ -495,7 +498,7 @@ def main():
     if args.workload == "batched":
         out = batched_workload(M, units, nodesets, np, torch)
         out["small_samples"] = batched_workload(M, units, nodesets, np, torch, n_samples=256,
-                                                n_range=(2_000, 20_000))
+                                                n_range=(2_000, 20_000), r_range=(0.05, 0.12))
         print(json.dumps(out), flush=True)
         return
     if args.workload == "warmstart":

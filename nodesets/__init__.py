@@ -429,7 +429,8 @@ def random_disks(phi_target: float, r_min: float, r_max: float, gap: float,
     [0, L)^2: radii uniform in [r_min, r_max], centres uniform, a candidate is
     rejected if it comes closer than `gap` to a placed disk (periodic images
     included).  Stops once the solid fraction reaches 1 - phi_target."""
-    disks = []
+    D = np.zeros((64, 3))
+    m = 0
     solid = 0.0
     target = (1.0 - phi_target) * L * L
     tries = 0
@@ -437,16 +438,17 @@ def random_disks(phi_target: float, r_min: float, r_max: float, gap: float,
         tries += 1
         rr = rng.uniform(r_min, r_max)
         c = rng.uniform(0.0, L, size=2)
-        ok = True
-        if disks:
-            D = np.asarray(disks)
-            d = D[:, :2] - c
+        if m:
+            d = D[:m, :2] - c
             d -= L * np.round(d / L)
-            ok = bool(np.all(np.hypot(d[:, 0], d[:, 1]) >= D[:, 2] + rr + gap))
-        if ok:
-            disks.append((c[0], c[1], rr))
-            solid += np.pi * rr * rr
-    return np.asarray(disks, dtype=np.float64).reshape(-1, 3)
+            if not np.all(np.hypot(d[:, 0], d[:, 1]) >= D[:m, 2] + rr + gap):
+                continue
+        if m == len(D):
+            D = np.concatenate([D, np.zeros_like(D)])
+        D[m] = (c[0], c[1], rr)
+        m += 1
+        solid += np.pi * rr * rr
+    return D[:m].copy()
 
 
 def porous(n_target: int = 1_000_000, phi: float = 0.7, seed: int = 231214789,
@@ -565,13 +567,19 @@ def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, b
 
 
 def porous_batch(n_samples: int = 64, seed: int = 231214789, n_range=(50_000, 400_000),
-                 phi_range=(0.55, 0.85)) -> list:
+                 phi_range=(0.55, 0.85), r_range=(0.01, 0.03), log=None) -> list:
     """n_samples porous media with node counts and porosities drawn uniformly
-    from the given ranges (sample s uses seed + s)."""
+    from the given ranges (sample s uses seed + s); log(message) every 32
+    samples if given."""
     rng = np.random.default_rng(seed)
     ns = rng.integers(n_range[0], n_range[1] + 1, size=n_samples)
     phis = rng.uniform(phi_range[0], phi_range[1], size=n_samples)
-    return [porous(int(ns[s]), float(phis[s]), seed=seed + 1 + s) for s in range(n_samples)]
+    out = []
+    for s in range(n_samples):
+        out.append(porous(int(ns[s]), float(phis[s]), seed=seed + 1 + s, r_range=r_range))
+        if log is not None and s % 32 == 31:
+            log(f"{s + 1}/{n_samples} samples")
+    return out
 
 
 # --------------------------------------------------------------------------
