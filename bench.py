@@ -284,6 +284,7 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_560_000
 
 ST_CASES = (("coarsened", "shared", (105, 126, 147, 168)),
             ("uniform", "shared", (105, 126, 147, 168)),
+            ("scattered", "shared", (105, 168)),
             ("coarsened", "per-departure", (105, 168)))
 
 
@@ -299,12 +300,16 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
     distances), f from the mean spacing of upward zero crossings (the peak of
     the zero-padded spectrum as a check).  Each case names the node set
     ("coarsened": h 1/200 on the cylinder to 1/25, the set the paper measures
-    St on; "uniform": 1/200 everywhere), the stencil form ("per-departure":
+    St on; "uniform": 1/200 everywhere, scattered only near the cylinder and
+    its wake; "scattered": 1/200 everywhere, all scattered: the paper's three
+    timing scenarios), the stencil form ("per-departure":
     the K nearest nodes of each departure point, as the paper states;
     "shared": one stencil per node for its eight departure points) and the
     Reynolds numbers."""
-    sets = {"coarsened": nodesets.karman_paper(),
-            "uniform": nodesets.karman_paper(h_max=1.0 / 200, grade=0.15, wake_stretch=0.3)}
+    names = {c[0] for c in cases}
+    recipes = {"coarsened": {}, "uniform": dict(h_max=1.0 / 200, grade=0.15, wake_stretch=0.3),
+               "scattered": dict(h_max=1.0 / 200, grade=10.0, wake_stretch=1.0)}
+    sets = {k: nodesets.karman_paper(**v) for k, v in recipes.items() if k in names}
     d, u0, tau = 0.14, 1e-2, 0.53
     tau_m = 0.5 + (3.0 / 16.0) / (tau - 0.5)
     nu_lb = units.nu_lattice(tau)
@@ -369,6 +374,7 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
                          "steps": n_steps, "St": round(float(st), 4), "St_fft": round(float(st_fft), 4),
                          "lift_amplitude": float(np.abs(tail).max()), "lift_rms": float(np.sqrt(np.mean(tail ** 2))),
                          "unstable_nodes": bad, "seconds": round(dt, 2),
+                         "ms_per_1000_steps": round(dt / n_steps * 1e6, 2),
                          "MNUPS": round(ns.n * n_steps / dt / 1e6, 1)})
             print(f"# {set_name} {mode} Re {re}: St {st:.4f}, {dt:.1f} s, unstable nodes {bad}", file=sys.stderr,
                   flush=True)
@@ -376,7 +382,7 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
     if dump:
         np.savez(dump, every=every, **series)
     return {"metric": "Strouhal number of the cylinder wake vs Re (the paper's configuration)",
-            "workload": "3x1 channel, d=0.14, U0=0.01, hybrid symmetric node sets "
+            "workload": "3x1 channel, d=0.14, U0=0.01, symmetric node sets "
                         + ", ".join(f"{k}: {v.n} nodes (h {v.h_min:g}..{v.h:g})" for k, v in sets.items())
                         + ", TRT tau+=0.53 Lambda=3/16, K=25, simple bounce-back, FP32, lift every "
                         + f"{every} steps, {transient} + {periods} periods",

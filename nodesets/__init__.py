@@ -491,7 +491,7 @@ def porous(n_target: int = 1_000_000, phi: float = 0.7, seed: int = 231214789,
 
 
 def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, band: float = 0.04,
-                   r_range=(0.06, 0.1), seed: int = 231214789, L: float = 1.0) -> NodeSet:
+                   r_range=(0.06, 0.1), seed: int = 231214789, L: float = 1.0, gap: float | None = None) -> NodeSet:
     """The porous sample of Sec. 3.2: the box [0, L]^2, periodic along x,
     no-slip walls on y = 0 and y = L (nodes on them), random non-overlapping
     disks (radii uniform in r_range, porosity phi, clear of the walls), and a
@@ -499,14 +499,15 @@ def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, b
     every disk, scattered nodes within the band whose spacing grows linearly
     from h_surf on the disk surfaces to h at the band's edge (placed by
     advancing Poisson-disk fronts from the surfaces), and nodes on every disk
-    surface at spacing h_surf."""
+    surface at spacing h_surf.  Disks keep `gap` (default 2 h_surf) from each
+    other and from the walls."""
     from scipy.spatial import cKDTree
 
     rng = np.random.default_rng(seed)
     # disks: random sequential addition, periodic along x only
     disks = []
     solid, target, tries = 0.0, (1.0 - phi) * L * L, 0
-    gap = 2.0 * h_surf
+    gap = 2.0 * h_surf if gap is None else gap
     while solid < target and tries < 200_000:
         tries += 1
         rr = rng.uniform(*r_range)
