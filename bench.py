@@ -96,6 +96,36 @@ def copy_calibration():
                       "GBps_read_plus_write": 2 * 4 * n / ms / 1e6}), flush=True)
 
 
+def karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m, scales=(2.0, 4.0), steps=50_000):
+    """The Karman workload at larger streaming-distance scales s (Re = 100 s at
+    fixed tau, Sec. 2.3): `steps` steps from rest on the same node set, each
+    checked for unstable nodes, with its throughput."""
+    rows = []
+    for s_ in scales:
+        dx = units.delta_x(ns.h_min, s_)
+        b = M.build_stencils_for(ns, args.K, dx, lattice_h=ns.h if args.hybrid else 0.0)
+        perm = b["perm"]
+        sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
+                           storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
+                           tile=args.tile, lagrange=b["lagrange"], w_lagrange=b["w_lagrange"])
+        sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, u, red = sim.macroscopic(dx)
+        red = red.cpu().numpy()
+        bad = int(red[M._lib.RED_N_BAD])
+        rows.append({"s": s_, "Re": 100.0 * s_, "dx": dx, "steps": steps, "unstable_nodes": bad,
+                     "max_speed": None if bad else float(u.norm(dim=1).max()),
+                     "MNUPS": round(ns.n * steps / dt / 1e6, 1)})
+        print(f"# s={s_:g}: {steps} steps, {bad} unstable nodes, {rows[-1]['MNUPS']} MNUPS", file=sys.stderr,
+              flush=True)
+        del sim
+    return rows
+
+
 def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
     """The porous workload (1e6 nodes, phi = 0.7, MLBM1, s = 1, Darcy regime
     Re ~ 0.1) run from rest to steady state with FP32, FP16 (scaled offsets)
@@ -472,6 +502,9 @@ def main():
     ap.add_argument("--hybrid", action="store_true",
                     help="hybrid node set: square lattice away from the cylinder and its wake, biquadratic "
                          "Lagrange weights at the block centres")
+    ap.add_argument("--stratified", action="store_true",
+                    help="Karman nodes by stratified (jittered) samples instead of Poisson-disk fronts")
+    ap.add_argument("--no-s-sweep", action="store_true", help="skip the s = 2, 4 stability runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
     ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
@@ -519,7 +552,8 @@ def main():
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]
     t0 = time.time()
-    ns = nodesets.karman(n_target=args.nodes, hybrid=args.hybrid)
+    poisson = not (args.stratified or args.hybrid)
+    ns = nodesets.karman(n_target=args.nodes, hybrid=args.hybrid, poisson=poisson)
     # streaming distance from the finest spacing (refined ring around the
     # cylinder): s = 1 keeps dx <= h everywhere
     dx = units.delta_x(ns.h_min, args.s)
@@ -561,7 +595,7 @@ def main():
     bpn_lag = units.block_centre_bytes_per_node(M.POPULATIONS, storage)
     bpn = ((n - n_lag) * bpn_rbf + n_lag * bpn_lag) / n
     achieved = bpn * n / per_launch_s / 1e9
-    workload = f"karman{'-hybrid' if args.hybrid else ''}-n{n}-K{K}-s{args.s:g}"
+    workload = f"karman{'-hybrid' if args.hybrid else ''}{'-poisson' if poisson else ''}-n{n}-K{K}-s{args.s:g}"
     kernel = "k_step_pop" + ("_lds" if args.tile else "")
     traffic = measured_traffic(kernel, workload)
     out = {
@@ -583,7 +617,8 @@ def main():
                                (f"{n} nodes, hybrid: {n_lag} on a square lattice (biquadratic Lagrange), "
                                 f"{n - n_lag} scattered near the cylinder and in its wake (4x denser within "
                                 "1D of the cylinder), " if args.hybrid else
-                                f"{n} scattered nodes (4x denser within 1D of the cylinder), ") +
+                                f"{n} scattered nodes ({'Poisson-disk, ' if poisson else 'stratified, '}"
+                                "4x denser within 1D of the cylinder), ") +
                                f"K={K}, s={args.s:g} (Re={re:g}), " + (f"TRT tau+={tau:.4f} tau-={tau_m:.4f}, " if args.trt else f"BGK tau={tau:.4f}, ") + 
                                f"{args.storage} populations",
                    "nodes": n, "block_centres": n_lag, "K": K, "s": args.s, "block": args.block,
@@ -596,8 +631,10 @@ def main():
                      "traffic": traffic, "kernel": kernel, "bytes_per_node": round(bpn, 2),
                      "avg_launch_us": round(per_launch_s * 1e6, 2)},
     }
+    del sim
+    if not args.no_s_sweep:
+        out["s_sweep"] = karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m)
     if not args.no_steady:
-        del sim
         out["time_to_steady"] = porous_time_to_steady(M, units, nodesets, np, torch)
     if not args.no_cpu_baseline:
         import copy

@@ -216,7 +216,7 @@ def _circle_nodes(cx, cy, r, h):
 
 def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
            u_max: float = 0.05, jitter: float = 0.35, hybrid: bool = False,
-           wake: float = 6.0) -> NodeSet:
+           wake: float = 6.0, poisson: bool = False) -> NodeSet:
     """Channel 22D x 4.1D with a cylinder of diameter D centred at (2D, 2D).
 
     Scattered nodes: stratified (jittered) samples at spacing h_b in the bulk
@@ -231,7 +231,14 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     its wake, a square lattice elsewhere): bulk nodes are jittered only within
     2D of the cylinder centre and in the wake box [2D, 2D + wake D] x
     [0.5D, 3.5D]; elsewhere they stay on the lattice of spacing h_b, which is
-    then D/(10 m) for an integer m so that it divides both channel sides."""
+    then D/(10 m) for an integer m so that it divides both channel sides.
+
+    poisson: Poisson-disk nodes instead of the stratified samples: advancing
+    fronts grown from the cylinder surface over the whole channel, spacing
+    h_f within 1D of the cylinder surface rising linearly to h_b over the next
+    4 h_f (h_b sized so that the set holds about n_target nodes)."""
+    if poisson and not hybrid:
+        return _karman_poisson(n_target, seed, D, u_max)
     rng = np.random.default_rng(seed)
     Lx, Ly = 22.0 * D, 4.1 * D
     cx, cy, r = 2.0 * D, 2.0 * D, 0.5 * D
@@ -293,8 +300,55 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
                    h_min=hf)
 
 
+# number of nodes per unit area of an advancing-front Poisson-disk fill of
+# spacing h, times h^2 (measured on open regions with the defaults of _front_fill)
+_FRONT_DENSITY = 0.89
+
+
+def _karman_poisson(n_target, seed, D, u_max):
+    rng = np.random.default_rng(seed)
+    Lx, Ly = 22.0 * D, 4.1 * D
+    cx, cy, r = 2.0 * D, 2.0 * D, 0.5 * D
+    ring = 1.0 * D
+    a_fine = np.pi * ((r + ring) ** 2 - r ** 2)
+    a_bulk = Lx * Ly - np.pi * (r + ring) ** 2
+    hb = math.sqrt(_FRONT_DENSITY * (a_bulk + 4.0 * a_fine) / n_target)
+    hf = 0.5 * hb
+    lo, hi = np.zeros(2), np.array([Lx, Ly])
+
+    def spacing(p):
+        t = np.clip((np.hypot(p[:, 0] - cx, p[:, 1] - cy) - r - ring) / (4.0 * hf), 0.0, 1.0)
+        return hf + (hb - hf) * t
+
+    def admit(c):
+        return ((c[:, 0] > 0.5 * hb) & (c[:, 0] < Lx - 0.5 * hb) & (c[:, 1] > 0.5 * hb) & (c[:, 1] < Ly - 0.5 * hb)
+                & (np.hypot(c[:, 0] - cx, c[:, 1] - cy) > r + 0.5 * hf))
+
+    surf = _circle_nodes(cx, cy, r, hf)
+    nbx, nby = int(round(Lx / hb)), int(round(Ly / hb))
+    xs = np.linspace(0.0, Lx, nbx + 1)
+    ys = np.linspace(0.0, Ly, nby + 1)[1:-1]
+    bnd = np.concatenate([
+        np.stack([xs, np.zeros_like(xs)], 1), np.stack([xs, np.full_like(xs, Ly)], 1),
+        np.stack([np.zeros_like(ys), ys], 1), np.stack([np.full_like(ys, Lx), ys], 1)])
+    fluid = _front_fill(bnd, surf, spacing, admit, rng, window=6)
+    xy = np.concatenate([fluid, surf, bnd])
+    kind = np.concatenate([np.zeros(len(fluid), np.uint8), np.full(len(surf), WALL, np.uint8),
+                           np.full(len(bnd), DIRICHLET, np.uint8)])
+    hloc = np.concatenate([spacing(fluid), np.full(len(surf), hf), np.full(len(bnd), hb)])
+    keep = _cleanup(xy, hloc, kind != FLUID, lo, hi, (False, False))
+    xy, kind = xy[keep], kind[keep]
+    bc = np.zeros((len(xy), 3))
+    bc[:, 0] = 1.0
+    inout = (kind == DIRICHLET) & ((np.isclose(xy[:, 0], 0.0)) | (np.isclose(xy[:, 0], Lx)))
+    y = xy[:, 1]
+    bc[inout, 1] = 4.0 * u_max * y[inout] * (Ly - y[inout]) / Ly ** 2
+    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(False, False),
+                   disks=np.array([[cx, cy, r]]), bc=bc, h=hb, name="karman-poisson", h_min=hf)
+
+
 def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_cand: int = 12,
-                period_x: float = 0.0) -> np.ndarray:
+                period_x: float = 0.0, window: int = 0) -> np.ndarray:
     """Poisson-disk node placement by advancing fronts (after Slak & Kosec,
     2019): every node of the current front proposes n_cand candidates on the
     circle of radius h(p) around itself (random rotation); a candidate is kept
@@ -302,7 +356,10 @@ def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_can
     0.99 h(p).  The kept candidates form the next front.  Returns the new
     nodes only (fixed and seeds are taken as already placed).  period_x > 0:
     periodic along x on [0, period_x) (candidates wrapped, distances by
-    minimum image)."""
+    minimum image).  window > 0: candidates are checked against the fixed
+    nodes, the seeds and the nodes of the last `window` fronts only (for large
+    sets; a front moves about one spacing per generation, so older nodes lie
+    behind it; callers clean up the rare close pair this misses)."""
     from scipy.spatial import cKDTree
 
     def tree(pts):
@@ -310,7 +367,8 @@ def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_can
             return cKDTree(pts, boxsize=[period_x, 1e30])
         return cKDTree(pts)
 
-    placed = np.concatenate([fixed, seeds])
+    base = np.concatenate([fixed, seeds])
+    placed = base
     front = seeds
     out = []
     ang0 = 2.0 * np.pi * np.arange(n_cand) / n_cand
@@ -340,7 +398,10 @@ def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_can
                 taken[i] = True
         front = cand[taken]
         out.append(front)
-        placed = np.concatenate([placed, front])
+        if window:
+            placed = np.concatenate([base] + out[-window:])
+        else:
+            placed = np.concatenate([placed, front])
     return np.concatenate(out) if out else np.zeros((0, 2))
 
 

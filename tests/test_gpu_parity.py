@@ -66,6 +66,15 @@ def _case(name):
         d = ns.kind == nodesets.DIRICHLET
         u0[~d] = 0.0
         c = (ns, st, 0, 0.6, 0.6, (0.0, 0.0), 300, rho0, u0, dx)
+    elif name == "karman_poisson_small":  # the bench's Poisson-disk channel, small
+        ns = nodesets.karman(n_target=4000, seed=5, poisson=True)
+        dx = ns.h_min / 2
+        st = omlbm.build_stencils(ns, 16, dx)
+        rho0, u0 = initial_fields(ns, 13, 0.02, 0.0)
+        rho0[:] = 1.0
+        d = ns.kind == nodesets.DIRICHLET
+        u0[~d] = 0.0
+        c = (ns, st, 0, 0.6, 0.6, (0.0, 0.0), 300, rho0, u0, dx)
     elif name == "porous_fields":  # MLBM1, grains, body force
         ns = nodesets.porous(3000, phi=0.7, seed=6, r_range=(0.05, 0.09))
         dx = ns.h / 1.5
@@ -148,8 +157,8 @@ def _run_gpu(M, name, storage, **kw):
     return sim, rho.cpu().numpy(), u.cpu().numpy(), red.cpu().numpy()
 
 
-@pytest.mark.parametrize("name", ["tgv64", "channel_trt", "karman_small", "porous_fields", "k25_fields",
-                                  "hybrid_tgv", "hybrid_pixels_fields"])
+@pytest.mark.parametrize("name", ["tgv64", "channel_trt", "karman_small", "karman_poisson_small", "porous_fields",
+                                  "k25_fields", "hybrid_tgv", "hybrid_pixels_fields"])
 @pytest.mark.parametrize("storage,tile", [(0, 256), (1, 256), (0, 0), (1, 0)])
 def test_step_parity(M, name, storage, tile):
     print(f"[parity] case={name} storage={storage} tile={tile}", flush=True)
@@ -330,8 +339,23 @@ def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed, la
     return rho[inv[pick]], u[inv[pick]], r_ref, u_ref, red.cpu().numpy(), sim, b
 
 
-def test_karman_full_size_sampled(M):
-    ns = nodesets.karman()          # ~5e5 nodes, 22D x 4.1D channel
+@pytest.mark.parametrize("s", [1.0, 4.0])
+def test_karman_full_size_sampled(M, s):
+    # the bench's workload: ~5e5 Poisson-disk nodes, 22D x 4.1D channel, Re = 100 s
+    ns = nodesets.karman(poisson=True)
+    print(f"[full] karman-poisson n={ns.n} s={s:g}", flush=True)
+    from paper_2312_14789_amd import units
+
+    dx = units.delta_x(ns.h_min, s)
+    tau = units.tau_for_reynolds(0.05, 1.0, dx, 100.0 * s)
+    r, u, r_ref, u_ref, red, sim, b = _sampled(M, ns, 16, dx, 0, 1, tau, tau, (0.0, 0.0), 0.05, 48, 21)
+    assert rel_l2(u, u_ref) < 1e-5
+    assert np.abs(r - r_ref).max() < 1e-6
+    assert red[8] == 0
+
+
+def test_stratified_karman_full_size_sampled(M):
+    ns = nodesets.karman()          # ~5e5 stratified nodes
     print(f"[full] karman n={ns.n}", flush=True)
     from paper_2312_14789_amd import units
 

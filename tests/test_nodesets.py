@@ -70,3 +70,24 @@ def test_hybrid_karman_lattice():
     g = ns.xy[fluid] / ns.h - 0.5
     on_lattice = np.all(np.abs(g - np.round(g)) < 1e-9, axis=1)
     assert on_lattice.mean() > 0.4
+
+
+def test_poisson_karman():
+    ns = nodesets.karman(n_target=20000, poisson=True)
+    assert abs(ns.n - 20000) < 0.1 * 20000
+    assert np.all((ns.xy >= ns.lo - 1e-12) & (ns.xy <= ns.hi + 1e-12))
+    assert not np.any(_inside_disks(ns.xy, ns.disks))
+    d, _ = cKDTree(ns.xy).query(ns.xy, k=2)
+    # no pair closer than (about) the local spacing; the fine ring keeps h_f
+    assert d[:, 1].min() > 0.95 * ns.h_min
+    fluid = ns.kind == nodesets.FLUID
+    r = np.hypot(ns.xy[:, 0] - 2.0, ns.xy[:, 1] - 2.0)
+    ring = fluid & (r > 0.6) & (r < 1.4)
+    far = fluid & (ns.xy[:, 0] > 6.0) & (ns.xy[:, 0] < 20.0) & (ns.xy[:, 1] > 0.3) & (ns.xy[:, 1] < 3.8)
+    # 4x the node density within 1D of the cylinder
+    dens_ring = ring.sum() / (np.pi * (1.4 ** 2 - 0.6 ** 2))
+    dens_far = far.sum() / (14.0 * 3.5)
+    assert 3.4 < dens_ring / dens_far < 4.6
+    # nearest-neighbour distances sit between h and 1.6 h: no holes, no clusters
+    nn_far = d[far, 1] / ns.h
+    assert np.percentile(nn_far, 1) > 0.98 and np.percentile(nn_far, 99) < 1.6
