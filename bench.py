@@ -126,11 +126,19 @@ def karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m, scales=(2
     return rows
 
 
-def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
-    """The porous workload (1e6 nodes, phi = 0.7, MLBM1, s = 1, Darcy regime
-    Re ~ 0.1) run from rest to steady state with FP32, FP16 (scaled offsets)
-    and BF16 state: steps, seconds and permeability, the 16-bit permeabilities
-    relative to the FP32 one.  Criteria: the field residual between checks
+TTS_RUNS = (("f32", "F32", 0, "field", 200_000), ("f32_mean", "F32", 0, "mean", 200_000),
+            ("f16s", "F16S", 0, "field", 60_000), ("f16s_sr_mean", "F16S", 1, "mean", 200_000),
+            ("bf16", "BF16", 0, "field", 60_000), ("bf16_sr_mean", "BF16", 1, "mean", 200_000))
+TTS_RUNS_INERTIAL = (("f32", "F32", 0, "field", 600_000), ("f16s_sr_mean", "F16S", 1, "mean", 600_000),
+                     ("bf16_sr_mean", "BF16", 1, "mean", 600_000))
+
+
+def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s=1.0, runs=TTS_RUNS):
+    """The porous workload (1e6 nodes, phi = 0.7, MLBM1; s = 1: Darcy regime,
+    Re ~ 0.1; s = 4: inertial, Re ~ 7) run from rest to steady state with
+    FP32, FP16 (scaled offsets) and BF16 state: steps, seconds and
+    permeability, the 16-bit permeabilities relative to the FP32 one (the
+    first run of `runs` must be FP32).  Criteria: the field residual between checks
     100 steps apart below tol (FP32; 16-bit rounding keeps the field residual
     near the storage ulp, so 16-bit runs stop at the step cap), and the
     relative change of the mean velocity between checks 1000 steps apart below
@@ -139,19 +147,17 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
     mean stays below it (the paper's criterion is a rate too, Sec. 3.2)."""
     t0 = time.time()
     ns = nodesets.porous()
-    dx = ns.h
+    dx = ns.h / s
     b = M.build_stencils_for(ns, 16, dx)
     perm = b["perm"]
     nu = units.nu_lattice(1.0)
     out = {"workload": f"porous unit box, {ns.n} nodes, phi={ns.fluid_area():.3f}, {len(ns.disks)} disks, "
-                       f"MLBM1 (tau=1), K=16, s=1, g_lb={g:g}", "tol": tol,
+                       f"MLBM1 (tau=1), K=16, s={s:g}, g_lb={g:g}", "tol": tol,
            "setup_s": None, "runs": {}}
     k_ref = None
     sigma = 0
-    runs = (("f32", M.F32, 0, "field", 200_000), ("f32_mean", M.F32, 0, "mean", 200_000),
-            ("f16s", M.F16S, 0, "field", 60_000), ("f16s_sr_mean", M.F16S, 1, "mean", 200_000),
-            ("bf16", M.BF16, 0, "field", 60_000), ("bf16_sr_mean", M.BF16, 1, "mean", 200_000))
-    for name, storage, sr, crit, cap in runs:
+    for name, storage_name, sr, crit, cap in runs:
+        storage = getattr(M, storage_name)
         sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.FIELDS,
                            storage=storage, tau_plus=1.0, g=(g, 0.0), scale_exp=sigma, stochastic_rounding=sr)
         if out["setup_s"] is None:
@@ -177,7 +183,8 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8):
             rec["scale_exp"] = sigma if storage == M.F16S else None
             rec["permeability_rel_err_vs_f32"] = abs(k / k_ref - 1.0)
         out["runs"][name] = rec
-        print(f"# steady {name}: {steps} steps, {dt:.2f} s, residual {res:.2e}", file=sys.stderr, flush=True)
+        print(f"# steady s={s:g} {name}: {steps} steps, {dt:.2f} s, residual {res:.2e}", file=sys.stderr,
+              flush=True)
         del sim
     return out
 
@@ -636,6 +643,8 @@ def main():
         out["s_sweep"] = karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m)
     if not args.no_steady:
         out["time_to_steady"] = porous_time_to_steady(M, units, nodesets, np, torch)
+        out["time_to_steady_inertial"] = porous_time_to_steady(M, units, nodesets, np, torch, s=4.0,
+                                                               runs=TTS_RUNS_INERTIAL)
     if not args.no_cpu_baseline:
         import copy
 
