@@ -129,8 +129,8 @@ def karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m, scales=(2
 TTS_RUNS = (("f32", "F32", 0, "field", 200_000), ("f32_mean", "F32", 0, "mean", 200_000),
             ("f16s", "F16S", 0, "field", 60_000), ("f16s_sr_mean", "F16S", 1, "mean", 200_000),
             ("bf16", "BF16", 0, "field", 60_000), ("bf16_sr_mean", "BF16", 1, "mean", 200_000))
-TTS_RUNS_INERTIAL = (("f32", "F32", 0, "field", 600_000), ("f16s_sr_mean", "F16S", 1, "mean", 600_000),
-                     ("bf16_sr_mean", "BF16", 1, "mean", 600_000))
+TTS_RUNS_INERTIAL = (("f32", "F32", 0, "field", 600_000), ("f32_mean", "F32", 0, "mean", 600_000),
+                     ("f16s_sr_mean", "F16S", 1, "mean", 600_000), ("bf16_sr_mean", "BF16", 1, "mean", 600_000))
 
 
 def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s=1.0, runs=TTS_RUNS):
