@@ -512,6 +512,8 @@ def main():
     ap.add_argument("--stratified", action="store_true",
                     help="Karman nodes by stratified (jittered) samples instead of Poisson-disk fronts")
     ap.add_argument("--no-s-sweep", action="store_true", help="skip the s = 2, 4 stability runs")
+    ap.add_argument("--reorder", type=int, default=1, choices=[0, 1, 2],
+                    help="node order: 0 as generated, 1 Morton, 2 reverse Cuthill-McKee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
     ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
@@ -568,7 +570,7 @@ def main():
     tau = units.tau_for_reynolds(0.05, 1.0, dx, re)
     tau_m = 0.5 + (3.0 / 16.0) / (tau - 0.5) if args.trt else tau
     K = args.K
-    b = M.build_stencils_for(ns, K, dx, lattice_h=ns.h if args.hybrid else 0.0)
+    b = M.build_stencils_for(ns, K, dx, lattice_h=ns.h if args.hybrid else 0.0, reorder=args.reorder)
     perm = b["perm"]
     n_lag = b["n_lagrange"]
     print(f"# built {ns.n} nodes ({n_lag} block centres), K={K}, dx={dx:.4g}, tau={tau:.4f} in "
@@ -631,7 +633,7 @@ def main():
                    "nodes": n, "block_centres": n_lag, "K": K, "s": args.s, "block": args.block,
                    "xcd_remap": args.xcd,
                    "fp32_arith": args.fp32_arith, "alternate_sweeps": args.sweeps,
-                   "cached_weights": args.cached, "tile": args.tile,
+                   "cached_weights": args.cached, "tile": args.tile, "reorder": args.reorder,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -79,7 +79,9 @@ typedef struct mlbm_geometry {
 
 typedef struct mlbm_stencil_params {
     int32_t K;               /* stencil size, 7 <= K <= 32 (nearest nodes, self included) */
-    int32_t reorder;         /* 0 keep the caller's order, 1 Morton (Z) order     */
+    int32_t reorder;         /* 0 keep the caller's order, 1 Morton (Z) order,
+                                2 reverse Cuthill-McKee order of the graph linking
+                                each node to its K nearest nodes                  */
     double dx;               /* streaming distance dx > 0, units of xy             */
     int32_t n_threads;       /* host threads; 0 = all hardware threads            */
     double lattice_h;        /* > 0: hybrid set whose regular part is a square

@@ -491,7 +491,7 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
     if (g->n_disks < 0 || (g->n_disks > 0 && !g->disks)) return fail(MLBM_ERR_ARG, "bad disk list");
     if (p->K < 7 || p->K > MAXK) return fail(MLBM_ERR_ARG, "K=%d outside [7, %d]", p->K, MAXK);
     if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(MLBM_ERR_ARG, "dx must be positive");
-    if (p->reorder != 0 && p->reorder != 1) return fail(MLBM_ERR_ARG, "reorder must be 0 or 1");
+    if (p->reorder < 0 || p->reorder > 2) return fail(MLBM_ERR_ARG, "reorder must be 0, 1 or 2");
     if (!(p->lattice_h >= 0.0) || !std::isfinite(p->lattice_h)) return fail(MLBM_ERR_ARG, "lattice_h must be >= 0");
     if (p->lattice_h > 0.0 && p->K < 10) return fail(MLBM_ERR_ARG, "hybrid stencils need K >= 10");
     const int64_t n = g->n;
@@ -578,6 +578,63 @@ extern "C" int mlbm_build_stencils(const mlbm_geometry *g, const mlbm_stencil_pa
         std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
             return lag[a] != lag[b] ? lag[a] < lag[b] : key[a] < key[b];
         });
+    } else if (p->reorder == 2) {
+        // reverse Cuthill-McKee order of the undirected graph that links every
+        // node with its K nearest nodes: breadth-first from a far node of each
+        // connected part, unvisited neighbours in order of increasing degree
+        // (ties: nearer first), the whole sequence reversed
+        const int Kg = p->K;
+        std::vector<int32_t> out_nb((size_t)n * Kg);
+        parallel([&](int64_t a, int64_t b, std::vector<Cand> &cand) {
+            Cand nb[8 * MAXK];
+            for (int64_t i = a; i < b; ++i) {
+                B.nearest_n(i, Kg, cand, nb);
+                for (int j = 0; j < Kg; ++j) out_nb[(size_t)i * Kg + j] = (int32_t)nb[j].j;
+            }
+        });
+        std::vector<int64_t> start(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) start[i + 1] += Kg;
+        for (size_t e = 0; e < out_nb.size(); ++e) start[out_nb[e] + 1] += 1;
+        for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
+        std::vector<int32_t> nbr(start[n]);
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int j = 0; j < Kg; ++j) nbr[fill[i]++] = out_nb[(size_t)i * Kg + j];
+        for (int64_t i = 0; i < n; ++i)
+            for (int j = 0; j < Kg; ++j) {
+                const int32_t w = out_nb[(size_t)i * Kg + j];
+                nbr[fill[w]++] = (int32_t)i;
+            }
+        auto degree = [&](int64_t v) { return start[v + 1] - start[v]; };
+        for (int64_t i = 0; i < n; ++i)
+            std::stable_sort(nbr.begin() + start[i], nbr.begin() + start[i + 1],
+                             [&](int32_t x, int32_t y) { return degree(x) < degree(y); });
+        // visit stamps: 0 unvisited, 1 placed, 2 + c reached by the trial search of part c
+        std::vector<int64_t> mark(n, 0), trial;
+        std::vector<int64_t> order;
+        order.reserve(n);
+        auto bfs = [&](int64_t s0, std::vector<int64_t> &seq, int64_t stamp) {
+            size_t head = seq.size();
+            seq.push_back(s0);
+            mark[s0] = stamp;
+            while (head < seq.size()) {
+                const int64_t v = seq[head++];
+                for (int64_t e = start[v]; e < start[v + 1]; ++e) {
+                    const int64_t w = nbr[e];
+                    if (mark[w] != stamp && mark[w] != 1) { mark[w] = stamp; seq.push_back(w); }
+                }
+            }
+        };
+        int64_t part = 0;
+        for (int64_t s0 = 0; s0 < n; ++s0) {
+            if (mark[s0] == 1) continue;
+            trial.clear();
+            bfs(s0, trial, 2 + part++);   // the last node reached lies far from s0
+            bfs(trial.back(), order, 1);
+        }
+        std::reverse(order.begin(), order.end());
+        perm = order;
+        std::stable_partition(perm.begin(), perm.end(), [&](int64_t v) { return lag[v] == 0; });
     }
     for (int64_t i = 0; i < n; ++i) inv[perm[i]] = i;
 

@@ -315,8 +315,8 @@ def test_zero_steps_and_errors(M):
 # Full-size workloads: library-built stencils, sampled oracle nodes
 # ---------------------------------------------------------------------------
 
-def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed, lattice_h=None):
-    b = M.build_stencils_for(ns, K, dx, lattice_h=lattice_h or 0.0)
+def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed, lattice_h=None, reorder=1):
+    b = M.build_stencils_for(ns, K, dx, lattice_h=lattice_h or 0.0, reorder=reorder)
     perm = b["perm"]
     rho0, u0 = initial_fields(ns, seed, amp_u, 0.002)
     sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=variant,
@@ -339,16 +339,18 @@ def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed, la
     return rho[inv[pick]], u[inv[pick]], r_ref, u_ref, red.cpu().numpy(), sim, b
 
 
-@pytest.mark.parametrize("s", [1.0, 4.0])
-def test_karman_full_size_sampled(M, s):
-    # the bench's workload: ~5e5 Poisson-disk nodes, 22D x 4.1D channel, Re = 100 s
+@pytest.mark.parametrize("s,reorder", [(1.0, 1), (4.0, 1), (1.0, 2)])
+def test_karman_full_size_sampled(M, s, reorder):
+    # the bench's workload: ~5e5 Poisson-disk nodes, 22D x 4.1D channel, Re = 100 s;
+    # Morton (1) or reverse Cuthill-McKee (2) node order
     ns = nodesets.karman(poisson=True)
-    print(f"[full] karman-poisson n={ns.n} s={s:g}", flush=True)
+    print(f"[full] karman-poisson n={ns.n} s={s:g} reorder={reorder}", flush=True)
     from paper_2312_14789_amd import units
 
     dx = units.delta_x(ns.h_min, s)
     tau = units.tau_for_reynolds(0.05, 1.0, dx, 100.0 * s)
-    r, u, r_ref, u_ref, red, sim, b = _sampled(M, ns, 16, dx, 0, 1, tau, tau, (0.0, 0.0), 0.05, 48, 21)
+    r, u, r_ref, u_ref, red, sim, b = _sampled(M, ns, 16, dx, 0, 1, tau, tau, (0.0, 0.0), 0.05, 48, 21,
+                                               reorder=reorder)
     assert rel_l2(u, u_ref) < 1e-5
     assert np.abs(r - r_ref).max() < 1e-6
     assert red[8] == 0

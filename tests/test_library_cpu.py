@@ -49,12 +49,13 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("reorder", [1, 2])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_builder_matches_oracle(case):
+def test_builder_matches_oracle(case, reorder):
     ns, K, dx, *lat = CASES[case]()
     lat = lat[0] if lat else None
     dx = ns.h / 2.0 if dx is None else dx
-    b = M.build_stencils_for(ns, K, dx, reorder=1, n_threads=4, lattice_h=lat or 0.0)
+    b = M.build_stencils_for(ns, K, dx, reorder=reorder, n_threads=4, lattice_h=lat or 0.0)
     st = omlbm.build_stencils(ns, K, dx, lattice_h=lat)
     perm = b["perm"]
     assert sorted(perm.tolist()) == list(range(ns.n))
@@ -226,3 +227,21 @@ def test_tile_halo_packing():
             assert np.isin(nodes, hl).all()
     with pytest.raises(M.MlbmError):
         M.pack_tiles(b["idx"], 100)
+
+
+def test_reverse_cuthill_mckee_order():
+    # on a periodic lattice with 5-node stencils (the node and its four
+    # nearest) the order keeps every stencil within a narrow band of indices
+    ns = nodesets.jittered_grid(40, seed=2, jitter=0.05)
+    n = ns.n
+    b0 = M.build_stencils_for(ns, 9, 1.0 / 40 / 1.5, reorder=0, n_threads=4)
+    b2 = M.build_stencils_for(ns, 9, 1.0 / 40 / 1.5, reorder=2, n_threads=4)
+    assert sorted(b2["perm"].tolist()) == list(range(n))
+    bw0 = np.abs(b0["idx"] - np.arange(n)[:, None]).max()
+    bw2 = np.abs(b2["idx"] - np.arange(n)[:, None]).max()
+    # row-major order of a periodic 40 x 40 grid wraps: bandwidth ~ n; the
+    # breadth-first order keeps it near the size of a few fronts
+    assert bw2 < 0.25 * bw0
+    # the same stencils, renumbered (reorder 0 keeps the caller's order)
+    np.testing.assert_array_equal(b0["perm"], np.arange(n))
+    np.testing.assert_array_equal(b2["perm"][b2["idx"]], b0["idx"][b2["perm"]])
