@@ -561,6 +561,9 @@ def main():
 
     storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]
     t0 = time.time()
+    # Poisson-disk nodes for the fully scattered set; the hybrid set keeps its
+    # jittered-lattice zone, which meets the lattice without a seam (a
+    # Poisson-disk zone against the lattice diverges at s = 2)
     poisson = not (args.stratified or args.hybrid)
     ns = nodesets.karman(n_target=args.nodes, hybrid=args.hybrid, poisson=poisson)
     # streaming distance from the finest spacing (refined ring around the
@@ -624,7 +627,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "Karman street channel 22Dx4.1D, cylinder D at (2D,2D), " +
                                (f"{n} nodes, hybrid: {n_lag} on a square lattice (biquadratic Lagrange), "
-                                f"{n - n_lag} scattered near the cylinder and in its wake (4x denser within "
+                                f"{n - n_lag} scattered near the cylinder and in its wake "
+                                f"({'Poisson-disk, ' if poisson else 'stratified, '}4x denser within "
                                 "1D of the cylinder), " if args.hybrid else
                                 f"{n} scattered nodes ({'Poisson-disk, ' if poisson else 'stratified, '}"
                                 "4x denser within 1D of the cylinder), ") +

@@ -234,11 +234,12 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     then D/(10 m) for an integer m so that it divides both channel sides.
 
     poisson: Poisson-disk nodes instead of the stratified samples: advancing
-    fronts grown from the cylinder surface over the whole channel, spacing
-    h_f within 1D of the cylinder surface rising linearly to h_b over the next
-    4 h_f (h_b sized so that the set holds about n_target nodes)."""
-    if poisson and not hybrid:
-        return _karman_poisson(n_target, seed, D, u_max)
+    fronts grown from the cylinder surface, spacing h_f within 1D of the
+    cylinder surface rising linearly to h_b over the next 4 h_f; over the whole
+    channel (h_b sized so that the set holds about n_target nodes), or with
+    hybrid over the scattered zone only, up to the fixed lattice."""
+    if poisson:
+        return _karman_poisson(n_target, seed, D, u_max, hybrid, wake)
     rng = np.random.default_rng(seed)
     Lx, Ly = 22.0 * D, 4.1 * D
     cx, cy, r = 2.0 * D, 2.0 * D, 0.5 * D
@@ -305,7 +306,7 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
 _FRONT_DENSITY = 0.89
 
 
-def _karman_poisson(n_target, seed, D, u_max):
+def _karman_poisson(n_target, seed, D, u_max, hybrid=False, wake=6.0):
     rng = np.random.default_rng(seed)
     Lx, Ly = 22.0 * D, 4.1 * D
     cx, cy, r = 2.0 * D, 2.0 * D, 0.5 * D
@@ -313,6 +314,8 @@ def _karman_poisson(n_target, seed, D, u_max):
     a_fine = np.pi * ((r + ring) ** 2 - r ** 2)
     a_bulk = Lx * Ly - np.pi * (r + ring) ** 2
     hb = math.sqrt(_FRONT_DENSITY * (a_bulk + 4.0 * a_fine) / n_target)
+    if hybrid:
+        hb = 0.1 * D / max(1, round(0.1 * D / hb))
     hf = 0.5 * hb
     lo, hi = np.zeros(2), np.array([Lx, Ly])
 
@@ -320,9 +323,18 @@ def _karman_poisson(n_target, seed, D, u_max):
         t = np.clip((np.hypot(p[:, 0] - cx, p[:, 1] - cy) - r - ring) / (4.0 * hf), 0.0, 1.0)
         return hf + (hb - hf) * t
 
+    def in_zone(p, margin=0.0):
+        # the scattered zone of the hybrid set: within 2D of the cylinder centre
+        # and the wake box [2D, 2D + wake D] x [0.5D, 3.5D]
+        near = np.hypot(p[:, 0] - cx, p[:, 1] - cy) < 2.0 * D + margin
+        box = ((p[:, 0] >= cx - margin) & (p[:, 0] <= cx + wake * D + margin)
+               & (np.abs(p[:, 1] - cy) <= 1.5 * D + margin))
+        return near | box
+
     def admit(c):
-        return ((c[:, 0] > 0.5 * hb) & (c[:, 0] < Lx - 0.5 * hb) & (c[:, 1] > 0.5 * hb) & (c[:, 1] < Ly - 0.5 * hb)
-                & (np.hypot(c[:, 0] - cx, c[:, 1] - cy) > r + 0.5 * hf))
+        ok = ((c[:, 0] > 0.5 * hb) & (c[:, 0] < Lx - 0.5 * hb) & (c[:, 1] > 0.5 * hb) & (c[:, 1] < Ly - 0.5 * hb)
+              & (np.hypot(c[:, 0] - cx, c[:, 1] - cy) > r + 0.5 * hf))
+        return ok & in_zone(c, 0.5 * hb) if hybrid else ok
 
     surf = _circle_nodes(cx, cy, r, hf)
     nbx, nby = int(round(Lx / hb)), int(round(Ly / hb))
@@ -331,20 +343,25 @@ def _karman_poisson(n_target, seed, D, u_max):
     bnd = np.concatenate([
         np.stack([xs, np.zeros_like(xs)], 1), np.stack([xs, np.full_like(xs, Ly)], 1),
         np.stack([np.zeros_like(ys), ys], 1), np.stack([np.full_like(ys, Lx), ys], 1)])
-    fluid = _front_fill(bnd, surf, spacing, admit, rng, window=6)
-    xy = np.concatenate([fluid, surf, bnd])
-    kind = np.concatenate([np.zeros(len(fluid), np.uint8), np.full(len(surf), WALL, np.uint8),
+    lat = np.zeros((0, 2))
+    if hybrid:
+        lat = _grid(lo, hi, hb)
+        lat = lat[~in_zone(lat)]
+    fluid = _front_fill(np.concatenate([bnd, lat]), surf, spacing, admit, rng, window=6)
+    xy = np.concatenate([lat, fluid, surf, bnd])
+    kind = np.concatenate([np.zeros(len(lat) + len(fluid), np.uint8), np.full(len(surf), WALL, np.uint8),
                            np.full(len(bnd), DIRICHLET, np.uint8)])
-    hloc = np.concatenate([spacing(fluid), np.full(len(surf), hf), np.full(len(bnd), hb)])
-    keep = _cleanup(xy, hloc, kind != FLUID, lo, hi, (False, False))
+    hloc = np.concatenate([np.full(len(lat), hb), spacing(fluid), np.full(len(surf), hf), np.full(len(bnd), hb)])
+    fixed = np.concatenate([np.ones(len(lat), bool), np.zeros(len(fluid), bool), np.ones(len(surf) + len(bnd), bool)])
+    keep = _cleanup(xy, hloc, fixed, lo, hi, (False, False))
     xy, kind = xy[keep], kind[keep]
     bc = np.zeros((len(xy), 3))
     bc[:, 0] = 1.0
     inout = (kind == DIRICHLET) & ((np.isclose(xy[:, 0], 0.0)) | (np.isclose(xy[:, 0], Lx)))
     y = xy[:, 1]
     bc[inout, 1] = 4.0 * u_max * y[inout] * (Ly - y[inout]) / Ly ** 2
-    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(False, False),
-                   disks=np.array([[cx, cy, r]]), bc=bc, h=hb, name="karman-poisson", h_min=hf)
+    return NodeSet(xy=xy, kind=kind, lo=lo, hi=hi, periodic=(False, False), disks=np.array([[cx, cy, r]]), bc=bc,
+                   h=hb, name="karman-hybrid-poisson" if hybrid else "karman-poisson", h_min=hf)
 
 
 def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_cand: int = 12,
@@ -367,8 +384,7 @@ def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_can
             return cKDTree(pts, boxsize=[period_x, 1e30])
         return cKDTree(pts)
 
-    base = np.concatenate([fixed, seeds])
-    placed = base
+    base_tree = tree(np.concatenate([fixed, seeds]))
     front = seeds
     out = []
     ang0 = 2.0 * np.pi * np.arange(n_cand) / n_cand
@@ -385,7 +401,10 @@ def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_can
         cand, hc = cand[ok], hc[ok]
         if len(cand) == 0:
             break
-        dist, _ = tree(placed).query(cand)
+        dist, _ = base_tree.query(cand)
+        recent = out[-window:] if window else out
+        if recent:
+            dist = np.minimum(dist, tree(np.concatenate(recent)).query(cand)[0])
         ok = dist >= 0.99 * hc
         cand, hc = cand[ok], hc[ok]
         if len(cand) == 0:
@@ -398,10 +417,6 @@ def _front_fill(fixed: np.ndarray, seeds: np.ndarray, spacing, admit, rng, n_can
                 taken[i] = True
         front = cand[taken]
         out.append(front)
-        if window:
-            placed = np.concatenate([base] + out[-window:])
-        else:
-            placed = np.concatenate([placed, front])
     return np.concatenate(out) if out else np.zeros((0, 2))
 
 
