@@ -567,7 +567,8 @@ def porous(n_target: int = 1_000_000, phi: float = 0.7, seed: int = 231214789,
 
 
 def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, band: float = 0.04,
-                   r_range=(0.06, 0.1), seed: int = 231214789, L: float = 1.0, gap: float | None = None) -> NodeSet:
+                   r_range=(0.06, 0.1), seed: int = 231214789, L: float = 1.0, gap: float | None = None,
+                   seam: float = 0.01, seam_jitter: float = 0.25) -> NodeSet:
     """The porous sample of Sec. 3.2: the box [0, L]^2, periodic along x,
     no-slip walls on y = 0 and y = L (nodes on them), random non-overlapping
     disks (radii uniform in r_range, porosity phi, clear of the walls), and a
@@ -576,7 +577,10 @@ def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, b
     from h_surf on the disk surfaces to h at the band's edge (placed by
     advancing Poisson-disk fronts from the surfaces), and nodes on every disk
     surface at spacing h_surf.  Disks keep `gap` (default 2 h_surf) from each
-    other and from the walls."""
+    other and from the walls.  seam > 0: the outer `seam` of the band holds
+    lattice positions moved by U(-seam_jitter h, seam_jitter h) instead of
+    front-filled nodes, so the fronts meet a jittered lattice and the exact
+    lattice starts behind it."""
     from scipy.spatial import cKDTree
 
     rng = np.random.default_rng(seed)
@@ -612,6 +616,12 @@ def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, b
     X, Y = np.meshgrid(np.arange(nx) * (L / nx), np.arange(ny + 1) * (L / ny), indexing="xy")
     lat = np.stack([X.ravel(), Y.ravel()], axis=1)
     dl = surface_distance(lat)
+    jit = np.zeros((0, 2))
+    if seam > 0.0:
+        jit = lat[(dl > band - seam) & (dl <= band)]
+        jit = jit[(jit[:, 1] > 0.5 * h) & (jit[:, 1] < L - 0.5 * h)]
+        jit = jit + rng.uniform(-seam_jitter * h, seam_jitter * h, size=jit.shape)
+        jit[:, 0] = np.mod(jit[:, 0], L)
     lat = lat[dl > band]
     surf = np.concatenate([_circle_nodes(c[0], c[1], c[2], h_surf) for c in disks]) if len(disks) else np.zeros((0, 2))
     surf[:, 0] = np.mod(surf[:, 0], L)
@@ -628,9 +638,11 @@ def porous_channel(phi: float = 0.64, h: float = 5e-3, h_surf: float = 2.5e-3, b
 
     def admit(c):
         dc = surface_distance(c)
-        return (c[:, 1] > 0.5 * h_surf) & (c[:, 1] < L - 0.5 * h_surf) & (dc > 0.5 * h_surf) & (dc <= band + 0.5 * h)
+        return ((c[:, 1] > 0.5 * h_surf) & (c[:, 1] < L - 0.5 * h_surf) & (dc > 0.5 * h_surf)
+                & (dc <= band - seam + 0.5 * h))
 
-    cand = _front_fill(np.concatenate([lat_in, walls]), surf, spacing, admit, rng, period_x=L)
+    cand = _front_fill(np.concatenate([lat_in, walls, jit]), surf, spacing, admit, rng, period_x=L)
+    cand = np.concatenate([jit, cand])
     hloc_c = spacing(cand)
     xy = np.concatenate([lat_in, cand, surf, walls])
     kind = np.concatenate([np.zeros(len(lat_in) + len(cand), np.uint8), np.full(len(surf) + len(walls), WALL, np.uint8)])
