@@ -131,8 +131,8 @@ typedef struct mlbm_stencils {
  * lattice neighbours x + lattice_h e_1 .. e_8, member 8 is the node itself,
  * any further members the node itself with weight 0, and its weights are the
  * tensor-product quadratic Lagrange weights through the block, the same for
- * every block centre (w_lagrange).  With reorder = 1 the block centres follow
- * every other node.
+ * every block centre (w_lagrange).  With reorder = 1 or 2 the block centres
+ * follow every other node.
  * Errors: MLBM_ERR_ARG (null pointers, K out of range, dx <= 0),
  * MLBM_ERR_GEOMETRY (K > n, node inside a solid, empty box, node outside the
  * box), MLBM_ERR_SINGULAR (a local system is singular or fails to reproduce
