@@ -128,9 +128,11 @@ def karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m, scales=(2
 
 TTS_RUNS = (("f32", "F32", 0, "field", 200_000), ("f32_mean", "F32", 0, "mean", 200_000),
             ("f16s", "F16S", 0, "field", 60_000), ("f16s_sr_mean", "F16S", 1, "mean", 200_000),
-            ("bf16", "BF16", 0, "field", 60_000), ("bf16_sr_mean", "BF16", 1, "mean", 200_000))
+            ("bf16", "BF16", 0, "field", 60_000), ("bf16_sr_mean", "BF16", 1, "mean", 200_000),
+            ("f16s_sr_mean_w16", "F16S", 1, "mean", 200_000), ("bf16_sr_mean_w16", "BF16", 1, "mean", 200_000))
 TTS_RUNS_INERTIAL = (("f32", "F32", 0, "field", 600_000), ("f32_mean", "F32", 0, "mean", 600_000),
-                     ("f16s_sr_mean", "F16S", 1, "mean", 600_000), ("bf16_sr_mean", "BF16", 1, "mean", 600_000))
+                     ("f16s_sr_mean", "F16S", 1, "mean", 600_000), ("bf16_sr_mean", "BF16", 1, "mean", 600_000),
+                     ("f16s_sr_mean_w16", "F16S", 1, "mean", 600_000))
 
 
 def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s=1.0, runs=TTS_RUNS):
@@ -138,7 +140,7 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s
     Re ~ 0.1; s = 4: inertial, Re ~ 7) run from rest to steady state with
     FP32, FP16 (scaled offsets) and BF16 state: steps, seconds and
     permeability, the 16-bit permeabilities relative to the FP32 one (the
-    first run of `runs` must be FP32).  Criteria: the field residual between checks
+    first run of `runs` must be FP32; runs named *_w16 read FP16 weights).  Criteria: the field residual between checks
     100 steps apart below tol (FP32; 16-bit rounding keeps the field residual
     near the storage ulp, so 16-bit runs stop at the step cap), and the
     relative change of the mean velocity between checks 1000 steps apart below
@@ -159,7 +161,8 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s
     for name, storage_name, sr, crit, cap in runs:
         storage = getattr(M, storage_name)
         sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.FIELDS,
-                           storage=storage, tau_plus=1.0, g=(g, 0.0), scale_exp=sigma, stochastic_rounding=sr)
+                           storage=storage, tau_plus=1.0, g=(g, 0.0), scale_exp=sigma, stochastic_rounding=sr,
+                           weights16=name.endswith("_w16"))
         if out["setup_s"] is None:
             out["setup_s"] = round(time.time() - t0, 2)
         sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
@@ -171,7 +174,8 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s
         dt = time.perf_counter() - t1
         k = nu * (red[M._lib.RED_INT_UX] / 1.0) / g * dx * dx
         umean = red[M._lib.RED_INT_UX] / ns.fluid_area()
-        rec = {"criterion": crit, "check_every": every, "tol": tol_c, "stochastic_rounding": sr, "steps": steps,
+        rec = {"criterion": crit, "check_every": every, "tol": tol_c, "stochastic_rounding": sr,
+               "weights": "f16" if name.endswith("_w16") else ("f32" if storage != M.F64 else "f64"), "steps": steps,
                "converged": bool(res < tol_c),
                "seconds": round(dt, 3), "residual": res, "permeability": k,
                "Re": umean / dx / nu, "MNUPS": round(ns.n * steps / dt / 1e6, 1)}
@@ -512,6 +516,8 @@ def main():
     ap.add_argument("--stratified", action="store_true",
                     help="Karman nodes by stratified (jittered) samples instead of Poisson-disk fronts")
     ap.add_argument("--no-s-sweep", action="store_true", help="skip the s = 2, 4 stability runs")
+    ap.add_argument("--weights16", type=int, default=0, help="FP16 weights (with --storage f16s or bf16)")
+    ap.add_argument("--sr", type=int, default=0, help="stochastic rounding of 16-bit stores")
     ap.add_argument("--reorder", type=int, default=1, choices=[0, 1, 2],
                     help="node order: 0 as generated, 1 Morton, 2 reverse Cuthill-McKee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -582,7 +588,8 @@ def main():
                        storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
                        block=args.block, xcd_remap=args.xcd, scale_exp=12, fp32_arith=args.fp32_arith,
                        alternate_sweeps=args.sweeps, cached_weights=args.cached,
-                       tile=args.tile, lagrange=b["lagrange"], w_lagrange=b["w_lagrange"])
+                       tile=args.tile, lagrange=b["lagrange"], w_lagrange=b["w_lagrange"],
+                       stochastic_rounding=args.sr, weights16=args.weights16)
     n = ns.n
     sim.init_state(np.ones(n), np.zeros((n, 2)))
     sim.step(args.warmup)
@@ -603,7 +610,7 @@ def main():
         print(f"# warning: {int(red[M._lib.RED_N_BAD])} unstable nodes", file=sys.stderr)
     mnups = n * args.steps / (ms / 1e3) / 1e6
     kp = sim.sizes.k_padded
-    bpn_rbf = units.algorithmic_bytes_per_node(M.POPULATIONS, storage, kp)
+    bpn_rbf = units.algorithmic_bytes_per_node(M.POPULATIONS, storage, kp, args.weights16)
     bpn_lag = units.block_centre_bytes_per_node(M.POPULATIONS, storage)
     bpn = ((n - n_lag) * bpn_rbf + n_lag * bpn_lag) / n
     achieved = bpn * n / per_launch_s / 1e9
@@ -622,8 +629,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32" if args.fp32_arith else "f32 state+weights, f64 registers",
-                  "f16s": "f16 state (scaled offsets), f32 weights+registers",
-                  "bf16": "bf16 state, f32 weights+registers"}[args.storage],
+                  "f16s": f"f16 state (scaled offsets), {'f16' if args.weights16 else 'f32'} weights, f32 registers",
+                  "bf16": f"bf16 state, {'f16' if args.weights16 else 'f32'} weights, f32 registers"}[args.storage],
         "data": "synthetic",
         "config": {"workload": "Karman street channel 22Dx4.1D, cylinder D at (2D,2D), " +
                                (f"{n} nodes, hybrid: {n_lag} on a square lattice (biquadratic Lagrange), "

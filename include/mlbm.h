@@ -180,6 +180,16 @@ int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t n, int32_t
                              void *idx_packed, void *w_packed, uint16_t *flags);
 
 /*
+ * FP16 copy of packed FP32 weights for mlbm_step_params.weights16 (16-bit
+ * states; not in the paper, whose weights are doubles, Sec. 3.2 Eq. 27):
+ * out[i] = in[i] rounded to the nearest FP16 value, ties to even, in the same
+ * layout (count = w_bytes / 4 of the FP32 packing).  Host buffers, caller
+ * owned.  Errors: MLBM_ERR_ARG (null pointers, count < 0, a value that is not
+ * finite or whose magnitude reaches 65520, beyond FP16's range).
+ */
+int mlbm_weights_to_f16(int64_t count, const float *in, uint16_t *out);
+
+/*
  * Sets MLBM_FLAG_LAGRANGE in packed flags[i] where lagrange[i] != 0 (the
  * builder's lagrange output), so that mlbm_step takes those nodes' weights
  * from mlbm_device_state.w_lagrange.  Errors: MLBM_ERR_ARG.
@@ -232,6 +242,11 @@ typedef struct mlbm_step_params {
                                 from a counter-based hash of node, component and
                                 mlbm_device_state.step_count); 0 = to nearest even.
                                 Batched runs always round to nearest.              */
+    int32_t weights16;       /* MLBM_F16S / MLBM_BF16 only: 1 = the packed weights are
+                                FP16 (mlbm_weights_to_f16), half the weight bytes;
+                                their sum is then taken as exactly 1 by the step and
+                                by the momentum exchange of mlbm_macroscopic, as
+                                for FP32 weights.  0 = FP32 weights               */
 } mlbm_step_params;
 
 typedef struct mlbm_device_state {

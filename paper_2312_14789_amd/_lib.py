@@ -58,7 +58,8 @@ class StepParams(ctypes.Structure):
                 ("g", ctypes.c_double * 2), ("scale_exp", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("fp32_arith", ctypes.c_int32), ("alternate_sweeps", ctypes.c_int32),
-                ("cached_weights", ctypes.c_int32), ("stochastic_rounding", ctypes.c_int32)]
+                ("cached_weights", ctypes.c_int32), ("stochastic_rounding", ctypes.c_int32),
+                ("weights16", ctypes.c_int32)]
 
 
 class DeviceState(ctypes.Structure):
@@ -113,6 +114,7 @@ def _load():
                                                     ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p,
                                                     _p, _p]),
         "mlbm_mark_lagrange": (ctypes.c_int, [ctypes.c_int64, _p, _p]),
+        "mlbm_weights_to_f16": (ctypes.c_int, [ctypes.c_int64, _p, _p]),
         "mlbm_batch_init": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), _p]),
         "mlbm_step_batched": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), ctypes.c_int32,
                                              ctypes.c_double, ctypes.c_int32, P(ctypes.c_int32), _p]),
@@ -158,7 +160,7 @@ lib = _load()
 
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_pack_stencils_range",
-           "mlbm_mark_lagrange",
+           "mlbm_mark_lagrange", "mlbm_weights_to_f16",
            "mlbm_tile_sizes", "mlbm_pack_tiles", "mlbm_init_state", "mlbm_batch_init", "mlbm_step_batched",
            "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
            "mlbm_version"]

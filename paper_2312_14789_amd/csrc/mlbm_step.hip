@@ -221,8 +221,9 @@ __device__ __forceinline__ T stream_load(const T *p, int cached) {
     return cached ? *p : __builtin_nontemporal_load(p);
 }
 
-// four weights (stencil members 4q..4q+3) of arriving population k+1
-template <int S, int KQ, class C>
+// four weights (stencil members 4q..4q+3) of arriving population k+1; W16
+// (16-bit states only): the weights are FP16 in the same layout
+template <int S, int KQ, bool W16 = false, class C>
 __device__ __forceinline__ void load_w4(const void *w, int64_t n, int64_t i, int k, int q, C *o,
                                         int cached = 0) {
     if constexpr (S == MLBM_F64) {
@@ -230,6 +231,19 @@ __device__ __forceinline__ void load_w4(const void *w, int64_t n, int64_t i, int
         d2 a = stream_load(p + ((int64_t)(k * 2 * KQ + 2 * q) * n + i), cached);
         d2 b = stream_load(p + ((int64_t)(k * 2 * KQ + 2 * q + 1) * n + i), cached);
         o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    } else if constexpr (S == MLBM_F16S || S == MLBM_BF16) {
+        if constexpr (W16) {
+            const u2 *p = (const u2 *)w;
+            u2 a = stream_load(p + ((int64_t)(k * KQ + q) * n + i), cached);
+            o[0] = half_to_float((unsigned short)(a.x & 0xffffu));
+            o[1] = half_to_float((unsigned short)(a.x >> 16));
+            o[2] = half_to_float((unsigned short)(a.y & 0xffffu));
+            o[3] = half_to_float((unsigned short)(a.y >> 16));
+        } else {
+            const f4 *p = (const f4 *)w;
+            f4 a = stream_load(p + ((int64_t)(k * KQ + q) * n + i), cached);
+            o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+        }
     } else {
         const f4 *p = (const f4 *)w;
         f4 a = stream_load(p + ((int64_t)(k * KQ + q) * n + i), cached);
@@ -465,7 +479,7 @@ __device__ __forceinline__ void for_quads(F &&f) {
 // instantiates the block-centre kernel of a hybrid set: every node it visits
 // is a block centre with the shared weights (a node without the flag gets a
 // NaN state, so a wrong node range shows up at once).
-template <int S, class CG, class C, int KQ, bool LDS>
+template <int S, class CG, class C, int KQ, bool LDS, bool W16 = false>
 __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int64_t i, int self) {
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
@@ -522,7 +536,7 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 CG wv[4];
-                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
+                load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
                 const bool flip = (bb >> k) & 1u;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -553,7 +567,7 @@ __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int
 // are left to the compiler, 1 = no constraint).
 template <int S, int KQ> constexpr int block_waves() { return KQ != 0 ? 1 : (S == MLBM_F64 ? 3 : 6); }
 
-template <int S, class CG, class C, int KQ, bool LDS>
+template <int S, class CG, class C, int KQ, bool LDS, bool W16 = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_waves<S, KQ>()))) k_step_pop(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
@@ -561,14 +575,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_
         if constexpr (LDS) stage_halo<pop_bytes<S>(), KQ == 0>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
         if (i < a.n)
-            pop_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i,
+            pop_node<S, CG, C, KQ, LDS, W16>(a, LDS ? (const void *)smem : a.in, i,
                                         KQ == 0 && LDS ? self0 + (int)threadIdx.x : (int)i);
     });
 }
 
 // ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
 
-template <int S, class CG, class C, int KQ, bool LDS>
+template <int S, class CG, class C, int KQ, bool LDS, bool W16 = false>
 __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, int64_t i, int self) {
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
@@ -621,7 +635,7 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 CG wv[4];
-                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
+                load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     ar[k] = fma(wv[j], m[j][0], ar[k]);
@@ -662,7 +676,7 @@ __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, 
     store3<S>(a.out, i, out, a.scale, step_rnd(a, i));
 }
 
-template <int S, class CG, class C, int KQ, bool LDS>
+template <int S, class CG, class C, int KQ, bool LDS, bool W16 = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_waves<S, KQ>()))) k_step_fields(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
@@ -670,7 +684,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_
         if constexpr (LDS) stage_halo<field_bytes<S>(), KQ == 0>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
         if (i < a.n)
-            fields_node<S, CG, C, KQ, LDS>(a, LDS ? (const void *)smem : a.in, i,
+            fields_node<S, CG, C, KQ, LDS, W16>(a, LDS ? (const void *)smem : a.in, i,
                                            KQ == 0 && LDS ? self0 + (int)threadIdx.x : (int)i);
     });
 }
@@ -701,7 +715,7 @@ __device__ __forceinline__ void members_pd(const StepArgs &a, int64_t n, int64_t
     m[3] = (int)(hi >> 16);
 }
 
-template <int S, class CG, class C, int KQ>
+template <int S, class CG, class C, int KQ, bool W16 = false>
 __device__ __forceinline__ void pop_node_pd(const StepArgs &a, const void *src, int64_t i) {
     constexpr int K8Q = (KQ + 1) / 2;  // index planes per departure point
     const int64_t n = a.n;
@@ -724,7 +738,7 @@ __device__ __forceinline__ void pop_node_pd(const StepArgs &a, const void *src, 
                 int m[4];
                 members_pd(a, n, i, k * K8Q + (q >> 1), q & 1, lv, m);
                 CG wv[4];
-                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
+                load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     acc = fma(wv[j], load_comp<S, CG>(src, m[j], c, a.inv_scale), acc);
@@ -746,18 +760,18 @@ __device__ __forceinline__ void pop_node_pd(const StepArgs &a, const void *src, 
     }
 }
 
-template <int S, class CG, class C, int KQ>
+template <int S, class CG, class C, int KQ, bool W16 = false>
 __global__ void __launch_bounds__(256) k_step_pop_pd(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
     for_tiles(a, [&](int64_t tile) __attribute__((always_inline)) {
         stage_halo<pop_bytes<S>(), false>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
-        if (i < a.n) pop_node_pd<S, CG, C, KQ>(a, (const void *)smem, i);
+        if (i < a.n) pop_node_pd<S, CG, C, KQ, W16>(a, (const void *)smem, i);
     });
 }
 
-template <int S, class CG, class C, int KQ>
+template <int S, class CG, class C, int KQ, bool W16 = false>
 __device__ __forceinline__ void fields_node_pd(const StepArgs &a, const void *src, int64_t i) {
     constexpr int K8Q = (KQ + 1) / 2;
     const int64_t n = a.n;
@@ -785,7 +799,7 @@ __device__ __forceinline__ void fields_node_pd(const StepArgs &a, const void *sr
                 int mi[4];
                 members_pd(a, n, i, k * K8Q + (q >> 1), q & 1, lv, mi);
                 CG wv[4];
-                load_w4<S, KQ>(a.w, n, i, k, q, wv, a.cached);
+                load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     CG m[3];
@@ -813,14 +827,14 @@ __device__ __forceinline__ void fields_node_pd(const StepArgs &a, const void *sr
     store3<S>(a.out, i, out, a.scale, step_rnd(a, i));
 }
 
-template <int S, class CG, class C, int KQ>
+template <int S, class CG, class C, int KQ, bool W16 = false>
 __global__ void __launch_bounds__(256) k_step_fields_pd(const StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int self0;
     for_tiles(a, [&](int64_t tile) __attribute__((always_inline)) {
         stage_halo<field_bytes<S>(), false>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
-        if (i < a.n) fields_node_pd<S, CG, C, KQ>(a, (const void *)smem, i);
+        if (i < a.n) fields_node_pd<S, CG, C, KQ, W16>(a, (const void *)smem, i);
     });
 }
 
@@ -876,6 +890,7 @@ struct MacroArgs {
     double gx, gy, inv_dx2;
     float inv_scale;
     int pd;  // idx holds one stencil per departure point: [8][Kp/4][n][4]
+    int w16; // FP16 weights; their sum is then taken as 1, as the step does
 };
 
 // wave64 then workgroup tree sum in a fixed order; lane 0 of wave 0 holds the result
@@ -979,7 +994,8 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                     for (int q = 0; q < KQ; ++q) {
                         const i4 id = load_idx4(a.idx, n, i, a.pd ? k * KQ + q : q);
                         C wv[4];
-                        load_w4<S, KQ>(a.w, n, i, k, q, wv);
+                        if (a.w16) load_w4<S, KQ, true>(a.w, n, i, k, q, wv);
+                        else load_w4<S, KQ, false>(a.w, n, i, k, q, wv);
                         const int ids[4] = {id.x, id.y, id.z, id.w};
                         for (int j = 0; j < 4; ++j) {
                             C sj[8];
@@ -988,7 +1004,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                             sw += (double)wv[j];
                         }
                     }
-                    fback = s + (sw - 1.0) * (double)omega<double>(kp + 1);
+                    fback = s + (a.w16 ? 0.0 : (sw - 1.0) * (double)omega<double>(kp + 1));
                 } else {
                     const double r0 = 1.0 + (double)m[0];
                     fout = feq_off<double>(kp + 1, 1.0, (double)m[0], r0, (double)m[1], (double)m[2]) +
@@ -997,7 +1013,8 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                     for (int q = 0; q < KQ; ++q) {
                         const i4 id = load_idx4(a.idx, n, i, a.pd ? k * KQ + q : q);
                         C wv[4];
-                        load_w4<S, KQ>(a.w, n, i, k, q, wv);
+                        if (a.w16) load_w4<S, KQ, true>(a.w, n, i, k, q, wv);
+                        else load_w4<S, KQ, false>(a.w, n, i, k, q, wv);
                         const int ids[4] = {id.x, id.y, id.z, id.w};
                         for (int j = 0; j < 4; ++j) {
                             C mj[3];
@@ -1008,7 +1025,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
                             sw += (double)wv[j];
                         }
                     }
-                    const double rh = 1.0 + ir + (sw - 1.0);
+                    const double rh = 1.0 + ir + (a.w16 ? 0.0 : sw - 1.0);
                     fback = feq_off<double>(kp + 1, 1.0, rh - 1.0, rh, iu, iv) +
                             0.5 * force_k<double>(kp + 1, 1.0, rh, iu, iv, a.gx, a.gy);
                 }
@@ -1058,6 +1075,9 @@ int check_common(const mlbm_step_params *p, const mlbm_device_state *st) {
         return fail(MLBM_ERR_ARG, "relaxation times must exceed 1/2");
     if (p->storage == MLBM_F16S && (p->scale_exp < -30 || p->scale_exp > 30)) return fail(MLBM_ERR_ARG, "scale_exp out of range");
     if (st->w_lagrange && st->K < 10) return fail(MLBM_ERR_ARG, "block weights need stencils of K >= 10");
+    if (p->weights16 != 0 && p->weights16 != 1) return fail(MLBM_ERR_ARG, "weights16 must be 0 or 1");
+    if (p->weights16 && p->storage != MLBM_F16S && p->storage != MLBM_BF16)
+        return fail(MLBM_ERR_UNSUPPORTED, "FP16 weights go with 16-bit states only");
     return MLBM_OK;
 }
 
@@ -1070,15 +1090,15 @@ int block_of(const mlbm_step_params *p) {
 
 using StepFn = void (*)(const StepArgs);
 
-template <int S, class CG, class C>
+template <int S, class CG, class C, bool W16 = false>
 StepFn pick_step(int variant, int kq, bool lds) {
 #define MLBM_CASE(Q)                                                                            \
     case Q:                                                                                     \
         if (lds)                                                                                \
-            return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, CG, C, Q, true>          \
-                                               : (StepFn)k_step_fields<S, CG, C, Q, true>;      \
-        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, CG, C, Q, false>             \
-                                           : (StepFn)k_step_fields<S, CG, C, Q, false>;
+            return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, CG, C, Q, true, W16>     \
+                                               : (StepFn)k_step_fields<S, CG, C, Q, true, W16>; \
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop<S, CG, C, Q, false, W16>        \
+                                           : (StepFn)k_step_fields<S, CG, C, Q, false, W16>;
     switch (kq) {
         MLBM_CASE(0)
         MLBM_CASE(2)
@@ -1099,11 +1119,12 @@ StepFn pick_step(int variant, int kq, bool lds) {
 // the collision (the interpolation in FP32 adds nothing measurable), and the
 // FP64 collision costs little in a kernel bound by memory traffic.  16-bit
 // states use FP32 throughout.
-template <int S, class CG, class C>
+template <int S, class CG, class C, bool W16 = false>
 StepFn pick_step_pd(int variant, int kq) {
 #define MLBM_CASE(Q)                                                                              \
     case Q:                                                                                       \
-        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop_pd<S, CG, C, Q> : (StepFn)k_step_fields_pd<S, CG, C, Q>;
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop_pd<S, CG, C, Q, W16>              \
+                                           : (StepFn)k_step_fields_pd<S, CG, C, Q, W16>;
     switch (kq) {
         MLBM_CASE(2)
         MLBM_CASE(3)
@@ -1119,26 +1140,36 @@ StepFn pick_step_pd(int variant, int kq) {
 }
 
 // per-departure stencils: the same arithmetic choices as pick_step_any
-StepFn pick_step_pd_any(int storage, int variant, int kq, int fp32_arith) {
+StepFn pick_step_pd_any(int storage, int variant, int kq, int fp32_arith, int w16) {
     switch (storage) {
         case MLBM_F64: return pick_step_pd<MLBM_F64, double, double>(variant, kq);
         case MLBM_F32:
             return fp32_arith ? pick_step_pd<MLBM_F32, float, float>(variant, kq)
                               : pick_step_pd<MLBM_F32, float, double>(variant, kq);
-        case MLBM_F16S: return pick_step_pd<MLBM_F16S, float, float>(variant, kq);
-        case MLBM_BF16: return pick_step_pd<MLBM_BF16, float, float>(variant, kq);
+        case MLBM_F16S:
+            return w16 ? pick_step_pd<MLBM_F16S, float, float, true>(variant, kq)
+                       : pick_step_pd<MLBM_F16S, float, float>(variant, kq);
+        case MLBM_BF16:
+            return w16 ? pick_step_pd<MLBM_BF16, float, float, true>(variant, kq)
+                       : pick_step_pd<MLBM_BF16, float, float>(variant, kq);
     }
     return nullptr;
 }
 
-StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith, bool lds) {
+// w16: FP16 weights (16-bit states; block-centre launches, kq = 0, read no
+// per-node weights and take w16 = 0)
+StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith, bool lds, int w16) {
     switch (storage) {
         case MLBM_F64: return pick_step<MLBM_F64, double, double>(variant, kq, lds);
         case MLBM_F32:
             return fp32_arith ? pick_step<MLBM_F32, float, float>(variant, kq, lds)
                               : pick_step<MLBM_F32, float, double>(variant, kq, lds);
-        case MLBM_F16S: return pick_step<MLBM_F16S, float, float>(variant, kq, lds);
-        case MLBM_BF16: return pick_step<MLBM_BF16, float, float>(variant, kq, lds);
+        case MLBM_F16S:
+            return w16 && kq ? pick_step<MLBM_F16S, float, float, true>(variant, kq, lds)
+                             : pick_step<MLBM_F16S, float, float>(variant, kq, lds);
+        case MLBM_BF16:
+            return w16 && kq ? pick_step<MLBM_BF16, float, float, true>(variant, kq, lds)
+                             : pick_step<MLBM_BF16, float, float>(variant, kq, lds);
     }
     return nullptr;
 }
@@ -1238,8 +1269,8 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     }
     if (st->per_departure && !lds) return fail(MLBM_ERR_UNSUPPORTED, "per-departure stencils need tiles");
     if (st->per_departure && st->w_lagrange) return fail(MLBM_ERR_ARG, "per-departure stencils take no block weights");
-    StepFn fn = st->per_departure ? pick_step_pd_any(p->storage, p->variant, kq, p->fp32_arith)
-                                  : pick_step_any(p->storage, p->variant, kq, p->fp32_arith, lds);
+    StepFn fn = st->per_departure ? pick_step_pd_any(p->storage, p->variant, kq, p->fp32_arith, p->weights16)
+                                  : pick_step_any(p->storage, p->variant, kq, p->fp32_arith, lds, p->weights16);
     if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
         return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
@@ -1272,7 +1303,7 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     if (st->w_lagrange && st->lagrange_begin < st->n) {
         if (st->lagrange_begin < 0) return fail(MLBM_ERR_ARG, "lagrange_begin must be >= 0");
         split = (st->lagrange_begin + blk - 1) / blk;
-        fb = pick_step_any(p->storage, p->variant, 0, p->fp32_arith, lds);
+        fb = pick_step_any(p->storage, p->variant, 0, p->fp32_arith, lds, 0);
         if (!fb) return fail(MLBM_ERR_UNSUPPORTED, "no block-centre kernel for storage %d", p->storage);
     }
     const int64_t ranges[2][2] = {{0, split}, {split, nb}};
@@ -1335,6 +1366,7 @@ extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_sta
     a.gy = p->g[1];
     a.inv_dx2 = 1.0 / (dx * dx);
     a.inv_scale = std::ldexp(1.0f, -p->scale_exp);
+    a.w16 = p->weights16 ? 1 : 0;
     const int64_t nb = (st->n + RED_BLOCK - 1) / RED_BLOCK;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(RED_BLOCK), 0, s, a);
@@ -1622,7 +1654,7 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     if (use_graph && !stream) return fail(MLBM_ERR_ARG, "graph capture needs a non-default stream");
     const int kq = (st->K + 3) / 4;
     if (st->per_departure) return fail(MLBM_ERR_UNSUPPORTED, "batched runs take one stencil per node");
-    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith, true);
+    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith, true, p->weights16);
     RedFn red = pick_red(p->storage, p->variant);
     if (!fn || !red) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
@@ -1712,8 +1744,8 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     std::vector<hipGraphExec_t> execs(b->n_groups + 1, nullptr);
     std::vector<char> graph_full(b->n_groups, 0);
     auto release = [&](int k) {
-        if (execs[k]) hipGraphExecDestroy(execs[k]);
-        if (graphs[k]) hipGraphDestroy(graphs[k]);
+        if (execs[k]) (void)hipGraphExecDestroy(execs[k]);
+        if (graphs[k]) (void)hipGraphDestroy(graphs[k]);
         execs[k] = nullptr;
         graphs[k] = nullptr;
     };

@@ -741,6 +741,42 @@ extern "C" int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t
     return MLBM_OK;
 }
 
+// IEEE binary32 -> binary16, round to nearest with ties to even (finite
+// inputs below 65520 in magnitude, checked by the caller)
+static uint16_t f32_to_f16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t sign = (u >> 16) & 0x8000u;
+    const int32_t e = (int32_t)((u >> 23) & 0xffu) - 127;  // unbiased exponent
+    uint32_t m = u & 0x7fffffu;
+    if (e < -25) return (uint16_t)sign;  // below half the smallest subnormal: 0
+    if (e < -14) {
+        // subnormal result: value = m' * 2^-24 with m' = (1.m) * 2^(e + 24)
+        m |= 0x800000u;
+        const int shift = -e - 1;  // 14 .. 24: bits dropped from the 24-bit significand
+        const uint32_t q = m >> shift, rem = m & ((1u << shift) - 1u), half = 1u << (shift - 1);
+        const uint32_t r = q + ((rem > half || (rem == half && (q & 1u))) ? 1u : 0u);
+        return (uint16_t)(sign | r);  // r = 0x400 is the smallest normal: still right
+    }
+    // normal result: keep 10 of the 23 fraction bits
+    uint32_t h = ((uint32_t)(e + 15) << 10) | (m >> 13);
+    const uint32_t rem = m & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) h += 1;  // may carry into the exponent
+    return (uint16_t)(sign | h);
+}
+
+extern "C" int mlbm_weights_to_f16(int64_t count, const float *in, uint16_t *out) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (count < 0 || (count > 0 && (!in || !out))) return fail(MLBM_ERR_ARG, "null buffer or negative count");
+    for (int64_t i = 0; i < count; ++i) {
+        if (!std::isfinite(in[i]) || std::fabs(in[i]) >= 65520.0f)
+            return fail(MLBM_ERR_ARG, "weight %lld (%g) outside the FP16 range", (long long)i, (double)in[i]);
+        out[i] = f32_to_f16_rne(in[i]);
+    }
+    return MLBM_OK;
+}
+
 extern "C" int mlbm_pack_stencils(int64_t n, int32_t K, int32_t storage, const int32_t *idx, const double *w,
                                   const uint8_t *bb, const uint8_t *kind, void *idx_packed, void *w_packed,
                                   uint16_t *flags) {

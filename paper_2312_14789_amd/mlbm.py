@@ -103,6 +103,15 @@ def pack_stencils(idx, w, bb, kind, storage):
     return ip, wp, fl
 
 
+def weights_to_f16(w_packed):
+    """mlbm_weights_to_f16: FP16 copy (uint16 array) of packed FP32 weights
+    (uint8 or float32 host array)."""
+    w32 = np.ascontiguousarray(w_packed).view(np.float32)
+    out = np.zeros(w32.size, np.uint16)
+    check(lib.mlbm_weights_to_f16(w32.size, _ptr(w32), _ptr(out)))
+    return out
+
+
 def pack_tiles(idx, tile):
     """mlbm_tile_sizes + mlbm_pack_tiles: (halo_off, halo, lidx, max_halo).
     idx (n, K), or (n, 8, K) for per-departure stencils (each departure
@@ -135,7 +144,7 @@ class Simulation:
     def __init__(self, idx, w, bb, kind, area, *, variant=POPULATIONS, storage=F32, tau_plus=0.8,
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
                  fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda",
-                 packed=None, lagrange=None, w_lagrange=None, stochastic_rounding=0):
+                 packed=None, lagrange=None, w_lagrange=None, stochastic_rounding=0, weights16=0):
         import torch
 
         self.torch = torch
@@ -164,6 +173,10 @@ class Simulation:
             wt = np.float64 if storage == F64 else np.float32
             self.wl_d = torch.from_numpy(np.ascontiguousarray(w_lagrange, dtype=wt)).to(dev)
         self.idx_d = torch.from_numpy(ip).to(dev)
+        if weights16:
+            if storage not in (F16S, BF16):
+                raise MlbmError(-5, "FP16 weights go with 16-bit states only")
+            wp = weights_to_f16(wp).view(np.uint8)
         self.w_d = torch.from_numpy(wp).to(dev)
         self.flags_d = torch.from_numpy(fl.view(np.int16)).to(dev)
         if bc is None:
@@ -188,6 +201,7 @@ class Simulation:
         self.params.alternate_sweeps = int(alternate_sweeps)
         self.params.cached_weights = int(cached_weights)
         self.params.stochastic_rounding = int(stochastic_rounding)
+        self.params.weights16 = int(bool(weights16))
         self.ds = DeviceState()
         self.ds.n = n
         self.ds.K = K

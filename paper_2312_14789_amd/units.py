@@ -70,14 +70,14 @@ def lbm1_nodes(porosity: float, dx: float) -> float:
     return float(round(porosity / (dx * dx)))
 
 
-def algorithmic_bytes_per_node(variant: int, storage: int, k_padded: int) -> int:
+def algorithmic_bytes_per_node(variant: int, storage: int, k_padded: int, weights16: bool = False) -> int:
     """Bytes one node update must move between HBM and the chip in the packed
     device layout: read and write of its own state, its weights, its stencil
     indices and its flags (gathered neighbour state counted once, at the
     owner).  variant 0 = populations, 1 = fields; storage 0 F64, 1 F32,
-    2 F16S, 3 BF16."""
+    2 F16S, 3 BF16; weights16: FP16 weights (16-bit states)."""
     tb = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
-    wb = 8 if storage == 0 else 4
+    wb = 8 if storage == 0 else (2 if weights16 else 4)
     state = (9 if variant == 0 else 4) * tb
     return 2 * state + 8 * k_padded * wb + 4 * k_padded + 2
 

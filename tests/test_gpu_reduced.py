@@ -130,3 +130,44 @@ def test_stochastic_rounding_accumulates_small_increments(M, storage):
     # sqrt(n / nodes), 2e-4 (FP16) and 3e-3 (BF16) of n g here
     assert e_near > 0.05
     assert e_sr < 1e-2
+
+
+# FP16 weights with the 16-bit states (half the weight bytes, which dominate
+# a step's traffic), stochastic rounding of the stores: bars as for the
+# 16-bit states, 2e-3 on velocity (5e-3 for a BF16 snapshot, as above) and
+# 0.5 % on permeability
+@pytest.mark.parametrize("storage,bar", [(2, 2e-3), (3, 5e-3)])
+def test_fields_fp16_weights(M, storage, bar):
+    ns, st, dx, g, steps, r_ref, u_ref = _porous_case()
+    sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, g, scale_exp=_sigma(M, u_ref),
+                          stochastic_rounding=1, weights16=1)
+    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+    sim.step(steps)
+    rho, u, red = sim.macroscopic(dx)
+    u = u.cpu().numpy()
+    red = red.cpu().numpy()
+    err = rel_l2(u, u_ref)
+    k_ref = omlbm.permeability(omlbm.reductions(r_ref, u_ref, st.area), 1.0, 1.0 / 6.0, g[0], dx)
+    k = 1.0 / 6.0 * (red[1] / 1.0) / g[0] * dx * dx
+    print(f"[reduced-w16] fields storage={storage} rel_l2_u={err:.3e} k_err={abs(k / k_ref - 1):.3e}", flush=True)
+    assert err <= bar
+    assert abs(k / k_ref - 1) <= 5e-3
+
+
+@pytest.mark.parametrize("storage,bar", [(2, 2e-3), (3, 5e-3)])
+def test_populations_fp16_weights(M, storage, bar):
+    ns, st, dx, g, steps, r_ref, u_ref, tp, tm = _channel_case()
+    sim = sim_from_oracle(M, ns, st, 0, storage, tp, tm, g, scale_exp=_sigma(M, u_ref),
+                          stochastic_rounding=1, weights16=1)
+    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+    sim.step(steps)
+    rho, u, red = sim.macroscopic(dx)
+    err = rel_l2(u.cpu().numpy(), u_ref)
+    print(f"[reduced-w16] populations storage={storage} rel_l2_u={err:.3e}", flush=True)
+    assert err <= bar
+
+
+def test_fp16_weights_need_16bit_states(M):
+    ns, st, dx, g, steps, r_ref, u_ref = _porous_case()
+    with pytest.raises(M.MlbmError):
+        sim_from_oracle(M, ns, st, 1, 1, 1.0, 1.0, g, weights16=1)

@@ -245,3 +245,20 @@ def test_reverse_cuthill_mckee_order():
     # the same stencils, renumbered (reorder 0 keeps the caller's order)
     np.testing.assert_array_equal(b0["perm"], np.arange(n))
     np.testing.assert_array_equal(b2["perm"][b2["idx"]], b0["idx"][b2["perm"]])
+
+
+def test_weights_to_f16_matches_ieee_rounding():
+    # round to nearest, ties to even, as numpy's float32 -> float16 cast;
+    # normal, subnormal, tie and boundary cases included
+    rng = np.random.default_rng(5)
+    w = np.concatenate([rng.normal(0.0, 0.3, 4000), rng.uniform(-3, 3, 4000),
+                        np.ldexp(rng.uniform(1, 2, 2000), rng.integers(-30, -10, 2000)),
+                        [0.0, -0.0, 1.0, -1.0, 65504.0, 65519.0, -65519.0, 2.0 ** -24, 2.0 ** -25,
+                         3 * 2.0 ** -26, 2.0 ** -14, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11]]).astype(np.float32)
+    got = M.weights_to_f16(w)
+    want = w.astype(np.float16).view(np.uint16)
+    np.testing.assert_array_equal(got, want)
+    with pytest.raises(M.MlbmError):
+        M.weights_to_f16(np.array([65520.0], np.float32))
+    with pytest.raises(M.MlbmError):
+        M.weights_to_f16(np.array([np.nan], np.float32))
