@@ -614,7 +614,8 @@ def main():
     bpn_lag = units.block_centre_bytes_per_node(M.POPULATIONS, storage)
     bpn = ((n - n_lag) * bpn_rbf + n_lag * bpn_lag) / n
     achieved = bpn * n / per_launch_s / 1e9
-    workload = f"karman{'-hybrid' if args.hybrid else ''}{'-poisson' if poisson else ''}-n{n}-K{K}-s{args.s:g}"
+    workload = (f"karman{'-hybrid' if args.hybrid else ''}{'-poisson' if poisson else ''}-n{n}-K{K}-s{args.s:g}"
+                + ("" if args.storage == "f32" else f"-{args.storage}") + ("-w16" if args.weights16 else ""))
     kernel = "k_step_pop" + ("_lds" if args.tile else "")
     traffic = measured_traffic(kernel, workload)
     out = {
