@@ -73,6 +73,51 @@ def cpu_baseline(ns_perm, b, tau, budget_s=15.0):
                       f"({dt:.1f} s, numpy single thread)"}
 
 
+def porous_throughput(args, M, units, nodesets, np, torch):
+    """MLBM1 (tau = 1, the porous workload's variant) on the 1e6-node porous
+    sample: the fused fields step timed like the Karman line, with its
+    roofline and, while the kernel source matches, the measured traffic."""
+    storage = {"f64": M.F64, "f32": M.F32, "f16s": M.F16S, "bf16": M.BF16}[args.storage]
+    ns = nodesets.porous()
+    dx = ns.h / args.s
+    g = 3.242e-8
+    b = M.build_stencils_for(ns, args.K, dx)
+    perm = b["perm"]
+    sigma = 23 if storage == M.F16S else 0
+    sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.FIELDS, storage=storage,
+                       tau_plus=1.0, g=(g, 0.0), scale_exp=sigma, tile=args.tile, xcd_remap=args.xcd,
+                       alternate_sweeps=args.sweeps, stochastic_rounding=args.sr, weights16=args.weights16)
+    n = ns.n
+    sim.init_state(np.ones(n), np.zeros((n, 2)))
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    per_launch_s = ms / 1e3 / args.steps
+    _, _, red = sim.macroscopic(dx, want_fields=False)
+    bad = int(red.cpu().numpy()[M._lib.RED_N_BAD])
+    kp = sim.sizes.k_padded
+    bpn = units.algorithmic_bytes_per_node(M.FIELDS, storage, kp, args.weights16)
+    achieved = bpn * n / per_launch_s / 1e9
+    workload = (f"porous-n{n}-K{args.K}-s{args.s:g}" + ("" if args.storage == "f32" else f"-{args.storage}")
+                + ("-w16" if args.weights16 else ""))
+    return {"metric": "MNUPS and HBM fraction of the fused MLBM1 step", "value": round(n * args.steps / (ms / 1e3) / 1e6, 1),
+            "unit": "MNUPS", "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+            "dtype": args.storage + (" state, f16 weights" if args.weights16 else ""),
+            "config": {"workload": f"porous unit box, {n} nodes, phi={ns.fluid_area():.3f}, {len(ns.disks)} disks, "
+                                   f"MLBM1 (tau=1), K={args.K}, s={args.s:g}, g_lb={g:g}", "unstable_nodes": bad},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_step_fields_lds", workload),
+                         "kernel": "k_step_fields_lds", "bytes_per_node": bpn,
+                         "avg_launch_us": round(per_launch_s * 1e6, 2)}}
+
+
 def copy_calibration():
     """A plain 1 GiB device-to-device copy: the reference that scales the HBM
     byte counters and the practical bandwidth of the box."""
@@ -523,8 +568,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
     ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
-    ap.add_argument("--workload", default="karman", choices=["karman", "batched", "warmstart", "darcy", "strouhal"],
-                    help="karman: the fused-step throughput line; batched: 64 porous samples to steady "
+    ap.add_argument("--workload", default="karman",
+                    choices=["karman", "porous", "batched", "warmstart", "darcy", "strouhal"],
+                    help="karman: the fused-step throughput line; porous: the MLBM1 step on the 1e6-node "
+                         "porous sample; batched: 64 porous samples to steady "
                          "state; warmstart: train the warm-start network and compare time to steady state; "
                          "darcy: mean velocity and tortuosity of the porous channel over a sweep of dx; "
                          "strouhal: the paper's cylinder channel, St from the lift over Re 105-168")
@@ -557,6 +604,9 @@ def main():
         return
     if args.workload == "warmstart":
         print(json.dumps(warmstart_workload(args, np, torch)), flush=True)
+        return
+    if args.workload == "porous":
+        print(json.dumps(porous_throughput(args, M, units, nodesets, np, torch)), flush=True)
         return
     if args.workload == "darcy":
         print(json.dumps(darcy_workload(M, units, nodesets, np, torch)), flush=True)
