@@ -181,13 +181,19 @@ int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t n, int32_t
 
 /*
  * FP16 copy of packed FP32 weights for mlbm_step_params.weights16 (16-bit
- * states; not in the paper, whose weights are doubles, Sec. 3.2 Eq. 27):
- * out[i] = in[i] rounded to the nearest FP16 value, ties to even, in the same
- * layout (count = w_bytes / 4 of the FP32 packing).  Host buffers, caller
- * owned.  Errors: MLBM_ERR_ARG (null pointers, count < 0, a value that is not
- * finite or whose magnitude reaches 65520, beyond FP16's range).
+ * states; not in the paper, whose weights are doubles, Sec. 3.2 Eq. 27), in
+ * the same layout [8][k_padded/4][n][4].  Every weight becomes one of its two
+ * neighbouring FP16 values: first the nearest (ties to even), then, row by
+ * row (one row = the k_padded weights of one direction of one node), single
+ * weights move to their other neighbour while that brings the row's summed
+ * rounding error closer to zero, so each row keeps its FP32 sum as closely as
+ * FP16 allows (an interpolation that keeps reproducing constants).  Zero
+ * (padding) weights stay zero.  Host buffers, caller owned.
+ * Errors: MLBM_ERR_ARG (null pointers, n < 0, k_padded not a positive
+ * multiple of 4 within the stencil limit, a weight that is not finite or
+ * whose magnitude reaches 65504).
  */
-int mlbm_weights_to_f16(int64_t count, const float *in, uint16_t *out);
+int mlbm_weights_to_f16(int64_t n, int32_t k_padded, const float *in, uint16_t *out);
 
 /*
  * Sets MLBM_FLAG_LAGRANGE in packed flags[i] where lagrange[i] != 0 (the

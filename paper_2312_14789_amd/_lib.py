@@ -114,7 +114,7 @@ def _load():
                                                     ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p,
                                                     _p, _p]),
         "mlbm_mark_lagrange": (ctypes.c_int, [ctypes.c_int64, _p, _p]),
-        "mlbm_weights_to_f16": (ctypes.c_int, [ctypes.c_int64, _p, _p]),
+        "mlbm_weights_to_f16": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _p, _p]),
         "mlbm_batch_init": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), _p]),
         "mlbm_step_batched": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), ctypes.c_int32,
                                              ctypes.c_double, ctypes.c_int32, P(ctypes.c_int32), _p]),

@@ -765,15 +765,74 @@ static uint16_t f32_to_f16_rne(float f) {
     return (uint16_t)(sign | h);
 }
 
-extern "C" int mlbm_weights_to_f16(int64_t count, const float *in, uint16_t *out) {
+static double f16_value(uint16_t h) {
+    const int e = (h >> 10) & 0x1f;
+    const double m = (double)(h & 0x3ff);
+    const double v = e == 0 ? std::ldexp(m, -24) : std::ldexp(1024.0 + m, e - 25);
+    return (h & 0x8000u) ? -v : v;
+}
+
+// the FP16 value next to h towards +infinity (up) or -infinity
+static uint16_t f16_step(uint16_t h, bool up) {
+    const bool neg = (h & 0x8000u) != 0, zero = (h & 0x7fffu) == 0;
+    if (zero) return up ? 0x0001u : 0x8001u;
+    return (uint16_t)(up != neg ? h + 1 : h - 1);
+}
+
+extern "C" int mlbm_weights_to_f16(int64_t n, int32_t k_padded, const float *in, uint16_t *out) {
     using mlbm::fail;
     mlbm::clear_error();
-    if (count < 0 || (count > 0 && (!in || !out))) return fail(MLBM_ERR_ARG, "null buffer or negative count");
-    for (int64_t i = 0; i < count; ++i) {
-        if (!std::isfinite(in[i]) || std::fabs(in[i]) >= 65520.0f)
-            return fail(MLBM_ERR_ARG, "weight %lld (%g) outside the FP16 range", (long long)i, (double)in[i]);
-        out[i] = f32_to_f16_rne(in[i]);
-    }
+    if (n < 0 || k_padded < 4 || k_padded % 4 != 0 || k_padded > MAXK + 3 || (n > 0 && (!in || !out)))
+        return fail(MLBM_ERR_ARG, "bad n, k_padded or null buffer");
+    const int64_t count = 8 * (int64_t)k_padded * n;
+    for (int64_t t = 0; t < count; ++t)
+        if (!std::isfinite(in[t]) || std::fabs(in[t]) >= 65504.0f)
+            return fail(MLBM_ERR_ARG, "weight %lld (%g) outside the FP16 range", (long long)t, (double)in[t]);
+    const int kq = k_padded / 4;
+    // every (direction, node) row: round each weight to nearest, then move
+    // single weights to their other FP16 neighbour while that brings the
+    // row's sum of rounding errors closer to zero (rows are independent:
+    // node ranges on all host threads)
+    auto rows = [&](int64_t i0, int64_t i1) {
+    for (int k = 0; k < 8; ++k)
+        for (int64_t i = i0; i < i1; ++i) {
+            int64_t at[4 * (MAXK + 3)];
+            double d[4 * (MAXK + 3)];
+            uint16_t alt[4 * (MAXK + 3)];
+            double err = 0.0;
+            int m = 0;
+            for (int q = 0; q < kq; ++q)
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t t = (((int64_t)k * kq + q) * n + i) * 4 + j;
+                    const uint16_t h = f32_to_f16_rne(in[t]);
+                    out[t] = h;
+                    const double r = f16_value(h) - (double)in[t];
+                    err += r;
+                    if (r != 0.0) {
+                        alt[m] = f16_step(h, r < 0.0);
+                        d[m] = f16_value(alt[m]) - f16_value(h);
+                        at[m++] = t;
+                    }
+                }
+            for (;;) {
+                int best = -1;
+                double best_err = std::fabs(err);
+                for (int c = 0; c < m; ++c)
+                    if (at[c] >= 0 && std::fabs(err + d[c]) < best_err) { best = c; best_err = std::fabs(err + d[c]); }
+                if (best < 0) break;
+                out[at[best]] = alt[best];
+                err += d[best];
+                at[best] = -1;
+            }
+        }
+    };
+    const int nt = (int)std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+    const int64_t chunk = (n + nt - 1) / nt;
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t)
+        if (t * chunk < n) pool.emplace_back(rows, t * chunk, std::min(n, (t + 1) * chunk));
+    rows(0, std::min(n, chunk));
+    for (auto &th : pool) th.join();
     return MLBM_OK;
 }
 

@@ -103,12 +103,15 @@ def pack_stencils(idx, w, bb, kind, storage):
     return ip, wp, fl
 
 
-def weights_to_f16(w_packed):
+def weights_to_f16(w_packed, n, k_padded):
     """mlbm_weights_to_f16: FP16 copy (uint16 array) of packed FP32 weights
-    (uint8 or float32 host array)."""
+    (uint8 or float32 host array, layout [8][k_padded/4][n][4]), each row's
+    sum kept as closely as FP16 allows."""
     w32 = np.ascontiguousarray(w_packed).view(np.float32)
+    if w32.size != 8 * k_padded * n:
+        raise ValueError("packed weights do not match n and k_padded")
     out = np.zeros(w32.size, np.uint16)
-    check(lib.mlbm_weights_to_f16(w32.size, _ptr(w32), _ptr(out)))
+    check(lib.mlbm_weights_to_f16(n, k_padded, _ptr(w32), _ptr(out)))
     return out
 
 
@@ -176,7 +179,7 @@ class Simulation:
         if weights16:
             if storage not in (F16S, BF16):
                 raise MlbmError(-5, "FP16 weights go with 16-bit states only")
-            wp = weights_to_f16(wp).view(np.uint8)
+            wp = weights_to_f16(wp, n, packed_sizes(n, K, variant, storage).k_padded).view(np.uint8)
         self.w_d = torch.from_numpy(wp).to(dev)
         self.flags_d = torch.from_numpy(fl.view(np.int16)).to(dev)
         if bc is None:
