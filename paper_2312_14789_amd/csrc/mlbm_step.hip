@@ -327,6 +327,9 @@ struct StepArgs {
     const unsigned short *lidx;  // LDS staging: tile-local member positions [K8/8][n][8]
     const void *wl;            // block weights [8][9] (FP64 storage: double, else float)
     int64_t tile0, tile1;      // tiles [tile0, tile1) of this launch (non-batched)
+    int64_t lag0;              // first node of the trailing run of block centres (n: none);
+                               // the tile holding it is visited by both launches, each
+                               // updating its own nodes
     int sr;                    // stochastic rounding of 16-bit stores
     unsigned seed;             // this step's random key
     const int *queue;          // batched launches: list of active tiles (NULL: every tile)
@@ -476,11 +479,13 @@ __device__ __forceinline__ void for_quads(F &&f) {
 // ---- population MLBM step ------------------------------------------------------
 
 // CG: gather (interpolation) arithmetic; C: collision arithmetic.  KQ = 0
-// instantiates the block-centre kernel of a hybrid set: every node it visits
-// is a block centre with the shared weights (a node without the flag gets a
-// NaN state, so a wrong node range shows up at once).
+// instantiates the block-centre kernel of a hybrid set: it updates the nodes
+// from lag0 on, every one a block centre with the shared weights (a node
+// without the flag gets a NaN state, so a wrong node range shows up at once);
+// the per-node kernels update the nodes before lag0.
 template <int S, class CG, class C, int KQ, bool LDS, bool W16 = false>
 __device__ __forceinline__ void pop_node(const StepArgs &a, const void *src, int64_t i, int self) {
+    if ((KQ == 0) != (i >= a.lag0)) return;  // the other launch's node
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
@@ -584,6 +589,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_
 
 template <int S, class CG, class C, int KQ, bool LDS, bool W16 = false>
 __device__ __forceinline__ void fields_node(const StepArgs &a, const void *src, int64_t i, int self) {
+    if ((KQ == 0) != (i >= a.lag0)) return;  // the other launch's node
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     const unsigned bb = fl & 0xffu;
@@ -1295,18 +1301,21 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     a.queue = nullptr;
     a.queue_range = nullptr;
     a.group = 0;
-    // tiles [0, split) run the per-node weights; in a hybrid set the tiles
-    // made only of block centres, [split, nb), run the block-centre kernel
+    // nodes [0, lag0) run the per-node weights; in a hybrid set the trailing
+    // block centres [lag0, n) run the block-centre kernel.  Each launch covers
+    // the tiles holding its nodes, so a tile holding both kinds is visited by
+    // both launches, each updating only its own nodes
     const int64_t nb = (st->n + blk - 1) / blk;
-    int64_t split = nb;
+    int64_t lag0 = st->n;
     StepFn fb = nullptr;
     if (st->w_lagrange && st->lagrange_begin < st->n) {
         if (st->lagrange_begin < 0) return fail(MLBM_ERR_ARG, "lagrange_begin must be >= 0");
-        split = (st->lagrange_begin + blk - 1) / blk;
+        lag0 = st->lagrange_begin;
         fb = pick_step_any(p->storage, p->variant, 0, p->fp32_arith, lds, 0);
         if (!fb) return fail(MLBM_ERR_UNSUPPORTED, "no block-centre kernel for storage %d", p->storage);
     }
-    const int64_t ranges[2][2] = {{0, split}, {split, nb}};
+    a.lag0 = lag0;
+    const int64_t ranges[2][2] = {{0, (lag0 + blk - 1) / blk}, {lag0 / blk, fb ? nb : 0}};
     const StepFn fns[2] = {fn, fb};
     hipStream_t s = (hipStream_t)stream;
     a.sr = (p->stochastic_rounding && (p->storage == MLBM_F16S || p->storage == MLBM_BF16)) ? 1 : 0;
@@ -1683,6 +1692,7 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     a.halo = st->halo;
     a.lidx = st->lidx;
     a.wl = nullptr;  // batched runs use every node's own weights
+    a.lag0 = st->n;  // (no block-centre launch)
     a.tile0 = a.tile1 = 0;
     a.sr = 0;        // and round to nearest (a captured graph replays fixed keys)
     a.seed = 0;

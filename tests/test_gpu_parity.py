@@ -403,12 +403,11 @@ def test_porous_full_size_sampled(M):
 @pytest.mark.parametrize("name", ["hybrid_tgv", "hybrid_pixels_fields"])
 def test_hybrid_16bit_states_with_fp16_weights(M, name):
     # block centres (shared FP32 table) and RBF-FD rows (FP32 or FP16
-    # weights) in one step on the FP16 state with stochastic rounding.  With
-    # FP32 weights both cases meet the 2e-3 bar (3.8e-4, 6.1e-4).  FP16
-    # weights meet it on the forced porous case (6.2e-4) but not on the freely
-    # decaying Taylor-Green flow at dx/h = 2/3, where several weights per row
-    # are O(1) and their rounding acts on every one of 300 steps with nothing
-    # to restore the solution (3.8e-3, asserted at 5e-3 as a regression guard)
+    # weights) in one step on the FP16 state with stochastic rounding, the
+    # reduced-storage bar 2e-3.  Block centres must all take the shared table:
+    # when those of the tile shared with scattered nodes took their own rows in
+    # FP16, the common rounding error of their row sums scaled the offsets of
+    # ~200 nodes coherently every step (3.8e-3 on the Taylor-Green case)
     print(f"[parity-w16] case={name}", flush=True)
     ns, st, var, tp, tm, g, steps, rho0, u0, dx, r_ref, u_ref, _ = _case(name)
     from paper_2312_14789_amd import units
@@ -421,5 +420,4 @@ def test_hybrid_16bit_states_with_fp16_weights(M, name):
         assert red[8] == 0
     print(f"[parity-w16] case={name} rel_l2_u fp32 weights {errs[0]:.3e} fp16 weights {errs[1]:.3e}", flush=True)
     assert errs[0] <= 2e-3
-    BAR_W16 = {"hybrid_tgv": 5e-3, "hybrid_pixels_fields": 2e-3}
-    assert errs[1] <= BAR_W16[name]
+    assert errs[1] <= 2e-3
