@@ -215,11 +215,12 @@ def _circle_nodes(cx, cy, r, h):
 
 
 def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
-           u_max: float = 0.05, jitter: float = 0.35, hybrid: bool = False,
+           u_max: float = 0.05, jitter: float | None = None, hybrid: bool = False,
            wake: float = 6.0, poisson: bool = False) -> NodeSet:
     """Channel 22D x 4.1D with a cylinder of diameter D centred at (2D, 2D).
 
-    Scattered nodes: stratified (jittered) samples at spacing h_b in the bulk
+    Scattered nodes: stratified samples (jittered by jitter h, default 0.35;
+    0.2 in the hybrid zone) at spacing h_b in the bulk
     and h_f = h_b / 2 (4x the node density) within 1D of the cylinder surface,
     cleaned of close pairs; nodes exactly on the cylinder surface (spacing h_f,
     no-slip); Dirichlet nodes on the four straight boundaries (spacing h_b):
@@ -240,6 +241,10 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     hybrid over the scattered zone only, up to the fixed lattice."""
     if poisson:
         return _karman_poisson(n_target, seed, D, u_max, hybrid, wake)
+    if jitter is None:
+        # the hybrid zone's jitter: 0.35 h_b diverges at s = 4 on the seam with
+        # the lattice, 0.2 h_b does not
+        jitter = 0.2 if hybrid else 0.35
     rng = np.random.default_rng(seed)
     Lx, Ly = 22.0 * D, 4.1 * D
     cx, cy, r = 2.0 * D, 2.0 * D, 0.5 * D
@@ -252,8 +257,17 @@ def karman(n_target: int = 500_000, seed: int = 231214789, D: float = 1.0,
     hf = 0.5 * hb
     lo, hi = np.zeros(2), np.array([Lx, Ly])
 
-    # Bulk: jittered grid away from the boundaries.
-    bulk = _grid(lo, hi, hb)
+    # Bulk: jittered grid away from the boundaries.  The hybrid set's lattice
+    # sits on the vertices i h_b, j h_b, so that it continues into the
+    # Dirichlet nodes of the sides (a cell-centred lattice leaves a
+    # half-spacing layer of irregular stencils along every side)
+    if hybrid:
+        gx = np.arange(1, int(round(Lx / hb))) * hb
+        gy = np.arange(1, int(round(Ly / hb))) * hb
+        GX, GY = np.meshgrid(gx, gy, indexing="xy")
+        bulk = np.stack([GX.ravel(), GY.ravel()], axis=1)
+    else:
+        bulk = _grid(lo, hi, hb)
     off = rng.uniform(-jitter * hb, jitter * hb, size=bulk.shape)
     if hybrid:
         near = np.hypot(bulk[:, 0] - cx, bulk[:, 1] - cy) < 2.0 * D

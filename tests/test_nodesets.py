@@ -67,9 +67,14 @@ def test_hybrid_karman_lattice():
     ns = nodesets.karman(n_target=20000, hybrid=True)
     assert abs(22.0 / ns.h - round(22.0 / ns.h)) < 1e-9 and abs(4.1 / ns.h - round(4.1 / ns.h)) < 1e-9
     fluid = ns.kind == nodesets.FLUID
-    g = ns.xy[fluid] / ns.h - 0.5
+    # the lattice part sits on the vertices i h, j h, continuing into the
+    # Dirichlet nodes of the sides
+    g = ns.xy[fluid] / ns.h
     on_lattice = np.all(np.abs(g - np.round(g)) < 1e-9, axis=1)
     assert on_lattice.mean() > 0.4
+    dirich = ns.kind == nodesets.DIRICHLET
+    gd = ns.xy[dirich] / ns.h
+    assert np.all(np.abs(gd - np.round(gd)) < 1e-9)
 
 
 def test_poisson_karman():
