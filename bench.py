@@ -390,8 +390,8 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
     its wake; "scattered": 1/200 everywhere, all scattered: the paper's three
     timing scenarios), the stencil form ("per-departure":
     the K nearest nodes of each departure point, as the paper states;
-    "shared": one stencil per node for its eight departure points) and the
-    Reynolds numbers."""
+    "shared": one stencil per node for its eight departure points), the
+    Reynolds numbers and optionally the stencil size (default 25)."""
     names = {c[0] for c in cases}
     recipes = {"coarsened": {}, "uniform": dict(h_max=1.0 / 200, grade=0.15, wake_stretch=0.3),
                "scattered": dict(h_max=1.0 / 200, grade=10.0, wake_stretch=1.0)}
@@ -401,11 +401,13 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
     nu_lb = units.nu_lattice(tau)
     rows = []
     series = {}
-    for set_name, mode, reynolds in cases:
+    for case in cases:
+        set_name, mode, reynolds = case[:3]
+        K = case[3] if len(case) > 3 else 25
         ns = sets[set_name]
         for re in reynolds:
             dx = u0 * d / (re * nu_lb)
-            b = M.build_stencils_for(ns, 25, dx, lattice_h=ns.h, per_departure=mode == "per-departure",
+            b = M.build_stencils_for(ns, K, dx, lattice_h=ns.h, per_departure=mode == "per-departure",
                                      simple_bounce_back=True)
             perm = b["perm"]
             # per-departure rows of block centres carry their block weights
@@ -454,8 +456,8 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
             else:
                 st = float("nan")
             n_steps = n_samples * every
-            series[f"{set_name}_{mode}_Re{re}"] = lift
-            rows.append({"nodes": set_name, "n": ns.n, "block_centres": int(b["n_lagrange"]), "stencils": mode,
+            series[f"{set_name}_{mode}_K{K}_Re{re}"] = lift
+            rows.append({"nodes": set_name, "n": ns.n, "block_centres": int(b["n_lagrange"]), "stencils": mode, "K": K,
                          "Re": re, "dx": dx, "s_min": round(ns.h_min / dx, 3), "s_max": round(ns.h / dx, 3),
                          "steps": n_steps, "St": round(float(st), 4), "St_fft": round(float(st_fft), 4),
                          "lift_amplitude": float(np.abs(tail).max()), "lift_rms": float(np.sqrt(np.mean(tail ** 2))),
