@@ -100,8 +100,8 @@ def _load():
     except ImportError:
         pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                          "(python paper_2312_14789_amd/build.py)")
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "python paper_2312_14789_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     sig = {

@@ -3,7 +3,7 @@
 A network maps the rasterised geometry of a periodic porous sample to the
 steady velocity and density field; the MLBM1 run then starts from that field
 instead of from rest, and converges to the same steady state (the plain run
-from rest is the fallback and the judge).  Training data are steady states the
+from rest is the fallback and the reference its result is checked against).  Training data are steady states the
 library itself computes (batched runs); the network is trained on the GPU by
 the library's own forward and backward kernels.
 

@@ -1,7 +1,8 @@
 """The learned warm start end to end at a small size: steady states from
 batched library runs, training with the library's kernels, and what the
-trained network gains over starting from rest (the plain run is the judge:
-the warm-started run must converge to its permeability within 0.5 %)."""
+trained network gains over starting from rest (the plain run is the
+reference: the warm-started run must converge to its permeability within
+0.5 %)."""
 import numpy as np
 import pytest
 
