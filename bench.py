@@ -12,6 +12,7 @@ fraction of the step kernel from its algorithmic bytes, and the CPU oracle
 timed on a bounded sample of the same workload.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -139,6 +140,29 @@ def copy_calibration():
     ms = e0.elapsed_time(e1) / 10
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": ms,
                       "GBps_read_plus_write": 2 * 4 * n / ms / 1e6}), flush=True)
+    # a read-only stream of 2 GiB (mlbm_read_probe): the practical bandwidth of
+    # a kernel that, like the step, mostly reads
+    from paper_2312_14789_amd import _lib
+
+    z = torch.ones(2 * n, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for per_thread in (2, 4, 8):
+        out = torch.empty(8 * n // (16 * per_thread), dtype=torch.float32, device="cuda")
+        call = lambda: _lib.check(_lib.lib.mlbm_read_probe(z.data_ptr(), 8 * n, per_thread, out.data_ptr(),  # noqa: E731
+                                                           ctypes.c_void_p(stream.cuda_stream)))
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(10):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        res[per_thread] = {"ms": ms, "GBps_read": 8 * n / ms / 1e6,
+                           "GBps_read_plus_write": (8 * n + 4 * out.numel()) / ms / 1e6}
+    print(json.dumps({"read_probe_bytes": 8 * n, "per_thread": res}), flush=True)
 
 
 def karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m, scales=(2.0, 4.0), steps=50_000):

@@ -195,6 +195,19 @@ int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t n, int32_t
  */
 int mlbm_weights_to_f16(int64_t n, int32_t k_padded, const float *in, uint16_t *out);
 
+/* ---- measurement helper (not part of the method) ----------------------------- */
+
+/*
+ * Streaming-read probe: one kernel that reads the device buffer buf (bytes,
+ * 16-byte aligned, a multiple of 16 * 256 * per_thread) once with 16-byte
+ * non-temporal loads, per_thread (2, 4 or 8) loads per thread, and writes one
+ * float per thread to the device array out (bytes / (16 * per_thread) floats,
+ * caller-owned).  Timing it gives the practical read bandwidth that bounds a
+ * kernel which, like the step, mostly reads.  Asynchronous on stream.
+ * Errors: MLBM_ERR_ARG (null or misaligned buffers, bad sizes), MLBM_ERR_HIP.
+ */
+int mlbm_read_probe(const void *buf, int64_t bytes, int32_t per_thread, float *out, void *stream);
+
 /*
  * Sets MLBM_FLAG_LAGRANGE in packed flags[i] where lagrange[i] != 0 (the
  * builder's lagrange output), so that mlbm_step takes those nodes' weights

@@ -115,6 +115,7 @@ def _load():
                                                     _p, _p]),
         "mlbm_mark_lagrange": (ctypes.c_int, [ctypes.c_int64, _p, _p]),
         "mlbm_weights_to_f16": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _p, _p]),
+        "mlbm_read_probe": (ctypes.c_int, [_p, ctypes.c_int64, ctypes.c_int32, _p, _p]),
         "mlbm_batch_init": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), _p]),
         "mlbm_step_batched": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), ctypes.c_int32,
                                              ctypes.c_double, ctypes.c_int32, P(ctypes.c_int32), _p]),
@@ -160,7 +161,7 @@ lib = _load()
 
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_pack_stencils_range",
-           "mlbm_mark_lagrange", "mlbm_weights_to_f16",
+           "mlbm_mark_lagrange", "mlbm_weights_to_f16", "mlbm_read_probe",
            "mlbm_tile_sizes", "mlbm_pack_tiles", "mlbm_init_state", "mlbm_batch_init", "mlbm_step_batched",
            "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
            "mlbm_version"]

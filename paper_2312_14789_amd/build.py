@@ -21,7 +21,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", 
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
 HOST_SOURCES = ["stencil_build.cpp", "mlbm_common.cpp"]
-HIP_SOURCES = ["mlbm_step.hip", "unet.hip"]
+HIP_SOURCES = ["mlbm_step.hip", "unet.hip", "bw_probe.hip"]
 
 
 def _run(cmd):
