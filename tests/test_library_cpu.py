@@ -277,3 +277,15 @@ def test_weights_to_f16_rounding():
         M.weights_to_f16(np.full((8, 1, 1, 4), 65504.0, np.float32), 1, 4)
     with pytest.raises(M.MlbmError):
         M.weights_to_f16(np.full((8, 1, 1, 4), np.nan, np.float32), 1, 4)
+
+
+def test_read_probe_rejects_bad_arguments():
+    # argument checks run on the host before any launch
+    lib = _lib.lib
+    out = ctypes.c_float()
+    assert lib.mlbm_read_probe(None, 1 << 20, 4, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
+    buf = ctypes.c_void_p(16)  # never dereferenced: the size check fails first
+    assert lib.mlbm_read_probe(buf, 1000, 4, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
+    assert lib.mlbm_read_probe(buf, 1 << 20, 3, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
+    assert lib.mlbm_read_probe(ctypes.c_void_p(17), 1 << 20, 4, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
+    assert "per_thread" in lib.mlbm_last_error().decode() or "aligned" in lib.mlbm_last_error().decode()
