@@ -393,6 +393,7 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_560_000
 
 
 ST_CASES = (("coarsened", "shared", (105, 126, 147, 168)),
+            ("coarsened", "shared", (105, 126, 147, 168), 32),
             ("uniform", "shared", (105, 126, 147, 168)),
             ("scattered", "shared", (105, 168)),
             ("coarsened", "per-departure", (105, 168)))
