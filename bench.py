@@ -497,7 +497,7 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
     return {"metric": "Strouhal number of the cylinder wake vs Re (the paper's configuration)",
             "workload": "3x1 channel, d=0.14, U0=0.01, symmetric node sets "
                         + ", ".join(f"{k}: {v.n} nodes (h {v.h_min:g}..{v.h:g})" for k, v in sets.items())
-                        + ", TRT tau+=0.53 Lambda=3/16, K=25, simple bounce-back, FP32, lift every "
+                        + ", TRT tau+=0.53 Lambda=3/16, K per row (25 by default), simple bounce-back, FP32, lift every "
                         + f"{every} steps, {transient} + {periods} periods",
             "rows": rows}
 
