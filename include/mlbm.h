@@ -290,13 +290,16 @@ typedef struct mlbm_device_state {
                                 storage, float otherwise) or NULL                 */
     int64_t lagrange_begin;  /* with w_lagrange: nodes [lagrange_begin, n) are all
                                 block centres flagged MLBM_FLAG_LAGRANGE (the
-                                builder's order puts them last); the tiles made
-                                only of them run a kernel that reads the shared
-                                weights and eight neighbour indices per node, every
-                                other node its own packed weights (which the
-                                builder also fills for block centres).  A node of
-                                that range without the flag gets a NaN state.
-                                Batched runs use the packed weights throughout.   */
+                                builder's order puts them last); they are updated
+                                by a kernel that reads the shared weights and
+                                eight neighbour indices per node, every other
+                                node by its own packed weights (which the builder
+                                also fills for block centres).  lagrange_begin
+                                need not fall on a tile boundary: the tile holding
+                                it is visited by both kernels, each updating its
+                                own nodes.  A node of that range without the flag
+                                gets a NaN state.  Batched runs use the packed
+                                weights throughout.                                */
     uint64_t step_count;     /* steps taken (key of the stochastic rounding);
                                 mlbm_step adds nsteps                              */
     int32_t per_departure;   /* 1: one stencil per departure point (builder's
