@@ -582,6 +582,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=1, help="alternate the tile sweep direction")
     ap.add_argument("--cached", type=int, default=0, help="ordinary (not non-temporal) weight loads")
     ap.add_argument("--nodes", type=int, default=500_000, help="target node count of the workload")
+    ap.add_argument("--hybrid-launches", type=int, default=0, choices=(0, 2),
+                    help="hybrid set: 0 = one launch per step for both node kinds, 2 = one launch per kind")
     ap.add_argument("--hybrid", action="store_true",
                     help="hybrid node set: square lattice away from the cylinder and its wake, biquadratic "
                          "Lagrange weights at the block centres")
@@ -666,7 +668,8 @@ def main():
                        block=args.block, xcd_remap=args.xcd, scale_exp=12, fp32_arith=args.fp32_arith,
                        alternate_sweeps=args.sweeps, cached_weights=args.cached,
                        tile=args.tile, lagrange=b["lagrange"], w_lagrange=b["w_lagrange"],
-                       stochastic_rounding=args.sr, weights16=args.weights16)
+                       stochastic_rounding=args.sr, weights16=args.weights16,
+                       hybrid_launches=args.hybrid_launches)
     n = ns.n
     sim.init_state(np.ones(n), np.zeros((n, 2)))
     sim.step(args.warmup)
@@ -694,6 +697,8 @@ def main():
     workload = (f"karman{'-hybrid' if args.hybrid else ''}{'-poisson' if poisson else ''}-n{n}-K{K}-s{args.s:g}"
                 + ("" if args.storage == "f32" else f"-{args.storage}") + ("-w16" if args.weights16 else ""))
     kernel = "k_step_pop" + ("_lds" if args.tile else "")
+    if args.hybrid and args.tile and args.hybrid_launches == 0:
+        kernel = "k_step_pop_hyb"       # both node kinds in one launch per step
     traffic = measured_traffic(kernel, workload)
     out = {
         "metric": METRIC,

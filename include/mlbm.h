@@ -266,6 +266,10 @@ typedef struct mlbm_step_params {
                                 their sum is then taken as exactly 1 by the step and
                                 by the momentum exchange of mlbm_macroscopic, as
                                 for FP32 weights.  0 = FP32 weights               */
+    int32_t hybrid_launches; /* hybrid sets (w_lagrange set) with tiles: 0 = one launch
+                                per step for both node kinds (workgroups of the
+                                per-node tiles first, then the block-centre tiles);
+                                2 = one launch per kind.  The results are identical */
 } mlbm_step_params;
 
 typedef struct mlbm_device_state {

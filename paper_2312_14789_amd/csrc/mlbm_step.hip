@@ -327,6 +327,9 @@ struct StepArgs {
     const unsigned short *lidx;  // LDS staging: tile-local member positions [K8/8][n][8]
     const void *wl;            // block weights [8][9] (FP64 storage: double, else float)
     int64_t tile0, tile1;      // tiles [tile0, tile1) of this launch (non-batched)
+    int64_t split;             // hybrid sets in one launch: workgroups [split, ...) walk the
+    int64_t tile0b, tile1b;    //   block-centre tiles [tile0b, tile1b) over grid8b workgroups
+    int64_t grid8b;
     int64_t lag0;              // first node of the trailing run of block centres (n: none);
                                // the tile holding it is visited by both launches, each
                                // updating its own nodes
@@ -349,17 +352,17 @@ __device__ __forceinline__ Rnd step_rnd(const StepArgs &a, int64_t i) {
 // a contiguous range of tiles.  With reverse the tiles are visited in the
 // opposite order, so alternating sweeps start where the previous one ended and
 // meet its most recently cached data first.
-__device__ __forceinline__ int64_t tile_of(const StepArgs &a) {
-    int64_t b = blockIdx.x;
+__device__ __forceinline__ int64_t tile_at(const StepArgs &a, int64_t b, int64_t grid8) {
     if (a.xcd) {
-        const int64_t per = a.grid8 >> 3;
+        const int64_t per = grid8 >> 3;
         const int64_t r = b >> 3;
         b = (b & 7) * per + (a.reverse ? per - 1 - r : r);
     } else if (a.reverse) {
-        b = a.grid8 - 1 - b;
+        b = grid8 - 1 - b;
     }
     return b;
 }
+__device__ __forceinline__ int64_t tile_of(const StepArgs &a) { return tile_at(a, blockIdx.x, a.grid8); }
 
 // Copies the state of every halo node of `tile` into LDS (NB bytes per node,
 // same layout as the global state), coalesced over 16-byte (or 8-byte) units.
@@ -585,6 +588,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_
     });
 }
 
+// A hybrid set in one launch: workgroups [0, split) take the tiles of the nodes
+// with per-node weights, the later ones the block-centre tiles.  The two kinds
+// write disjoint nodes and read only the previous state, so nothing orders
+// them; in one launch the short block-centre tiles fill the tail of the
+// per-node ones instead of waiting for it (two launches leave the chip to drain
+// in between, and the block-centre launch alone is too short to hide its
+// latency).  The tile holding both kinds is visited from both sides.
+template <int S, class CG, class C, int KQ, bool W16>
+__global__ void __launch_bounds__(256) k_step_pop_hyb(const StepArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int self0;
+    const int64_t b = blockIdx.x;
+    if (b < a.split) {
+        const int64_t tile = a.tile0 + tile_at(a, b, a.grid8);
+        if (tile >= a.tile1) return;
+        stage_halo<pop_bytes<S>(), false>(a, tile, smem, &self0);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) pop_node<S, CG, C, KQ, true, W16>(a, (const void *)smem, i, (int)i);
+    } else {
+        const int64_t tile = a.tile0b + tile_at(a, b - a.split, a.grid8b);
+        if (tile >= a.tile1b) return;
+        stage_halo<pop_bytes<S>(), true>(a, tile, smem, &self0);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) pop_node<S, CG, C, 0, true, false>(a, (const void *)smem, i, self0 + (int)threadIdx.x);
+    }
+}
+
 // ---- MLBM1 step (tau = 1, fields only) -------------------------------------------
 
 template <int S, class CG, class C, int KQ, bool LDS, bool W16 = false>
@@ -693,6 +723,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_
             fields_node<S, CG, C, KQ, LDS, W16>(a, LDS ? (const void *)smem : a.in, i,
                                            KQ == 0 && LDS ? self0 + (int)threadIdx.x : (int)i);
     });
+}
+
+// the MLBM1 step of a hybrid set in one launch (as k_step_pop_hyb)
+template <int S, class CG, class C, int KQ, bool W16>
+__global__ void __launch_bounds__(256) k_step_fields_hyb(const StepArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int self0;
+    const int64_t b = blockIdx.x;
+    if (b < a.split) {
+        const int64_t tile = a.tile0 + tile_at(a, b, a.grid8);
+        if (tile >= a.tile1) return;
+        stage_halo<field_bytes<S>(), false>(a, tile, smem, &self0);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) fields_node<S, CG, C, KQ, true, W16>(a, (const void *)smem, i, (int)i);
+    } else {
+        const int64_t tile = a.tile0b + tile_at(a, b - a.split, a.grid8b);
+        if (tile >= a.tile1b) return;
+        stage_halo<field_bytes<S>(), true>(a, tile, smem, &self0);
+        const int64_t i = tile * blockDim.x + threadIdx.x;
+        if (i < a.n) fields_node<S, CG, C, 0, true, false>(a, (const void *)smem, i, self0 + (int)threadIdx.x);
+    }
 }
 
 // ---- one stencil per departure point (the paper's stencils) ----------------------------
@@ -1180,6 +1231,43 @@ StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith, bool lds,
     return nullptr;
 }
 
+// hybrid sets with tiles in one launch (kq >= 2: the per-node part)
+template <int S, class CG, class C, bool W16 = false>
+StepFn pick_step_hyb(int variant, int kq) {
+#define MLBM_CASE(Q)                                                                              \
+    case Q:                                                                                       \
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop_hyb<S, CG, C, Q, W16>             \
+                                           : (StepFn)k_step_fields_hyb<S, CG, C, Q, W16>;
+    switch (kq) {
+        MLBM_CASE(2)
+        MLBM_CASE(3)
+        MLBM_CASE(4)
+        MLBM_CASE(5)
+        MLBM_CASE(6)
+        MLBM_CASE(7)
+        MLBM_CASE(8)
+        default:
+            return nullptr;
+    }
+#undef MLBM_CASE
+}
+
+StepFn pick_step_hyb_any(int storage, int variant, int kq, int fp32_arith, int w16) {
+    switch (storage) {
+        case MLBM_F64: return pick_step_hyb<MLBM_F64, double, double>(variant, kq);
+        case MLBM_F32:
+            return fp32_arith ? pick_step_hyb<MLBM_F32, float, float>(variant, kq)
+                              : pick_step_hyb<MLBM_F32, float, double>(variant, kq);
+        case MLBM_F16S:
+            return w16 ? pick_step_hyb<MLBM_F16S, float, float, true>(variant, kq)
+                       : pick_step_hyb<MLBM_F16S, float, float>(variant, kq);
+        case MLBM_BF16:
+            return w16 ? pick_step_hyb<MLBM_BF16, float, float, true>(variant, kq)
+                       : pick_step_hyb<MLBM_BF16, float, float>(variant, kq);
+    }
+    return nullptr;
+}
+
 using MacroFn = void (*)(const MacroArgs);
 
 template <int S>
@@ -1316,7 +1404,22 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     }
     a.lag0 = lag0;
     const int64_t ranges[2][2] = {{0, (lag0 + blk - 1) / blk}, {lag0 / blk, fb ? nb : 0}};
-    const StepFn fns[2] = {fn, fb};
+    StepFn fns[2] = {fn, fb};
+    if (p->hybrid_launches != 0 && p->hybrid_launches != 2) return fail(MLBM_ERR_ARG, "hybrid_launches must be 0 or 2");
+    // one launch for both node kinds: the per-node tiles' workgroups first (the
+    // longer ones), then the block-centre tiles'
+    const bool fuse = fb && lds && p->hybrid_launches == 0 && ranges[0][1] > 0;
+    a.split = 0;
+    a.tile0b = a.tile1b = a.grid8b = 0;
+    if (fuse) {
+        fns[0] = pick_step_hyb_any(p->storage, p->variant, kq, p->fp32_arith, p->weights16);
+        if (!fns[0]) return fail(MLBM_ERR_UNSUPPORTED, "no hybrid kernel for storage %d, K=%d", p->storage, st->K);
+        fns[1] = nullptr;
+        const int64_t cb = ranges[1][1] - ranges[1][0];
+        a.tile0b = ranges[1][0];
+        a.tile1b = ranges[1][1];
+        a.grid8b = p->xcd_remap ? (cb + 7) / 8 * 8 : cb;
+    }
     hipStream_t s = (hipStream_t)stream;
     a.sr = (p->stochastic_rounding && (p->storage == MLBM_F16S || p->storage == MLBM_BF16)) ? 1 : 0;
     for (int t = 0; t < nsteps; ++t) {
@@ -1328,10 +1431,12 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
         for (int r = 0; r < 2; ++r) {
             const int64_t cnt = ranges[r][1] - ranges[r][0];
             if (cnt <= 0) continue;
+            if (!fns[r]) continue;
             a.tile0 = ranges[r][0];
             a.tile1 = ranges[r][1];
             a.grid8 = a.xcd ? (cnt + 7) / 8 * 8 : cnt;
-            hipLaunchKernelGGL(fns[r], dim3((unsigned)a.grid8), dim3(blk), shmem, s, a);
+            if (fuse) a.split = a.grid8;
+            hipLaunchKernelGGL(fns[r], dim3((unsigned)(a.grid8 + a.grid8b)), dim3(blk), shmem, s, a);
         }
         rc = hip_check("mlbm_step launch");
         if (rc) return rc;
@@ -1694,6 +1799,7 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     a.wl = nullptr;  // batched runs use every node's own weights
     a.lag0 = st->n;  // (no block-centre launch)
     a.tile0 = a.tile1 = 0;
+    a.split = a.tile0b = a.tile1b = a.grid8b = 0;
     a.sr = 0;        // and round to nearest (a captured graph replays fixed keys)
     a.seed = 0;
     a.queue = b->queue;

@@ -147,7 +147,8 @@ class Simulation:
     def __init__(self, idx, w, bb, kind, area, *, variant=POPULATIONS, storage=F32, tau_plus=0.8,
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
                  fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda",
-                 packed=None, lagrange=None, w_lagrange=None, stochastic_rounding=0, weights16=0):
+                 packed=None, lagrange=None, w_lagrange=None, stochastic_rounding=0, weights16=0,
+                 hybrid_launches=0):
         import torch
 
         self.torch = torch
@@ -205,6 +206,7 @@ class Simulation:
         self.params.cached_weights = int(cached_weights)
         self.params.stochastic_rounding = int(stochastic_rounding)
         self.params.weights16 = int(bool(weights16))
+        self.params.hybrid_launches = int(hybrid_launches)
         self.ds = DeviceState()
         self.ds.n = n
         self.ds.K = K

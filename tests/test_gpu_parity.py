@@ -196,6 +196,31 @@ def test_block_centre_kernel_equals_per_node_weights(M, name, storage, tile):
     assert err <= {0: 1e-13, 1: 1e-6, 2: 1e-3}[storage]
 
 
+@pytest.mark.parametrize("name", ["hybrid_tgv", "hybrid_pixels_fields"])
+@pytest.mark.parametrize("storage,kw", [(0, {}), (1, {}), (1, {"fp32_arith": 1}),
+                                        (2, {"stochastic_rounding": 1, "weights16": 1}),
+                                        (3, {"weights16": 1}), (1, {"xcd_remap": 0})])
+def test_hybrid_one_launch_equals_two(M, name, storage, kw):
+    # one launch for both node kinds runs the same node code as the two
+    # launches, so the states agree (FMA contraction may differ between the
+    # two compiled kernels: FP64 and FP32 to rounding, 16-bit to a storage ulp)
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case(name)
+    out, raw = [], []
+    for launches in (0, 2):
+        sim = sim_from_oracle(M, ns, st, var, storage, tp, tm, g, tile=256, scale_exp=14,
+                              hybrid_launches=launches, **kw)
+        assert 0 < sim.ds.lagrange_begin < ns.n - 256
+        sim.init_state(rho0, u0)
+        sim.step(51)
+        _, u, _ = sim.macroscopic(dx)
+        out.append(u.cpu().numpy())
+        raw.append(sim.state_bytes().copy())
+    same = bool(np.array_equal(raw[0], raw[1]))
+    err = rel_l2(out[0], out[1])
+    print(f"[one-launch] case={name} storage={storage} {kw} identical={same} rel_l2_u={err:.3e}", flush=True)
+    assert err <= {0: 1e-13, 1: 1e-6, 2: 1e-3, 3: 3e-3}[storage]
+
+
 @pytest.mark.parametrize("name", ["pd_tgv", "pd_karman_trt", "pd_porous_fields", "pd_hybrid_patch",
                                   "pd_cylinder_channel"])
 @pytest.mark.parametrize("storage", [0, 1])
