@@ -397,22 +397,28 @@ __device__ __forceinline__ void stage_halo(const StepArgs &a, int64_t tile, void
 
 // Calls f(tile) for the tiles of this workgroup: one tile per workgroup over
 // the whole node range, or (batched launches) a contiguous chunk of the active
-// tile list per persistent workgroup, chunks XCD-contiguous like the tiles.
+// tile list per persistent workgroup.  With xcd the active entries are split
+// evenly over the 8 XCDs (the grid is a multiple of 8), each XCD's contiguous
+// share over its own workgroups: the grid is sized for a group's full tile
+// count, so splitting by workgroup alone would leave the last XCDs idle once
+// samples of the group have retired.
 template <class F>
 __device__ __forceinline__ void for_tiles(const StepArgs &a, F &&f) {
     if (a.queue) {
         const int q0 = a.queue_range[a.group], na = a.queue_range[a.group + 1] - q0;
-        const int G = gridDim.x;
-        int b = blockIdx.x;
+        int b = blockIdx.x, nw = gridDim.x, lo = 0, cnt = na;
         if (a.xcd) {
-            const int r = b >> 3, per = G >> 3;
-            b = (b & 7) * per + (a.reverse ? per - 1 - r : r);
-        } else if (a.reverse) {
-            b = G - 1 - b;
+            const int x = b & 7;
+            nw >>= 3;
+            b >>= 3;
+            if (b >= nw) return;  // (a grid that is not a multiple of 8)
+            lo = (int)(((int64_t)na * x) >> 3);
+            cnt = (int)(((int64_t)na * (x + 1)) >> 3) - lo;
         }
-        const int chunk = (na + G - 1) / G;
-        const int c1 = min(na, (b + 1) * chunk);
-        for (int c = b * chunk; c < c1; ++c) f((int64_t)a.queue[q0 + c]);
+        if (a.reverse) b = nw - 1 - b;
+        const int chunk = (cnt + nw - 1) / nw;
+        const int c1 = lo + min(cnt, (b + 1) * chunk);
+        for (int c = lo + b * chunk; c < c1; ++c) f((int64_t)a.queue[q0 + c]);
     } else {
         const int64_t tile = a.tile0 + tile_of(a);
         if (tile < a.tile1) f(tile);
