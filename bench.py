@@ -165,6 +165,54 @@ def copy_calibration():
     print(json.dumps({"read_probe_bytes": 8 * n, "per_thread": res}), flush=True)
 
 
+def batched_intervals(M, nodesets, np, torch, n_samples=64, tol=1e-6, g=3.242e-8, grid=2048, group_bytes=240e6):
+    """The 64-sample batch of the batched workload run 100 steps at a time
+    (direct launches, a host synchronisation after each interval), each
+    interval timed with its active node count: the throughput of the batched
+    kernels while samples retire, by phase."""
+    t0 = time.time()
+    sets = nodesets.porous_batch(n_samples, n_range=(50_000, 400_000), r_range=(0.01, 0.03))
+    built = [M.build_stencils_for(ns, 16, ns.h) for ns in sets]
+    print(f"# {n_samples} samples built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for b, ns in zip(built, sets)], variant=M.FIELDS,
+                              storage=M.F32, tau_plus=1.0, g=(g, 0.0), tile=256, check_every=100, grid=grid,
+                              group_bytes=group_bytes)
+    sizes = np.array(batch.sizes)
+
+    def rest():
+        batch.init_state([np.ones(n) for n in sizes], [np.zeros((n, 2)) for n in sizes])
+
+    rest()
+    batch.run(200, tol=0.0, use_graph=False)  # warm-up; tol 0 retires nothing
+    rest()
+    torch.cuda.synchronize()
+    rows = []
+    while len(rows) < 1000:
+        steps, _, _ = batch.results()
+        active = sizes[steps <= 0]
+        if active.size == 0:
+            break
+        t = time.perf_counter()
+        batch.run(100, tol=tol, use_graph=False)
+        batch.stream.synchronize()
+        rows.append((int(active.size), int(active.sum()), time.perf_counter() - t))
+        if len(rows) % 50 == 0:
+            print(f"# interval {len(rows)}: {active.size} samples active", file=sys.stderr, flush=True)
+    n_act = np.array([r[0] for r in rows])
+    upd = np.array([r[1] for r in rows], float) * 100
+    dt = np.array([r[2] for r in rows])
+    phases = {}
+    for name, sel in (("all active", n_act == n_samples), ("partly retired", (n_act < n_samples) & (n_act > 4)),
+                      ("last 4 or fewer", n_act <= 4)):
+        if sel.any():
+            phases[name] = {"intervals": int(sel.sum()), "seconds": round(float(dt[sel].sum()), 3),
+                            "MNUPS": round(float(upd[sel].sum() / dt[sel].sum() / 1e6), 1)}
+    return {"metric": "batched throughput by phase", "workload": f"{n_samples} porous samples, {int(sizes.sum())} "
+            f"nodes, MLBM1 FP32, K=16, 100-step intervals without graphs, grid {grid}, groups of "
+            f"{group_bytes:g} B", "seconds": round(float(dt.sum()), 3),
+            "MNUPS": round(float(upd.sum() / dt.sum() / 1e6), 1), "phases": phases}
+
+
 def karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m, scales=(2.0, 4.0), steps=50_000):
     """The Karman workload at larger streaming-distance scales s (Re = 100 s at
     fixed tau, Sec. 2.3): `steps` steps from rest on the same node set, each
@@ -598,10 +646,11 @@ def main():
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
     ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
     ap.add_argument("--workload", default="karman",
-                    choices=["karman", "porous", "batched", "warmstart", "darcy", "strouhal"],
+                    choices=["karman", "porous", "batched", "batched-intervals", "warmstart", "darcy", "strouhal"],
                     help="karman: the fused-step throughput line; porous: the MLBM1 step on the 1e6-node "
                          "porous sample; batched: 64 porous samples to steady "
-                         "state; warmstart: train the warm-start network and compare time to steady state; "
+                         "state; batched-intervals: the same batch timed per 100-step interval, by phase; "
+                         "warmstart: train the warm-start network and compare time to steady state; "
                          "darcy: mean velocity and tortuosity of the porous channel over a sweep of dx; "
                          "strouhal: the paper's cylinder channel, St from the lift over Re 105-168")
     ap.add_argument("--ws-train", type=int, default=2000)
@@ -630,6 +679,9 @@ def main():
         out["small_samples"] = batched_workload(M, units, nodesets, np, torch, n_samples=256,
                                                 n_range=(2_000, 20_000), r_range=(0.05, 0.12))
         print(json.dumps(out), flush=True)
+        return
+    if args.workload == "batched-intervals":
+        print(json.dumps(batched_intervals(M, nodesets, np, torch)), flush=True)
         return
     if args.workload == "warmstart":
         print(json.dumps(warmstart_workload(args, np, torch)), flush=True)
