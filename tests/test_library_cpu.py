@@ -289,3 +289,23 @@ def test_read_probe_rejects_bad_arguments():
     assert lib.mlbm_read_probe(buf, 1 << 20, 3, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
     assert lib.mlbm_read_probe(ctypes.c_void_p(17), 1 << 20, 4, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
     assert "per_thread" in lib.mlbm_last_error().decode() or "aligned" in lib.mlbm_last_error().decode()
+
+
+def test_step_rejects_bad_hybrid_launches():
+    # the launch-form check runs on the host before any launch; the buffers
+    # are never dereferenced
+    lib = _lib.lib
+    p = _lib.StepParams()
+    p.variant, p.storage, p.tau_plus, p.tau_minus = 0, 1, 0.8, 0.8
+    st = _lib.DeviceState()
+    st.n, st.K, st.cur, st.tile = 1000, 16, 0, 0
+    fake = 256
+    st.idx = st.w = st.flags = st.w_lagrange = fake
+    st.state[0] = st.state[1] = fake
+    st.lagrange_begin = 500
+    for bad in (1, 3, -1):
+        p.hybrid_launches = bad
+        assert lib.mlbm_step(ctypes.byref(p), ctypes.byref(st), 1, None) == _lib.MLBM_ERR_ARG
+        assert "hybrid_launches" in lib.mlbm_last_error().decode()
+    p.hybrid_launches = 2
+    assert lib.mlbm_step(ctypes.byref(p), ctypes.byref(st), 0, None) == _lib.MLBM_OK  # zero steps: no launch
