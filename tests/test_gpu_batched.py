@@ -68,12 +68,14 @@ def test_batched_state_equals_single_runs(M, variant, storage, group_bytes):
             assert _rows(raw, batch.N, a, m, variant, tb) == _rows(single, m, 0, m, variant, tb), (s_, use_graph)
 
 
-@pytest.mark.parametrize("group_bytes", [160e6, 2e6])
-def test_batched_retirement(M, group_bytes):
+@pytest.mark.parametrize("group_bytes,xcd", [(160e6, 1), (2e6, 1), (160e6, 0)])
+def test_batched_retirement(M, group_bytes, xcd):
+    # once a sample retires, its group's persistent workgroups walk the
+    # shortened active-tile list (split evenly over the XCDs with xcd)
     samples = _samples(M, sizes=(1200, 2000, 3200, 900), seed=50)
     g = (2e-6, 0.0)
     batch = M.BatchSimulation([(b, ns.kind[b["perm"]], None) for ns, b in samples], variant=1, storage=1,
-                              g=g, tile=128, check_every=100, group_bytes=group_bytes)
+                              g=g, tile=128, check_every=100, group_bytes=group_bytes, xcd_remap=xcd)
     batch.init_state([np.ones(b["idx"].shape[0]) for _, b in samples],
                      [np.zeros((b["idx"].shape[0], 2)) for _, b in samples])
     ran = batch.run(200000, tol=1e-6, use_graph=True)

@@ -221,6 +221,32 @@ def test_hybrid_one_launch_equals_two(M, name, storage, kw):
     assert err <= {0: 1e-13, 1: 1e-6, 2: 1e-3, 3: 3e-3}[storage]
 
 
+@pytest.mark.parametrize("name", ["hybrid_tgv", "hybrid_pixels_fields"])
+@pytest.mark.parametrize("launches,xcd", [(0, 1), (0, 0), (2, 1)])
+def test_hybrid_split_on_a_tile_boundary(M, name, launches, xcd):
+    # block centres just past the first one also have full per-node rows (the
+    # shared weights, zeros past member 8), so moving the start of the
+    # block-centre range up to the next tile boundary is another valid split:
+    # then no tile holds both kinds and the block-centre workgroups start at
+    # a tile of their own.  The fields agree with the unmoved split to rounding.
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case(name)
+    out = []
+    for move in (False, True):
+        sim = sim_from_oracle(M, ns, st, var, 0, tp, tm, g, tile=256, hybrid_launches=launches, xcd_remap=xcd)
+        lag0 = sim.ds.lagrange_begin
+        if move:
+            up = (lag0 + 255) // 256 * 256
+            assert lag0 < up < ns.n - 256
+            sim.ds.lagrange_begin = up
+        sim.init_state(rho0, u0)
+        sim.step(51)
+        _, u, _ = sim.macroscopic(dx)
+        out.append(u.cpu().numpy())
+    err = rel_l2(out[0], out[1])
+    print(f"[split] case={name} launches={launches} xcd={xcd} lag0={lag0} rel_l2_u={err:.3e}", flush=True)
+    assert err <= 1e-13
+
+
 @pytest.mark.parametrize("name", ["pd_tgv", "pd_karman_trt", "pd_porous_fields", "pd_hybrid_patch",
                                   "pd_cylinder_channel"])
 @pytest.mark.parametrize("storage", [0, 1])
