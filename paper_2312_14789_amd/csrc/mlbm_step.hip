@@ -594,6 +594,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(block_
     });
 }
 
+// Block-centre tiles of a one-launch hybrid step: 16-bit states stage the
+// tile's halo in LDS as the per-node tiles do; 32- and 64-bit states gather
+// the eight lattice neighbours straight from global memory (they sit in the
+// same or an adjacent Morton tile, so most of them hit in L2), which spares
+// the staging pass and its barriers.  Measured on the hybrid Karman set: FP32
+// 29.6 -> 28.1 us per step with global gathers; FP16 17.5 us staged against
+// 18.9 us with global gathers.
+template <int S> constexpr bool block_tiles_staged() { return Fmt<S>::TB == 2; }
+
 // A hybrid set in one launch: workgroups [0, split) take the tiles of the nodes
 // with per-node weights, the later ones the block-centre tiles.  The two kinds
 // write disjoint nodes and read only the previous state, so nothing orders
@@ -615,9 +624,13 @@ __global__ void __launch_bounds__(256) k_step_pop_hyb(const StepArgs a) {
     } else {
         const int64_t tile = a.tile0b + tile_at(a, b - a.split, a.grid8b);
         if (tile >= a.tile1b) return;
-        stage_halo<pop_bytes<S>(), true>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
-        if (i < a.n) pop_node<S, CG, C, 0, true, false>(a, (const void *)smem, i, self0 + (int)threadIdx.x);
+        if constexpr (block_tiles_staged<S>()) {
+            stage_halo<pop_bytes<S>(), true>(a, tile, smem, &self0);
+            if (i < a.n) pop_node<S, CG, C, 0, true, false>(a, (const void *)smem, i, self0 + (int)threadIdx.x);
+        } else {
+            if (i < a.n) pop_node<S, CG, C, 0, false, false>(a, a.in, i, (int)i);
+        }
     }
 }
 
@@ -746,9 +759,13 @@ __global__ void __launch_bounds__(256) k_step_fields_hyb(const StepArgs a) {
     } else {
         const int64_t tile = a.tile0b + tile_at(a, b - a.split, a.grid8b);
         if (tile >= a.tile1b) return;
-        stage_halo<field_bytes<S>(), true>(a, tile, smem, &self0);
         const int64_t i = tile * blockDim.x + threadIdx.x;
-        if (i < a.n) fields_node<S, CG, C, 0, true, false>(a, (const void *)smem, i, self0 + (int)threadIdx.x);
+        if constexpr (block_tiles_staged<S>()) {
+            stage_halo<field_bytes<S>(), true>(a, tile, smem, &self0);
+            if (i < a.n) fields_node<S, CG, C, 0, true, false>(a, (const void *)smem, i, self0 + (int)threadIdx.x);
+        } else {
+            if (i < a.n) fields_node<S, CG, C, 0, false, false>(a, a.in, i, (int)i);
+        }
     }
 }
 
