@@ -49,7 +49,8 @@ int64_t mlbm_conv_wgrad_workspace(const mlbm_conv_desc *desc, int32_t splits);
 /*
  * dw[o][tap][i] = sum_p dy[p, o] x[p + tap, i] (FP32, written) and, if db is
  * non-NULL, db[o] = sum_p dy[p, o]; the pixel sum is split into `splits`
- * parts whose partials are added in a fixed order (deterministic).
+ * parts whose partials are added in a fixed order (deterministic).  x and dy
+ * must be 16-byte aligned (MLBM_ERR_ARG otherwise).
  */
 int mlbm_conv_wgrad(const mlbm_conv_desc *desc, const void *x, const void *dy, float *dw, float *db, int32_t splits,
                     void *workspace, void *hip_stream);

@@ -93,6 +93,57 @@ __global__ void __launch_bounds__(256) k_conv_fwd(mlbm_conv_desc d, const unsign
     }
 }
 
+// Register-blocked forward convolution for c_out a multiple of 64: each wave
+// computes 2 x 2 MFMA tiles (64 pixels x 64 output channels), so every operand
+// fragment it loads feeds two MFMAs (half the loads per MFMA of k_conv_fwd);
+// 2 waves per block over 128 pixels.
+__global__ void __launch_bounds__(128) k_conv_fwd_rb(mlbm_conv_desc d, const unsigned short *x,
+                                                    const unsigned short *w, const float *bias, void *y, int relu,
+                                                    int y_f32) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p0 = (int64_t)blockIdx.x * 128 + wave * 64;
+    const int co0 = blockIdx.y * 64;
+    const int row = lane & 31, khalf = (lane >> 5) * 8;
+    const int ks = d.ksize, r = ks / 2, taps = ks * ks;
+    f32x16 acc[2][2] = {};
+    for (int t = 0; t < taps; ++t) {
+        const unsigned short *xa[2], *wb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t ps = shifted(p0 + 32 * i + row, d.h, d.w, t / ks - r, t % ks - r);
+            xa[i] = x + ps * d.x_stride + d.x_offset + khalf;
+            wb[i] = w + ((int64_t)(co0 + 32 * i + row) * taps + t) * d.c_in + khalf;
+        }
+        for (int c = 0; c < d.c_in; c += 16) {
+            const bf16x8 a0 = load_bf8(xa[0] + c), a1 = load_bf8(xa[1] + c);
+            const bf16x8 b0 = load_bf8(wb[0] + c), b1 = load_bf8(wb[1] + c);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = co0 + 32 * j + row;  // output channel of this lane
+        const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int64_t pp = p0 + 32 * i + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+                float v = acc[i][j][q] + bv;
+                if (relu) v = fmaxf(v, 0.0f);
+                if (col < d.c_store) {
+                    const int64_t o = pp * d.y_stride + d.y_offset + col;
+                    if (y_f32) ((float *)y)[o] = v;
+                    else ((unsigned short *)y)[o] = f2bf(v);
+                }
+            }
+        }
+    }
+}
+
 // ---- weight gradient ----------------------------------------------------------------
 // One wave per (32 output channels) x (32 input channels) x tap tile and pixel
 // split; 64-pixel chunks of dy and of the shifted x are transposed through LDS
@@ -156,15 +207,39 @@ __global__ void k_sum_splits(const float *ws, int splits, int64_t m, float *dw, 
 }
 
 // bias gradient: per-channel sums of dy in a fixed order (partials per block)
+// Partial bias gradient of px_per_block pixels: thread t reads channels
+// 8 (t % G) .. 8 (t % G) + 7 (one 16-byte load) of every (256 / G)-th pixel,
+// G = c_out / 8 channel groups; the rows of the block are then summed per
+// channel through LDS in a fixed order (deterministic).  c_out <= 256.
 __global__ void __launch_bounds__(256) k_bias_partial(mlbm_conv_desc d, const unsigned short *dy, float *ws,
                                                      int64_t px_per_block) {
-    const int c = threadIdx.x;  // one thread per channel (c_out <= 256)
-    if (c >= d.c_out) return;
+    __shared__ float red[256][9];
+    const int G = d.c_out >> 3, rows = (int)blockDim.x / G;
+    const int g = (int)threadIdx.x % G, r = (int)threadIdx.x / G;
     const int64_t P = (int64_t)d.n * d.h * d.w;
     const int64_t a = blockIdx.x * px_per_block, b = min(P, a + px_per_block);
-    float s = 0.0f;
-    for (int64_t p = a; p < b; ++p) s += bf2f(dy[p * d.y_stride + d.y_offset + c]);
-    ws[(int64_t)blockIdx.x * d.c_out + c] = s;
+    float s[8] = {};
+    if (r < rows) {
+#pragma unroll 4
+        for (int64_t p = a + r; p < b; p += rows) {
+            const u4 v = *(const u4 *)(dy + p * d.y_stride + d.y_offset + 8 * g);
+            const unsigned h[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[2 * k] += __uint_as_float(h[k] << 16);
+                s[2 * k + 1] += __uint_as_float(h[k] & 0xffff0000u);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = s[k];
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < d.c_out) {
+        float acc = 0.0f;
+        for (int rr = 0; rr < rows; ++rr) acc += red[rr * G + (c >> 3)][c & 7];
+        ws[(int64_t)blockIdx.x * d.c_out + c] = acc;
+    }
 }
 
 __global__ void k_bias_sum(const float *ws, int blocks, int c_out, float *db) {
@@ -347,8 +422,8 @@ extern "C" int mlbm_conv_forward(const mlbm_conv_desc *d, const void *x, const v
     if (d->y_offset + d->c_store > d->y_stride) return mlbm::fail(MLBM_ERR_ARG, "output view exceeds its stride");
     const int64_t P = (int64_t)d->n * d->h * d->w;
     hipStream_t s = (hipStream_t)stream;
-    if (d->c_out % 64 == 0)
-        hipLaunchKernelGGL(k_conv_fwd<64>, dim3((unsigned)(P / 64), d->c_out / 64), dim3(256), 0, s, *d,
+    if (d->c_out % 64 == 0)  // (the pixel count is a multiple of 128: check_desc)
+        hipLaunchKernelGGL(k_conv_fwd_rb, dim3((unsigned)(P / 128), d->c_out / 64), dim3(128), 0, s, *d,
                            (const unsigned short *)x, (const unsigned short *)w, bias, y, relu, y_f32);
     else
         hipLaunchKernelGGL(k_conv_fwd<32>, dim3((unsigned)(P / 128), d->c_out / 32), dim3(256), 0, s, *d,
@@ -371,6 +446,7 @@ extern "C" int mlbm_conv_wgrad(const mlbm_conv_desc *d, const void *x, const voi
     if (rc) return rc;
     if (!x || !dy || !dw || !workspace || splits < 1) return mlbm::fail(MLBM_ERR_ARG, "null pointer or splits < 1");
     if (db && d->c_out > 256) return mlbm::fail(MLBM_ERR_ARG, "bias gradient needs c_out <= 256");
+    if (((uintptr_t)x | (uintptr_t)dy) & 15) return mlbm::fail(MLBM_ERR_ARG, "x and dy must be 16-byte aligned");
     if (d->y_offset + d->c_out > d->y_stride) return mlbm::fail(MLBM_ERR_ARG, "gradient view exceeds its stride");
     const int64_t P = (int64_t)d->n * d->h * d->w;
     const int taps = d->ksize * d->ksize;
