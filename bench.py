@@ -594,8 +594,8 @@ def warmstart_workload(args, np, torch):
     rest_s = np.array([r["rest"]["seconds"] for r in rows])
     warm_s = np.array([r["warm"]["seconds"] for r in rows])
     kerr = np.array([abs(r["warm"]["permeability"] / r["rest"]["permeability"] - 1) for r in rows])
-    np.savez(os.path.join(ROOT, "gpurun_out", "warmstart_weights.npz"), **net.state_dict()) \
-        if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+    if args.ws_save:
+        np.savez(args.ws_save, **net.state_dict())
     fl = 0.0
     for name, k, ci, co in net.shapes:
         fl += 2.0 * k * k * ci * co * (res >> (int(name[3]) if name != "head" else 0)) ** 2
@@ -656,6 +656,7 @@ def main():
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-test", type=int, default=200)
     ap.add_argument("--ws-epochs", type=int, default=20)
+    ap.add_argument("--ws-save", default="", help="write the trained warm-start network's weights here (.npz)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a 1 GiB device copy (reference for byte counters and bandwidth)")
     args = ap.parse_args()
