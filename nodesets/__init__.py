@@ -162,6 +162,26 @@ def channel(nx: int, ny: int, jitter: float = 0.0, seed: int = 231214789,
                    walls_y=(True, True), h=H / (ny - 1), name=f"channel{nx}x{ny}")
 
 
+def dirichlet_channel(nx: int, ny: int, u_top: float = 0.0, jitter: float = 0.0,
+                      seed: int = 231214789, H: float = 1.0) -> NodeSet:
+    """The plane channel of `channel` (square cells: Lx = nx H / (ny - 1)),
+    but its bottom and top rows are Dirichlet lines instead of no-slip walls
+    (the straight-boundary arrangement of Sec. 3.1): prescribed rho = 1 and
+    velocity (0, 0) at y = 0 and (u_top, 0) at y = H.  No solid lies beyond
+    the lines, so departure points below y = 0 or above y = H stay where
+    they are."""
+    ns = channel(nx, ny, jitter=jitter, seed=seed, Lx=nx * H / (ny - 1), H=H)
+    top = np.isclose(ns.xy[:, 1], H)
+    bottom = np.isclose(ns.xy[:, 1], 0.0)
+    kind = np.zeros(ns.n, np.uint8)
+    kind[top | bottom] = DIRICHLET
+    bc = np.zeros((ns.n, 3))
+    bc[:, 0] = 1.0
+    bc[top, 1] = u_top
+    return NodeSet(xy=ns.xy, kind=kind, lo=ns.lo, hi=ns.hi, periodic=(True, False),
+                   walls_y=(False, False), bc=bc, h=ns.h, name=f"dirichlet_channel{nx}x{ny}")
+
+
 # --------------------------------------------------------------------------
 # Scattered node sets with refinement and obstacles
 # --------------------------------------------------------------------------

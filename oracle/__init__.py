@@ -21,8 +21,11 @@ Modules
   lbm      the standard lattice LBM and LBM1 on a periodic square lattice
            (Sec. 2.1), used only to pin the meshless step at s = 1.
 
-Parity status: every function is pinned except the momentum-exchange drag
-and the permeability formula, whose physics is "parity unpinned" (the paper
-reports neither on scattered nodes); they are checked only for consistency
-between the oracle and the library.
+Parity status: every function is pinned.  The wall force (momentum
+exchange, not in the paper) is pinned by the steady momentum balance of a
+channel and by the one-step momentum budget of a periodic sample with disks,
+where the rest-state subtraction matters; the Dirichlet overwrite by plane
+Couette flow (exact on the lattice at tau = 1) and by flows between Dirichlet
+lines converging to their closed forms; the permeability formula by the
+plane channel's k = H^2 / 12.
 """

@@ -158,7 +158,9 @@ def build_stencils(ns, K, dx, lattice_h=None, per_departure=False, simple_bb=Fal
 
 def dirichlet_overwrite(fpost, ns):
     """Overwrite all populations of Dirichlet nodes with the equilibrium of the
-    prescribed density and velocity (Sec. 3.1)."""
+    prescribed density and velocity (Sec. 3.1).  Pinned by plane Couette flow
+    between two Dirichlet lines (exact on the lattice at s = 1, tau = 1) and
+    by the convergence of flows between such lines to their closed forms."""
     d = ns.kind == DIRICHLET
     if np.any(d):
         bc = ns.boundary_values()
@@ -275,7 +277,8 @@ def mlbm1_bounce_back_force(rho, u, ns, st, g, dx, area=None):
     bounce_back_force): the post-collision population k' at the node is its
     equilibrium plus half the force term (tau = 1), the returning population
     k the same at the interpolated fields of the mirrored point; both
-    relative to the rest state."""
+    relative to the rest state.  Pinned, like bounce_back_force, by the
+    one-step momentum budget of a periodic sample with disks."""
     area = st.area if area is None else area
     g = np.asarray(g, dtype=np.float64)
     own = lt.equilibrium(rho, u) + 0.5 * lt.guo_force(rho, u, g)
@@ -331,6 +334,7 @@ def tortuosity(red):
 def permeability(red, box_area, nu_lb, g_lb, dx):
     """Darcy permeability k = nu U_s / g with the superficial velocity
     U_s = int_D u dOmega / |D|, converted from lattice units (dx = 1) to the
-    node coordinates' units.  Parity unpinned (the paper reports none)."""
+    node coordinates' units.  Pinned by a plane channel, whose permeability
+    is H^2 / 12 (the paper reports none on scattered nodes)."""
     U_s = red["int_ux"] / box_area
     return nu_lb * U_s / g_lb * dx * dx
