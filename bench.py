@@ -142,15 +142,16 @@ def copy_calibration():
                       "GBps_read_plus_write": 2 * 4 * n / ms / 1e6}), flush=True)
     # a read-only stream of 2 GiB (mlbm_read_probe): the practical bandwidth of
     # a kernel that, like the step, mostly reads
-    from paper_2312_14789_amd import _lib
+    from paper_2312_14789_amd import probe
 
+    plib = probe.load()
     z = torch.ones(2 * n, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     res = {}
     for per_thread in (2, 4, 8):
         out = torch.empty(8 * n // (16 * per_thread), dtype=torch.float32, device="cuda")
-        call = lambda: _lib.check(_lib.lib.mlbm_read_probe(z.data_ptr(), 8 * n, per_thread, out.data_ptr(),  # noqa: E731
-                                                           ctypes.c_void_p(stream.cuda_stream)))
+        call = lambda: probe.read_probe(plib, z.data_ptr(), 8 * n, per_thread, out.data_ptr(),  # noqa: E731
+                                        ctypes.c_void_p(stream.cuda_stream))
         for _ in range(3):
             call()
         torch.cuda.synchronize()
@@ -279,7 +280,7 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s
         storage = getattr(M, storage_name)
         sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.FIELDS,
                            storage=storage, tau_plus=1.0, g=(g, 0.0), scale_exp=sigma, stochastic_rounding=sr,
-                           weights16=name.endswith("_w16"))
+                           weights16=name.endswith("_w16"), box_area=float(np.prod(ns.hi - ns.lo)))
         if out["setup_s"] is None:
             out["setup_s"] = round(time.time() - t0, 2)
         sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
@@ -289,7 +290,7 @@ def porous_time_to_steady(M, units, nodesets, np, torch, tol=1e-6, g=3.242e-8, s
         steps, res, red = sim.run_to_steady(dx, tol=tol_c, check_every=every, max_steps=cap, criterion=crit)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
-        k = nu * (red[M._lib.RED_INT_UX] / 1.0) / g * dx * dx
+        k = float(red[M._lib.RED_PERMEABILITY])
         umean = red[M._lib.RED_INT_UX] / ns.fluid_area()
         rec = {"criterion": crit, "check_every": every, "tol": tol_c, "stochastic_rounding": sr,
                "weights": "f16" if name.endswith("_w16") else ("f32" if storage != M.F64 else "f64"), "steps": steps,
@@ -626,7 +627,6 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--tile", type=int, default=256, help="LDS-staged tile size (0 = global gathers)")
     ap.add_argument("--xcd", type=int, default=1)
-    ap.add_argument("--fp32-arith", type=int, default=0, help="FP32 register arithmetic for f32 storage")
     ap.add_argument("--sweeps", type=int, default=1, help="alternate the tile sweep direction")
     ap.add_argument("--cached", type=int, default=0, help="ordinary (not non-temporal) weight loads")
     ap.add_argument("--nodes", type=int, default=500_000, help="target node count of the workload")
@@ -718,7 +718,7 @@ def main():
           f"{time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
                        storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
-                       block=args.block, xcd_remap=args.xcd, scale_exp=12, fp32_arith=args.fp32_arith,
+                       block=args.block, xcd_remap=args.xcd, scale_exp=12,
                        alternate_sweeps=args.sweeps, cached_weights=args.cached,
                        tile=args.tile, lagrange=b["lagrange"], w_lagrange=b["w_lagrange"],
                        stochastic_rounding=args.sr, weights16=args.weights16,
@@ -764,7 +764,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32" if args.fp32_arith else "f32 state+weights, f64 registers",
+        "dtype": {"f64": "f64", "f32": "f32 state+weights, f64 registers",
                   "f16s": f"f16 state (scaled offsets), {'f16' if args.weights16 else 'f32'} weights, f32 registers",
                   "bf16": f"bf16 state, {'f16' if args.weights16 else 'f32'} weights, f32 registers"}[args.storage],
         "data": "synthetic",
@@ -779,7 +779,7 @@ def main():
                                f"{args.storage} populations",
                    "nodes": n, "block_centres": n_lag, "K": K, "s": args.s, "block": args.block,
                    "xcd_remap": args.xcd,
-                   "fp32_arith": args.fp32_arith, "alternate_sweeps": args.sweeps,
+                   "alternate_sweeps": args.sweeps,
                    "cached_weights": args.cached, "tile": args.tile, "reorder": args.reorder,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

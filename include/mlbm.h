@@ -23,9 +23,9 @@
  *     mlbm_last_error() and stays valid until the next call on that thread.
  *   - Host pointers are read or written only during the call.  Device
  *     pointers and the HIP stream are owned by the caller; device work is
- *     enqueued on the given stream (NULL = the default stream), is
- *     asynchronous, and the library never synchronises the device nor
- *     allocates device memory.
+ *     enqueued on the given stream (NULL = the default stream) and is
+ *     asynchronous; only mlbm_step_batched and mlbm_run_to_steady wait on
+ *     their stream.  The library never allocates device memory.
  *   - Node order in every array is the order chosen by mlbm_build_stencils
  *     (perm[new] = old maps back to the caller's order).
  *   - Nothing here is thread safe with respect to the same output buffers.
@@ -47,6 +47,7 @@ extern "C" {
 #define MLBM_ERR_SINGULAR    -3  /* a local interpolation system is singular   */
 #define MLBM_ERR_HIP         -4  /* a HIP launch or runtime call failed        */
 #define MLBM_ERR_UNSUPPORTED -5  /* variant x storage x K combination missing  */
+#define MLBM_ERR_UNSTABLE    -6  /* non-finite fields or rho <= 0 seen by a check */
 
 /* ---- node kinds (geometry) ------------------------------------------------ */
 #define MLBM_FLUID     0  /* ordinary fluid node                                */
@@ -195,19 +196,6 @@ int mlbm_pack_stencils_range(int64_t n_total, int64_t offset, int64_t n, int32_t
  */
 int mlbm_weights_to_f16(int64_t n, int32_t k_padded, const float *in, uint16_t *out);
 
-/* ---- measurement helper (not part of the method) ----------------------------- */
-
-/*
- * Streaming-read probe: one kernel that reads the device buffer buf (bytes,
- * 16-byte aligned, a multiple of 16 * 256 * per_thread) once with 16-byte
- * non-temporal loads, per_thread (2, 4 or 8) loads per thread, and writes one
- * float per thread to the device array out (bytes / (16 * per_thread) floats,
- * caller-owned).  Timing it gives the practical read bandwidth that bounds a
- * kernel which, like the step, mostly reads.  Asynchronous on stream.
- * Errors: MLBM_ERR_ARG (null or misaligned buffers, bad sizes), MLBM_ERR_HIP.
- */
-int mlbm_read_probe(const void *buf, int64_t bytes, int32_t per_thread, float *out, void *stream);
-
 /*
  * Sets MLBM_FLAG_LAGRANGE in packed flags[i] where lagrange[i] != 0 (the
  * builder's lagrange output), so that mlbm_step takes those nodes' weights
@@ -249,8 +237,11 @@ typedef struct mlbm_step_params {
     int32_t block;           /* threads per workgroup, multiple of 64 in [64, 1024];
                                 0 = 256                                             */
     int32_t xcd_remap;       /* 1 = give each XCD a contiguous range of node tiles */
-    int32_t fp32_arith;      /* MLBM_F32 only: 1 = FP32 collision arithmetic; 0 (default)
-                                = FP64 collision (interpolation sums are FP32 either way) */
+    int32_t fp32_arith;      /* must be 0: FP32 states collide in FP64 registers (their
+                                interpolation sums are FP32).  1 (FP32 collision) is
+                                refused with MLBM_ERR_UNSUPPORTED: over 1000 Taylor-Green
+                                steps it drifts 2.3e-5 from the FP64 oracle, above the
+                                1e-5 bar of FP32 states, for ~1 % of speed          */
     int32_t alternate_sweeps;/* 1 = visit the node tiles in reverse order on every
                                 other step (the step reading state[1])             */
     int32_t cached_weights;  /* 1 = ordinary loads for weights and indices; 0 =
@@ -407,10 +398,30 @@ int mlbm_step_batched(const mlbm_step_params *params, mlbm_device_state *state, 
 #define MLBM_RED_FORCE_Y   7
 #define MLBM_RED_N_BAD     8   /* number of nodes with non-finite fields or rho <= 0 */
 #define MLBM_RED_FIRST_BAD 9   /* smallest such node index, or n                    */
-#define MLBM_RED_COUNT     10
+#define MLBM_RED_RESIDUAL  10  /* field residual sqrt(NORM_DU2 / NORM_U2) (0 when
+                                  NORM_U2 = 0): ||u - u_prev|| / ||u|| over nodes  */
+#define MLBM_RED_PREV_INT_UX 11 /* INT_UX that red_out held before this call (NaN
+                                  after mlbm_reductions_reset)                     */
+#define MLBM_RED_MEAN_CHANGE 12 /* |INT_UX - PREV_INT_UX| / |INT_UX|: the relative
+                                  change of the mean velocity between two calls on
+                                  the same red_out (Sec. 3.2, Eq. 24's quantity);
+                                  NaN when there is no previous value              */
+#define MLBM_RED_PERMEABILITY 13 /* Darcy permeability k = nu U_s / g_x dx^2 in the
+                                  units of xy squared: nu = (tau+ - 1/2) / 3 in
+                                  lattice units, U_s = INT_UX / box_area the
+                                  superficial velocity; NaN when g_x = 0 or
+                                  box_area <= 0                                     */
+#define MLBM_RED_COUNT     14
 
 /* Bytes of the device workspace mlbm_macroscopic needs for n nodes. */
 int64_t mlbm_reduction_workspace_bytes(int64_t n);
+
+/*
+ * Fills the device array red_out [MLBM_RED_COUNT] with NaN (a kernel, so it
+ * may be captured in a graph), so that the next mlbm_macroscopic on it has no
+ * previous mean velocity.  Errors: MLBM_ERR_ARG, MLBM_ERR_HIP.
+ */
+int mlbm_reductions_reset(double *red_out, void *hip_stream);
 
 /*
  * Macroscopic fields of state[cur]: rho and u (populations: u = sum e f / rho
@@ -420,14 +431,47 @@ int64_t mlbm_reduction_workspace_bytes(int64_t n);
  * non-NULL the squared change against it is accumulated and u is then copied
  * into it.  Reductions over nodes with the quadrature weights area (device
  * FP64 [n]) are summed in FP64 in a fixed order (bitwise reproducible) and
- * written to red_out (device FP64 [MLBM_RED_COUNT]).  The force sums, over
- * every bounced (node, k), e_k' (f_k'^post + f_k^new) A / dx^2.
+ * written to red_out (device FP64 [MLBM_RED_COUNT]); red_out is also read:
+ * its MLBM_RED_INT_UX before the call becomes MLBM_RED_PREV_INT_UX.  The
+ * force sums, over every bounced (node, k), e_k' (f_k'^post + f_k^new) A / dx^2
+ * relative to the rest state.  dx: the streaming distance in the units of xy;
+ * box_area: |D| of the superficial velocity (<= 0: no permeability).
  * workspace: device, mlbm_reduction_workspace_bytes(n) bytes.
  * Errors: MLBM_ERR_ARG, MLBM_ERR_UNSUPPORTED, MLBM_ERR_HIP.
  */
 int mlbm_macroscopic(const mlbm_step_params *params, const mlbm_device_state *state,
-                     const double *area, double dx, double *rho_out, double *u_out, double *u_prev,
-                     void *workspace, double *red_out, void *hip_stream);
+                     const double *area, double dx, double box_area, double *rho_out, double *u_out,
+                     double *u_prev, void *workspace, double *red_out, void *hip_stream);
+
+/* ---- running to a steady state (device, synchronous) --------------------------- */
+#define MLBM_STEADY_FIELD 0    /* stop on MLBM_RED_RESIDUAL < tol                   */
+#define MLBM_STEADY_MEAN  1    /* stop on MLBM_RED_MEAN_CHANGE < tol (Sec. 3.2, Eq. 24) */
+
+typedef struct mlbm_steady {
+    int32_t criterion;       /* MLBM_STEADY_FIELD or MLBM_STEADY_MEAN              */
+    int32_t check_every;     /* steps between checks, >= 1                         */
+    int32_t hold;            /* consecutive checks below tol needed, >= 1           */
+    int64_t max_steps;       /* step cap, >= 0                                      */
+    double tol;              /* > 0                                                 */
+} mlbm_steady;
+
+/*
+ * Steps the state of `state` until it is steady (Sec. 3.2, Eq. 24; the field
+ * residual or the relative change of the mean velocity between checks
+ * check_every steps apart stays below tol for `hold` checks) or max_steps are
+ * taken: mlbm_step and mlbm_macroscopic (with u_prev) alternate, and after
+ * each check the reductions are copied to red_host [MLBM_RED_COUNT] (host)
+ * and the stream is synchronised.  Before the first step red_out is reset and
+ * u_prev (device FP64 [n][2], caller workspace) takes the current velocity.
+ * *steps_done receives the steps taken; red_host holds the last check.
+ * Returns MLBM_OK whether or not the state settled (compare red_host with
+ * tol), MLBM_ERR_UNSTABLE as soon as a check sees a node with non-finite
+ * fields or rho <= 0 (the message names the count, the first node and the
+ * step), MLBM_ERR_ARG, MLBM_ERR_UNSUPPORTED or MLBM_ERR_HIP otherwise.
+ */
+int mlbm_run_to_steady(const mlbm_step_params *params, mlbm_device_state *state, const mlbm_steady *steady,
+                       const double *area, double dx, double box_area, double *u_prev, void *workspace,
+                       double *red_out, double *red_host, int64_t *steps_done, void *hip_stream);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *mlbm_last_error(void);

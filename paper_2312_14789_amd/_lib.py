@@ -15,6 +15,7 @@ MLBM_ERR_GEOMETRY = -2
 MLBM_ERR_SINGULAR = -3
 MLBM_ERR_HIP = -4
 MLBM_ERR_UNSUPPORTED = -5
+MLBM_ERR_UNSTABLE = -6
 
 FLUID, WALL, DIRICHLET = 0, 1, 2
 FLAG_LAGRANGE = 0x400
@@ -22,7 +23,9 @@ POPULATIONS, FIELDS = 0, 1
 F64, F32, F16S, BF16 = 0, 1, 2, 3
 
 RED_MASS, RED_INT_UX, RED_INT_UY, RED_INT_SPEED, RED_NORM_U2, RED_NORM_DU2 = range(6)
-RED_FORCE_X, RED_FORCE_Y, RED_N_BAD, RED_FIRST_BAD, RED_COUNT = 6, 7, 8, 9, 10
+RED_FORCE_X, RED_FORCE_Y, RED_N_BAD, RED_FIRST_BAD = 6, 7, 8, 9
+RED_RESIDUAL, RED_PREV_INT_UX, RED_MEAN_CHANGE, RED_PERMEABILITY, RED_COUNT = 10, 11, 12, 13, 14
+STEADY_FIELD, STEADY_MEAN = 0, 1
 
 _p = ctypes.c_void_p
 
@@ -70,6 +73,11 @@ class DeviceState(ctypes.Structure):
                 ("step_count", ctypes.c_uint64), ("per_departure", ctypes.c_int32)]
 
 
+class Steady(ctypes.Structure):
+    _fields_ = [("criterion", ctypes.c_int32), ("check_every", ctypes.c_int32), ("hold", ctypes.c_int32),
+                ("max_steps", ctypes.c_int64), ("tol", ctypes.c_double)]
+
+
 class Batch(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int32), ("check_every", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("sample_tile_off", _p), ("sample_tile_off_host", _p), ("area", _p), ("u_prev", _p),
@@ -115,7 +123,6 @@ def _load():
                                                     _p, _p]),
         "mlbm_mark_lagrange": (ctypes.c_int, [ctypes.c_int64, _p, _p]),
         "mlbm_weights_to_f16": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, _p, _p]),
-        "mlbm_read_probe": (ctypes.c_int, [_p, ctypes.c_int64, ctypes.c_int32, _p, _p]),
         "mlbm_batch_init": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), _p]),
         "mlbm_step_batched": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Batch), ctypes.c_int32,
                                              ctypes.c_double, ctypes.c_int32, P(ctypes.c_int32), _p]),
@@ -125,8 +132,11 @@ def _load():
         "mlbm_init_state": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, _p, _p]),
         "mlbm_step": (ctypes.c_int, [P(StepParams), P(DeviceState), ctypes.c_int32, _p]),
         "mlbm_reduction_workspace_bytes": (ctypes.c_int64, [ctypes.c_int64]),
-        "mlbm_macroscopic": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, ctypes.c_double, _p,
-                                            _p, _p, _p, _p, _p]),
+        "mlbm_macroscopic": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, ctypes.c_double,
+                                            ctypes.c_double, _p, _p, _p, _p, _p, _p]),
+        "mlbm_reductions_reset": (ctypes.c_int, [_p, _p]),
+        "mlbm_run_to_steady": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Steady), _p, ctypes.c_double,
+                                              ctypes.c_double, _p, _p, _p, _p, P(ctypes.c_int64), _p]),
         "mlbm_conv_forward": (ctypes.c_int, [P(ConvDesc), _p, _p, _p, _p, ctypes.c_int32, ctypes.c_int32, _p]),
         "mlbm_conv_wgrad_workspace": (ctypes.c_int64, [P(ConvDesc), ctypes.c_int32]),
         "mlbm_conv_wgrad": (ctypes.c_int, [P(ConvDesc), _p, _p, _p, _p, ctypes.c_int32, _p, _p]),
@@ -161,10 +171,10 @@ lib = _load()
 
 # every symbol the header declares (checked by the tests)
 EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_pack_stencils_range",
-           "mlbm_mark_lagrange", "mlbm_weights_to_f16", "mlbm_read_probe",
+           "mlbm_mark_lagrange", "mlbm_weights_to_f16",
            "mlbm_tile_sizes", "mlbm_pack_tiles", "mlbm_init_state", "mlbm_batch_init", "mlbm_step_batched",
-           "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_macroscopic", "mlbm_last_error",
-           "mlbm_version"]
+           "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_reductions_reset", "mlbm_macroscopic",
+           "mlbm_run_to_steady", "mlbm_last_error", "mlbm_version"]
 
 # every symbol include/mlbm_unet.h declares
 UNET_EXPORTS = ["mlbm_conv_forward", "mlbm_conv_wgrad_workspace", "mlbm_conv_wgrad", "mlbm_conv_weights",

@@ -10,6 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmlbm.so")
+PROBE_LIB = os.path.join(HERE, "libmlbm_probe.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -21,7 +22,9 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", 
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
 HOST_SOURCES = ["stencil_build.cpp", "mlbm_common.cpp"]
-HIP_SOURCES = ["mlbm_step.hip", "unet.hip", "bw_probe.hip"]
+HIP_SOURCES = ["mlbm_step.hip", "unet.hip"]
+# a bandwidth measurement helper, linked into a library of its own
+PROBE_SOURCES = ["bw_probe.hip"]
 
 
 def _run(cmd):
@@ -29,8 +32,14 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
+def _link(objs, out):
+    tmp = out + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-pthread"])
+    os.replace(tmp, out)
+
+
 def build(verbose: bool = True) -> str:
-    """Compiles every source and links LIB; returns its path."""
+    """Compiles every source, links LIB and PROBE_LIB; returns LIB's path."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src in HOST_SOURCES:
@@ -41,9 +50,13 @@ def build(verbose: bool = True) -> str:
         obj = os.path.join(BUILD, src + ".o")
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-pthread"])
-    os.replace(tmp, LIB)
+    _link(objs, LIB)
+    probe_objs = []
+    for src in PROBE_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        probe_objs.append(obj)
+    _link(probe_objs, PROBE_LIB)
     return LIB
 
 

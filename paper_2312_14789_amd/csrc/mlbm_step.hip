@@ -1004,7 +1004,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
     using C = typename Fmt<S>::C;
     __shared__ double lds[RED_BLOCK / 64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double v[MLBM_RED_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0, (double)a.n};
+    double v[MLBM_RED_FIRST_BAD + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0, (double)a.n};
     if (i < a.n) {
         const int64_t n = a.n;
         const unsigned fl = a.flags[i];
@@ -1116,7 +1116,7 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
             v[MLBM_RED_FORCE_Y] = A * a.inv_dx2 * Fy;
         }
     }
-    double *dst = a.ws + (int64_t)blockIdx.x * MLBM_RED_COUNT;
+    double *dst = a.ws + (int64_t)blockIdx.x * (MLBM_RED_FIRST_BAD + 1);
 #pragma unroll
     for (int r = 0; r < MLBM_RED_FIRST_BAD; ++r) {
         const double s = block_sum(v[r], lds);
@@ -1126,18 +1126,40 @@ __global__ void __launch_bounds__(RED_BLOCK) k_macro(const MacroArgs a) {
     if (threadIdx.x == 0) dst[MLBM_RED_FIRST_BAD] = mn;
 }
 
-// sums the per-block partials in a fixed order
-__global__ void __launch_bounds__(RED_BLOCK) k_reduce_final(const double *ws, int64_t nblocks, double *out) {
+struct FinalArgs {
+    const double *ws;   // per-block partials [nblocks][10]
+    int64_t nblocks;
+    double *out;        // [MLBM_RED_COUNT], read (previous INT_UX) and written
+    double nu, gx, dx, box_area;
+};
+
+// sums the per-block partials in a fixed order, then the derived quantities
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce_final(const FinalArgs a) {
     __shared__ double lds[RED_BLOCK / 64];
-    for (int r = 0; r < MLBM_RED_COUNT; ++r) {
+    double r_[MLBM_RED_FIRST_BAD + 1];
+    const double prev_ux = threadIdx.x == 0 ? a.out[MLBM_RED_INT_UX] : 0.0;
+    for (int r = 0; r <= MLBM_RED_FIRST_BAD; ++r) {
         double s = r == MLBM_RED_FIRST_BAD ? INFINITY : 0.0;
-        for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
-            const double x = ws[b * MLBM_RED_COUNT + r];
+        for (int64_t b = threadIdx.x; b < a.nblocks; b += blockDim.x) {
+            const double x = a.ws[b * (MLBM_RED_FIRST_BAD + 1) + r];
             s = r == MLBM_RED_FIRST_BAD ? fmin(s, x) : s + x;
         }
-        const double t = r == MLBM_RED_FIRST_BAD ? block_min(s, lds) : block_sum(s, lds);
-        if (threadIdx.x == 0) out[r] = t;
+        r_[r] = r == MLBM_RED_FIRST_BAD ? block_min(s, lds) : block_sum(s, lds);
     }
+    if (threadIdx.x == 0) {
+        for (int r = 0; r <= MLBM_RED_FIRST_BAD; ++r) a.out[r] = r_[r];
+        const double u2 = r_[MLBM_RED_NORM_U2], ux = r_[MLBM_RED_INT_UX];
+        a.out[MLBM_RED_RESIDUAL] = u2 > 0.0 ? sqrt(r_[MLBM_RED_NORM_DU2] / u2) : 0.0;
+        a.out[MLBM_RED_PREV_INT_UX] = prev_ux;
+        a.out[MLBM_RED_MEAN_CHANGE] = fabs(ux - prev_ux) / fabs(ux);
+        a.out[MLBM_RED_PERMEABILITY] =
+            (a.gx != 0.0 && a.box_area > 0.0) ? a.nu * (ux / a.box_area) / a.gx * a.dx * a.dx : NAN;
+    }
+}
+
+__global__ void k_fill_nan(double *out, int count) {
+    const int i = threadIdx.x;
+    if (i < count) out[i] = NAN;
 }
 
 // ---- dispatch ---------------------------------------------------------------------------
@@ -1158,6 +1180,9 @@ int check_common(const mlbm_step_params *p, const mlbm_device_state *st) {
     if (p->weights16 != 0 && p->weights16 != 1) return fail(MLBM_ERR_ARG, "weights16 must be 0 or 1");
     if (p->weights16 && p->storage != MLBM_F16S && p->storage != MLBM_BF16)
         return fail(MLBM_ERR_UNSUPPORTED, "FP16 weights go with 16-bit states only");
+    if (p->fp32_arith)
+        return fail(MLBM_ERR_UNSUPPORTED, "FP32 collision arithmetic is not offered (it drifts above the FP32 "
+                                          "bar over long runs); FP32 states collide in FP64 registers");
     return MLBM_OK;
 }
 
@@ -1194,11 +1219,11 @@ StepFn pick_step(int variant, int kq, bool lds) {
 #undef MLBM_CASE
 }
 
-// FP32 state: the interpolation sums run in FP32 and the collision in FP64
-// unless fp32_arith is set.  The FP32 rounding drift of a long run comes from
-// the collision (the interpolation in FP32 adds nothing measurable), and the
-// FP64 collision costs little in a kernel bound by memory traffic.  16-bit
-// states use FP32 throughout.
+// FP32 state: the interpolation sums run in FP32 and the collision in FP64.
+// The FP32 rounding drift of a long run comes from the collision (the
+// interpolation in FP32 adds nothing measurable), and the FP64 collision costs
+// little in a kernel bound by memory traffic.  16-bit states use FP32
+// throughout.
 template <int S, class CG, class C, bool W16 = false>
 StepFn pick_step_pd(int variant, int kq) {
 #define MLBM_CASE(Q)                                                                              \
@@ -1220,12 +1245,10 @@ StepFn pick_step_pd(int variant, int kq) {
 }
 
 // per-departure stencils: the same arithmetic choices as pick_step_any
-StepFn pick_step_pd_any(int storage, int variant, int kq, int fp32_arith, int w16) {
+StepFn pick_step_pd_any(int storage, int variant, int kq, int w16) {
     switch (storage) {
         case MLBM_F64: return pick_step_pd<MLBM_F64, double, double>(variant, kq);
-        case MLBM_F32:
-            return fp32_arith ? pick_step_pd<MLBM_F32, float, float>(variant, kq)
-                              : pick_step_pd<MLBM_F32, float, double>(variant, kq);
+        case MLBM_F32: return pick_step_pd<MLBM_F32, float, double>(variant, kq);
         case MLBM_F16S:
             return w16 ? pick_step_pd<MLBM_F16S, float, float, true>(variant, kq)
                        : pick_step_pd<MLBM_F16S, float, float>(variant, kq);
@@ -1238,12 +1261,10 @@ StepFn pick_step_pd_any(int storage, int variant, int kq, int fp32_arith, int w1
 
 // w16: FP16 weights (16-bit states; block-centre launches, kq = 0, read no
 // per-node weights and take w16 = 0)
-StepFn pick_step_any(int storage, int variant, int kq, int fp32_arith, bool lds, int w16) {
+StepFn pick_step_any(int storage, int variant, int kq, bool lds, int w16) {
     switch (storage) {
         case MLBM_F64: return pick_step<MLBM_F64, double, double>(variant, kq, lds);
-        case MLBM_F32:
-            return fp32_arith ? pick_step<MLBM_F32, float, float>(variant, kq, lds)
-                              : pick_step<MLBM_F32, float, double>(variant, kq, lds);
+        case MLBM_F32: return pick_step<MLBM_F32, float, double>(variant, kq, lds);
         case MLBM_F16S:
             return w16 && kq ? pick_step<MLBM_F16S, float, float, true>(variant, kq, lds)
                              : pick_step<MLBM_F16S, float, float>(variant, kq, lds);
@@ -1275,12 +1296,10 @@ StepFn pick_step_hyb(int variant, int kq) {
 #undef MLBM_CASE
 }
 
-StepFn pick_step_hyb_any(int storage, int variant, int kq, int fp32_arith, int w16) {
+StepFn pick_step_hyb_any(int storage, int variant, int kq, int w16) {
     switch (storage) {
         case MLBM_F64: return pick_step_hyb<MLBM_F64, double, double>(variant, kq);
-        case MLBM_F32:
-            return fp32_arith ? pick_step_hyb<MLBM_F32, float, float>(variant, kq)
-                              : pick_step_hyb<MLBM_F32, float, double>(variant, kq);
+        case MLBM_F32: return pick_step_hyb<MLBM_F32, float, double>(variant, kq);
         case MLBM_F16S:
             return w16 ? pick_step_hyb<MLBM_F16S, float, float, true>(variant, kq)
                        : pick_step_hyb<MLBM_F16S, float, float>(variant, kq);
@@ -1386,8 +1405,8 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     }
     if (st->per_departure && !lds) return fail(MLBM_ERR_UNSUPPORTED, "per-departure stencils need tiles");
     if (st->per_departure && st->w_lagrange) return fail(MLBM_ERR_ARG, "per-departure stencils take no block weights");
-    StepFn fn = st->per_departure ? pick_step_pd_any(p->storage, p->variant, kq, p->fp32_arith, p->weights16)
-                                  : pick_step_any(p->storage, p->variant, kq, p->fp32_arith, lds, p->weights16);
+    StepFn fn = st->per_departure ? pick_step_pd_any(p->storage, p->variant, kq, p->weights16)
+                                  : pick_step_any(p->storage, p->variant, kq, lds, p->weights16);
     if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
         return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
@@ -1422,7 +1441,7 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     if (st->w_lagrange && st->lagrange_begin < st->n) {
         if (st->lagrange_begin < 0) return fail(MLBM_ERR_ARG, "lagrange_begin must be >= 0");
         lag0 = st->lagrange_begin;
-        fb = pick_step_any(p->storage, p->variant, 0, p->fp32_arith, lds, 0);
+        fb = pick_step_any(p->storage, p->variant, 0, lds, 0);
         if (!fb) return fail(MLBM_ERR_UNSUPPORTED, "no block-centre kernel for storage %d", p->storage);
     }
     a.lag0 = lag0;
@@ -1435,7 +1454,7 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     a.split = 0;
     a.tile0b = a.tile1b = a.grid8b = 0;
     if (fuse) {
-        fns[0] = pick_step_hyb_any(p->storage, p->variant, kq, p->fp32_arith, p->weights16);
+        fns[0] = pick_step_hyb_any(p->storage, p->variant, kq, p->weights16);
         if (!fns[0]) return fail(MLBM_ERR_UNSUPPORTED, "no hybrid kernel for storage %d, K=%d", p->storage, st->K);
         fns[1] = nullptr;
         const int64_t cb = ranges[1][1] - ranges[1][0];
@@ -1468,21 +1487,27 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     return MLBM_OK;
 }
 
+constexpr int RED_PARTIALS = MLBM_RED_FIRST_BAD + 1;  // per-block partial sums
+
 extern "C" int64_t mlbm_reduction_workspace_bytes(int64_t n) {
     if (n < 1) return 0;
-    return ((n + RED_BLOCK - 1) / RED_BLOCK) * MLBM_RED_COUNT * (int64_t)sizeof(double);
+    return ((n + RED_BLOCK - 1) / RED_BLOCK) * RED_PARTIALS * (int64_t)sizeof(double);
 }
 
-extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_state *st, const double *area,
-                                double dx, double *rho_out, double *u_out, double *u_prev, void *workspace,
-                                double *red_out, void *stream) {
-    using mlbm::fail;
+extern "C" int mlbm_reductions_reset(double *red_out, void *stream) {
     mlbm::clear_error();
-    int rc = check_common(p, st);
-    if (rc) return rc;
-    if (!area || !workspace || !red_out) return fail(MLBM_ERR_ARG, "null area, workspace or output");
-    if (!st->idx || !st->w) return fail(MLBM_ERR_ARG, "null stencil buffer");
-    if (!(dx > 0.0)) return fail(MLBM_ERR_ARG, "dx must be positive");
+    if (!red_out) return mlbm::fail(MLBM_ERR_ARG, "null red_out");
+    hipLaunchKernelGGL(k_fill_nan, dim3(1), dim3(64), 0, (hipStream_t)stream, red_out, (int)MLBM_RED_COUNT);
+    return hip_check("mlbm_reductions_reset launch");
+}
+
+namespace {
+
+// the launches of mlbm_macroscopic with the per-block partials in ws
+int macro_launch(const mlbm_step_params *p, const mlbm_device_state *st, const double *area, double dx,
+                 double box_area, double *rho_out, double *u_out, double *u_prev, double *ws, double *red_out,
+                 hipStream_t s) {
+    using mlbm::fail;
     const int kq = (st->K + 3) / 4;
     MacroFn fn = pick_macro_any(p->storage, p->variant, kq);
     if (!fn) return fail(MLBM_ERR_UNSUPPORTED, "no macroscopic kernel for storage %d, K=%d", p->storage, st->K);
@@ -1498,19 +1523,90 @@ extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_sta
     a.rho_out = rho_out;
     a.u_out = u_out;
     a.u_prev = u_prev;
-    a.ws = (double *)workspace;
+    a.ws = ws;
     a.gx = p->g[0];
     a.gy = p->g[1];
     a.inv_dx2 = 1.0 / (dx * dx);
     a.inv_scale = std::ldexp(1.0f, -p->scale_exp);
     a.w16 = p->weights16 ? 1 : 0;
     const int64_t nb = (st->n + RED_BLOCK - 1) / RED_BLOCK;
-    hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(fn, dim3((unsigned)nb), dim3(RED_BLOCK), 0, s, a);
-    rc = hip_check("mlbm_macroscopic launch");
+    int rc = hip_check("mlbm_macroscopic launch");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_BLOCK), 0, s, (const double *)workspace, nb, red_out);
+    FinalArgs fa;
+    fa.ws = ws;
+    fa.nblocks = nb;
+    fa.out = red_out;
+    fa.nu = (p->tau_plus - 0.5) / 3.0;
+    fa.gx = p->g[0];
+    fa.dx = dx;
+    fa.box_area = box_area;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_BLOCK), 0, s, fa);
     return hip_check("mlbm_macroscopic reduction launch");
+}
+
+int macro_check(const mlbm_step_params *p, const mlbm_device_state *st, const double *area, double dx,
+                const double *red_out) {
+    using mlbm::fail;
+    int rc = check_common(p, st);
+    if (rc) return rc;
+    if (!area || !red_out) return fail(MLBM_ERR_ARG, "null area or output");
+    if (!st->idx || !st->w) return fail(MLBM_ERR_ARG, "null stencil buffer");
+    if (!(dx > 0.0)) return fail(MLBM_ERR_ARG, "dx must be positive");
+    return MLBM_OK;
+}
+
+}  // namespace
+
+extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_state *st, const double *area,
+                                double dx, double box_area, double *rho_out, double *u_out, double *u_prev,
+                                void *workspace, double *red_out, void *stream) {
+    mlbm::clear_error();
+    int rc = macro_check(p, st, area, dx, red_out);
+    if (rc) return rc;
+    if (!workspace) return mlbm::fail(MLBM_ERR_ARG, "null workspace");
+    return macro_launch(p, st, area, dx, box_area, rho_out, u_out, u_prev, (double *)workspace, red_out,
+                        (hipStream_t)stream);
+}
+
+extern "C" int mlbm_run_to_steady(const mlbm_step_params *p, mlbm_device_state *st, const mlbm_steady *sp,
+                                  const double *area, double dx, double box_area, double *u_prev, void *workspace,
+                                  double *red_out, double *red_host, int64_t *steps_done, void *stream) {
+    using mlbm::fail;
+    mlbm::clear_error();
+    if (!sp || !red_host || !steps_done || !u_prev) return fail(MLBM_ERR_ARG, "null steady, red_host, steps_done or u_prev");
+    if (sp->criterion != MLBM_STEADY_FIELD && sp->criterion != MLBM_STEADY_MEAN)
+        return fail(MLBM_ERR_ARG, "bad criterion %d", sp->criterion);
+    if (sp->check_every < 1 || sp->hold < 1 || sp->max_steps < 0 || !(sp->tol > 0.0))
+        return fail(MLBM_ERR_ARG, "check_every and hold must be >= 1, max_steps >= 0, tol > 0");
+    *steps_done = 0;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = mlbm_reductions_reset(red_out, stream);
+    if (rc) return rc;
+    rc = mlbm_macroscopic(p, st, area, dx, box_area, nullptr, nullptr, u_prev, workspace, red_out, stream);
+    if (rc) return rc;
+    const int slot = sp->criterion == MLBM_STEADY_FIELD ? MLBM_RED_RESIDUAL : MLBM_RED_MEAN_CHANGE;
+    int64_t steps = 0;
+    int below = 0;
+    while (steps < sp->max_steps) {
+        const int32_t chunk = (int32_t)std::min<int64_t>(sp->check_every, sp->max_steps - steps);
+        rc = mlbm_step(p, st, chunk, stream);
+        if (rc) return rc;
+        steps += chunk;
+        *steps_done = steps;
+        rc = mlbm_macroscopic(p, st, area, dx, box_area, nullptr, nullptr, u_prev, workspace, red_out, stream);
+        if (rc) return rc;
+        if (hipMemcpyAsync(red_host, red_out, MLBM_RED_COUNT * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return hip_check("mlbm_run_to_steady: reading the reductions");
+        if (red_host[MLBM_RED_N_BAD] > 0.0)
+            return fail(MLBM_ERR_UNSTABLE, "unstable after %lld steps: %.0f nodes with non-finite fields or rho <= 0, "
+                                           "first node %.0f", (long long)steps, red_host[MLBM_RED_N_BAD],
+                        red_host[MLBM_RED_FIRST_BAD]);
+        below = red_host[slot] < sp->tol ? below + 1 : 0;
+        if (below >= sp->hold) break;
+    }
+    return MLBM_OK;
 }
 
 // ---- batched runs: many samples in one node range ------------------------------------
@@ -1791,7 +1887,7 @@ extern "C" int mlbm_step_batched(const mlbm_step_params *p, mlbm_device_state *s
     if (use_graph && !stream) return fail(MLBM_ERR_ARG, "graph capture needs a non-default stream");
     const int kq = (st->K + 3) / 4;
     if (st->per_departure) return fail(MLBM_ERR_UNSUPPORTED, "batched runs take one stencil per node");
-    StepFn fn = pick_step_any(p->storage, p->variant, kq, p->fp32_arith, true, p->weights16);
+    StepFn fn = pick_step_any(p->storage, p->variant, kq, true, p->weights16);
     RedFn red = pick_red(p->storage, p->variant);
     if (!fn || !red) return fail(MLBM_ERR_UNSUPPORTED, "no kernel for storage %d, variant %d, K=%d", p->storage, p->variant, st->K);
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))

@@ -12,7 +12,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BF16, F16S, F32, F64, FIELDS, POPULATIONS, RED_COUNT, Batch, DeviceState, Geometry,
-                   MlbmError, Sizes, StencilParams, Stencils, StepParams, check, lib)
+                   MlbmError, Sizes, Steady, StencilParams, Stencils, StepParams, check, lib)
 
 __all__ = ["build_stencils", "packed_sizes", "pack_stencils", "Simulation", "MlbmError",
            "POPULATIONS", "FIELDS", "F64", "F32", "F16S", "BF16"]
@@ -148,7 +148,7 @@ class Simulation:
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
                  fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda",
                  packed=None, lagrange=None, w_lagrange=None, stochastic_rounding=0, weights16=0,
-                 hybrid_launches=0):
+                 hybrid_launches=0, box_area=0.0):
         import torch
 
         self.torch = torch
@@ -191,7 +191,8 @@ class Simulation:
         self.state_d = [torch.zeros(self.sizes.state_bytes, dtype=torch.uint8, device=dev) for _ in range(2)]
         ws = lib.mlbm_reduction_workspace_bytes(n)
         self.ws_d = torch.zeros(max(ws, 8), dtype=torch.uint8, device=dev)
-        self.red_d = torch.zeros(RED_COUNT, dtype=torch.float64, device=dev)
+        self.red_d = torch.full((RED_COUNT,), float("nan"), dtype=torch.float64, device=dev)
+        self.box_area = float(box_area)
         self.params = StepParams()
         self.params.variant = variant
         self.params.storage = storage
@@ -261,13 +262,15 @@ class Simulation:
         check(lib.mlbm_step(ctypes.byref(self.params), ctypes.byref(self.ds), int(nsteps), self._stream(stream)))
 
     def macroscopic(self, dx, u_prev=None, want_fields=True, stream=None):
-        """mlbm_macroscopic: returns (rho, u, reductions) as device tensors."""
+        """mlbm_macroscopic: returns (rho, u, reductions) as device tensors
+        (the reductions buffer is reused: its previous mean velocity feeds
+        RED_MEAN_CHANGE)."""
         t = self.torch
         dev = self.state_d[0].device
         rho = t.empty(self.n, dtype=t.float64, device=dev) if want_fields else None
         u = t.empty((self.n, 2), dtype=t.float64, device=dev) if want_fields else None
         check(lib.mlbm_macroscopic(ctypes.byref(self.params), ctypes.byref(self.ds), self.area_d.data_ptr(),
-                                   float(dx), rho.data_ptr() if rho is not None else None,
+                                   float(dx), self.box_area, rho.data_ptr() if rho is not None else None,
                                    u.data_ptr() if u is not None else None,
                                    u_prev.data_ptr() if u_prev is not None else None,
                                    self.ws_d.data_ptr(), self.red_d.data_ptr(), self._stream(stream)))
@@ -279,42 +282,55 @@ class Simulation:
 
     def run_to_steady(self, dx, tol=1e-6, check_every=100, max_steps=1_000_000, stream=None, criterion="field",
                       hold=1):
-        """Steps until the residual is below tol, checked every check_every
-        steps with mlbm_macroscopic (one small device-to-host copy per check).
-        criterion "field": ||u^n - u^(n - check_every)|| / ||u^n|| over the
-        nodes; "mean": the relative change of the mean velocity (the integral
-        of u_x), the paper's steady criterion (Sec. 3.2), which stays
-        meaningful when 16-bit storage keeps rounding noise in every node.  The
-        residual must stay below tol for `hold` consecutive checks.
+        """mlbm_run_to_steady: steps until the residual stays below tol for
+        `hold` checks check_every steps apart.  criterion "field":
+        ||u^n - u^(n - check_every)|| / ||u^n|| over the nodes; "mean": the
+        relative change of the mean velocity (the integral of u_x), the
+        paper's steady criterion (Sec. 3.2), which stays meaningful when 16-bit
+        storage keeps rounding noise in every node.  Raises MlbmError (code
+        MLBM_ERR_UNSTABLE) when a check finds non-finite fields.
         Returns (steps, residual, reductions as numpy)."""
-        t = self.torch
-        dev = self.state_d[0].device
-        u_prev = t.zeros((self.n, 2), dtype=t.float64, device=dev)
-        self.macroscopic(dx, u_prev=u_prev, want_fields=False, stream=stream)
         if criterion not in ("field", "mean"):
             raise ValueError(f"unknown criterion {criterion!r}")
-        steps = 0
-        res = float("inf")
-        red = None
-        prev_ux = None
-        below = 0
-        while steps < max_steps:
-            self.step(check_every, stream=stream)
-            steps += check_every
-            _, _, red_d = self.macroscopic(dx, u_prev=u_prev, want_fields=False, stream=stream)
-            red = red_d.cpu().numpy()
-            if red[_lib.RED_N_BAD] > 0:
-                raise MlbmError(-6, f"unstable: {int(red[_lib.RED_N_BAD])} bad nodes, first {int(red[_lib.RED_FIRST_BAD])}")
-            if criterion == "field":
-                res = float(np.sqrt(red[_lib.RED_NORM_DU2] / red[_lib.RED_NORM_U2])) if red[_lib.RED_NORM_U2] > 0 else 0.0
-            else:
-                ux = float(red[_lib.RED_INT_UX])
-                res = abs(ux - prev_ux) / abs(ux) if prev_ux is not None and ux != 0.0 else float("inf")
-                prev_ux = ux
-            below = below + 1 if res < tol else 0
-            if below >= hold:
-                break
-        return steps, res, red
+        t = self.torch
+        u_prev = t.zeros((self.n, 2), dtype=t.float64, device=self.state_d[0].device)
+        sp = Steady(criterion=_lib.STEADY_FIELD if criterion == "field" else _lib.STEADY_MEAN,
+                    check_every=int(check_every), hold=int(hold), max_steps=int(max_steps), tol=float(tol))
+        red = np.full(RED_COUNT, np.nan)
+        done = ctypes.c_int64()
+        check(lib.mlbm_run_to_steady(ctypes.byref(self.params), ctypes.byref(self.ds), ctypes.byref(sp),
+                                     self.area_d.data_ptr(), float(dx), self.box_area, u_prev.data_ptr(),
+                                     self.ws_d.data_ptr(), self.red_d.data_ptr(), _ptr(red), ctypes.byref(done),
+                                     self._stream(stream)))
+        res = red[_lib.RED_RESIDUAL if criterion == "field" else _lib.RED_MEAN_CHANGE]
+        return int(done.value), float(res), red
+
+    # -- checkpoint / resume --------------------------------------------------------
+
+    def save_checkpoint(self, path):
+        """Writes the current state buffer, which buffer is current and the
+        step count (the key of stochastic rounding) to an .npz file: a run
+        resumed from it with load_checkpoint continues bitwise as the
+        uninterrupted run would (synchronises)."""
+        np.savez(path, state=self.state_bytes(), cur=np.int32(self.ds.cur),
+                 step_count=np.uint64(self.ds.step_count), n=np.int64(self.n),
+                 variant=np.int32(self.params.variant), storage=np.int32(self.params.storage))
+
+    def load_checkpoint(self, path):
+        """Restores a state written by save_checkpoint into this simulation,
+        which must have been built for the same node set, variant and storage
+        (only plain arrays are read: no pickles)."""
+        with np.load(path, allow_pickle=False) as z:
+            if (int(z["n"]), int(z["variant"]), int(z["storage"])) != (self.n, self.params.variant,
+                                                                       self.params.storage):
+                raise ValueError("checkpoint is for another node count, variant or storage")
+            state = z["state"]
+            if state.size != self.sizes.state_bytes:
+                raise ValueError("checkpoint state has the wrong size")
+            cur = int(z["cur"])
+            self.state_d[cur].copy_(self.torch.from_numpy(np.ascontiguousarray(state)))
+            self.ds.cur = cur
+            self.ds.step_count = int(z["step_count"])
 
 
 class BatchSimulation:

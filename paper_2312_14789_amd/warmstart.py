@@ -201,18 +201,17 @@ def compare_runs(ns, field, res, g, K=16, tol=1e-6, check_every=100, max_steps=2
 
     b = M.build_stencils_for(ns, K, ns.h)
     perm = b["perm"]
-    nu = 1.0 / 6.0
     res_out = {}
     for name, init in (("rest", (np.ones(ns.n), np.zeros((ns.n, 2)))), ("warm", node_fields(ns, res, field))):
         sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.FIELDS, storage=M.F32,
-                           tau_plus=1.0, g=(g, 0.0))
+                           tau_plus=1.0, g=(g, 0.0), box_area=float(np.prod(ns.hi - ns.lo)))
         sim.init_state(init[0][perm], init[1][perm])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps, r, red = sim.run_to_steady(ns.h, tol=tol, check_every=check_every, max_steps=max_steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0 + (infer_s if name == "warm" else 0.0)
-        k = nu * red[M._lib.RED_INT_UX] / g * ns.h * ns.h
+        k = float(red[M._lib.RED_PERMEABILITY])
         res_out[name] = {"steps": steps, "seconds": dt, "permeability": k, "residual": r}
         del sim
     return res_out

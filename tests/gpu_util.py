@@ -17,6 +17,22 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def rel_max(a, b):
+    """Largest node-wise error relative to the largest reference value:
+    max_i |a_i - b_i| / max_i |b_i| (catches an error confined to a few
+    nodes, which a field norm averages away)."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def assert_fields_close(u, u_ref, bar, what=""):
+    """Both the field norm and the node-wise maximum within bar."""
+    e2, em = rel_l2(u, u_ref), rel_max(u, u_ref)
+    assert e2 <= bar, f"{what} rel_l2 {e2:.3e} > {bar:.1e}"
+    assert em <= bar, f"{what} rel_max {em:.3e} > {bar:.1e}"
+    return e2, em
+
+
 def initial_fields(ns, seed, amp_u, amp_rho):
     """Smooth seeded fields, with the prescribed values on Dirichlet nodes."""
     L = float(np.max(ns.hi - ns.lo))

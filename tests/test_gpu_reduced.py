@@ -1,28 +1,37 @@
 """Reduced-precision state storage (FP16 offsets scaled by 2^sigma, BF16
-offsets; FP32 weights and arithmetic) against the FP64 oracle on the same
-seeded inputs, over long runs towards a steady state.
+offsets; FP32 weights and arithmetic, or FP16 weights) against the FP64 oracle
+on the same seeded inputs.
 
-Bars: FP32 state 1e-5 (relative L2 of velocity); 16-bit storage 2e-3 on the
-velocity field and 0.5 % on permeability.  Met: FP32 everywhere; FP16 fields
-(MLBM1, the porous workload's variant) on velocity and permeability; BF16
-fields on permeability.  Not met with rounding to nearest, asserted at the
-measured level as regression guards: BF16 fields velocity (5e-3), FP16
-populations (3e-3) and BF16 populations (9e-2: the per-step forcing increment
-of a slow body-force-driven channel is below half a BF16 ulp of the stored
-offsets, so round-to-nearest stagnates).  Stochastic rounding of the stores
-keeps the expected value of every stored quantity: FP16 meets the 2e-3 bar
-and both formats keep the permeability within 5e-4; a BF16 snapshot of the
-velocity field keeps rounding noise of the order of its 8-bit mantissa
-(2^-8 = 3.9e-3 relative), asserted at 5e-3."""
+Bars: FP32 state 1e-5; 16-bit storage 2e-3 on the velocity field (relative
+L2 error and largest node-wise error relative to the largest velocity) and
+0.5 % on permeability.
+
+Supported 16-bit mode: FP16 offsets (scaled) with stochastic rounding of the
+stores, with FP32 or FP16 weights, for both variants.  It meets the bars over
+long transients and at the steady state of a 1.26e4-node porous sample
+(reference: the oracle's steady state, stored by
+tests/golden/make_porous_steady.py).
+
+Not supported (xfail, with the error measured when the mode was last run):
+  - rounding to nearest, FP16 or BF16: once the per-step change of a stored
+    value falls below half an ulp it is rounded away and the flow stalls
+    short of its steady state;
+  - BF16 with stochastic rounding: its 8-bit mantissa leaves rounding noise of
+    ~2^-8 of each stored value in every snapshot, above the 2e-3 bar.
+"""
+import os
+
 import numpy as np
 import pytest
 
 import nodesets
 from oracle import mlbm as omlbm
 
-from gpu_util import rel_l2, run_oracle, sim_from_oracle
+from gpu_util import rel_l2, rel_max, run_oracle, sim_from_oracle
 
 pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @pytest.fixture(scope="module")
@@ -67,45 +76,77 @@ def _channel_case():
     return _REF["channel"]
 
 
-def _sigma(M, u):
+def _sigma(u):
     from paper_2312_14789_amd import units
 
     return units.f16_scale_exp(float(np.abs(u).max()))
 
 
-@pytest.mark.parametrize("storage,sr,bar", [(1, 0, 1e-5), (2, 0, 2e-3), (3, 0, 1e-2), (2, 1, 2e-3), (3, 1, 5e-3)])
-def test_fields_reduced_storage(M, storage, sr, bar):
+def _unsupported(measured):
+    return pytest.mark.xfail(strict=False, reason=f"unsupported mode, measured {measured}")
+
+
+F32, F16S, BF16 = 1, 2, 3
+
+FIELD_MODES = [
+    pytest.param(F32, 0, 0, 1e-5, id="f32"),
+    pytest.param(F16S, 1, 0, 2e-3, id="f16s-sr"),
+    pytest.param(F16S, 1, 1, 2e-3, id="f16s-sr-w16"),
+    pytest.param(F16S, 0, 0, 2e-3, id="f16s-nearest", marks=_unsupported("u 1.3e-3 here, stalls at steady state")),
+    pytest.param(BF16, 0, 0, 2e-3, id="bf16-nearest", marks=_unsupported("u 5.0e-3")),
+    pytest.param(BF16, 1, 0, 2e-3, id="bf16-sr", marks=_unsupported("u 3.9e-3")),
+    pytest.param(BF16, 1, 1, 2e-3, id="bf16-sr-w16", marks=_unsupported("u 3.7e-3")),
+]
+
+
+@pytest.mark.parametrize("storage,sr,w16,bar", FIELD_MODES)
+def test_fields_reduced_storage(M, storage, sr, w16, bar):
     ns, st, dx, g, steps, r_ref, u_ref = _porous_case()
-    sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, g, scale_exp=_sigma(M, u_ref),
-                          stochastic_rounding=sr)
+    from paper_2312_14789_amd import _lib
+
+    sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, g, scale_exp=_sigma(u_ref),
+                          stochastic_rounding=sr, weights16=w16, box_area=1.0)
     sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
     sim.step(steps)
     rho, u, red = sim.macroscopic(dx)
     u = u.cpu().numpy()
     red = red.cpu().numpy()
-    err = rel_l2(u, u_ref)
+    e2, em = rel_l2(u, u_ref), rel_max(u, u_ref)
     k_ref = omlbm.permeability(omlbm.reductions(r_ref, u_ref, st.area), 1.0, 1.0 / 6.0, g[0], dx)
-    k = 1.0 / 6.0 * (red[1] / 1.0) / g[0] * dx * dx
-    print(f"[reduced] fields storage={storage} sr={sr} rel_l2_u={err:.3e} k_err={abs(k / k_ref - 1):.3e}",
-          flush=True)
-    assert err <= bar
-    assert abs(k / k_ref - 1) <= (5e-4 if sr else 5e-3)
+    k_err = abs(red[_lib.RED_PERMEABILITY] / k_ref - 1)
+    print(f"[reduced] fields storage={storage} sr={sr} w16={w16} rel_l2_u={e2:.3e} rel_max_u={em:.3e} "
+          f"k_err={k_err:.3e}", flush=True)
+    assert e2 <= bar and em <= bar
+    assert k_err <= 5e-3
 
 
-@pytest.mark.parametrize("storage,sr,bar", [(1, 0, 1e-5), (2, 0, 5e-3), (3, 0, 0.15), (2, 1, 2e-3), (3, 1, 5e-3)])
-def test_populations_reduced_storage(M, storage, sr, bar):
+POP_MODES = [
+    pytest.param(F32, 0, 0, 1e-5, id="f32"),
+    pytest.param(F16S, 1, 0, 2e-3, id="f16s-sr"),
+    pytest.param(F16S, 1, 1, 2e-3, id="f16s-sr-w16"),
+    pytest.param(F16S, 0, 0, 2e-3, id="f16s-nearest", marks=_unsupported("u 3.0e-3")),
+    pytest.param(BF16, 0, 0, 2e-3, id="bf16-nearest", marks=_unsupported("u 8.7e-2, stalls")),
+    pytest.param(BF16, 1, 0, 2e-3, id="bf16-sr", marks=_unsupported("u 2.3e-3")),
+    pytest.param(BF16, 1, 1, 2e-3, id="bf16-sr-w16", marks=_unsupported("u 2.6e-3")),
+]
+
+
+@pytest.mark.parametrize("storage,sr,w16,bar", POP_MODES)
+def test_populations_reduced_storage(M, storage, sr, w16, bar):
     ns, st, dx, g, steps, r_ref, u_ref, tp, tm = _channel_case()
-    sim = sim_from_oracle(M, ns, st, 0, storage, tp, tm, g, scale_exp=_sigma(M, u_ref),
-                          stochastic_rounding=sr)
+    sim = sim_from_oracle(M, ns, st, 0, storage, tp, tm, g, scale_exp=_sigma(u_ref),
+                          stochastic_rounding=sr, weights16=w16)
     sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
     sim.step(steps)
     rho, u, red = sim.macroscopic(dx)
-    err = rel_l2(u.cpu().numpy(), u_ref)
-    print(f"[reduced] populations storage={storage} sr={sr} rel_l2_u={err:.3e}", flush=True)
-    assert err <= bar
+    u = u.cpu().numpy()
+    e2, em = rel_l2(u, u_ref), rel_max(u, u_ref)
+    print(f"[reduced] populations storage={storage} sr={sr} w16={w16} rel_l2_u={e2:.3e} rel_max_u={em:.3e}",
+          flush=True)
+    assert e2 <= bar and em <= bar
 
 
-@pytest.mark.parametrize("storage", [2, 3])
+@pytest.mark.parametrize("storage", [F16S, BF16])
 def test_stochastic_rounding_accumulates_small_increments(M, storage):
     # Uniform body force on a periodic lattice with dx = h (MLBM1 = LBM1): the
     # velocity grows by exactly g per step.  Once g is below half a storage
@@ -115,7 +156,7 @@ def test_stochastic_rounding_accumulates_small_increments(M, storage):
     ns = nodesets.regular_grid(64)
     st = omlbm.build_stencils(ns, 12, ns.h)
     g, steps = 2e-7, 3000
-    sigma = 19 if storage == 2 else 0
+    sigma = 19 if storage == F16S else 0
     means = {}
     for sr in (0, 1):
         sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, (g, 0.0), scale_exp=sigma, stochastic_rounding=sr)
@@ -132,42 +173,86 @@ def test_stochastic_rounding_accumulates_small_increments(M, storage):
     assert e_sr < 1e-2
 
 
-# FP16 weights with the 16-bit states (half the weight bytes, which dominate
-# a step's traffic), stochastic rounding of the stores: bars as for the
-# 16-bit states, 2e-3 on velocity (5e-3 for a BF16 snapshot, as above) and
-# 0.5 % on permeability
-@pytest.mark.parametrize("storage,bar", [(2, 2e-3), (3, 5e-3)])
-def test_fields_fp16_weights(M, storage, bar):
-    ns, st, dx, g, steps, r_ref, u_ref = _porous_case()
-    sim = sim_from_oracle(M, ns, st, 1, storage, 1.0, 1.0, g, scale_exp=_sigma(M, u_ref),
-                          stochastic_rounding=1, weights16=1)
-    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
-    sim.step(steps)
-    rho, u, red = sim.macroscopic(dx)
-    u = u.cpu().numpy()
-    red = red.cpu().numpy()
-    err = rel_l2(u, u_ref)
-    k_ref = omlbm.permeability(omlbm.reductions(r_ref, u_ref, st.area), 1.0, 1.0 / 6.0, g[0], dx)
-    k = 1.0 / 6.0 * (red[1] / 1.0) / g[0] * dx * dx
-    print(f"[reduced-w16] fields storage={storage} rel_l2_u={err:.3e} k_err={abs(k / k_ref - 1):.3e}", flush=True)
-    assert err <= bar
-    assert abs(k / k_ref - 1) <= 5e-3
-
-
-@pytest.mark.parametrize("storage,bar", [(2, 2e-3), (3, 5e-3)])
-def test_populations_fp16_weights(M, storage, bar):
-    ns, st, dx, g, steps, r_ref, u_ref, tp, tm = _channel_case()
-    sim = sim_from_oracle(M, ns, st, 0, storage, tp, tm, g, scale_exp=_sigma(M, u_ref),
-                          stochastic_rounding=1, weights16=1)
-    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
-    sim.step(steps)
-    rho, u, red = sim.macroscopic(dx)
-    err = rel_l2(u.cpu().numpy(), u_ref)
-    print(f"[reduced-w16] populations storage={storage} rel_l2_u={err:.3e}", flush=True)
-    assert err <= bar
-
-
 def test_fp16_weights_need_16bit_states(M):
     ns, st, dx, g, steps, r_ref, u_ref = _porous_case()
     with pytest.raises(M.MlbmError):
-        sim_from_oracle(M, ns, st, 1, 1, 1.0, 1.0, g, weights16=1)
+        sim_from_oracle(M, ns, st, 1, F32, 1.0, 1.0, g, weights16=1)
+
+
+# ---------------------------------------------------------------------------
+# steady state of a 1.26e4-node porous sample against the oracle's
+# ---------------------------------------------------------------------------
+
+_STEADY = {}
+
+
+def _golden_steady():
+    """The oracle's steady state (tests/golden/make_porous_steady.py) and the
+    library's stencils of the same seeded node set."""
+    if not _STEADY:
+        import sys
+
+        sys.path.insert(0, os.path.join(HERE, "golden"))
+        import make_porous_steady as mk
+
+        from paper_2312_14789_amd import mlbm as M
+
+        z = np.load(os.path.join(HERE, "golden", "porous_steady_mlbm1.npz"), allow_pickle=False)
+        ns = mk.node_set()
+        assert ns.n == int(z["n"]) and mk.xy_digest(ns.xy) == str(z["xy_sha256"]), "node set differs from the stored one"
+        b = M.build_stencils_for(ns, int(z["K"]), float(z["dx"]))
+        _STEADY.update(ns=ns, b=b, u=z["u"], rho=z["rho"], k=float(z["permeability"]), g=float(z["g"]),
+                       dx=float(z["dx"]))
+    return _STEADY
+
+
+STEADY_MODES = [
+    pytest.param(F32, 0, 0, "field", 1e-5, 1e-4, id="f32"),
+    pytest.param(F16S, 1, 0, "mean", 2e-3, 5e-3, id="f16s-sr"),
+    pytest.param(F16S, 1, 1, "mean", 2e-3, 5e-3, id="f16s-sr-w16"),
+    pytest.param(F16S, 0, 0, "mean", 2e-3, 5e-3, id="f16s-nearest", marks=_unsupported("stalls: k 1.9e-2 low")),
+    pytest.param(BF16, 1, 0, "mean", 2e-3, 5e-3, id="bf16-sr", marks=_unsupported("u 3.9e-3")),
+]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("storage,sr,w16,criterion,bar,k_bar", STEADY_MODES)
+def test_steady_state_against_the_oracle(M, storage, sr, w16, criterion, bar, k_bar):
+    # library builder and kernels end to end, from rest to the steady state
+    # (field residual 1e-7 per 100 steps for FP32; for 16-bit states the mean
+    # velocity's relative change 1e-5 per 1000 steps), against the oracle's
+    # steady state (residual 1e-9)
+    from paper_2312_14789_amd import _lib, units
+
+    d = _STEADY or _golden_steady()
+    ns, b = d["ns"], d["b"]
+    perm = b["perm"]
+    print(f"[steady] storage={storage} sr={sr} w16={w16} n={ns.n}", flush=True)
+    if storage == F32:
+        sigma = 0
+    else:
+        # the scale comes from the library's own FP32 run, as a user would take it
+        if "sigma" not in d:
+            ref = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=1, storage=F32,
+                               tau_plus=1.0, g=(d["g"], 0.0))
+            ref.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+            ref.run_to_steady(d["dx"], tol=1e-6, check_every=100, max_steps=200_000)
+            _, u32, _ = ref.macroscopic(d["dx"])
+            d["sigma"] = units.f16_scale_exp(float(u32.abs().max()))
+        sigma = d["sigma"]
+    sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=1, storage=storage,
+                       tau_plus=1.0, g=(d["g"], 0.0), scale_exp=sigma, stochastic_rounding=sr, weights16=w16,
+                       box_area=1.0)
+    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+    every, tol = (100, 1e-7) if criterion == "field" else (1000, 1e-5)
+    steps, res, red = sim.run_to_steady(d["dx"], tol=tol, check_every=every, max_steps=200_000, criterion=criterion)
+    _, u, _ = sim.macroscopic(d["dx"])
+    u_old = np.empty_like(d["u"])
+    u_old[perm] = u.cpu().numpy()      # back to the generator's node order
+    e2, em = rel_l2(u_old, d["u"]), rel_max(u_old, d["u"])
+    k_err = abs(red[_lib.RED_PERMEABILITY] / d["k"] - 1)
+    print(f"[steady] storage={storage} sr={sr} w16={w16} steps={steps} residual={res:.2e} rel_l2_u={e2:.3e} "
+          f"rel_max_u={em:.3e} k_err={k_err:.3e}", flush=True)
+    assert res < tol
+    assert e2 <= bar and em <= bar
+    assert k_err <= k_bar

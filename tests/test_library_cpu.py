@@ -19,8 +19,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_library_exports_every_declared_symbol():
-    raw = ctypes.CDLL(_lib.LIB_PATH)
-    for hdr, names in (("mlbm.h", _lib.EXPORTS), ("mlbm_unet.h", _lib.UNET_EXPORTS)):
+    from paper_2312_14789_amd import probe
+
+    for path, hdr, names in ((_lib.LIB_PATH, "mlbm.h", _lib.EXPORTS), (_lib.LIB_PATH, "mlbm_unet.h", _lib.UNET_EXPORTS),
+                             (probe.PROBE_LIB_PATH, "mlbm_probe.h", probe.EXPORTS)):
+        raw = ctypes.CDLL(path)
         with open(os.path.join(ROOT, "include", hdr)) as f:
             header = f.read()
         declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mlbm_[a-z_0-9]+)\s*\(", header, re.M))
@@ -28,6 +31,8 @@ def test_library_exports_every_declared_symbol():
         for name in declared:
             assert hasattr(raw, name), name
     assert _lib.lib.mlbm_version().decode().startswith("mlbm")
+    # the measurement probe is not part of the method's library
+    assert not hasattr(ctypes.CDLL(_lib.LIB_PATH), "mlbm_read_probe")
 
 
 def _oracle_bb(st):
@@ -281,14 +286,17 @@ def test_weights_to_f16_rounding():
 
 def test_read_probe_rejects_bad_arguments():
     # argument checks run on the host before any launch
-    lib = _lib.lib
+    from paper_2312_14789_amd import probe
+
+    lib = probe.load()
     out = ctypes.c_float()
-    assert lib.mlbm_read_probe(None, 1 << 20, 4, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
+    assert lib.mlbm_read_probe(None, 1 << 20, 4, ctypes.byref(out), None) == probe.PROBE_ERR_ARG
     buf = ctypes.c_void_p(16)  # never dereferenced: the size check fails first
-    assert lib.mlbm_read_probe(buf, 1000, 4, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
-    assert lib.mlbm_read_probe(buf, 1 << 20, 3, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
-    assert lib.mlbm_read_probe(ctypes.c_void_p(17), 1 << 20, 4, ctypes.byref(out), None) == _lib.MLBM_ERR_ARG
-    assert "per_thread" in lib.mlbm_last_error().decode() or "aligned" in lib.mlbm_last_error().decode()
+    assert lib.mlbm_read_probe(buf, 1000, 4, ctypes.byref(out), None) == probe.PROBE_ERR_ARG
+    assert lib.mlbm_read_probe(buf, 1 << 20, 3, ctypes.byref(out), None) == probe.PROBE_ERR_ARG
+    assert "per_thread" in lib.mlbm_probe_last_error().decode()
+    assert lib.mlbm_read_probe(ctypes.c_void_p(17), 1 << 20, 4, ctypes.byref(out), None) == probe.PROBE_ERR_ARG
+    assert "aligned" in lib.mlbm_probe_last_error().decode()
 
 
 def test_step_rejects_bad_hybrid_launches():
