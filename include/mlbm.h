@@ -443,6 +443,24 @@ int mlbm_macroscopic(const mlbm_step_params *params, const mlbm_device_state *st
                      const double *area, double dx, double box_area, double *rho_out, double *u_out,
                      double *u_prev, void *workspace, double *red_out, void *hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fields and reductions as mlbm_macroscopic, with the same kernels, but the
+ * per-block partial sums are kept in a static device array inside the
+ * library (MLBM_STATIC_MAX_NODES / 256 * 10 doubles = 5 MiB per GPU, held
+ * until the process ends) instead of a caller workspace.  The call allocates
+ * nothing.  All calls on one GPU share that array: calls that overlap on one
+ * GPU (different streams, or threads) race, so serialise them.  Its address
+ * is looked up once per device, on the first call with that device current.
+ * Errors: as mlbm_macroscopic, plus MLBM_ERR_ARG when n exceeds
+ * MLBM_STATIC_MAX_NODES.
+ */
+#define MLBM_STATIC_MAX_NODES 16777216LL   /* 2^24 nodes */
+int mlbm_macroscopic_static(const mlbm_step_params *params, const mlbm_device_state *state,
+                            const double *area, double dx, double box_area, double *rho_out, double *u_out,
+                            double *u_prev, double *red_out, void *hip_stream);
+
 /* ---- running to a steady state (device, synchronous) --------------------------- */
 #define MLBM_STEADY_FIELD 0    /* stop on MLBM_RED_RESIDUAL < tol                   */
 #define MLBM_STEADY_MEAN  1    /* stop on MLBM_RED_MEAN_CHANGE < tol (Sec. 3.2, Eq. 24) */

@@ -26,6 +26,7 @@ RED_MASS, RED_INT_UX, RED_INT_UY, RED_INT_SPEED, RED_NORM_U2, RED_NORM_DU2 = ran
 RED_FORCE_X, RED_FORCE_Y, RED_N_BAD, RED_FIRST_BAD = 6, 7, 8, 9
 RED_RESIDUAL, RED_PREV_INT_UX, RED_MEAN_CHANGE, RED_PERMEABILITY, RED_COUNT = 10, 11, 12, 13, 14
 STEADY_FIELD, STEADY_MEAN = 0, 1
+STATIC_MAX_NODES = 1 << 24
 
 _p = ctypes.c_void_p
 
@@ -135,6 +136,8 @@ def _load():
         "mlbm_macroscopic": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, ctypes.c_double,
                                             ctypes.c_double, _p, _p, _p, _p, _p, _p]),
         "mlbm_reductions_reset": (ctypes.c_int, [_p, _p]),
+        "mlbm_macroscopic_static": (ctypes.c_int, [P(StepParams), P(DeviceState), _p, ctypes.c_double,
+                                                   ctypes.c_double, _p, _p, _p, _p, _p]),
         "mlbm_run_to_steady": (ctypes.c_int, [P(StepParams), P(DeviceState), P(Steady), _p, ctypes.c_double,
                                               ctypes.c_double, _p, _p, _p, _p, P(ctypes.c_int64), _p]),
         "mlbm_conv_forward": (ctypes.c_int, [P(ConvDesc), _p, _p, _p, _p, ctypes.c_int32, ctypes.c_int32, _p]),
@@ -173,7 +176,7 @@ lib = _load()
 EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "mlbm_pack_stencils_range",
            "mlbm_mark_lagrange", "mlbm_weights_to_f16",
            "mlbm_tile_sizes", "mlbm_pack_tiles", "mlbm_init_state", "mlbm_batch_init", "mlbm_step_batched",
-           "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_reductions_reset", "mlbm_macroscopic",
+           "mlbm_step", "mlbm_reduction_workspace_bytes", "mlbm_reductions_reset", "mlbm_macroscopic", "mlbm_macroscopic_static",
            "mlbm_run_to_steady", "mlbm_last_error", "mlbm_version"]
 
 # every symbol include/mlbm_unet.h declares

@@ -17,6 +17,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include <cmath>
@@ -1567,6 +1568,58 @@ extern "C" int mlbm_macroscopic(const mlbm_step_params *p, const mlbm_device_sta
     if (!workspace) return mlbm::fail(MLBM_ERR_ARG, "null workspace");
     return macro_launch(p, st, area, dx, box_area, rho_out, u_out, u_prev, (double *)workspace, red_out,
                         (hipStream_t)stream);
+}
+
+// ---- allocation-free reductions ----------------------------------------------------------
+// The per-block partial sums of mlbm_macroscopic_static live in this
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code never passes its name to a kernel: the name is a host-side
+// stand-in, so each device's address is looked up once with
+// hipGetSymbolAddress and kept per device.  Every block writes all of its
+// partials before the final sum reads them, so nothing needs clearing.
+
+static __device__ __align__(256) double scratch[(MLBM_STATIC_MAX_NODES / RED_BLOCK) * RED_PARTIALS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch`, looked up on its first use
+int scratch_ptr(double **out) {
+    using mlbm::fail;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_check("hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MLBM_ERR_ARG, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MLBM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MLBM_OK;
+}
+
+}  // namespace
+
+extern "C" int mlbm_macroscopic_static(const mlbm_step_params *p, const mlbm_device_state *st, const double *area,
+                                       double dx, double box_area, double *rho_out, double *u_out, double *u_prev,
+                                       double *red_out, void *stream) {
+    mlbm::clear_error();
+    int rc = macro_check(p, st, area, dx, red_out);
+    if (rc) return rc;
+    if (st->n > MLBM_STATIC_MAX_NODES)
+        return mlbm::fail(MLBM_ERR_ARG, "n = %lld exceeds the %lld nodes of the static reduction buffer; "
+                                        "use mlbm_macroscopic with a workspace", (long long)st->n,
+                          (long long)MLBM_STATIC_MAX_NODES);
+    double *ws = nullptr;
+    rc = scratch_ptr(&ws);
+    if (rc) return rc;
+    return macro_launch(p, st, area, dx, box_area, rho_out, u_out, u_prev, ws, red_out, (hipStream_t)stream);
 }
 
 extern "C" int mlbm_run_to_steady(const mlbm_step_params *p, mlbm_device_state *st, const mlbm_steady *sp,
