@@ -27,9 +27,18 @@ METRIC = "MNUPS and HBM fraction of fused step; time-to-steady-state plain vs wa
 
 
 def kernel_source_digest():
+    """Digest of what decides a step kernel's traffic: the device code of
+    mlbm_step.hip (everything before its dispatch section) and mlbm_step's
+    launch logic; host-only entry points elsewhere in the file do not void
+    the stored counters."""
+    with open(os.path.join(ROOT, "paper_2312_14789_amd", "csrc", "mlbm_step.hip")) as f:
+        src = f.read()
+    device = src[:src.index("// ---- dispatch")]
+    a = src.index('extern "C" int mlbm_step(')
+    launch = src[a:src.index("\n}\n", a)]
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2312_14789_amd", "csrc", "mlbm_step.hip"), "rb") as f:
-        h.update(f.read())
+    h.update(device.encode())
+    h.update(launch.encode())
     return h.hexdigest()[:16]
 
 
@@ -47,19 +56,26 @@ def measured_traffic(kernel, workload):
     return ent.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(ns_perm, b, tau, budget_s=15.0):
-    """The oracle's population step (collide all nodes, then stream all nodes)
-    on the full node set, timed on the host; stencil arrays in the oracle's
-    format are taken from the library builder (the oracle's own builder is not
-    part of the step)."""
+def _oracle_stencils(b):
+    """The builder's arrays in the oracle's format (source populations from
+    the bounce-back bits); the oracle's own builder is not part of the step."""
     import numpy as np
 
     from oracle import mlbm as omlbm
 
-    n, K = b["idx"].shape
     src = np.where((b["bb"][:, None] >> np.arange(8)[None, :]) & 1,
                    np.array([3, 4, 1, 2, 7, 8, 5, 6])[None, :], np.arange(1, 9)[None, :])
-    st = omlbm.Stencils(idx=b["idx"].astype(np.int64), w=b["w"], src=src, point=None, area=b["area"])
+    return omlbm.Stencils(idx=b["idx"].astype(np.int64), w=b["w"], src=src, point=None, area=b["area"])
+
+
+def _oracle_steps(ns_perm, st, tau, budget_s):
+    """(steps, seconds) of the oracle's population step (collide all nodes,
+    then stream all nodes) from rest on all nodes, about budget_s long."""
+    import numpy as np
+
+    from oracle import mlbm as omlbm
+
+    n = ns_perm.n
     f = omlbm.init_populations(np.ones(n), np.zeros((n, 2)))
     t0 = time.perf_counter()
     f = omlbm.step(f, ns_perm, st, tau, tau)
@@ -68,10 +84,103 @@ def cpu_baseline(ns_perm, b, tau, budget_s=15.0):
     t0 = time.perf_counter()
     for _ in range(steps):
         f = omlbm.step(f, ns_perm, st, tau, tau)
-    dt = time.perf_counter() - t0
-    return {"value": n * steps / dt / 1e6, "unit": "MNUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} oracle FP64 steps on all {n} nodes of the same workload "
-                      f"({dt:.1f} s, numpy single thread)"}
+    return steps, time.perf_counter() - t0
+
+
+_FORK_ARGS = None
+
+
+def _oracle_worker(_):
+    ns_perm, st, tau, budget_s = _FORK_ARGS
+    return _oracle_steps(ns_perm, st, tau, budget_s)
+
+
+def cpu_baseline(ns_perm, b, tau, budget_s=15.0, workers=0):
+    """The oracle's step on the full node set, timed on the host: one process
+    (numpy runs the step on one thread), and, with workers > 1, that many
+    forked processes stepping their own copy of the same workload at once
+    (all-core throughput: the sum of their rates).  Must run before the
+    process touches the GPU (the workers are forked)."""
+    global _FORK_ARGS
+    import multiprocessing as mp
+
+    n = ns_perm.n
+    st = _oracle_stencils(b)
+    steps, dt = _oracle_steps(ns_perm, st, tau, budget_s)
+    out = {"value": n * steps / dt / 1e6, "unit": "MNUPS", "cores": 1, "kind": "oracle",
+           "sample": f"{steps} oracle FP64 steps on all {n} nodes of the same workload "
+                     f"({dt:.1f} s, numpy, one thread)"}
+    if workers > 1:
+        _FORK_ARGS = (ns_perm, st, tau, budget_s)
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_worker, range(workers))
+        _FORK_ARGS = None
+        rate = sum(n * k / t for k, t in res) / 1e6
+        out["all_cores"] = {"value": rate, "unit": "MNUPS", "cores": workers, "kind": "oracle",
+                            "sample": f"{workers} processes, each {min(k for k, _ in res)}-{max(k for k, _ in res)} "
+                                      f"oracle FP64 steps on its own copy of all {n} nodes (~{budget_s:g} s each)"}
+    return out
+
+
+def timed_steps(sim, steps, warmup, torch):
+    """Average launch time (s) of `steps` steps after `warmup`, HIP events on
+    the stream the library launches on."""
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def karman_precision_row(M, units, np, torch, ns, b, tau, tau_m, storage_name, steps=2000, warmup=100):
+    """The headline workload with another state storage, e.g. FP64 state,
+    weights and arithmetic (the paper's precision: doubles, Sec. 3.2 memory
+    model): MNUPS and the HBM fraction from its own algorithmic bytes."""
+    storage = getattr(M, storage_name)
+    perm = b["perm"]
+    sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
+                       storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm], tile=256)
+    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+    per = timed_steps(sim, steps, warmup, torch)
+    _, _, red = sim.macroscopic(1.0, want_fields=False)
+    bad = int(red[M._lib.RED_N_BAD].item())
+    bpn = units.algorithmic_bytes_per_node(M.POPULATIONS, storage, sim.sizes.k_padded)
+    del sim
+    return {"storage": storage_name.lower(), "MNUPS": round(ns.n / per / 1e6, 1), "avg_launch_us": round(per * 1e6, 2),
+            "steps": steps, "bytes_per_node": bpn, "achieved_GBps": round(bpn * ns.n / per / 1e9, 1),
+            "frac": round(bpn * ns.n / per / 1e9 / HBM_PEAK_GBS, 4), "unstable_nodes": bad}
+
+
+def karman_large_row(M, units, nodesets, np, torch, n_target=2_000_000, steps=2000, warmup=100):
+    """The FP32 step on a Karman channel of ~2e6 stratified nodes (same
+    geometry and refinement, s = 1), whose per-step traffic (~1.3 GB) is five
+    times the 256 MB memory-side cache: its HBM fraction has no help from
+    that cache, unlike the ~0.32 GB of the headline set."""
+    t0 = time.time()
+    ns = nodesets.karman(n_target=n_target, poisson=False)
+    dx = units.delta_x(ns.h_min, 1.0)
+    tau = units.tau_for_reynolds(0.05, 1.0, dx, 100.0)
+    b = M.build_stencils_for(ns, 16, dx)
+    perm = b["perm"]
+    print(f"# large Karman set: {ns.n} nodes built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
+                       storage=M.F32, tau_plus=tau, tau_minus=tau, bc=ns.boundary_values()[perm], tile=256)
+    sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+    per = timed_steps(sim, steps, warmup, torch)
+    _, _, red = sim.macroscopic(dx, want_fields=False)
+    bad = int(red[M._lib.RED_N_BAD].item())
+    bpn = units.algorithmic_bytes_per_node(M.POPULATIONS, M.F32, sim.sizes.k_padded)
+    del sim
+    return {"workload": f"Karman street channel 22Dx4.1D, {ns.n} stratified nodes (4x denser within 1D of the "
+                        f"cylinder), K=16, s=1, BGK tau={tau:.4f}, f32 populations",
+            "nodes": ns.n, "bytes_per_step": bpn * ns.n, "MNUPS": round(ns.n / per / 1e6, 1),
+            "avg_launch_us": round(per * 1e6, 2), "achieved_GBps": round(bpn * ns.n / per / 1e9, 1),
+            "frac": round(bpn * ns.n / per / 1e9 / HBM_PEAK_GBS, 4), "unstable_nodes": bad}
 
 
 def porous_throughput(args, M, units, nodesets, np, torch):
@@ -441,6 +550,41 @@ def darcy_workload(M, units, nodesets, np, torch, g_lb=1e-7, max_steps=1_560_000
             "rows": rows}
 
 
+def strouhal_from_lift(lift, every, d_lattice, u0, hysteresis=0.5):
+    """St = f d / U0 from a lift series sampled every `every` steps (after
+    the transient), in lattice units (f in cycles per step, d in streaming
+    distances).  Returns (St from the mean period between the first and last
+    upward crossings of the mean-free signal; St from the peak of its
+    Hann-windowed spectrum, zero-padded 8x).  An upward crossing counts once
+    the signal has risen from below -theta to above +theta (theta =
+    `hysteresis` x its RMS), so noise near zero adds no crossings; its time is
+    the last sign change inside that rise, linearly interpolated between
+    samples.  NaN if there are fewer than three crossings."""
+    import numpy as np
+
+    tail = np.asarray(lift, dtype=np.float64)
+    tail = tail - tail.mean()
+    spec = np.abs(np.fft.rfft(tail * np.hanning(len(tail)), n=8 * len(tail)))
+    freqs = np.fft.rfftfreq(8 * len(tail), d=every)
+    st_fft = freqs[int(np.argmax(spec[1:]) + 1)] * d_lattice / u0
+    theta = hysteresis * float(np.sqrt(np.mean(tail * tail)))
+    crossings = []
+    low, last_up = False, None
+    for j in range(len(tail)):
+        if tail[j] < -theta:
+            low, last_up = True, None
+        elif low and j > 0 and tail[j - 1] < 0.0 <= tail[j]:
+            last_up = j - 1
+        if low and tail[j] > theta and last_up is not None:
+            i = last_up
+            crossings.append(i + (-tail[i]) / (tail[i + 1] - tail[i]))
+            low = False
+    if len(crossings) < 3:
+        return float("nan"), float(st_fft)
+    period_steps = (crossings[-1] - crossings[0]) / (len(crossings) - 1) * every
+    return float(d_lattice / (period_steps * u0)), float(st_fft)
+
+
 ST_CASES = (("coarsened", "shared", (105, 126, 147, 168)),
             ("coarsened", "shared", (105, 126, 147, 168), 32),
             ("uniform", "shared", (105, 126, 147, 168)),
@@ -489,7 +633,7 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
             lag = dict(lagrange=b["lagrange"], w_lagrange=b["w_lagrange"]) if mode == "shared" else {}
             sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
                                storage=M.F32, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
-                               tile=256, **lag)
+                               tile=256, graph_steps=every, **lag)
             # at rest, boundary values on the Dirichlet nodes, and a small transverse
             # kick behind the cylinder so the shedding does not wait for round-off
             xy = ns.xy[perm]
@@ -502,11 +646,13 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
             t_shed = (d / dx) / (0.2 * u0)  # steps per period for St ~ 0.2
             n_samples = int((transient + periods) * t_shed / every)
             lift = np.zeros(n_samples)
+            stream = torch.cuda.Stream()     # graph replay needs a stream of its own
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for s_ in range(n_samples):
-                sim.step(every)
-                _, _, red = sim.macroscopic(dx, want_fields=False)
+                sim.step(every, stream=stream)
+                _, _, red = sim.macroscopic(dx, want_fields=False, stream=stream)
+                stream.synchronize()
                 lift[s_] = float(red[M._lib.RED_FORCE_Y].item())
                 if s_ % 4000 == 3999:
                     print(f"# {set_name} {mode} Re {re}: {s_ + 1}/{n_samples} lift samples", file=sys.stderr,
@@ -516,19 +662,8 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
             _, _, red = sim.macroscopic(dx, want_fields=False)
             bad = int(red[M._lib.RED_N_BAD].item())
             tail = lift[int(transient * t_shed / every):]
+            st, st_fft = strouhal_from_lift(tail, every, d / dx, u0)
             tail = tail - tail.mean()
-            spec = np.abs(np.fft.rfft(tail * np.hanning(len(tail)), n=8 * len(tail)))
-            freqs = np.fft.rfftfreq(8 * len(tail), d=every)
-            st_fft = freqs[int(np.argmax(spec[1:]) + 1)] * (d / dx) / u0
-            # mean period between the first and last upward zero crossings
-            # (linear interpolation between samples)
-            sg = np.sign(tail)
-            up = np.nonzero((sg[:-1] < 0) & (sg[1:] >= 0))[0]
-            if len(up) >= 3:
-                tc = up + (-tail[up]) / (tail[up + 1] - tail[up])
-                st = (d / dx) / ((tc[-1] - tc[0]) / (len(tc) - 1) * every * u0)
-            else:
-                st = float("nan")
             n_steps = n_samples * every
             series[f"{set_name}_{mode}_K{K}_Re{re}"] = lift
             rows.append({"nodes": set_name, "n": ns.n, "block_centres": int(b["n_lagrange"]), "stencils": mode, "K": K,
@@ -644,6 +779,8 @@ def main():
                     help="node order: 0 as generated, 1 Morton, 2 reverse Cuthill-McKee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
+    ap.add_argument("--no-extra-rows", action="store_true",
+                    help="skip the FP64 row and the large (beyond the memory-side cache) Karman set")
     ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
     ap.add_argument("--workload", default="karman",
                     choices=["karman", "porous", "batched", "batched-intervals", "warmstart", "darcy", "strouhal"],
@@ -716,6 +853,22 @@ def main():
     n_lag = b["n_lagrange"]
     print(f"# built {ns.n} nodes ({n_lag} block centres), K={K}, dx={dx:.4g}, tau={tau:.4f} in "
           f"{time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    cpu_out = None
+    if not args.no_cpu_baseline:
+        # the oracle on the host, before anything touches the GPU (its
+        # all-core leg forks worker processes)
+        import copy
+
+        nsp = copy.copy(ns)
+        nsp.xy = ns.xy[perm]
+        nsp.kind = ns.kind[perm]
+        nsp.bc = ns.boundary_values()[perm]
+        workers = min(16, os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16")))
+        cpu_out = cpu_baseline(nsp, b, tau, workers=workers)
+        cpu_out["host_threads_available"] = os.cpu_count()
+        print(f"# oracle on the host: {cpu_out['value']:.3f} MNUPS on 1 core, "
+              f"{cpu_out.get('all_cores', {}).get('value', float('nan')):.3f} on {workers}", file=sys.stderr,
+              flush=True)
     sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
                        storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
                        block=args.block, xcd_remap=args.xcd, scale_exp=12,
@@ -725,18 +878,8 @@ def main():
                        hybrid_launches=args.hybrid_launches)
     n = ns.n
     sim.init_state(np.ones(n), np.zeros((n, 2)))
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    per_launch_s = ms / 1e3 / args.steps
+    per_launch_s = timed_steps(sim, args.steps, args.warmup, torch)
+    ms = per_launch_s * 1e3 * args.steps
     _, _, red = sim.macroscopic(dx, want_fields=False)
     red = red.cpu().numpy()
     if red[M._lib.RED_N_BAD] != 0:
@@ -790,19 +933,20 @@ def main():
     del sim
     if not args.no_s_sweep:
         out["s_sweep"] = karman_s_sweep(M, units, np, torch, ns, args, storage, tau, tau_m)
+    if not args.no_extra_rows and not args.hybrid:
+        # the paper's precision (FP64) on the same set, and the FP32 step on a
+        # set five times the memory-side cache
+        out["fp64"] = karman_precision_row(M, units, np, torch, ns, b, tau, tau_m, "F64")
+        print(f"# f64 row: {out['fp64']['MNUPS']} MNUPS, frac {out['fp64']['frac']}", file=sys.stderr, flush=True)
+        out["large_set"] = karman_large_row(M, units, nodesets, np, torch)
+        print(f"# large set: {out['large_set']['MNUPS']} MNUPS, frac {out['large_set']['frac']}", file=sys.stderr,
+              flush=True)
     if not args.no_steady:
         out["time_to_steady"] = porous_time_to_steady(M, units, nodesets, np, torch)
         out["time_to_steady_inertial"] = porous_time_to_steady(M, units, nodesets, np, torch, s=4.0,
                                                                runs=TTS_RUNS_INERTIAL)
-    if not args.no_cpu_baseline:
-        import copy
-
-        nsp = copy.copy(ns)
-        nsp.xy = ns.xy[perm]
-        nsp.kind = ns.kind[perm]
-        nsp.bc = ns.boundary_values()[perm]
-        out["cpu_baseline"] = cpu_baseline(nsp, b, tau)
-        out["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+    if cpu_out is not None:
+        out["cpu_baseline"] = cpu_out
     print(json.dumps(out), flush=True)
 
 

@@ -261,6 +261,16 @@ typedef struct mlbm_step_params {
                                 per step for both node kinds (workgroups of the
                                 per-node tiles first, then the block-centre tiles);
                                 2 = one launch per kind.  The results are identical */
+    int32_t graph_steps;     /* 0: mlbm_step launches every step from the host.  An even
+                                G in [2, 4096]: the launches of G steps are captured once
+                                into a HIP graph on the caller's stream (not the default
+                                stream), kept by the library for later calls with the
+                                same arguments (16 graphs, least recently used dropped),
+                                and replayed nsteps / G times; the remaining steps are
+                                launched directly.  Same results as direct launches;
+                                saves launch overhead on node sets too small to fill
+                                the GPU.  Not with stochastic rounding (its random bits
+                                change every step): MLBM_ERR_UNSUPPORTED.           */
 } mlbm_step_params;
 
 typedef struct mlbm_device_state {

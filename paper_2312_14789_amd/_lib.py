@@ -63,7 +63,8 @@ class StepParams(ctypes.Structure):
                 ("block", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("fp32_arith", ctypes.c_int32), ("alternate_sweeps", ctypes.c_int32),
                 ("cached_weights", ctypes.c_int32), ("stochastic_rounding", ctypes.c_int32),
-                ("weights16", ctypes.c_int32), ("hybrid_launches", ctypes.c_int32)]
+                ("weights16", ctypes.c_int32), ("hybrid_launches", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
 
 
 class DeviceState(ctypes.Structure):

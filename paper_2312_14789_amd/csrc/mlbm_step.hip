@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <type_traits>
 
 #include "mlbm.h"
@@ -1348,6 +1349,56 @@ int hip_check(const char *what) {
     return MLBM_OK;
 }
 
+// ---- graph cache of mlbm_step -----------------------------------------------------------
+// Every argument a replay depends on; the bytes of StepArgs are zeroed before
+// they are filled, so equal launches give equal keys.
+struct GraphKey {
+    unsigned char args[sizeof(StepArgs)];
+    const void *fn0, *fn1;
+    int64_t ranges[2][2];
+    int64_t shmem;
+    int32_t blk, gsteps, cur, device;
+    void *stream;
+};
+
+constexpr int kGraphCacheSize = 16;
+std::mutex g_graph_mutex;
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    uint64_t used;
+};
+GraphEntry g_graphs[kGraphCacheSize];
+int g_graph_count = 0;
+uint64_t g_graph_clock = 0;
+
+hipGraphExec_t graph_cache_find(const GraphKey &k) {
+    std::lock_guard<std::mutex> lock(g_graph_mutex);
+    for (int i = 0; i < g_graph_count; ++i)
+        if (std::memcmp(&g_graphs[i].key, &k, sizeof(k)) == 0) {
+            g_graphs[i].used = ++g_graph_clock;
+            return g_graphs[i].exec;
+        }
+    return nullptr;
+}
+
+// keeps exec; the least recently used entry is destroyed when the cache is full
+void graph_cache_put(const GraphKey &k, hipGraphExec_t exec) {
+    std::lock_guard<std::mutex> lock(g_graph_mutex);
+    int slot = g_graph_count;
+    if (g_graph_count == kGraphCacheSize) {
+        slot = 0;
+        for (int i = 1; i < kGraphCacheSize; ++i)
+            if (g_graphs[i].used < g_graphs[slot].used) slot = i;
+        hipGraphExecDestroy(g_graphs[slot].exec);
+    } else {
+        ++g_graph_count;
+    }
+    g_graphs[slot].key = k;
+    g_graphs[slot].exec = exec;
+    g_graphs[slot].used = ++g_graph_clock;
+}
+
 }  // namespace
 
 extern "C" int mlbm_init_state(const mlbm_step_params *p, mlbm_device_state *st, const double *rho,
@@ -1412,6 +1463,7 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     if (p->variant == MLBM_FIELDS && (p->tau_plus != 1.0 || p->tau_minus != 1.0))
         return fail(MLBM_ERR_ARG, "the fields variant fixes tau = 1");
     StepArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.n = st->n;
     a.idx = (const int *)st->idx;
     a.w = st->w;
@@ -1465,12 +1517,19 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     }
     hipStream_t s = (hipStream_t)stream;
     a.sr = (p->stochastic_rounding && (p->storage == MLBM_F16S || p->storage == MLBM_BF16)) ? 1 : 0;
-    for (int t = 0; t < nsteps; ++t) {
+    const int gsteps = p->graph_steps;
+    if (gsteps != 0 && (gsteps < 2 || gsteps > 4096 || (gsteps & 1)))
+        return fail(MLBM_ERR_ARG, "graph_steps must be 0 or an even number in [2, 4096]");
+    if (gsteps && a.sr)
+        return fail(MLBM_ERR_UNSUPPORTED, "graph replay with stochastic rounding (its random bits change every step)");
+    if (gsteps && !stream) return fail(MLBM_ERR_ARG, "graph replay needs a stream other than the default stream");
+    // one step: the launches of its tile ranges (direct, or recorded while capturing)
+    auto launch_step = [&]() -> int {
         a.in = st->state[st->cur];
         a.out = st->state[st->cur ^ 1];
         a.reverse = p->alternate_sweeps && st->cur == 1;
         const uint64_t step = st->step_count++;
-        a.seed = mix32((unsigned)step ^ mix32((unsigned)(step >> 32) + 0x6a09e667u));
+        a.seed = a.sr ? mix32((unsigned)step ^ mix32((unsigned)(step >> 32) + 0x6a09e667u)) : 0u;
         for (int r = 0; r < 2; ++r) {
             const int64_t cnt = ranges[r][1] - ranges[r][0];
             if (cnt <= 0) continue;
@@ -1481,9 +1540,63 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
             if (fuse) a.split = a.grid8;
             hipLaunchKernelGGL(fns[r], dim3((unsigned)(a.grid8 + a.grid8b)), dim3(blk), shmem, s, a);
         }
-        rc = hip_check("mlbm_step launch");
-        if (rc) return rc;
+        const int rc_ = hip_check("mlbm_step launch");
+        if (rc_) return rc_;
         st->cur ^= 1;
+        return MLBM_OK;
+    };
+    int32_t left = nsteps;
+    if (gsteps && nsteps >= gsteps) {
+        // gsteps steps (even: cur comes back to its value) as one graph, captured on
+        // first use and kept for later calls that would launch the same kernels
+        // with the same arguments; replays cover whole multiples of gsteps
+        GraphKey key;
+        std::memset(&key, 0, sizeof(key));
+        a.in = st->state[st->cur];
+        a.out = st->state[st->cur ^ 1];
+        a.reverse = p->alternate_sweeps && st->cur == 1;
+        a.seed = 0;
+        std::memcpy(key.args, &a, sizeof(a));
+        key.fn0 = (const void *)fns[0];
+        key.fn1 = (const void *)fns[1];
+        std::memcpy(key.ranges, ranges, sizeof(ranges));
+        key.blk = blk;
+        key.shmem = (int64_t)shmem;
+        key.gsteps = gsteps;
+        key.stream = stream;
+        key.cur = st->cur;
+        if (hipGetDevice(&key.device) != hipSuccess) return hip_check("hipGetDevice");
+        hipGraphExec_t exec = graph_cache_find(key);
+        if (!exec) {
+            const int cur0 = st->cur;
+            const uint64_t count0 = st->step_count;
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return hip_check("mlbm_step: hipStreamBeginCapture");
+            int rcc = MLBM_OK;
+            for (int t = 0; t < gsteps && rcc == MLBM_OK; ++t) rcc = launch_step();
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(s, &graph);
+            st->cur = cur0;
+            st->step_count = count0;
+            if (rcc) {
+                if (graph) hipGraphDestroy(graph);
+                return rcc;
+            }
+            if (ec != hipSuccess || !graph) return fail(MLBM_ERR_HIP, "mlbm_step: hipStreamEndCapture: %s", hipGetErrorString(ec));
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (ei != hipSuccess) return fail(MLBM_ERR_HIP, "mlbm_step: hipGraphInstantiate: %s", hipGetErrorString(ei));
+            graph_cache_put(key, exec);
+        }
+        const int32_t reps = nsteps / gsteps;
+        for (int32_t r = 0; r < reps; ++r)
+            if (hipGraphLaunch(exec, s) != hipSuccess) return hip_check("mlbm_step: hipGraphLaunch");
+        st->step_count += (uint64_t)reps * (uint64_t)gsteps;
+        left = nsteps - reps * gsteps;
+    }
+    for (int32_t t = 0; t < left; ++t) {
+        rc = launch_step();
+        if (rc) return rc;
     }
     return MLBM_OK;
 }

@@ -74,11 +74,14 @@ def algorithmic_bytes_per_node(variant: int, storage: int, k_padded: int, weight
     """Bytes one node update must move between HBM and the chip in the packed
     device layout: read and write of its own state, its weights, its stencil
     indices and its flags (gathered neighbour state counted once, at the
-    owner).  variant 0 = populations, 1 = fields; storage 0 F64, 1 F32,
-    2 F16S, 3 BF16; weights16: FP16 weights (16-bit states)."""
+    owner).  The state is what the method stores: nine populations, or the
+    three fields (rho, u, v) of MLBM1 (the device layout pads these to four
+    for 16-byte loads; the padding is layout, not algorithm).  variant 0 =
+    populations, 1 = fields; storage 0 F64, 1 F32, 2 F16S, 3 BF16;
+    weights16: FP16 weights (16-bit states)."""
     tb = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
     wb = 8 if storage == 0 else (2 if weights16 else 4)
-    state = (9 if variant == 0 else 4) * tb
+    state = (9 if variant == 0 else 3) * tb
     return 2 * state + 8 * k_padded * wb + 4 * k_padded + 2
 
 
@@ -87,7 +90,7 @@ def block_centre_bytes_per_node(variant: int, storage: int) -> int:
     indices replace the stencil indices, and its weights are shared by all
     block centres (read once per launch, not per node)."""
     tb = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
-    state = (9 if variant == 0 else 4) * tb
+    state = (9 if variant == 0 else 3) * tb
     return 2 * state + 8 * 4 + 2
 
 

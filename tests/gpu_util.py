@@ -33,6 +33,30 @@ def assert_fields_close(u, u_ref, bar, what=""):
     return e2, em
 
 
+def morton_reordered(ns):
+    """The node set renumbered in Morton (Z) order of its coordinates
+    (16-bit cells per axis), so that consecutive nodes are close and a tile's
+    halo stays small; a plain renumbering, computed here."""
+    import copy
+
+    q = ((ns.xy - ns.lo) / (ns.hi - ns.lo) * 65535.0).astype(np.uint64)
+
+    def spread(v):
+        v = v & np.uint64(0xFFFF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x00FF00FF)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x0F0F0F0F)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x33333333)
+        v = (v | (v << np.uint64(1))) & np.uint64(0x55555555)
+        return v
+
+    order = np.argsort(spread(q[:, 0]) | (spread(q[:, 1]) << np.uint64(1)), kind="stable")
+    out = copy.copy(ns)
+    out.xy = ns.xy[order]
+    out.kind = ns.kind[order]
+    out.bc = ns.boundary_values()[order]
+    return out
+
+
 def initial_fields(ns, seed, amp_u, amp_rho):
     """Smooth seeded fields, with the prescribed values on Dirichlet nodes."""
     L = float(np.max(ns.hi - ns.lo))

@@ -16,8 +16,8 @@ import nodesets
 from oracle import lattice as lt
 from oracle import mlbm as omlbm
 
-from gpu_util import (assert_fields_close, initial_fields, lagrange_last, oracle_bb, oracle_one_step_at, rel_l2,
-                      rel_max, run_oracle, sim_from_oracle)
+from gpu_util import (assert_fields_close, initial_fields, lagrange_last, morton_reordered, oracle_bb,
+                      oracle_one_step_at, rel_l2, rel_max, run_oracle, sim_from_oracle)
 
 pytestmark = pytest.mark.gpu
 
@@ -349,6 +349,48 @@ def test_launch_shape_and_determinism(M):
         np.testing.assert_array_equal(r, outs[0][1])
 
 
+@pytest.mark.parametrize("name,storage,kw", [("channel_trt", 1, {}), ("hybrid_tgv", 1, {}),
+                                               ("porous_fields", 0, {"alternate_sweeps": 0}),
+                                               ("hybrid_pixels_fields", 2, {"hybrid_launches": 2})])
+def test_graph_replay_equals_direct_launches(M, name, storage, kw):
+    # graph_steps = G: G steps captured once and replayed; 103 steps = 12
+    # replays of 8 plus 7 direct steps, then a second call replays the cached
+    # graph; the state must be bitwise the one of 103 + 37 direct launches
+    import torch
+
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case(name)
+    out = []
+    for graph in (0, 8):
+        sim = sim_from_oracle(M, ns, st, var, storage, tp, tm, g, tile=256, scale_exp=14, graph_steps=graph, **kw)
+        sim.init_state(rho0, u0)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            sim.step(103, stream=stream)
+            sim.step(37, stream=stream)
+        stream.synchronize()
+        assert sim.ds.step_count == 140
+        out.append(sim.state_bytes().copy())
+    print(f"[graph] case={name} storage={storage} {kw} identical={bool(np.array_equal(out[0], out[1]))}", flush=True)
+    np.testing.assert_array_equal(out[1], out[0])
+
+
+def test_graph_replay_refusals(M):
+    import torch
+
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case("channel_trt")
+    sim = sim_from_oracle(M, ns, st, 0, 2, tp, tm, g, scale_exp=14, graph_steps=8, stochastic_rounding=1)
+    sim.init_state(rho0, u0)
+    stream = torch.cuda.Stream()
+    with pytest.raises(M.MlbmError) as e:
+        sim.step(16, stream=stream)
+    assert e.value.code == -5
+    sim.params.stochastic_rounding = 0
+    sim.params.graph_steps = 7
+    with pytest.raises(M.MlbmError) as e:
+        sim.step(16, stream=stream)
+    assert e.value.code == -1
+
+
 def test_fp32_collision_arithmetic_is_refused(M):
     ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case("channel_trt")
     sim = sim_from_oracle(M, ns, st, 0, 1, tp, tm, g)
@@ -387,6 +429,47 @@ def test_zero_steps_and_errors(M):
     sim.ds.n = 0
     with pytest.raises(M.MlbmError):
         sim.step(1)
+
+
+_K25K = {}
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("s", [1.0, 4.0])
+def test_karman_poisson_25k_nodes_1000_steps(M, s):
+    # the bench's Poisson-disk generator at ~2.5e4 nodes (22D x 4.1D channel,
+    # cylinder, Dirichlet sides), K = 16, BGK at Re = 100 s, 1000 steps from
+    # the parabolic channel profile with a small seeded perturbation: FP64
+    # and FP32 states against the whole oracle run, node by node (nodes in
+    # Morton order, so 256-node LDS tiles have small halos)
+    from paper_2312_14789_amd import units
+
+    if s not in _K25K:
+        ns = morton_reordered(nodesets.karman(n_target=25000, poisson=True, seed=7))
+        dx = units.delta_x(ns.h_min, s)
+        tau = units.tau_for_reynolds(0.05, 1.0, dx, 100.0 * s)
+        st = omlbm.build_stencils(ns, 16, dx)
+        rho0, u0 = initial_fields(ns, 27, 0.005, 0.0)
+        rho0[:] = 1.0
+        H = ns.hi[1] - ns.lo[1]
+        y = ns.xy[:, 1] - ns.lo[1]
+        fl = ns.kind != nodesets.DIRICHLET
+        u0[fl, 0] += 4 * 0.05 * y[fl] * (H - y[fl]) / H ** 2
+        (r_ref, u_ref), _ = run_oracle(ns, st, 0, 1000, rho0, u0, tau, tau, (0.0, 0.0))
+        _K25K[s] = (ns, st, dx, tau, rho0, u0, r_ref, u_ref)
+    ns, st, dx, tau, rho0, u0, r_ref, u_ref = _K25K[s]
+    print(f"[karman-25k] n={ns.n} s={s:g} tau={tau:.4f}", flush=True)
+    for storage in (0, 1):
+        # FP64 halos (64 B per node) of 256-node tiles can exceed the LDS: 128-node tiles
+        sim = sim_from_oracle(M, ns, st, 0, storage, tau, tau, (0.0, 0.0), tile=128 if storage == 0 else 256)
+        sim.init_state(rho0, u0)
+        sim.step(1000)
+        _, u, red = sim.macroscopic(dx)
+        u = u.cpu().numpy()
+        print(f"[karman-25k] s={s:g} storage={storage} rel_l2_u={rel_l2(u, u_ref):.3e} "
+              f"rel_max_u={rel_max(u, u_ref):.3e}", flush=True)
+        assert_fields_close(u, u_ref, BAR[storage], f"karman 25k s={s:g}")
+        assert red[8].item() == 0
 
 
 # ---------------------------------------------------------------------------
