@@ -703,7 +703,9 @@ def warmstart_workload(args, np, torch):
     t0 = time.time()
     fields, steps = warmstart.steady_states(train_g, g, batch_size=64, log=log)
     t_data = time.time() - t0
-    print(f"# steady states in {t_data:.1f} s, steps {min(steps)}..{max(steps)}", file=sys.stderr, flush=True)
+    train_g, fields, steps, dropped = warmstart.converged_only(train_g, fields, steps)
+    print(f"# steady states in {t_data:.1f} s, steps {min(steps)}..{max(steps)}, {dropped} not converged (dropped)",
+          file=sys.stderr, flush=True)
     data = warmstart.Dataset(train_g, fields, res)
     del fields
     net = unet.UNet((32, 64, 128, 256, 256), res=res, batch=16, seed=1)
@@ -747,7 +749,7 @@ def warmstart_workload(args, np, torch):
                       "iters": iters, "ms_per_iter": round(1e3 * t_train / max(iters, 1), 2),
                       "tflops_fwd_bwd": round(3 * fl * net.batch * iters / t_train / 1e12, 2)},
             "data": {"geometry_s": round(t_geo, 1), "steady_states_s": round(t_data, 1),
-                     "steps_min_max": [int(min(steps)), int(max(steps))]}}
+                     "steps_min_max": [int(min(steps)), int(max(steps))], "unconverged_dropped": dropped}}
 
 
 def main():

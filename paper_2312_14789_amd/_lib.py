@@ -95,6 +95,24 @@ class ConvDesc(ctypes.Structure):
                 ("y_stride", ctypes.c_int32), ("y_offset", ctypes.c_int32), ("c_store", ctypes.c_int32)]
 
 
+class UNetDesc(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("channels", ctypes.c_int32 * 6), ("batch", ctypes.c_int32),
+                ("res", ctypes.c_int32), ("c_in", ctypes.c_int32), ("c_out", ctypes.c_int32),
+                ("params", _p), ("grads", _p), ("adam_m", _p), ("adam_v", _p), ("w_bf16", _p), ("act", _p),
+                ("act_grad", _p), ("work", _p)]
+
+
+class UNetBuffers(ctypes.Structure):
+    _fields_ = [("n_params", ctypes.c_int64), ("w_bf16_bytes", ctypes.c_int64), ("act_bytes", ctypes.c_int64),
+                ("work_bytes", ctypes.c_int64), ("n_layers", ctypes.c_int32)]
+
+
+class UNetLayerInfo(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 8), ("ksize", ctypes.c_int32), ("c_in", ctypes.c_int32),
+                ("c_out", ctypes.c_int32), ("res", ctypes.c_int32), ("w_offset", ctypes.c_int64),
+                ("b_offset", ctypes.c_int64)]
+
+
 class MlbmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"mlbm error {code}: {msg}")
@@ -161,6 +179,14 @@ def _load():
                                            ctypes.c_float, _p, _p, _p, _p]),
         "mlbm_adam": (ctypes.c_int, [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, _p]),
+        "mlbm_unet_sizes": (ctypes.c_int, [P(UNetDesc), P(UNetBuffers)]),
+        "mlbm_unet_layer": (ctypes.c_int, [P(UNetDesc), ctypes.c_int32, P(UNetLayerInfo)]),
+        "mlbm_unet_refresh": (ctypes.c_int, [P(UNetDesc), _p]),
+        "mlbm_unet_forward": (ctypes.c_int, [P(UNetDesc), _p, _p, _p]),
+        "mlbm_unet_loss": (ctypes.c_int, [P(UNetDesc), _p, _p, _p, _p, _p]),
+        "mlbm_unet_backward": (ctypes.c_int, [P(UNetDesc), _p, _p]),
+        "mlbm_unet_adam": (ctypes.c_int, [P(UNetDesc), ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_float, ctypes.c_int32, _p]),
         "mlbm_last_error": (ctypes.c_char_p, []),
         "mlbm_version": (ctypes.c_char_p, []),
     }
@@ -181,7 +207,8 @@ EXPORTS = ["mlbm_build_stencils", "mlbm_packed_sizes", "mlbm_pack_stencils", "ml
            "mlbm_run_to_steady", "mlbm_last_error", "mlbm_version"]
 
 # every symbol include/mlbm_unet.h declares
-UNET_EXPORTS = ["mlbm_conv_forward", "mlbm_conv_wgrad_workspace", "mlbm_conv_wgrad", "mlbm_conv_weights",
+UNET_EXPORTS = ["mlbm_unet_sizes", "mlbm_unet_layer", "mlbm_unet_refresh", "mlbm_unet_forward", "mlbm_unet_loss",
+                "mlbm_unet_backward", "mlbm_unet_adam", "mlbm_conv_forward", "mlbm_conv_wgrad_workspace", "mlbm_conv_wgrad", "mlbm_conv_weights",
                 "mlbm_relu_backward", "mlbm_pool_forward", "mlbm_pool_backward", "mlbm_upsample_forward",
                 "mlbm_upsample_backward", "mlbm_mse_workspace", "mlbm_masked_mse", "mlbm_adam"]
 

@@ -13,8 +13,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
 
 #include "mlbm_internal.h"
 #include "mlbm.h"
@@ -39,161 +43,196 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
     return __builtin_bit_cast(bf16x8, v);
 }
 
-// pixel index -> (n, y, x) and the periodic neighbour at offset (oy, ox)
-__device__ __forceinline__ int64_t shifted(int64_t p, int H, int W, int oy, int ox) {
-    const int64_t hw = (int64_t)H * W;
-    const int64_t n = p / hw;
-    const int rem = (int)(p - n * hw);
-    int y = rem / W + oy, x = rem % W + ox;
-    y = y < 0 ? y + H : (y >= H ? y - H : y);
-    x = x < 0 ? x + W : (x >= W ? x - W : x);
-    return n * hw + (int64_t)y * W + x;
-}
+// ---- convolution tiles (forward and data gradient) ----------------------------------------
+// One workgroup computes a TH x TW pixel tile of one image for BN output
+// channels, as an implicit GEMM on v_mfma_f32_32x32x16_bf16: each wave owns 32
+// pixels x 32 channels.  Per 32-channel slice of the input, the tile's input
+// halo ((TH + 2) x (TW + 2) pixels, periodic) and the slice of the weights for
+// every tap are staged in LDS with 16-byte copies, so each staged input value
+// feeds all taps and every MFMA operand is one 16-byte LDS read.  Row pitches
+// of 40 halves (80 B) keep the 16 lanes of each LDS read on distinct banks.
+// Epilogue: bias, ReLU, and optionally a gate (the ReLU gradient of the layer
+// whose output gradient this is: zero where that layer's output is <= 0).
+constexpr int KC = 32, XP = KC + 8;
 
-// ---- forward convolution ----------------------------------------------------------
-// Block: 4 waves.  BN = 64: waves in a 2x2 grid over 64 pixels x 64 output
-// channels; BN = 32: 4 waves over 128 pixels x 32 channels.
-template <int BN>
-__global__ void __launch_bounds__(256) k_conv_fwd(mlbm_conv_desc d, const unsigned short *x,
-                                                 const unsigned short *w, const float *bias, void *y, int relu,
-                                                 int y_f32) {
-    constexpr int WAVES_PX = BN == 64 ? 2 : 4;
-    constexpr int BM = 32 * WAVES_PX;
+template <int TH, int TW, int BN>
+__global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
+    k_conv_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
+                const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
+                const unsigned short *__restrict__ gate, int gate_stride, int gate_offset) {
+    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = 64 * WPX * (BN / 32);
+    __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
+    __shared__ __align__(16) unsigned short wsm[9 * BN * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wr = wave % WAVES_PX, wc = wave / WAVES_PX;
-    const int64_t p0 = (int64_t)blockIdx.x * BM + wr * 32;
-    const int co0 = blockIdx.y * BN + wc * 32;
-    const int row = lane & 31, khalf = (lane >> 5) * 8;
-    const int64_t p = p0 + row;
-    const int co = co0 + row;
-    const int ks = d.ksize, r = ks / 2, taps = ks * ks;
+    const int wp = wave % WPX, wc = wave / WPX;
+    const int tiles_x = d.w / TW, tiles_img = tiles_x * (d.h / TH);
+    const int n = blockIdx.x / tiles_img, rem = blockIdx.x % tiles_img;
+    const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
+    const int co0 = blockIdx.y * BN;
+    const int ks = d.ksize, r = ks >> 1, taps = ks * ks;
+    const int row = lane & 31, kh = (lane >> 5) * 8;
+    const int pb = wp * 32 + row;
+    const int py = pb / TW, px = pb % TW;
     f32x16 acc = {};
-    for (int t = 0; t < taps; ++t) {
-        const int64_t ps = shifted(p, d.h, d.w, t / ks - r, t % ks - r);
-        const unsigned short *xa = x + ps * d.x_stride + d.x_offset + khalf;
-        const unsigned short *wb = w + ((int64_t)co * taps + t) * d.c_in + khalf;
-        for (int c = 0; c < d.c_in; c += 16) {
-            const bf16x8 a = load_bf8(xa + c);
-            const bf16x8 b = load_bf8(wb + c);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    for (int c0 = 0; c0 < d.c_in; c0 += KC) {
+        __syncthreads();
+        for (int it = threadIdx.x; it < HH * HWD * 4; it += NT) {
+            const int hp = it >> 2, q = it & 3;
+            const int hy = hp / HWD, hx = hp - hy * HWD;
+            int gy = y0 + hy - 1, gx = x0 + hx - 1;
+            gy += gy < 0 ? d.h : 0;
+            gy -= gy >= d.h ? d.h : 0;
+            gx += gx < 0 ? d.w : 0;
+            gx -= gx >= d.w ? d.w : 0;
+            const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+            *(u4 *)&xs[hp * XP + 8 * q] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + c0 + 8 * q);
+        }
+        for (int it = threadIdx.x; it < taps * BN * 4; it += NT) {
+            const int q = it & 3, rest = it >> 2;
+            const int t = rest % taps, co = rest / taps;
+            *(u4 *)&wsm[(t * BN + co) * XP + 8 * q] =
+                *(const u4 *)(w + ((int64_t)(co0 + co) * taps + t) * d.c_in + c0 + 8 * q);
+        }
+        __syncthreads();
+        for (int t = 0; t < taps; ++t) {
+            const int oy = t / ks - r, ox = t % ks - r;
+            const unsigned short *ap = &xs[((py + 1 + oy) * HWD + (px + 1 + ox)) * XP + kh];
+            const unsigned short *bp = &wsm[(t * BN + wc * 32 + row) * XP + kh];
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 16)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf8(ap + kk), load_bf8(bp + kk), acc, 0, 0, 0);
         }
     }
-    const int col = co0 + row;  // output channel of this lane
+    const int col = co0 + wc * 32 + row;
     const float bv = bias ? bias[col] : 0.0f;
+    if (col >= d.c_store) return;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const int64_t pp = p0 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+        const int pt = wp * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+        const int ty = pt / TW, tx = pt % TW;
+        const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
         float v = acc[q] + bv;
         if (relu) v = fmaxf(v, 0.0f);
-        if (col < d.c_store) {
-            const int64_t o = pp * d.y_stride + d.y_offset + col;
-            if (y_f32) ((float *)y)[o] = v;
-            else ((unsigned short *)y)[o] = f2bf(v);
-        }
+        if (gate && !(bf2f(gate[gp * gate_stride + gate_offset + col]) > 0.0f)) v = 0.0f;
+        const int64_t o = gp * d.y_stride + d.y_offset + col;
+        if (y_f32) ((float *)y)[o] = v;
+        else ((unsigned short *)y)[o] = f2bf(v);
     }
 }
 
-// Register-blocked forward convolution for c_out a multiple of 64: each wave
-// computes 2 x 2 MFMA tiles (64 pixels x 64 output channels), so every operand
-// fragment it loads feeds two MFMAs (half the loads per MFMA of k_conv_fwd);
-// 2 waves per block over 128 pixels.
-__global__ void __launch_bounds__(128) k_conv_fwd_rb(mlbm_conv_desc d, const unsigned short *x,
-                                                    const unsigned short *w, const float *bias, void *y, int relu,
-                                                    int y_f32) {
+// ---- weight gradient -------------------------------------------------------------------------
+// dw[o][tap][i] = sum_p dy[p, o] x[p + tap, i]: an MFMA product whose summed
+// index is the pixel, so both operands need 8 consecutive pixels of one
+// channel per lane.  One workgroup takes BCO output x 32 input channels and
+// every tap, over a range of TH x TW pixel tiles: it stages the tile's output
+// gradient transposed ([channel][pixel]) and the input halo transposed in KS
+// copies, copy s holding halo columns s .. s + TW - 1 of each halo row, so the
+// operand of any tap starts on a 16-byte boundary.  Transposes run in
+// registers on 8 x 8 blocks (8 pixels x 8 channels, one 16-byte load each)
+// and are written with 16-byte LDS stores.  Wave (co half h, tap row j) sums
+// the KS taps of its row.  Partials per split go to ws[split][c_out][taps][c_in].
+
+// in[r] = 8 values of row r (value 2k in the low half of dword k); out[c] = column c
+__device__ __forceinline__ void transpose8x8(const u4 in[8], u4 out[8]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        unsigned o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned lo = in[2 * k][c >> 1], hi = in[2 * k + 1][c >> 1];
+            o[k] = (c & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+        }
+        out[c] = u4{o[0], o[1], o[2], o[3]};
+    }
+}
+
+constexpr int XTS = 16 * 10 + 8;  // halves per channel of a transposed halo copy (up to 10 rows of 16, padded)
+
+template <int TH, int TW, int BCO, int KS>
+__global__ void __launch_bounds__(64 * (BCO / 32) * KS)
+    k_wgrad_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
+                 float *__restrict__ ws, int tiles_per_split) {
+    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / 32) * KS, PP = BM + 8;
+    static_assert(HH <= 10 && TW <= 16, "transposed halo copies hold up to 10 rows of 16");
+    __shared__ __align__(16) unsigned short dyT[BCO * PP];
+    __shared__ __align__(16) unsigned short xT[KS * 32 * XTS];
+    __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t p0 = (int64_t)blockIdx.x * 128 + wave * 64;
-    const int co0 = blockIdx.y * 64;
-    const int row = lane & 31, khalf = (lane >> 5) * 8;
-    const int ks = d.ksize, r = ks / 2, taps = ks * ks;
-    f32x16 acc[2][2] = {};
-    for (int t = 0; t < taps; ++t) {
-        const unsigned short *xa[2], *wb[2];
+    const int ch = wave / KS, trow = wave % KS;
+    const int co0 = blockIdx.x * BCO, ci0 = blockIdx.y * 32, split = blockIdx.z;
+    const int r = KS >> 1, taps = KS * KS;
+    const int tiles_x = d.w / TW, tiles_img = tiles_x * (d.h / TH);
+    const int n_tiles = d.n * tiles_img;
+    const int ta = split * tiles_per_split, tb = min(n_tiles, ta + tiles_per_split);
+    const int row = lane & 31, kh = (lane >> 5) * 8;
+    f32x16 acc[KS];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int64_t ps = shifted(p0 + 32 * i + row, d.h, d.w, t / ks - r, t % ks - r);
-            xa[i] = x + ps * d.x_stride + d.x_offset + khalf;
-            wb[i] = w + ((int64_t)(co0 + 32 * i + row) * taps + t) * d.c_in + khalf;
+    for (int s = 0; s < KS; ++s) acc[s] = f32x16{};
+    for (int tile = ta; tile < tb; ++tile) {
+        const int n = tile / tiles_img, rem = tile % tiles_img;
+        const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
+        __syncthreads();
+        // output gradient: 8 pixels x 8 channels per item, transposed into dyT
+        for (int it = threadIdx.x; it < (BM / 8) * (BCO / 8); it += NT) {
+            const int g = it % (BM / 8), c8 = it / (BM / 8);
+            const int p0 = g * 8, ty = p0 / TW, tx = p0 % TW;
+            const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
+            u4 in[8], out[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) in[j] = *(const u4 *)(dy + (gp + j) * d.y_stride + d.y_offset + co0 + 8 * c8);
+            transpose8x8(in, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u4 *)&dyT[(c8 * 8 + c) * PP + p0] = out[c];
         }
-        for (int c = 0; c < d.c_in; c += 16) {
-            const bf16x8 a0 = load_bf8(xa[0] + c), a1 = load_bf8(xa[1] + c);
-            const bf16x8 b0 = load_bf8(wb[0] + c), b1 = load_bf8(wb[1] + c);
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        // input halo, pixel-major
+        for (int it = threadIdx.x; it < HH * HWD * 4; it += NT) {
+            const int hp = it >> 2, q = it & 3;
+            const int hy = hp / HWD, hx = hp - hy * HWD;
+            int gy = y0 + hy - 1, gx = x0 + hx - 1;
+            gy += gy < 0 ? d.h : 0;
+            gy -= gy >= d.h ? d.h : 0;
+            gx += gx < 0 ? d.w : 0;
+            gx -= gx >= d.w ? d.w : 0;
+            const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+            *(u4 *)&xs[hp * XP + 8 * q] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
         }
-    }
+        __syncthreads();
+        // transposed copies: copy s holds halo columns (s + c), c < TW (KS = 1: the centre column c + 1)
+        for (int it = threadIdx.x; it < KS * 4 * HH * (TW / 8); it += NT) {
+            const int cg = it % (TW / 8), rest = it / (TW / 8);
+            const int hy = rest % HH, rest2 = rest / HH;
+            const int c8 = rest2 % 4, s = rest2 / 4;
+            const int hx0 = cg * 8 + (KS == 1 ? 1 : s);
+            u4 in[8], out[8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int col = co0 + 32 * j + row;  // output channel of this lane
-        const float bv = bias ? bias[col] : 0.0f;
+            for (int j = 0; j < 8; ++j) in[j] = *(const u4 *)&xs[(hy * HWD + hx0 + j) * XP + 8 * c8];
+            transpose8x8(in, out);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+            for (int c = 0; c < 8; ++c) *(u4 *)&xT[(s * 32 + c8 * 8 + c) * XTS + hy * 16 + cg * 8] = out[c];
+        }
+        __syncthreads();
+        const int oy = trow - r;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int64_t pp = p0 + 32 * i + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
-                float v = acc[i][j][q] + bv;
-                if (relu) v = fmaxf(v, 0.0f);
-                if (col < d.c_store) {
-                    const int64_t o = pp * d.y_stride + d.y_offset + col;
-                    if (y_f32) ((float *)y)[o] = v;
-                    else ((unsigned short *)y)[o] = f2bf(v);
-                }
+        for (int kb = 0; kb < BM / 16; ++kb) {
+            const int p0 = kb * 16 + kh;
+            const int ty = p0 / TW, tx = p0 % TW;
+            const bf16x8 a = load_bf8(&dyT[(ch * 32 + row) * PP + p0]);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const bf16x8 b = load_bf8(&xT[(s * 32 + row) * XTS + (ty + 1 + oy) * 16 + tx]);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[s], 0, 0, 0);
             }
         }
     }
-}
-
-// ---- weight gradient ----------------------------------------------------------------
-// One wave per (32 output channels) x (32 input channels) x tap tile and pixel
-// split; 64-pixel chunks of dy and of the shifted x are transposed through LDS
-// so every lane reads 8 consecutive pixels.  Partial sums go to ws[split].
-__global__ void __launch_bounds__(64) k_conv_wgrad(mlbm_conv_desc d, const unsigned short *x,
-                                                  const unsigned short *dy, float *ws, int64_t px_per_split) {
-    __shared__ __align__(16) unsigned short sa[32][64 + 8];  // [co][pixel]
-    __shared__ __align__(16) unsigned short sb[32][64 + 8];  // [ci][pixel]
-    const int lane = threadIdx.x;
-    const int co0 = blockIdx.x * 32, ci0 = blockIdx.y * 32;
-    const int taps = d.ksize * d.ksize, r = d.ksize / 2;
-    const int t = blockIdx.z % taps, split = blockIdx.z / taps;
-    const int oy = t / d.ksize - r, ox = t % d.ksize - r;
-    const int64_t P = (int64_t)d.n * d.h * d.w;
-    const int64_t pa = split * px_per_split, pb = min(P, pa + px_per_split);
-    f32x16 acc = {};
-    for (int64_t c0 = pa; c0 < pb; c0 += 64) {
-        // stage: lane handles pixel c0 + lane (zero past the end)
-        const int64_t p = c0 + lane;
-        const bool in = p < pb;
-        const int64_t ps = in ? shifted(p, d.h, d.w, oy, ox) : 0;
+    const int ci = ci0 + row;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            u4 va = in ? *(const u4 *)(dy + p * d.y_stride + d.y_offset + co0 + 8 * g) : u4{0, 0, 0, 0};
-            u4 vb = in ? *(const u4 *)(x + ps * d.x_stride + d.x_offset + ci0 + 8 * g) : u4{0, 0, 0, 0};
-            const unsigned a8[4] = {va.x, va.y, va.z, va.w}, b8[4] = {vb.x, vb.y, vb.z, vb.w};
+    for (int s = 0; s < KS; ++s) {
+        const int t = trow * KS + s;
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                sa[8 * g + 2 * h][lane] = (unsigned short)(a8[h] & 0xffff);
-                sa[8 * g + 2 * h + 1][lane] = (unsigned short)(a8[h] >> 16);
-                sb[8 * g + 2 * h][lane] = (unsigned short)(b8[h] & 0xffff);
-                sb[8 * g + 2 * h + 1][lane] = (unsigned short)(b8[h] >> 16);
-            }
+        for (int q = 0; q < 16; ++q) {
+            const int co = co0 + ch * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+            ws[(((int64_t)split * d.c_out + co) * taps + t) * d.c_in + ci] = acc[s][q];
         }
-        __syncthreads();
-        const int row = lane & 31, kh = (lane >> 5) * 8;
-#pragma unroll
-        for (int kk = 0; kk < 64; kk += 16) {
-            const bf16x8 a = load_bf8(&sa[row][kk + kh]);
-            const bf16x8 b = load_bf8(&sb[row][kk + kh]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-        }
-        __syncthreads();
-    }
-    // ws layout [split][c_out][taps][c_in]
-    const int ci = ci0 + (lane & 31);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int co = co0 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
-        ws[(((int64_t)split * d.c_out + co) * taps + t) * d.c_in + ci] = acc[q];
     }
 }
 
@@ -388,6 +427,81 @@ __global__ void k_adam(int64_t m, float *p, const float *g, float *mo, float *vo
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// masked MSE with the normalisation 1 / (C sum mask) read from the device
+__global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *pred, int ps, const float *target,
+                                                const float *mask, const float *inv_count, unsigned short *dpred,
+                                                double *partial) {
+    __shared__ double s1[256];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float ic = *inv_count;
+    double e = 0.0;
+    if (p < P) {
+        const float m = mask[p];
+        for (int c = 0; c < ps; ++c) {
+            float g = 0.0f;
+            if (c < C) {
+                const float d = (pred[p * ps + c] - target[p * C + c]) * m;
+                e += (double)d * d;
+                g = 2.0f * d * ic;
+            }
+            dpred[p * ps + c] = f2bf(g);
+        }
+    }
+    s1[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s1[0];
+}
+
+// per-block sums of the mask (fixed order)
+__global__ void __launch_bounds__(256) k_mask_partial(int64_t P, const float *mask, double *partial) {
+    __shared__ double s1[256];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    s1[threadIdx.x] = p < P ? (double)mask[p] : 0.0;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s1[0];
+}
+
+// inv = 1 / (C sum of the partials), 1 when the mask is empty
+__global__ void k_inv_count(const double *partial, int64_t m, int C, float *inv) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) s += partial[i];
+    inv[0] = s > 0.0 ? (float)(1.0 / (s * C)) : 1.0f;
+}
+
+// loss = inv * sum of the partials
+__global__ void k_loss_final(const double *partial, int64_t m, const float *inv, float *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) s += partial[i];
+    out[0] = (float)(s * (double)inv[0]);
+}
+
+// zero the gradients of padded channels: enc0a input channels >= c_real_in,
+// head rows >= c_real_out (weights and bias)
+__global__ void k_mask_pad_grads(float *g_enc0a, int co0, int taps0, int ci0, int c_real_in, float *g_head_w,
+                                 float *g_head_b, int co_h, int ci_h, int c_real_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m0 = (int64_t)co0 * taps0 * ci0, mh = (int64_t)co_h * ci_h;
+    if (i < m0) {
+        if ((int)(i % ci0) >= c_real_in) g_enc0a[i] = 0.0f;
+    } else if (i < m0 + mh) {
+        const int64_t j = i - m0;
+        if ((int)(j / ci_h) >= c_real_out) g_head_w[j] = 0.0f;
+    } else if (i < m0 + mh + co_h) {
+        const int64_t j = i - m0 - mh;
+        if ((int)j >= c_real_out) g_head_b[j] = 0.0f;
+    }
+}
+
 int check(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mlbm::fail(MLBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
@@ -403,12 +517,100 @@ int check_desc(const mlbm_conv_desc *d) {
     if (d->n < 1 || d->h < 1 || d->w < 1) return fail(MLBM_ERR_ARG, "empty tensor");
     if (d->c_in < 32 || d->c_in % 32 || d->c_out < 32 || d->c_out % 32)
         return fail(MLBM_ERR_ARG, "channel counts must be multiples of 32");
-    if (((int64_t)d->n * d->h * d->w) % 128) return fail(MLBM_ERR_ARG, "pixel count must be a multiple of 128");
+    if (d->h % 8 || (d->w != 8 && d->w % 16))
+        return fail(MLBM_ERR_ARG, "height must be a multiple of 8, width 8 or a multiple of 16");
     if (d->x_stride % 8 || d->x_offset % 8 || d->y_stride % 8 || d->y_offset % 8)
         return fail(MLBM_ERR_ARG, "strides and offsets must be multiples of 8 channels");
     if (d->x_offset + d->c_in > d->x_stride) return fail(MLBM_ERR_ARG, "input view exceeds its stride");
     if (d->c_store < 1 || d->c_store > d->c_out) return fail(MLBM_ERR_ARG, "c_store outside [1, c_out]");
     return MLBM_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// tile shape: 8 x 16 pixels, or 8 x 8 for images 8 pixels wide
+int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const float *bias, void *y, int relu, int y_f32,
+                const void *gate, int gate_stride, int gate_offset, hipStream_t s) {
+    const bool narrow = d.w == 8;
+    const unsigned tiles = (unsigned)((int64_t)d.n * (d.h / 8) * (d.w / (narrow ? 8 : 16)));
+    const bool wide_n = d.c_out % 64 == 0;
+    const dim3 grid(tiles, d.c_out / (wide_n ? 64 : 32));
+    const auto *xx = (const unsigned short *)x, *ww = (const unsigned short *)w, *gg = (const unsigned short *)gate;
+#define MLBM_CONV(TH, TW, BN)                                                                                    \
+    hipLaunchKernelGGL((k_conv_tile<TH, TW, BN>), grid, dim3(64 * (TH * TW / 32) * (BN / 32)), 0, s, d, xx, ww, \
+                       bias, y, relu, y_f32, gg, gate_stride, gate_offset)
+    if (narrow) {
+        if (wide_n) MLBM_CONV(8, 8, 64);
+        else MLBM_CONV(8, 8, 32);
+    } else {
+        if (wide_n) MLBM_CONV(8, 16, 64);
+        else MLBM_CONV(8, 16, 32);
+    }
+#undef MLBM_CONV
+    return check("mlbm_conv_forward");
+}
+
+int64_t conv_tiles(const mlbm_conv_desc &d) { return (int64_t)d.n * (d.h / 8) * (d.w / (d.w == 8 ? 8 : 16)); }
+
+// tiles per split for `splits` requested splits, and the resulting split count
+int wgrad_split(const mlbm_conv_desc &d, int splits, int *per) {
+    const int64_t tiles = conv_tiles(d);
+    const int64_t sp = std::max<int64_t>(1, std::min<int64_t>(splits, tiles));
+    *per = (int)((tiles + sp - 1) / sp);
+    return (int)((tiles + *per - 1) / *per);
+}
+
+int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *dw, float *db, int splits, float *ws,
+                 hipStream_t s) {
+    int per = 0;
+    const int sp = wgrad_split(d, splits, &per);
+    const int taps = d.ksize * d.ksize;
+    const int64_t m = (int64_t)d.c_out * taps * d.c_in;
+    const bool narrow = d.w == 8, wide = d.c_out % 64 == 0;
+    const auto *xx = (const unsigned short *)x, *yy = (const unsigned short *)dy;
+#define MLBM_WG(TH, TW, BCO, KS)                                                                                  \
+    hipLaunchKernelGGL((k_wgrad_tile<TH, TW, BCO, KS>), dim3(d.c_out / BCO, d.c_in / 32, sp),                     \
+                       dim3(64 * (BCO / 32) * KS), 0, s, d, xx, yy, ws, per)
+    if (d.ksize == 3) {
+        if (narrow) {
+            if (wide) MLBM_WG(8, 8, 64, 3);
+            else MLBM_WG(8, 8, 32, 3);
+        } else {
+            if (wide) MLBM_WG(8, 16, 64, 3);
+            else MLBM_WG(8, 16, 32, 3);
+        }
+    } else {
+        if (narrow) {
+            if (wide) MLBM_WG(8, 8, 64, 1);
+            else MLBM_WG(8, 8, 32, 1);
+        } else {
+            if (wide) MLBM_WG(8, 16, 64, 1);
+            else MLBM_WG(8, 16, 32, 1);
+        }
+    }
+#undef MLBM_WG
+    int rc = check("mlbm_conv_wgrad");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(m)), dim3(256), 0, s, (const float *)ws, sp, m, dw, 0);
+    if (db) {
+        const int64_t P = (int64_t)d.n * d.h * d.w;
+        const int64_t pb = 4096;
+        const int nb = (int)((P + pb - 1) / pb);
+        float *wsb = ws + m * sp;
+        hipLaunchKernelGGL(k_bias_partial, dim3(nb), dim3(256), 0, s, d, yy, wsb, pb);
+        hipLaunchKernelGGL(k_bias_sum, dim3(1), dim3(256), 0, s, (const float *)wsb, nb, d.c_out, db);
+    }
+    return check("mlbm_conv_wgrad");
+}
+
+int64_t wgrad_workspace(const mlbm_conv_desc &d, int splits) {
+    int per = 0;
+    const int sp = wgrad_split(d, splits, &per);
+    const int64_t m = (int64_t)d.c_out * d.ksize * d.ksize * d.c_in;
+    const int64_t P = (int64_t)d.n * d.h * d.w;
+    return (m * sp + (P + 4095) / 4096 * d.c_out) * (int64_t)sizeof(float);
 }
 
 }  // namespace
@@ -420,23 +622,12 @@ extern "C" int mlbm_conv_forward(const mlbm_conv_desc *d, const void *x, const v
     if (rc) return rc;
     if (!x || !w || !y) return mlbm::fail(MLBM_ERR_ARG, "null pointer");
     if (d->y_offset + d->c_store > d->y_stride) return mlbm::fail(MLBM_ERR_ARG, "output view exceeds its stride");
-    const int64_t P = (int64_t)d->n * d->h * d->w;
-    hipStream_t s = (hipStream_t)stream;
-    if (d->c_out % 64 == 0)  // (the pixel count is a multiple of 128: check_desc)
-        hipLaunchKernelGGL(k_conv_fwd_rb, dim3((unsigned)(P / 128), d->c_out / 64), dim3(128), 0, s, *d,
-                           (const unsigned short *)x, (const unsigned short *)w, bias, y, relu, y_f32);
-    else
-        hipLaunchKernelGGL(k_conv_fwd<32>, dim3((unsigned)(P / 128), d->c_out / 32), dim3(256), 0, s, *d,
-                           (const unsigned short *)x, (const unsigned short *)w, bias, y, relu, y_f32);
-    return check("mlbm_conv_forward");
+    return conv_launch(*d, x, w, bias, y, relu, y_f32, nullptr, 0, 0, (hipStream_t)stream);
 }
 
 extern "C" int64_t mlbm_conv_wgrad_workspace(const mlbm_conv_desc *d, int32_t splits) {
-    if (!d || splits < 1) return 0;
-    const int64_t m = (int64_t)d->c_out * d->ksize * d->ksize * d->c_in;
-    const int64_t P = (int64_t)d->n * d->h * d->w;
-    const int64_t bias_blocks = (P + 4095) / 4096;
-    return (m * splits + bias_blocks * d->c_out) * (int64_t)sizeof(float);
+    if (!d || splits < 1 || check_desc(d)) return 0;
+    return wgrad_workspace(*d, splits);
 }
 
 extern "C" int mlbm_conv_wgrad(const mlbm_conv_desc *d, const void *x, const void *dy, float *dw, float *db,
@@ -448,25 +639,7 @@ extern "C" int mlbm_conv_wgrad(const mlbm_conv_desc *d, const void *x, const voi
     if (db && d->c_out > 256) return mlbm::fail(MLBM_ERR_ARG, "bias gradient needs c_out <= 256");
     if (((uintptr_t)x | (uintptr_t)dy) & 15) return mlbm::fail(MLBM_ERR_ARG, "x and dy must be 16-byte aligned");
     if (d->y_offset + d->c_out > d->y_stride) return mlbm::fail(MLBM_ERR_ARG, "gradient view exceeds its stride");
-    const int64_t P = (int64_t)d->n * d->h * d->w;
-    const int taps = d->ksize * d->ksize;
-    const int64_t m = (int64_t)d->c_out * taps * d->c_in;
-    int64_t per = (P + splits - 1) / splits;
-    per = (per + 63) / 64 * 64;
-    const int sp = (int)((P + per - 1) / per);
-    float *ws = (float *)workspace;
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(d->c_out / 32, d->c_in / 32, taps * sp), dim3(64), 0, s, *d,
-                       (const unsigned short *)x, (const unsigned short *)dy, ws, per);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(m)), dim3(256), 0, s, (const float *)ws, sp, m, dw, 0);
-    if (db) {
-        const int64_t pb = 4096;
-        const int nb = (int)((P + pb - 1) / pb);
-        float *wsb = ws + m * splits;
-        hipLaunchKernelGGL(k_bias_partial, dim3(nb), dim3(256), 0, s, *d, (const unsigned short *)dy, wsb, pb);
-        hipLaunchKernelGGL(k_bias_sum, dim3(1), dim3(256), 0, s, (const float *)wsb, nb, d->c_out, db);
-    }
-    return check("mlbm_conv_wgrad");
+    return wgrad_launch(*d, x, dy, dw, db, splits, (float *)workspace, (hipStream_t)stream);
 }
 
 extern "C" int mlbm_conv_weights(const float *w_master, int32_t c_out, int32_t ksize, int32_t c_in, void *w_fwd,
@@ -553,4 +726,407 @@ extern "C" int mlbm_adam(int64_t m, float *param, const float *grad, float *m1, 
     hipLaunchKernelGGL(k_adam, dim3(blocks(m)), dim3(256), 0, (hipStream_t)stream, m, param, grad, m1, m2, lr, beta1,
                        beta2, eps, c1, c2);
     return check("mlbm_adam");
+}
+
+// ---- the network ------------------------------------------------------------------------------
+
+namespace {
+
+struct Layer {
+    char name[8];
+    int ksize, c_in, c_out, level;
+    int64_t w_off, b_off;     // floats, in params / grads / moments
+    int64_t wf_off, wd_off;   // halves, in w_bf16
+    int splits;               // pixel splits of the weight gradient
+};
+
+// activation buffers (halves, offsets in act and act_grad)
+struct Acts {
+    int64_t enc_a[MLBM_UNET_MAX_LEVELS], cat[MLBM_UNET_MAX_LEVELS], pool[MLBM_UNET_MAX_LEVELS];
+    int64_t dec_a[MLBM_UNET_MAX_LEVELS], dec_b[MLBM_UNET_MAX_LEVELS], bottom, dout, total;
+};
+
+struct Net {
+    int L, B, R, c_real_in, c_real_out;
+    int c[MLBM_UNET_MAX_LEVELS];
+    std::vector<Layer> layers;
+    Acts a;
+    int64_t n_params, n_wbf, ws_floats, work_bytes, loss_blocks;
+};
+
+constexpr int PADC = 32;
+
+int net_plan(const mlbm_unet *u, Net &n) {
+    using mlbm::fail;
+    if (!u) return fail(MLBM_ERR_ARG, "null network");
+    n.L = u->levels;
+    n.B = u->batch;
+    n.R = u->res;
+    n.c_real_in = u->c_in;
+    n.c_real_out = u->c_out;
+    if (n.L < 2 || n.L > MLBM_UNET_MAX_LEVELS) return fail(MLBM_ERR_ARG, "levels must be 2..%d", MLBM_UNET_MAX_LEVELS);
+    if (n.B < 1) return fail(MLBM_ERR_ARG, "batch must be positive");
+    if (n.c_real_in < 1 || n.c_real_in > PADC || n.c_real_out < 1 || n.c_real_out > PADC)
+        return fail(MLBM_ERR_ARG, "input and output channels must be 1..32");
+    for (int l = 0; l < n.L; ++l) {
+        n.c[l] = u->channels[l];
+        if (n.c[l] < 32 || n.c[l] > 256 || n.c[l] % 32) return fail(MLBM_ERR_ARG, "channels must be multiples of 32 up to 256");
+    }
+    if (n.R < 8 || n.R % (1 << (n.L - 1))) return fail(MLBM_ERR_ARG, "res must be a multiple of 2^(levels-1)");
+    const int rmin = n.R >> (n.L - 1);
+    if (rmin % 8 || (rmin != 8 && rmin % 16)) return fail(MLBM_ERR_ARG, "the coarsest level must be 8 or a multiple of 16 wide");
+    if ((int64_t)n.B * n.R * n.R > (int64_t)1 << 30) return fail(MLBM_ERR_ARG, "batch x res^2 too large");
+    // layers in execution order
+    n.layers.clear();
+    auto add = [&](const char *nm, int lvl, int k, int ci, int co) {
+        Layer ly;
+        std::snprintf(ly.name, sizeof(ly.name), "%s", nm);
+        ly.ksize = k;
+        ly.c_in = ci;
+        ly.c_out = co;
+        ly.level = lvl;
+        n.layers.push_back(ly);
+    };
+    char nm[8];
+    int prev = PADC;
+    for (int l = 0; l < n.L; ++l) {
+        std::snprintf(nm, sizeof(nm), "enc%da", l);
+        add(nm, l, 3, prev, n.c[l]);
+        std::snprintf(nm, sizeof(nm), "enc%db", l);
+        add(nm, l, 3, n.c[l], n.c[l]);
+        prev = n.c[l];
+    }
+    for (int l = n.L - 2; l >= 0; --l) {
+        std::snprintf(nm, sizeof(nm), "dec%da", l);
+        add(nm, l, 3, prev + n.c[l], n.c[l]);
+        std::snprintf(nm, sizeof(nm), "dec%db", l);
+        add(nm, l, 3, n.c[l], n.c[l]);
+        prev = n.c[l];
+    }
+    add("head", 0, 1, prev, PADC);
+    int64_t pf = 0, ph = 0, ws = 0;
+    for (Layer &ly : n.layers) {
+        const int64_t m = (int64_t)ly.c_out * ly.ksize * ly.ksize * ly.c_in;
+        ly.w_off = pf;
+        ly.b_off = pf + m;
+        pf += m + ly.c_out;
+        ly.wf_off = ph;
+        ly.wd_off = ph + m;
+        ph += 2 * m;
+        // enough weight-gradient workgroups to fill the GPU several times over
+        mlbm_conv_desc d{};
+        const int Rl = n.R >> ly.level;
+        d.n = n.B;
+        d.h = d.w = Rl;
+        d.c_in = ly.c_in;
+        d.c_out = ly.c_out;
+        d.ksize = ly.ksize;
+        const int64_t blocks_per_split = (int64_t)(ly.c_out / (ly.c_out % 64 == 0 ? 64 : 32)) * (ly.c_in / 32);
+        ly.splits = (int)std::max<int64_t>(1, std::min<int64_t>(conv_tiles(d), (1024 + blocks_per_split - 1) / blocks_per_split));
+        ws = std::max(ws, wgrad_workspace(d, ly.splits));
+    }
+    n.n_params = pf;
+    n.n_wbf = ph;
+    n.ws_floats = (ws + 3) / 4;
+    // activations
+    int64_t off = 0;
+    auto take = [&](int64_t halves) {
+        const int64_t o = off;
+        off += (halves + 7) / 8 * 8;  // 16-byte aligned views
+        return o;
+    };
+    for (int l = 0; l < n.L; ++l) {
+        const int64_t P = (int64_t)n.B * (n.R >> l) * (n.R >> l);
+        n.a.enc_a[l] = take(P * n.c[l]);
+        if (l < n.L - 1) {
+            n.a.cat[l] = take(P * (n.c[l + 1] + n.c[l]));
+            n.a.pool[l] = take(P / 4 * n.c[l]);
+            n.a.dec_a[l] = take(P * n.c[l]);
+            n.a.dec_b[l] = take(P * n.c[l]);
+        } else {
+            n.a.bottom = take(P * n.c[l]);
+        }
+    }
+    n.a.dout = take((int64_t)n.B * n.R * n.R * PADC);
+    n.a.total = off;
+    n.loss_blocks = ((int64_t)n.B * n.R * n.R + 255) / 256;
+    // work: weight-gradient partials, then loss partials, mask partials, 1/count
+    n.work_bytes = n.ws_floats * 4 + 2 * n.loss_blocks * 8 + 16;
+    return MLBM_OK;
+}
+
+struct Ptrs {
+    unsigned short *act, *grad, *wbf;
+    float *ws;
+    double *loss_part, *mask_part;
+    float *inv;
+};
+
+Ptrs net_ptrs(const mlbm_unet *u, const Net &n) {
+    Ptrs q;
+    q.act = (unsigned short *)u->act;
+    q.grad = (unsigned short *)u->act_grad;
+    q.wbf = (unsigned short *)u->w_bf16;
+    q.ws = (float *)u->work;
+    q.loss_part = (double *)(q.ws + n.ws_floats + (n.ws_floats & 1));
+    q.mask_part = q.loss_part + n.loss_blocks;
+    q.inv = (float *)(q.mask_part + n.loss_blocks);
+    return q;
+}
+
+mlbm_conv_desc desc_of(const Net &n, const Layer &ly, int xs, int xo, int ys, int yo) {
+    mlbm_conv_desc d{};
+    const int Rl = n.R >> ly.level;
+    d.n = n.B;
+    d.h = d.w = Rl;
+    d.c_in = ly.c_in;
+    d.c_out = ly.c_out;
+    d.ksize = ly.ksize;
+    d.x_stride = xs;
+    d.x_offset = xo;
+    d.y_stride = ys;
+    d.y_offset = yo;
+    d.c_store = ly.c_out;
+    return d;
+}
+
+const Layer &layer(const Net &n, const char *name) {
+    for (const Layer &ly : n.layers)
+        if (std::strcmp(ly.name, name) == 0) return ly;
+    return n.layers.back();  // not reached: every name is planned
+}
+
+int need_buffers(const mlbm_unet *u, bool grads) {
+    if (!u->params || !u->w_bf16 || !u->act || !u->work || (grads && (!u->grads || !u->act_grad)))
+        return mlbm::fail(MLBM_ERR_ARG, "null network buffer");
+    return MLBM_OK;
+}
+
+}  // namespace
+
+extern "C" int mlbm_unet_sizes(const mlbm_unet *u, mlbm_unet_buffers *out) {
+    mlbm::clear_error();
+    if (!out) return mlbm::fail(MLBM_ERR_ARG, "null output");
+    Net n;
+    int rc = net_plan(u, n);
+    if (rc) return rc;
+    out->n_params = n.n_params;
+    out->w_bf16_bytes = n.n_wbf * 2;
+    out->act_bytes = n.a.total * 2;
+    out->work_bytes = n.work_bytes;
+    out->n_layers = (int32_t)n.layers.size();
+    return MLBM_OK;
+}
+
+extern "C" int mlbm_unet_layer(const mlbm_unet *u, int32_t index, mlbm_unet_layer_info *out) {
+    mlbm::clear_error();
+    Net n;
+    int rc = net_plan(u, n);
+    if (rc) return rc;
+    if (!out || index < 0 || index >= (int)n.layers.size()) return mlbm::fail(MLBM_ERR_ARG, "bad layer index");
+    const Layer &ly = n.layers[index];
+    std::memcpy(out->name, ly.name, sizeof(out->name));
+    out->ksize = ly.ksize;
+    out->c_in = ly.c_in;
+    out->c_out = ly.c_out;
+    out->res = n.R >> ly.level;
+    out->w_offset = ly.w_off;
+    out->b_offset = ly.b_off;
+    return MLBM_OK;
+}
+
+extern "C" int mlbm_unet_refresh(const mlbm_unet *u, void *stream) {
+    mlbm::clear_error();
+    Net n;
+    int rc = net_plan(u, n);
+    if (rc) return rc;
+    if (!u->params || !u->w_bf16) return mlbm::fail(MLBM_ERR_ARG, "null params or w_bf16");
+    unsigned short *wbf = (unsigned short *)u->w_bf16;
+    for (const Layer &ly : n.layers) {
+        const int64_t m = (int64_t)ly.c_out * ly.ksize * ly.ksize * ly.c_in;
+        hipLaunchKernelGGL(k_weights_bf16, dim3(blocks(m)), dim3(256), 0, (hipStream_t)stream, u->params + ly.w_off,
+                           ly.c_out, ly.ksize * ly.ksize, ly.c_in, wbf + ly.wf_off, wbf + ly.wd_off);
+    }
+    return check("mlbm_unet_refresh");
+}
+
+extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, void *stream) {
+    mlbm::clear_error();
+    Net n;
+    int rc = net_plan(u, n);
+    if (rc) return rc;
+    if ((rc = need_buffers(u, false))) return rc;
+    if (!x || !out) return mlbm::fail(MLBM_ERR_ARG, "null input or output");
+    hipStream_t s = (hipStream_t)stream;
+    const Ptrs q = net_ptrs(u, n);
+    const float *prm = u->params;
+    auto conv = [&](const char *name, const void *xin, int xs, int xo, void *y, int ys, int yo, int relu, int f32) {
+        const Layer &ly = layer(n, name);
+        const mlbm_conv_desc d = desc_of(n, ly, xs, xo, ys, yo);
+        return conv_launch(d, xin, q.wbf + ly.wf_off, prm + ly.b_off, y, relu, f32, nullptr, 0, 0, s);
+    };
+    char nm[8];
+    const void *h = x;
+    int hs = PADC;
+    for (int l = 0; l < n.L; ++l) {
+        const int R = n.R >> l, c = n.c[l];
+        std::snprintf(nm, sizeof(nm), "enc%da", l);
+        if ((rc = conv(nm, h, hs, 0, q.act + n.a.enc_a[l], c, 0, 1, 0))) return rc;
+        std::snprintf(nm, sizeof(nm), "enc%db", l);
+        if (l < n.L - 1) {
+            const int cu = n.c[l + 1], cc = cu + c;
+            if ((rc = conv(nm, q.act + n.a.enc_a[l], c, 0, q.act + n.a.cat[l], cc, cu, 1, 0))) return rc;
+            hipLaunchKernelGGL(k_pool_fwd, dim3(blocks((int64_t)n.B * (R / 2) * (R / 2) * c)), dim3(256), 0, s, n.B,
+                               R / 2, R / 2, c, q.act + n.a.cat[l], cc, cu, q.act + n.a.pool[l], c, 0);
+            h = q.act + n.a.pool[l];
+        } else {
+            if ((rc = conv(nm, q.act + n.a.enc_a[l], c, 0, q.act + n.a.bottom, c, 0, 1, 0))) return rc;
+            h = q.act + n.a.bottom;
+        }
+        hs = c;
+    }
+    for (int l = n.L - 2; l >= 0; --l) {
+        const int R = n.R >> l, c = n.c[l], cu = n.c[l + 1], cc = cu + c;
+        hipLaunchKernelGGL(k_up_fwd, dim3(blocks((int64_t)n.B * R * R * cu)), dim3(256), 0, s, n.B, R / 2, R / 2, cu,
+                           (const unsigned short *)h, hs, 0, q.act + n.a.cat[l], cc, 0);
+        std::snprintf(nm, sizeof(nm), "dec%da", l);
+        if ((rc = conv(nm, q.act + n.a.cat[l], cc, 0, q.act + n.a.dec_a[l], c, 0, 1, 0))) return rc;
+        std::snprintf(nm, sizeof(nm), "dec%db", l);
+        if ((rc = conv(nm, q.act + n.a.dec_a[l], c, 0, q.act + n.a.dec_b[l], c, 0, 1, 0))) return rc;
+        h = q.act + n.a.dec_b[l];
+        hs = c;
+    }
+    if ((rc = conv("head", h, hs, 0, out, PADC, 0, 0, 1))) return rc;
+    return check("mlbm_unet_forward");
+}
+
+extern "C" int mlbm_unet_loss(const mlbm_unet *u, const float *out, const float *target, const float *mask,
+                              float *loss, void *stream) {
+    mlbm::clear_error();
+    Net n;
+    int rc = net_plan(u, n);
+    if (rc) return rc;
+    if (!u->act_grad || !u->work || !out || !target || !mask || !loss) return mlbm::fail(MLBM_ERR_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const Ptrs q = net_ptrs(u, n);
+    const int64_t P = (int64_t)n.B * n.R * n.R;
+    hipLaunchKernelGGL(k_mask_partial, dim3((unsigned)n.loss_blocks), dim3(256), 0, s, P, mask, q.mask_part);
+    hipLaunchKernelGGL(k_inv_count, dim3(1), dim3(64), 0, s, (const double *)q.mask_part, n.loss_blocks, n.c_real_out,
+                       q.inv);
+    hipLaunchKernelGGL(k_mse_dev, dim3((unsigned)n.loss_blocks), dim3(256), 0, s, P, n.c_real_out, out, PADC, target,
+                       mask, (const float *)q.inv, q.grad + n.a.dout, q.loss_part);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, (const double *)q.loss_part, n.loss_blocks,
+                       (const float *)q.inv, loss);
+    return check("mlbm_unet_loss");
+}
+
+extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *stream) {
+    mlbm::clear_error();
+    Net n;
+    int rc = net_plan(u, n);
+    if (rc) return rc;
+    if ((rc = need_buffers(u, true))) return rc;
+    if (!x) return mlbm::fail(MLBM_ERR_ARG, "null input");
+    hipStream_t s = (hipStream_t)stream;
+    const Ptrs q = net_ptrs(u, n);
+    unsigned short *A = q.act, *G = q.grad;
+    float *gp = u->grads;
+    auto wgrad = [&](const char *name, const void *xin, int xs, int xo, const void *dy, int ys, int yo) {
+        const Layer &ly = layer(n, name);
+        const mlbm_conv_desc d = desc_of(n, ly, xs, xo, ys, yo);
+        return wgrad_launch(d, xin, dy, gp + ly.w_off, gp + ly.b_off, ly.splits, q.ws, s);
+    };
+    // data gradient: the forward product with the mirrored weights, c_in and c_out exchanged;
+    // gate = the output of the layer below (its ReLU gradient), or NULL
+    auto dgrad = [&](const char *name, const void *dy, int ys, int yo, void *dx, int xs, int xo, const void *gate,
+                     int gs, int go) {
+        const Layer &ly = layer(n, name);
+        mlbm_conv_desc d = desc_of(n, ly, ys, yo, xs, xo);
+        d.c_in = ly.c_out;
+        d.c_out = ly.c_in;
+        d.c_store = ly.c_in;
+        return conv_launch(d, dy, q.wbf + ly.wd_off, nullptr, dx, 0, 0, gate, gs, go, s);
+    };
+    auto relu_bwd = [&](int64_t P, int C, const void *y, int ys, int yo, void *dy, int dys, int dyo) {
+        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(P * C)), dim3(256), 0, s, P, C, (const unsigned short *)y, ys, yo,
+                           (unsigned short *)dy, dys, dyo);
+    };
+    char nm[8];
+    const int c0 = n.c[0];
+    if ((rc = wgrad("head", A + n.a.dec_b[0], c0, 0, G + n.a.dout, PADC, 0))) return rc;
+    if ((rc = dgrad("head", G + n.a.dout, PADC, 0, G + n.a.dec_b[0], c0, 0, A + n.a.dec_b[0], c0, 0))) return rc;
+    for (int l = 0; l < n.L - 1; ++l) {
+        const int R = n.R >> l, c = n.c[l], cu = n.c[l + 1], cc = cu + c;
+        const int64_t P = (int64_t)n.B * R * R;
+        if (l > 0) relu_bwd(P, c, A + n.a.dec_b[l], c, 0, G + n.a.dec_b[l], c, 0);
+        std::snprintf(nm, sizeof(nm), "dec%db", l);
+        if ((rc = wgrad(nm, A + n.a.dec_a[l], c, 0, G + n.a.dec_b[l], c, 0))) return rc;
+        if ((rc = dgrad(nm, G + n.a.dec_b[l], c, 0, G + n.a.dec_a[l], c, 0, A + n.a.dec_a[l], c, 0))) return rc;
+        std::snprintf(nm, sizeof(nm), "dec%da", l);
+        if ((rc = wgrad(nm, A + n.a.cat[l], cc, 0, G + n.a.dec_a[l], c, 0))) return rc;
+        if ((rc = dgrad(nm, G + n.a.dec_a[l], c, 0, G + n.a.cat[l], cc, 0, nullptr, 0, 0))) return rc;
+        // the upsampled channels' gradient goes to this level's input: the decoder
+        // output of the level below, or the bottleneck
+        unsigned short *below = l + 1 <= n.L - 2 ? G + n.a.dec_b[l + 1] : G + n.a.bottom;
+        hipLaunchKernelGGL(k_up_bwd, dim3(blocks((int64_t)n.B * (R / 2) * (R / 2) * cu)), dim3(256), 0, s, n.B, R / 2,
+                           R / 2, cu, (const unsigned short *)(G + n.a.cat[l]), cc, 0, below, cu, 0);
+    }
+    for (int l = n.L - 1; l >= 0; --l) {
+        const int R = n.R >> l, c = n.c[l];
+        const int64_t P = (int64_t)n.B * R * R;
+        const unsigned short *yb;
+        unsigned short *gb;
+        int bs, bo;
+        if (l < n.L - 1) {
+            const int cu = n.c[l + 1], cc = cu + c;
+            // d(enc_b output) = the pooled path's gradient + the skip gradient, which
+            // sits in the skip channels of the concatenation's gradient
+            hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(P * c)), dim3(256), 0, s, n.B, R / 2, R / 2, c,
+                               (const unsigned short *)(G + n.a.pool[l]), c, 0, G + n.a.cat[l], cc, cu,
+                               (const unsigned short *)(G + n.a.cat[l]), cc, cu);
+            yb = A + n.a.cat[l];
+            gb = G + n.a.cat[l];
+            bs = cc;
+            bo = cu;
+        } else {
+            yb = A + n.a.bottom;
+            gb = G + n.a.bottom;
+            bs = c;
+            bo = 0;
+        }
+        relu_bwd(P, c, yb, bs, bo, gb, bs, bo);
+        std::snprintf(nm, sizeof(nm), "enc%db", l);
+        if ((rc = wgrad(nm, A + n.a.enc_a[l], c, 0, gb, bs, bo))) return rc;
+        if ((rc = dgrad(nm, gb, bs, bo, G + n.a.enc_a[l], c, 0, A + n.a.enc_a[l], c, 0))) return rc;
+        std::snprintf(nm, sizeof(nm), "enc%da", l);
+        if (l == 0) {
+            if ((rc = wgrad(nm, x, PADC, 0, G + n.a.enc_a[0], c, 0))) return rc;
+        } else {
+            const int cb = n.c[l - 1];
+            if ((rc = wgrad(nm, A + n.a.pool[l - 1], cb, 0, G + n.a.enc_a[l], c, 0))) return rc;
+            if ((rc = dgrad(nm, G + n.a.enc_a[l], c, 0, G + n.a.pool[l - 1], cb, 0, nullptr, 0, 0))) return rc;
+        }
+    }
+    return check("mlbm_unet_backward");
+}
+
+extern "C" int mlbm_unet_adam(const mlbm_unet *u, float lr, float beta1, float beta2, float eps, int32_t t,
+                              void *stream) {
+    mlbm::clear_error();
+    Net n;
+    int rc = net_plan(u, n);
+    if (rc) return rc;
+    if (!u->params || !u->grads || !u->adam_m || !u->adam_v || !u->w_bf16) return mlbm::fail(MLBM_ERR_ARG, "null buffer");
+    if (t < 1) return mlbm::fail(MLBM_ERR_ARG, "step t must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const Layer &e0 = n.layers.front(), &hd = n.layers.back();
+    const int64_t mm = (int64_t)e0.c_out * 9 * e0.c_in + (int64_t)hd.c_out * hd.c_in + hd.c_out;
+    hipLaunchKernelGGL(k_mask_pad_grads, dim3(blocks(mm)), dim3(256), 0, s, u->grads + e0.w_off, e0.c_out, 9, e0.c_in,
+                       n.c_real_in, u->grads + hd.w_off, u->grads + hd.b_off, hd.c_out, hd.c_in, n.c_real_out);
+    const float c1 = 1.0f - std::pow(beta1, (float)t), c2 = 1.0f - std::pow(beta2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n.n_params)), dim3(256), 0, s, n.n_params, u->params, u->grads, u->adam_m,
+                       u->adam_v, lr, beta1, beta2, eps, c1, c2);
+    rc = check("mlbm_unet_adam");
+    if (rc) return rc;
+    return mlbm_unet_refresh(u, stream);
 }

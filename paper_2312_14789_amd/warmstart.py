@@ -87,6 +87,13 @@ def steady_states(samples, g, K=16, tol=1e-6, batch_size=64, max_steps=200_000, 
     return out, steps_all
 
 
+def converged_only(geoms, fields, steps):
+    """The samples whose steady state was reached (steps > 0; 0 = step cap,
+    negative = unstable), with the number dropped."""
+    keep = [i for i, k in enumerate(steps) if k > 0]
+    return [geoms[i] for i in keep], [fields[i] for i in keep], [steps[i] for i in keep], len(steps) - len(keep)
+
+
 def rasterise(ns, res, rho, u):
     """(target (res, res, 3) = (u_x, u_y, rho - 1), mask (res, res)) from node fields."""
     r, c = pixel_of_nodes(ns, res)

@@ -26,14 +26,17 @@ def test_warm_start_gains_over_rest(W):
     from paper_2312_14789_amd import unet
 
     res, g = 64, 1e-5
-    geoms = W.make_geometries(56, res=res, seed=77, r_range=(0.04, 0.12), workers=4)
-    train_g, test_g = geoms[:48], geoms[48:]
-    fields, steps = W.steady_states(train_g, g, batch_size=48)
-    print(f"[warm] training steady states: steps {min(steps)}..{max(steps)}", flush=True)
-    assert min(steps) > 0
+    # geometries in this process (no workers forked from a process using the GPU)
+    geoms = W.make_geometries(104, res=res, seed=77, r_range=(0.04, 0.12), workers=1)
+    train_g, test_g = geoms[:96], geoms[96:]
+    fields, steps = W.steady_states(train_g, g, batch_size=96)
+    train_g, fields, steps, dropped = W.converged_only(train_g, fields, steps)
+    print(f"[warm] training steady states: steps {min(steps)}..{max(steps)}, {dropped} not converged", flush=True)
+    assert dropped == 0
     data = W.Dataset(train_g, fields, res)
-    net = unet.UNet((32, 64, 128, 256, 256), res=res, batch=8, seed=1)
-    hist = W.train(net, data, epochs=40, lr=2e-3)
+    # four levels: the coarsest is 8 pixels wide at res 64
+    net = unet.UNet((32, 64, 128, 256), res=res, batch=8, seed=1)
+    hist = W.train(net, data, epochs=60, lr=2e-3)
     print(f"[warm] loss {hist[0]:.4f} -> {hist[-1]:.4f}", flush=True)
     assert hist[-1] < 0.3 * hist[0]
     t0 = time.perf_counter()
@@ -47,4 +50,7 @@ def test_warm_start_gains_over_rest(W):
         assert rel <= 5e-3
         gains.append(r["rest"]["steps"] / r["warm"]["steps"])
     print(f"[warm] mean step ratio rest/warm {np.mean(gains):.2f}", flush=True)
-    assert np.mean(gains) > 1.0
+    # the residual decays at the rate of the slowest mode, so the steps saved
+    # grow with the logarithm of the prediction's accuracy: a few per cent
+    # here, at this small training set
+    assert np.mean(gains) >= 1.05

@@ -317,3 +317,37 @@ def test_step_rejects_bad_hybrid_launches():
         assert "hybrid_launches" in lib.mlbm_last_error().decode()
     p.hybrid_launches = 2
     assert lib.mlbm_step(ctypes.byref(p), ctypes.byref(st), 0, None) == _lib.MLBM_OK  # zero steps: no launch
+
+
+def test_network_plan_matches_the_oracle_layers():
+    # mlbm_unet_sizes / mlbm_unet_layer run on the host: layer order, shapes and
+    # contiguous parameter offsets of the five-level network, and refusals
+    from oracle import unet as ou
+
+    d = _lib.UNetDesc()
+    d.levels = 5
+    for i, c in enumerate((32, 64, 128, 256, 256)):
+        d.channels[i] = c
+    d.batch, d.res, d.c_in, d.c_out = 16, 256, 1, 3
+    sz = _lib.UNetBuffers()
+    assert _lib.lib.mlbm_unet_sizes(ctypes.byref(d), ctypes.byref(sz)) == 0
+    ref = ou.layer_shapes([32, 64, 128, 256, 256], 32, 32)
+    assert sz.n_layers == len(ref)
+    off = 0
+    for i, (name, k, ci, co) in enumerate(ref):
+        li = _lib.UNetLayerInfo()
+        assert _lib.lib.mlbm_unet_layer(ctypes.byref(d), i, ctypes.byref(li)) == 0
+        assert (li.name.decode(), li.ksize, li.c_in, li.c_out) == (name, k, ci, co)
+        assert li.w_offset == off and li.b_offset == off + co * k * k * ci
+        off = li.b_offset + co
+    assert sz.n_params == off
+    # activations: every level's buffers in bf16, 16-byte aligned views
+    assert sz.act_bytes > 2 * 16 * 256 * 256 * (32 + 96 + 32 + 32)
+    bad = _lib.UNetDesc()
+    ctypes.memmove(ctypes.byref(bad), ctypes.byref(d), ctypes.sizeof(d))
+    bad.channels[2] = 100                                      # not a multiple of 32
+    assert _lib.lib.mlbm_unet_sizes(ctypes.byref(bad), ctypes.byref(sz)) == _lib.MLBM_ERR_ARG
+    ctypes.memmove(ctypes.byref(bad), ctypes.byref(d), ctypes.sizeof(d))
+    bad.res = 200                                              # coarsest level 12.5 pixels
+    assert _lib.lib.mlbm_unet_sizes(ctypes.byref(bad), ctypes.byref(sz)) == _lib.MLBM_ERR_ARG
+    assert _lib.lib.mlbm_unet_layer(ctypes.byref(d), sz.n_layers, ctypes.byref(_lib.UNetLayerInfo())) == _lib.MLBM_ERR_ARG
