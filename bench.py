@@ -752,6 +752,62 @@ def warmstart_workload(args, np, torch):
                      "steps_min_max": [int(min(steps)), int(max(steps))], "unconverged_dropped": dropped}}
 
 
+def unet_workload(np, torch, steps=20, warmup=3):
+    """The warm-start network's own throughput at its training shape (5
+    levels, 32-256 channels, 256^2 rasters, batch 16) on synthetic masks:
+    milliseconds and TFLOP/s of a training iteration (forward, loss,
+    backward, Adam) and of a forward pass, against the 2.5 PFLOP/s dense bf16
+    peak.  FLOPs: 2 k^2 c_in c_out per output pixel per convolution; a
+    training iteration counts three such products (forward, data gradient,
+    weight gradient)."""
+    from paper_2312_14789_amd import unet
+
+    res, B = 256, 16
+    net = unet.UNet((32, 64, 128, 256, 256), res=res, batch=B, seed=1)
+    rng = np.random.default_rng(0)
+    x = torch.zeros((B, res, res, unet.PAD), dtype=torch.bfloat16, device="cuda")
+    fluid = (rng.uniform(size=(B, res, res)) > 0.3).astype(np.float32)
+    x[..., 0] = torch.from_numpy(fluid).cuda().to(torch.bfloat16)
+    xi = x.view(torch.int16)
+    target = torch.from_numpy(rng.normal(size=(B, res, res, 3)).astype(np.float32)).cuda()
+    mask = torch.from_numpy(fluid).cuda()
+
+    def iteration():
+        net.forward(xi)
+        net.loss_and_grad(target, mask)
+        net.backward()
+        net.adam_step(1e-4)
+
+    fl = 0.0
+    for name, k, ci, co in net.shapes:
+        R = res >> (int(name[3]) if name != "head" else 0)
+        fl += 2.0 * k * k * ci * co * R * R * B
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(warmup):
+        iteration()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        iteration()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_it = e0.elapsed_time(e1) / 1e3 / steps
+    e0.record(stream)
+    for _ in range(steps):
+        net.forward(xi)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_fw = e0.elapsed_time(e1) / 1e3 / steps
+    return {"metric": "warm-start network throughput (bf16 MFMA, FP32 accumulation)",
+            "workload": f"5-level encoder-decoder (32-256 channels), {res}^2 rasters, batch {B}, synthetic masks",
+            "train_ms_per_iter": round(t_it * 1e3, 3), "train_TFLOPs": round(3 * fl / t_it / 1e12, 1),
+            "forward_ms": round(t_fw * 1e3, 3), "forward_TFLOPs": round(fl / t_fw / 1e12, 1),
+            "inference_ms_per_sample": round(t_fw / B * 1e3, 4), "gflop_forward": round(fl / 1e9, 1),
+            "peak_TFLOPs_bf16": 2500.0, "frac_train": round(3 * fl / t_it / 1e12 / 2500.0, 4),
+            "frac_forward": round(fl / t_fw / 1e12 / 2500.0, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -785,13 +841,15 @@ def main():
                     help="skip the FP64 row and the large (beyond the memory-side cache) Karman set")
     ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
     ap.add_argument("--workload", default="karman",
-                    choices=["karman", "porous", "batched", "batched-intervals", "warmstart", "darcy", "strouhal"],
+                    choices=["karman", "porous", "batched", "batched-intervals", "warmstart", "darcy", "strouhal",
+                             "unet"],
                     help="karman: the fused-step throughput line; porous: the MLBM1 step on the 1e6-node "
                          "porous sample; batched: 64 porous samples to steady "
                          "state; batched-intervals: the same batch timed per 100-step interval, by phase; "
                          "warmstart: train the warm-start network and compare time to steady state; "
                          "darcy: mean velocity and tortuosity of the porous channel over a sweep of dx; "
-                         "strouhal: the paper's cylinder channel, St from the lift over Re 105-168")
+                         "strouhal: the paper's cylinder channel, St from the lift over Re 105-168; "
+                         "unet: training and inference throughput of the warm-start network")
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-test", type=int, default=200)
     ap.add_argument("--ws-epochs", type=int, default=20)
@@ -825,6 +883,9 @@ def main():
         return
     if args.workload == "warmstart":
         print(json.dumps(warmstart_workload(args, np, torch)), flush=True)
+        return
+    if args.workload == "unet":
+        print(json.dumps(unet_workload(np, torch, steps=args.steps, warmup=args.warmup)), flush=True)
         return
     if args.workload == "porous":
         print(json.dumps(porous_throughput(args, M, units, nodesets, np, torch)), flush=True)

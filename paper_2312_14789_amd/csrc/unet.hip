@@ -151,7 +151,7 @@ constexpr int XTS = 16 * 10 + 8;  // halves per channel of a transposed halo cop
 template <int TH, int TW, int BCO, int KS>
 __global__ void __launch_bounds__(64 * (BCO / 32) * KS)
     k_wgrad_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
-                 float *__restrict__ ws, int tiles_per_split) {
+                 float *__restrict__ ws, float *__restrict__ wsb, int tiles_per_split) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / 32) * KS, PP = BM + 8;
     static_assert(HH <= 10 && TW <= 16, "transposed halo copies hold up to 10 rows of 16");
     __shared__ __align__(16) unsigned short dyT[BCO * PP];
@@ -168,6 +168,9 @@ __global__ void __launch_bounds__(64 * (BCO / 32) * KS)
     f32x16 acc[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) acc[s] = f32x16{};
+    // bias gradient: the first input-channel block's workgroups also sum dy over their pixels
+    const bool bias_sum = wsb && blockIdx.y == 0 && (int)threadIdx.x < BCO;
+    float bsum = 0.0f;
     for (int tile = ta; tile < tb; ++tile) {
         const int n = tile / tiles_img, rem = tile % tiles_img;
         const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
@@ -197,6 +200,14 @@ __global__ void __launch_bounds__(64 * (BCO / 32) * KS)
             *(u4 *)&xs[hp * XP + 8 * q] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
         }
         __syncthreads();
+        if (bias_sum) {
+#pragma unroll
+            for (int p8 = 0; p8 < BM; p8 += 8) {
+                const u4 v = *(const u4 *)&dyT[threadIdx.x * PP + p8];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) bsum += bf2f((unsigned short)(v[k] & 0xffffu)) + bf2f((unsigned short)(v[k] >> 16));
+            }
+        }
         // transposed copies: copy s holds halo columns (s + c), c < TW (KS = 1: the centre column c + 1)
         for (int it = threadIdx.x; it < KS * 4 * HH * (TW / 8); it += NT) {
             const int cg = it % (TW / 8), rest = it / (TW / 8);
@@ -224,6 +235,7 @@ __global__ void __launch_bounds__(64 * (BCO / 32) * KS)
             }
         }
     }
+    if (bias_sum) wsb[(int64_t)split * d.c_out + co0 + threadIdx.x] = bsum;
     const int ci = ci0 + row;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -236,57 +248,35 @@ __global__ void __launch_bounds__(64 * (BCO / 32) * KS)
     }
 }
 
-// sum of the split partials in a fixed order; dw[c_out][taps][c_in]
-__global__ void k_sum_splits(const float *ws, int splits, int64_t m, float *dw, int accumulate) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+// sum of the split partials, dw[c_out][taps][c_in]: G lanes per element, lane
+// group g sums splits g, g + G, ..., then the G sums are added in a fixed tree
+// order (deterministic)
+template <int G>
+__global__ void __launch_bounds__(64 * G) k_sum_splits_g(const float *__restrict__ ws, int splits, int64_t m,
+                                                        float *__restrict__ dw) {
+    __shared__ float part[G][64];
+    const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + e;
     float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += ws[(int64_t)k * m + i];
-    dw[i] = accumulate ? dw[i] + s : s;
-}
-
-// bias gradient: per-channel sums of dy in a fixed order (partials per block)
-// Partial bias gradient of px_per_block pixels: thread t reads channels
-// 8 (t % G) .. 8 (t % G) + 7 (one 16-byte load) of every (256 / G)-th pixel,
-// G = c_out / 8 channel groups; the rows of the block are then summed per
-// channel through LDS in a fixed order (deterministic).  c_out <= 256.
-__global__ void __launch_bounds__(256) k_bias_partial(mlbm_conv_desc d, const unsigned short *dy, float *ws,
-                                                     int64_t px_per_block) {
-    __shared__ float red[256][9];
-    const int G = d.c_out >> 3, rows = (int)blockDim.x / G;
-    const int g = (int)threadIdx.x % G, r = (int)threadIdx.x / G;
-    const int64_t P = (int64_t)d.n * d.h * d.w;
-    const int64_t a = blockIdx.x * px_per_block, b = min(P, a + px_per_block);
-    float s[8] = {};
-    if (r < rows) {
-#pragma unroll 4
-        for (int64_t p = a + r; p < b; p += rows) {
-            const u4 v = *(const u4 *)(dy + p * d.y_stride + d.y_offset + 8 * g);
-            const unsigned h[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                s[2 * k] += __uint_as_float(h[k] << 16);
-                s[2 * k + 1] += __uint_as_float(h[k] & 0xffff0000u);
-            }
-        }
+    if (i < m) {
+#pragma unroll 8
+        for (int k = g; k < splits; k += G) s += ws[(int64_t)k * m + i];
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = s[k];
+    part[g][e] = s;
     __syncthreads();
-    const int c = threadIdx.x;
-    if (c < d.c_out) {
-        float acc = 0.0f;
-        for (int rr = 0; rr < rows; ++rr) acc += red[rr * G + (c >> 3)][c & 7];
-        ws[(int64_t)blockIdx.x * d.c_out + c] = acc;
+#pragma unroll
+    for (int h = G / 2; h > 0; h >>= 1) {
+        if (g < h) part[g][e] += part[g + h][e];
+        __syncthreads();
     }
+    if (g == 0 && i < m) dw[i] = part[0][e];
 }
 
-__global__ void k_bias_sum(const float *ws, int blocks, int c_out, float *db) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c_out) return;
-    float s = 0.0f;
-    for (int k = 0; k < blocks; ++k) s += ws[(int64_t)k * c_out + c];
-    db[c] = s;
+void sum_splits(const float *ws, int splits, int64_t m, float *dw, hipStream_t s) {
+    const dim3 grid((unsigned)((m + 63) / 64));
+    if (splits >= 64) hipLaunchKernelGGL(k_sum_splits_g<16>, grid, dim3(1024), 0, s, ws, splits, m, dw);
+    else if (splits >= 8) hipLaunchKernelGGL(k_sum_splits_g<4>, grid, dim3(256), 0, s, ws, splits, m, dw);
+    else hipLaunchKernelGGL(k_sum_splits_g<1>, grid, dim3(64), 0, s, ws, splits, m, dw);
 }
 
 // ---- weights: FP32 master -> bf16 forward layout and flipped data-gradient layout ------
@@ -379,6 +369,127 @@ __global__ void k_up_bwd(int n, int h, int w, int C, const unsigned short *dy, i
     dx[q * dxs + dxo + c] = f2bf(s);
 }
 
+// ---- the same layers on 8 channels per thread (16-byte loads and stores) -----------------
+// Used when the channel count, strides and offsets are multiples of 8.
+__device__ __forceinline__ void unpack8(u4 v, float f[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = __uint_as_float(v[k] << 16);
+        f[2 * k + 1] = __uint_as_float(v[k] & 0xffff0000u);
+    }
+}
+__device__ __forceinline__ u4 pack8(const float f[8]) {
+    u4 v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (unsigned)f2bf(f[2 * k]) | ((unsigned)f2bf(f[2 * k + 1]) << 16);
+    return v;
+}
+
+__global__ void k_relu_bwd_v8(int64_t P, int C8, const unsigned short *y, int y_stride, int y_offset,
+                              unsigned short *dy, int dy_stride, int dy_offset) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * C8) return;
+    const int64_t p = i / C8;
+    const int c = (int)(i - p * C8) * 8;
+    const u4 yv = *(const u4 *)(y + p * y_stride + y_offset + c);
+    u4 *dp = (u4 *)(dy + p * dy_stride + dy_offset + c);
+    u4 g = *dp;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned keep_lo = __uint_as_float(yv[k] << 16) > 0.0f ? 0x0000ffffu : 0u;
+        const unsigned keep_hi = __uint_as_float(yv[k] & 0xffff0000u) > 0.0f ? 0xffff0000u : 0u;
+        g[k] &= keep_lo | keep_hi;
+    }
+    *dp = g;
+}
+
+__global__ void k_pool_fwd_v8(int n, int h, int w, int C8, const unsigned short *x, int xs, int xo, unsigned short *y,
+                              int ys, int yo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)n * h * w * C8;
+    if (i >= tot) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
+    const int xx = (int)(q % w), yy = (int)((q / w) % h);
+    const int64_t nn = q / ((int64_t)w * h);
+    const int W2 = 2 * w;
+    const int64_t b = (nn * 2 * h + 2 * yy) * W2 + 2 * xx;
+    float a[8], t[8];
+    unpack8(*(const u4 *)(x + b * xs + xo + c), a);
+    unpack8(*(const u4 *)(x + (b + 1) * xs + xo + c), t);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += t[k];
+    unpack8(*(const u4 *)(x + (b + W2) * xs + xo + c), t);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += t[k];
+    unpack8(*(const u4 *)(x + (b + W2 + 1) * xs + xo + c), t);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = 0.25f * (a[k] + t[k]);
+    *(u4 *)(y + q * ys + yo + c) = pack8(a);
+}
+
+__global__ void k_pool_bwd_v8(int n, int h, int w, int C8, const unsigned short *dy, int dys, int dyo, unsigned short *dx,
+                              int dxs, int dxo, const unsigned short *add, int as, int ao) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)n * 4 * h * w * C8;
+    if (i >= tot) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
+    const int W2 = 2 * w;
+    const int xx = (int)(q % W2), yy = (int)((q / W2) % (2 * h));
+    const int64_t nn = q / ((int64_t)W2 * 2 * h);
+    const int64_t src = (nn * h + yy / 2) * w + xx / 2;
+    float v[8], a[8];
+    unpack8(*(const u4 *)(dy + src * dys + dyo + c), v);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] *= 0.25f;
+    if (add) {
+        unpack8(*(const u4 *)(add + q * as + ao + c), a);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] += a[k];
+    }
+    *(u4 *)(dx + q * dxs + dxo + c) = pack8(v);
+}
+
+__global__ void k_up_fwd_v8(int n, int h, int w, int C8, const unsigned short *x, int xs, int xo, unsigned short *y,
+                            int ys, int yo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)n * 4 * h * w * C8;
+    if (i >= tot) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
+    const int W2 = 2 * w;
+    const int xx = (int)(q % W2), yy = (int)((q / W2) % (2 * h));
+    const int64_t nn = q / ((int64_t)W2 * 2 * h);
+    const int64_t src = (nn * h + yy / 2) * w + xx / 2;
+    *(u4 *)(y + q * ys + yo + c) = *(const u4 *)(x + src * xs + xo + c);
+}
+
+__global__ void k_up_bwd_v8(int n, int h, int w, int C8, const unsigned short *dy, int dys, int dyo, unsigned short *dx,
+                            int dxs, int dxo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)n * h * w * C8;
+    if (i >= tot) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
+    const int xx = (int)(q % w), yy = (int)((q / w) % h);
+    const int64_t nn = q / ((int64_t)w * h);
+    const int W2 = 2 * w;
+    const int64_t b = (nn * 2 * h + 2 * yy) * W2 + 2 * xx;
+    float a[8], t[8];
+    unpack8(*(const u4 *)(dy + b * dys + dyo + c), a);
+    unpack8(*(const u4 *)(dy + (b + 1) * dys + dyo + c), t);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += t[k];
+    unpack8(*(const u4 *)(dy + (b + W2) * dys + dyo + c), t);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += t[k];
+    unpack8(*(const u4 *)(dy + (b + W2 + 1) * dys + dyo + c), t);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += t[k];
+    *(u4 *)(dx + q * dxs + dxo + c) = pack8(a);
+}
+
 // masked MSE over the first C channels of pred (fp32 [P][ps]): per-block partial
 // sums of the squared error and of the mask, and dpred (bf16 [P][ps], zero past C)
 __global__ void __launch_bounds__(256) k_mse(int64_t P, int C, const float *pred, int ps, const float *target,
@@ -427,7 +538,8 @@ __global__ void k_adam(int64_t m, float *p, const float *g, float *mo, float *vo
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// masked MSE with the normalisation 1 / (C sum mask) read from the device
+// masked MSE with the normalisation 1 / (C sum mask) read from the device;
+// pred FP32 [P][ps], dpred bf16 [P][ps] (ps a multiple of 8, zero past C)
 __global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *pred, int ps, const float *target,
                                                 const float *mask, const float *inv_count, unsigned short *dpred,
                                                 double *partial) {
@@ -437,14 +549,15 @@ __global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *
     double e = 0.0;
     if (p < P) {
         const float m = mask[p];
-        for (int c = 0; c < ps; ++c) {
-            float g = 0.0f;
-            if (c < C) {
+        for (int c8 = 0; c8 < ps; c8 += 8) {
+            unsigned w[4] = {0u, 0u, 0u, 0u};
+            for (int j = 0; j < 8 && c8 + j < C; ++j) {
+                const int c = c8 + j;
                 const float d = (pred[p * ps + c] - target[p * C + c]) * m;
                 e += (double)d * d;
-                g = 2.0f * d * ic;
+                w[j >> 1] |= (unsigned)f2bf(2.0f * d * ic) << (16 * (j & 1));
             }
-            dpred[p * ps + c] = f2bf(g);
+            *(u4 *)(dpred + p * ps + c8) = u4{w[0], w[1], w[2], w[3]};
         }
     }
     s1[threadIdx.x] = e;
@@ -469,20 +582,30 @@ __global__ void __launch_bounds__(256) k_mask_partial(int64_t P, const float *ma
     if (threadIdx.x == 0) partial[blockIdx.x] = s1[0];
 }
 
-// inv = 1 / (C sum of the partials), 1 when the mask is empty
-__global__ void k_inv_count(const double *partial, int64_t m, int C, float *inv) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// sum of m partials by one block of 256 threads in a fixed order
+__device__ double block_sum_partials(const double *partial, int64_t m) {
+    __shared__ double t[256];
     double s = 0.0;
-    for (int64_t i = 0; i < m; ++i) s += partial[i];
-    inv[0] = s > 0.0 ? (float)(1.0 / (s * C)) : 1.0f;
+    for (int64_t i = threadIdx.x; i < m; i += 256) s += partial[i];
+    t[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) t[threadIdx.x] += t[threadIdx.x + o];
+        __syncthreads();
+    }
+    return t[0];
+}
+
+// inv = 1 / (C sum of the partials), 1 when the mask is empty
+__global__ void __launch_bounds__(256) k_inv_count(const double *partial, int64_t m, int C, float *inv) {
+    const double s = block_sum_partials(partial, m);
+    if (threadIdx.x == 0) inv[0] = s > 0.0 ? (float)(1.0 / (s * C)) : 1.0f;
 }
 
 // loss = inv * sum of the partials
-__global__ void k_loss_final(const double *partial, int64_t m, const float *inv, float *out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int64_t i = 0; i < m; ++i) s += partial[i];
-    out[0] = (float)(s * (double)inv[0]);
+__global__ void __launch_bounds__(256) k_loss_final(const double *partial, int64_t m, const float *inv, float *out) {
+    const double s = block_sum_partials(partial, m);
+    if (threadIdx.x == 0) out[0] = (float)(s * (double)inv[0]);
 }
 
 // zero the gradients of padded channels: enc0a input channels >= c_real_in,
@@ -570,9 +693,10 @@ int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *
     const int64_t m = (int64_t)d.c_out * taps * d.c_in;
     const bool narrow = d.w == 8, wide = d.c_out % 64 == 0;
     const auto *xx = (const unsigned short *)x, *yy = (const unsigned short *)dy;
+    float *wsb = db ? ws + m * sp : nullptr;  // bias partials [split][c_out]
 #define MLBM_WG(TH, TW, BCO, KS)                                                                                  \
     hipLaunchKernelGGL((k_wgrad_tile<TH, TW, BCO, KS>), dim3(d.c_out / BCO, d.c_in / 32, sp),                     \
-                       dim3(64 * (BCO / 32) * KS), 0, s, d, xx, yy, ws, per)
+                       dim3(64 * (BCO / 32) * KS), 0, s, d, xx, yy, ws, wsb, per)
     if (d.ksize == 3) {
         if (narrow) {
             if (wide) MLBM_WG(8, 8, 64, 3);
@@ -593,15 +717,8 @@ int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *
 #undef MLBM_WG
     int rc = check("mlbm_conv_wgrad");
     if (rc) return rc;
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(m)), dim3(256), 0, s, (const float *)ws, sp, m, dw, 0);
-    if (db) {
-        const int64_t P = (int64_t)d.n * d.h * d.w;
-        const int64_t pb = 4096;
-        const int nb = (int)((P + pb - 1) / pb);
-        float *wsb = ws + m * sp;
-        hipLaunchKernelGGL(k_bias_partial, dim3(nb), dim3(256), 0, s, d, yy, wsb, pb);
-        hipLaunchKernelGGL(k_bias_sum, dim3(1), dim3(256), 0, s, (const float *)wsb, nb, d.c_out, db);
-    }
+    sum_splits(ws, sp, m, dw, s);
+    if (db) sum_splits(wsb, sp, d.c_out, db, s);
     return check("mlbm_conv_wgrad");
 }
 
@@ -609,8 +726,58 @@ int64_t wgrad_workspace(const mlbm_conv_desc &d, int splits) {
     int per = 0;
     const int sp = wgrad_split(d, splits, &per);
     const int64_t m = (int64_t)d.c_out * d.ksize * d.ksize * d.c_in;
-    const int64_t P = (int64_t)d.n * d.h * d.w;
-    return (m * sp + (P + 4095) / 4096 * d.c_out) * (int64_t)sizeof(float);
+    return (m + d.c_out) * sp * (int64_t)sizeof(float);
+}
+
+// 8-channel paths when every channel count, stride and offset is a multiple of 8
+bool v8(int c, int a, int b, int e, int f) { return ((c | a | b | e | f) & 7) == 0; }
+
+void relu_bwd_launch(int64_t P, int C, const unsigned short *y, int ys, int yo, unsigned short *dy, int dys, int dyo,
+                     hipStream_t s) {
+    if (v8(C, ys, yo, dys, dyo))
+        hipLaunchKernelGGL(k_relu_bwd_v8, dim3(blocks(P * (C / 8))), dim3(256), 0, s, P, C / 8, y, ys, yo, dy, dys, dyo);
+    else
+        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(P * C)), dim3(256), 0, s, P, C, y, ys, yo, dy, dys, dyo);
+}
+
+void pool_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs, int xo, unsigned short *y, int ys,
+                     int yo, hipStream_t s) {
+    if (v8(c, xs, xo, ys, yo))
+        hipLaunchKernelGGL(k_pool_fwd_v8, dim3(blocks((int64_t)n * h * w * (c / 8))), dim3(256), 0, s, n, h, w, c / 8, x,
+                           xs, xo, y, ys, yo);
+    else
+        hipLaunchKernelGGL(k_pool_fwd, dim3(blocks((int64_t)n * h * w * c)), dim3(256), 0, s, n, h, w, c, x, xs, xo, y,
+                           ys, yo);
+}
+
+void pool_bwd_launch(int n, int h, int w, int c, const unsigned short *dy, int dys, int dyo, unsigned short *dx, int dxs,
+                     int dxo, const unsigned short *add, int as, int ao, hipStream_t s) {
+    if (v8(c, dys, dyo, dxs, dxo) && (!add || v8(as, ao, 0, 0, 0)))
+        hipLaunchKernelGGL(k_pool_bwd_v8, dim3(blocks((int64_t)n * 4 * h * w * (c / 8))), dim3(256), 0, s, n, h, w,
+                           c / 8, dy, dys, dyo, dx, dxs, dxo, add, as, ao);
+    else
+        hipLaunchKernelGGL(k_pool_bwd, dim3(blocks((int64_t)n * 4 * h * w * c)), dim3(256), 0, s, n, h, w, c, dy, dys,
+                           dyo, dx, dxs, dxo, add, as, ao);
+}
+
+void up_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs, int xo, unsigned short *y, int ys,
+                   int yo, hipStream_t s) {
+    if (v8(c, xs, xo, ys, yo))
+        hipLaunchKernelGGL(k_up_fwd_v8, dim3(blocks((int64_t)n * 4 * h * w * (c / 8))), dim3(256), 0, s, n, h, w, c / 8,
+                           x, xs, xo, y, ys, yo);
+    else
+        hipLaunchKernelGGL(k_up_fwd, dim3(blocks((int64_t)n * 4 * h * w * c)), dim3(256), 0, s, n, h, w, c, x, xs, xo,
+                           y, ys, yo);
+}
+
+void up_bwd_launch(int n, int h, int w, int c, const unsigned short *dy, int dys, int dyo, unsigned short *dx, int dxs,
+                   int dxo, hipStream_t s) {
+    if (v8(c, dys, dyo, dxs, dxo))
+        hipLaunchKernelGGL(k_up_bwd_v8, dim3(blocks((int64_t)n * h * w * (c / 8))), dim3(256), 0, s, n, h, w, c / 8, dy,
+                           dys, dyo, dx, dxs, dxo);
+    else
+        hipLaunchKernelGGL(k_up_bwd, dim3(blocks((int64_t)n * h * w * c)), dim3(256), 0, s, n, h, w, c, dy, dys, dyo, dx,
+                           dxs, dxo);
 }
 
 }  // namespace
@@ -657,9 +824,8 @@ extern "C" int mlbm_relu_backward(int64_t pixels, int32_t channels, const void *
                                   void *dy, int32_t dy_stride, int32_t dy_offset, void *stream) {
     mlbm::clear_error();
     if (!y || !dy || pixels < 1 || channels < 1) return mlbm::fail(MLBM_ERR_ARG, "bad arguments");
-    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(pixels * channels)), dim3(256), 0, (hipStream_t)stream, pixels,
-                       channels, (const unsigned short *)y, y_stride, y_offset, (unsigned short *)dy, dy_stride,
-                       dy_offset);
+    relu_bwd_launch(pixels, channels, (const unsigned short *)y, y_stride, y_offset, (unsigned short *)dy, dy_stride,
+                    dy_offset, (hipStream_t)stream);
     return check("mlbm_relu_backward");
 }
 
@@ -667,8 +833,7 @@ extern "C" int mlbm_pool_forward(int32_t n, int32_t h, int32_t w, int32_t c, con
                                  void *y, int32_t ys, int32_t yo, void *stream) {
     mlbm::clear_error();
     if (!x || !y || n < 1 || h < 1 || w < 1 || c < 1) return mlbm::fail(MLBM_ERR_ARG, "bad arguments");
-    hipLaunchKernelGGL(k_pool_fwd, dim3(blocks((int64_t)n * h * w * c)), dim3(256), 0, (hipStream_t)stream, n, h, w, c,
-                       (const unsigned short *)x, xs, xo, (unsigned short *)y, ys, yo);
+    pool_fwd_launch(n, h, w, c, (const unsigned short *)x, xs, xo, (unsigned short *)y, ys, yo, (hipStream_t)stream);
     return check("mlbm_pool_forward");
 }
 
@@ -677,9 +842,8 @@ extern "C" int mlbm_pool_backward(int32_t n, int32_t h, int32_t w, int32_t c, co
                                   int32_t ao, void *stream) {
     mlbm::clear_error();
     if (!dy || !dx || n < 1 || h < 1 || w < 1 || c < 1) return mlbm::fail(MLBM_ERR_ARG, "bad arguments");
-    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks((int64_t)n * 4 * h * w * c)), dim3(256), 0, (hipStream_t)stream, n, h,
-                       w, c, (const unsigned short *)dy, dys, dyo, (unsigned short *)dx, dxs, dxo,
-                       (const unsigned short *)add, as, ao);
+    pool_bwd_launch(n, h, w, c, (const unsigned short *)dy, dys, dyo, (unsigned short *)dx, dxs, dxo,
+                    (const unsigned short *)add, as, ao, (hipStream_t)stream);
     return check("mlbm_pool_backward");
 }
 
@@ -687,8 +851,7 @@ extern "C" int mlbm_upsample_forward(int32_t n, int32_t h, int32_t w, int32_t c,
                                      int32_t xo, void *y, int32_t ys, int32_t yo, void *stream) {
     mlbm::clear_error();
     if (!x || !y || n < 1 || h < 1 || w < 1 || c < 1) return mlbm::fail(MLBM_ERR_ARG, "bad arguments");
-    hipLaunchKernelGGL(k_up_fwd, dim3(blocks((int64_t)n * 4 * h * w * c)), dim3(256), 0, (hipStream_t)stream, n, h, w,
-                       c, (const unsigned short *)x, xs, xo, (unsigned short *)y, ys, yo);
+    up_fwd_launch(n, h, w, c, (const unsigned short *)x, xs, xo, (unsigned short *)y, ys, yo, (hipStream_t)stream);
     return check("mlbm_upsample_forward");
 }
 
@@ -696,8 +859,7 @@ extern "C" int mlbm_upsample_backward(int32_t n, int32_t h, int32_t w, int32_t c
                                       int32_t dyo, void *dx, int32_t dxs, int32_t dxo, void *stream) {
     mlbm::clear_error();
     if (!dy || !dx || n < 1 || h < 1 || w < 1 || c < 1) return mlbm::fail(MLBM_ERR_ARG, "bad arguments");
-    hipLaunchKernelGGL(k_up_bwd, dim3(blocks((int64_t)n * h * w * c)), dim3(256), 0, (hipStream_t)stream, n, h, w, c,
-                       (const unsigned short *)dy, dys, dyo, (unsigned short *)dx, dxs, dxo);
+    up_bwd_launch(n, h, w, c, (const unsigned short *)dy, dys, dyo, (unsigned short *)dx, dxs, dxo, (hipStream_t)stream);
     return check("mlbm_upsample_backward");
 }
 
@@ -976,8 +1138,7 @@ extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, 
         if (l < n.L - 1) {
             const int cu = n.c[l + 1], cc = cu + c;
             if ((rc = conv(nm, q.act + n.a.enc_a[l], c, 0, q.act + n.a.cat[l], cc, cu, 1, 0))) return rc;
-            hipLaunchKernelGGL(k_pool_fwd, dim3(blocks((int64_t)n.B * (R / 2) * (R / 2) * c)), dim3(256), 0, s, n.B,
-                               R / 2, R / 2, c, q.act + n.a.cat[l], cc, cu, q.act + n.a.pool[l], c, 0);
+            pool_fwd_launch(n.B, R / 2, R / 2, c, q.act + n.a.cat[l], cc, cu, q.act + n.a.pool[l], c, 0, s);
             h = q.act + n.a.pool[l];
         } else {
             if ((rc = conv(nm, q.act + n.a.enc_a[l], c, 0, q.act + n.a.bottom, c, 0, 1, 0))) return rc;
@@ -987,8 +1148,7 @@ extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, 
     }
     for (int l = n.L - 2; l >= 0; --l) {
         const int R = n.R >> l, c = n.c[l], cu = n.c[l + 1], cc = cu + c;
-        hipLaunchKernelGGL(k_up_fwd, dim3(blocks((int64_t)n.B * R * R * cu)), dim3(256), 0, s, n.B, R / 2, R / 2, cu,
-                           (const unsigned short *)h, hs, 0, q.act + n.a.cat[l], cc, 0);
+        up_fwd_launch(n.B, R / 2, R / 2, cu, (const unsigned short *)h, hs, 0, q.act + n.a.cat[l], cc, 0, s);
         std::snprintf(nm, sizeof(nm), "dec%da", l);
         if ((rc = conv(nm, q.act + n.a.cat[l], cc, 0, q.act + n.a.dec_a[l], c, 0, 1, 0))) return rc;
         std::snprintf(nm, sizeof(nm), "dec%db", l);
@@ -1011,11 +1171,11 @@ extern "C" int mlbm_unet_loss(const mlbm_unet *u, const float *out, const float 
     const Ptrs q = net_ptrs(u, n);
     const int64_t P = (int64_t)n.B * n.R * n.R;
     hipLaunchKernelGGL(k_mask_partial, dim3((unsigned)n.loss_blocks), dim3(256), 0, s, P, mask, q.mask_part);
-    hipLaunchKernelGGL(k_inv_count, dim3(1), dim3(64), 0, s, (const double *)q.mask_part, n.loss_blocks, n.c_real_out,
+    hipLaunchKernelGGL(k_inv_count, dim3(1), dim3(256), 0, s, (const double *)q.mask_part, n.loss_blocks, n.c_real_out,
                        q.inv);
     hipLaunchKernelGGL(k_mse_dev, dim3((unsigned)n.loss_blocks), dim3(256), 0, s, P, n.c_real_out, out, PADC, target,
                        mask, (const float *)q.inv, q.grad + n.a.dout, q.loss_part);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, (const double *)q.loss_part, n.loss_blocks,
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, (const double *)q.loss_part, n.loss_blocks,
                        (const float *)q.inv, loss);
     return check("mlbm_unet_loss");
 }
@@ -1048,8 +1208,7 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
         return conv_launch(d, dy, q.wbf + ly.wd_off, nullptr, dx, 0, 0, gate, gs, go, s);
     };
     auto relu_bwd = [&](int64_t P, int C, const void *y, int ys, int yo, void *dy, int dys, int dyo) {
-        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks(P * C)), dim3(256), 0, s, P, C, (const unsigned short *)y, ys, yo,
-                           (unsigned short *)dy, dys, dyo);
+        relu_bwd_launch(P, C, (const unsigned short *)y, ys, yo, (unsigned short *)dy, dys, dyo, s);
     };
     char nm[8];
     const int c0 = n.c[0];
@@ -1068,8 +1227,7 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
         // the upsampled channels' gradient goes to this level's input: the decoder
         // output of the level below, or the bottleneck
         unsigned short *below = l + 1 <= n.L - 2 ? G + n.a.dec_b[l + 1] : G + n.a.bottom;
-        hipLaunchKernelGGL(k_up_bwd, dim3(blocks((int64_t)n.B * (R / 2) * (R / 2) * cu)), dim3(256), 0, s, n.B, R / 2,
-                           R / 2, cu, (const unsigned short *)(G + n.a.cat[l]), cc, 0, below, cu, 0);
+        up_bwd_launch(n.B, R / 2, R / 2, cu, (const unsigned short *)(G + n.a.cat[l]), cc, 0, below, cu, 0, s);
     }
     for (int l = n.L - 1; l >= 0; --l) {
         const int R = n.R >> l, c = n.c[l];
@@ -1081,9 +1239,8 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
             const int cu = n.c[l + 1], cc = cu + c;
             // d(enc_b output) = the pooled path's gradient + the skip gradient, which
             // sits in the skip channels of the concatenation's gradient
-            hipLaunchKernelGGL(k_pool_bwd, dim3(blocks(P * c)), dim3(256), 0, s, n.B, R / 2, R / 2, c,
-                               (const unsigned short *)(G + n.a.pool[l]), c, 0, G + n.a.cat[l], cc, cu,
-                               (const unsigned short *)(G + n.a.cat[l]), cc, cu);
+            pool_bwd_launch(n.B, R / 2, R / 2, c, (const unsigned short *)(G + n.a.pool[l]), c, 0, G + n.a.cat[l], cc, cu,
+                            (const unsigned short *)(G + n.a.cat[l]), cc, cu, s);
             yb = A + n.a.cat[l];
             gb = G + n.a.cat[l];
             bs = cc;
