@@ -28,10 +28,11 @@ METRIC = "MNUPS and HBM fraction of fused step; time-to-steady-state plain vs wa
 
 def kernel_source_digest():
     """Digest of what decides a step kernel's traffic: the device code of
-    mlbm_step.hip (everything before its dispatch section) and mlbm_step's
-    launch logic; host-only entry points elsewhere in the file do not void
-    the stored counters."""
-    with open(os.path.join(ROOT, "paper_2312_14789_amd", "csrc", "mlbm_step.hip")) as f:
+    mlbm_step.hip (everything before its dispatch section), mlbm_step's
+    launch logic, the shared device helpers and the eight-lane kernels;
+    host-only entry points elsewhere do not void the stored counters."""
+    csrc = os.path.join(ROOT, "paper_2312_14789_amd", "csrc")
+    with open(os.path.join(csrc, "mlbm_step.hip")) as f:
         src = f.read()
     device = src[:src.index("// ---- dispatch")]
     a = src.index('extern "C" int mlbm_step(')
@@ -39,6 +40,9 @@ def kernel_source_digest():
     h = hashlib.sha256()
     h.update(device.encode())
     h.update(launch.encode())
+    for name in ("mlbm_device.h", "mlbm_lanes.hip"):
+        with open(os.path.join(csrc, name)) as f:
+            h.update(f.read().encode())
     return h.hexdigest()[:16]
 
 
@@ -686,20 +690,41 @@ def strouhal_workload(M, units, nodesets, np, torch, cases=ST_CASES, periods=10,
             "rows": rows}
 
 
-def warmstart_workload(args, np, torch):
+WS_RES, WS_G = 256, 1e-5
+# warm-start leg of the default line: training media, held-out media, epochs
+# (the full workload, --workload warmstart, trains on 2000 media for 20 epochs
+# and compares on 200)
+WS_BENCH = (512, 32, 16)
+
+
+def warmstart_geometries(n):
+    """n random-disk media on 256^2 rasters (16 host worker processes);
+    returns (geometries, seconds)."""
+    from paper_2312_14789_amd import warmstart
+
+    t0 = time.time()
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
+    geoms = warmstart.make_geometries(n, res=WS_RES, workers=16, log=log)
+    dt = time.time() - t0
+    print(f"# {len(geoms)} warm-start geometries in {dt:.1f} s", file=sys.stderr, flush=True)
+    return geoms, dt
+
+
+def warmstart_workload(np, torch, n_train, n_test, epochs, save="", geoms=None):
     """Learned warm start (network of 5 levels, 32-256 channels, 256^2 rasters):
     train on steady states of random-disk media computed by batched library
     runs, then compare steps and wall time to a residual of 1e-6 from rest and
-    from the network's prediction on held-out samples."""
+    from the network's prediction on held-out samples.  geoms: the media, made
+    beforehand by warmstart_geometries (before the process touches the GPU,
+    since making them forks worker processes)."""
     from paper_2312_14789_amd import unet, warmstart
 
-    res, g = 256, 1e-5
-    t0 = time.time()
+    res, g = WS_RES, WS_G
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
-    geoms = warmstart.make_geometries(args.ws_train + args.ws_test, res=res, workers=16, log=log)
-    t_geo = time.time() - t0
-    print(f"# {len(geoms)} geometries in {t_geo:.1f} s", file=sys.stderr, flush=True)
-    train_g, test_g = geoms[:args.ws_train], geoms[args.ws_train:]
+    t_geo = 0.0
+    if geoms is None:
+        geoms, t_geo = warmstart_geometries(n_train + n_test)
+    train_g, test_g = geoms[:n_train], geoms[n_train:n_train + n_test]
     t0 = time.time()
     fields, steps = warmstart.steady_states(train_g, g, batch_size=64, log=log)
     t_data = time.time() - t0
@@ -710,10 +735,10 @@ def warmstart_workload(args, np, torch):
     del fields
     net = unet.UNet((32, 64, 128, 256, 256), res=res, batch=16, seed=1)
     t0 = time.time()
-    hist = warmstart.train(net, data, epochs=args.ws_epochs, lr=1e-3, log=log)
+    hist = warmstart.train(net, data, epochs=epochs, lr=1e-3, log=log)
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    iters = args.ws_epochs * (data.n // net.batch)
+    iters = epochs * (data.n // net.batch)
     # inference time per sample (one batch of 16)
     masks = [m for _, m in test_g]
     warmstart.predict(net, data, masks[:16], data.u_scale, data.r_scale)
@@ -732,24 +757,71 @@ def warmstart_workload(args, np, torch):
     rest_s = np.array([r["rest"]["seconds"] for r in rows])
     warm_s = np.array([r["warm"]["seconds"] for r in rows])
     kerr = np.array([abs(r["warm"]["permeability"] / r["rest"]["permeability"] - 1) for r in rows])
-    if args.ws_save:
-        np.savez(args.ws_save, **net.state_dict())
+    if save:
+        np.savez(save, **net.state_dict())
     fl = 0.0
     for name, k, ci, co in net.shapes:
         fl += 2.0 * k * k * ci * co * (res >> (int(name[3]) if name != "head" else 0)) ** 2
     return {"metric": "time-to-steady-state plain vs warm-start",
-            "workload": f"{args.ws_train} training + {len(test_g)} held-out random-disk media, {res}^2 rasters, "
+            "workload": f"{len(train_g)} training + {len(test_g)} held-out random-disk media, {res}^2 rasters, "
                         f"MLBM1 FP32 K=16 s=1 g_lb={g:g}, residual 1e-6",
             "steps_rest_mean": float(rest_steps.mean()), "steps_warm_mean": float(warm_steps.mean()),
             "step_ratio_rest_over_warm": float((rest_steps / warm_steps).mean()),
             "seconds_rest_mean": float(rest_s.mean()), "seconds_warm_mean_incl_inference": float(warm_s.mean()),
             "inference_ms_per_sample": round(1e3 * infer, 3),
             "permeability_rel_err_max": float(kerr.max()), "permeability_within_0.5pct": bool(kerr.max() <= 5e-3),
-            "train": {"epochs": args.ws_epochs, "loss_first": hist[0], "loss_last": hist[-1], "seconds": round(t_train, 1),
+            "steps_saved_mean": float((rest_steps - warm_steps).mean()),
+            "seconds_saved_mean": float((rest_s - warm_s).mean()),
+            "train": {"epochs": epochs, "loss_first": hist[0], "loss_last": hist[-1], "seconds": round(t_train, 1),
                       "iters": iters, "ms_per_iter": round(1e3 * t_train / max(iters, 1), 2),
                       "tflops_fwd_bwd": round(3 * fl * net.batch * iters / t_train / 1e12, 2)},
             "data": {"geometry_s": round(t_geo, 1), "steady_states_s": round(t_data, 1),
                      "steps_min_max": [int(min(steps)), int(max(steps))], "unconverged_dropped": dropped}}
+
+
+def mapping_workload(M, nodesets, np, torch, sides=(64, 128, 256, 512), steps=2000, warmup=200):
+    """One lane per node against a group of eight lanes per node, over node
+    sets from 4 096 to 262 144 nodes (periodic jittered grids, K = 16,
+    s = 1.5, FP32): microseconds per step of every launch shape (tile 0 =
+    global gathers, else LDS tiles of that many nodes), steps replayed as
+    graphs of 100 so launch overhead does not hide the kernels.  Population
+    form (BGK tau = 0.8) and fields form (tau = 1)."""
+    shapes = [(1, 0), (1, 64), (1, 128), (1, 256), (8, 0), (8, 64), (8, 128)]
+    rows = []
+    stream = torch.cuda.Stream()
+    for side in sides:
+        ns = nodesets.jittered_grid(side, seed=11)
+        dx = 1.0 / side / 1.5
+        b = M.build_stencils_for(ns, 16, dx)
+        perm = b["perm"]
+        rho0, u0 = nodesets.smooth_fields(ns.xy[perm], 3, amp_u=0.01, amp_rho=0.001)
+        for variant, tau in ((M.POPULATIONS, 0.8), (M.FIELDS, 1.0)):
+            row = {"nodes": ns.n, "variant": "populations" if variant == M.POPULATIONS else "fields", "us_per_step": {}}
+            for lanes, tile in shapes:
+                sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=variant,
+                                   storage=M.F32, tau_plus=tau, tile=tile, lanes_per_node=lanes, graph_steps=100)
+                sim.init_state(rho0, u0)
+                sim.step(warmup, stream=stream)
+                stream.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sim.step(steps, stream=stream)
+                e1.record(stream)
+                e1.synchronize()
+                row["us_per_step"][f"lanes{lanes}-tile{tile}"] = round(e0.elapsed_time(e1) * 1e3 / steps, 2)
+                del sim
+            best1 = min((v, k) for k, v in row["us_per_step"].items() if k.startswith("lanes1"))
+            best8 = min((v, k) for k, v in row["us_per_step"].items() if k.startswith("lanes8"))
+            row["best_one_lane"] = best1[1]
+            row["best_eight_lanes"] = best8[1]
+            row["speedup_eight_lanes"] = round(best1[0] / best8[0], 3)
+            row["MNUPS_best"] = round(ns.n / min(best1[0], best8[0]), 1)
+            print(f"# {ns.n} nodes {row['variant']}: one lane {best1[0]} us ({best1[1]}), eight lanes "
+                  f"{best8[0]} us ({best8[1]})", file=sys.stderr, flush=True)
+            rows.append(row)
+    return {"metric": "step time, one lane vs eight lanes per node",
+            "workload": "periodic jittered grids (jitter 0.3 h), K=16, s=1.5, FP32, graph replay of 100 steps",
+            "rows": rows}
 
 
 def unet_workload(np, torch, steps=20, warmup=3):
@@ -837,19 +909,22 @@ def main():
                     help="node order: 0 as generated, 1 Morton, 2 reverse Cuthill-McKee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the porous time-to-steady section")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the warm-start leg (steps and seconds to steady state, plain vs warm-start)")
     ap.add_argument("--no-extra-rows", action="store_true",
                     help="skip the FP64 row and the large (beyond the memory-side cache) Karman set")
     ap.add_argument("--st-dump", default=None, help="strouhal: save the lift series (npz) to this path")
     ap.add_argument("--workload", default="karman",
                     choices=["karman", "porous", "batched", "batched-intervals", "warmstart", "darcy", "strouhal",
-                             "unet"],
+                             "unet", "mapping"],
                     help="karman: the fused-step throughput line; porous: the MLBM1 step on the 1e6-node "
                          "porous sample; batched: 64 porous samples to steady "
                          "state; batched-intervals: the same batch timed per 100-step interval, by phase; "
                          "warmstart: train the warm-start network and compare time to steady state; "
                          "darcy: mean velocity and tortuosity of the porous channel over a sweep of dx; "
                          "strouhal: the paper's cylinder channel, St from the lift over Re 105-168; "
-                         "unet: training and inference throughput of the warm-start network")
+                         "unet: training and inference throughput of the warm-start network; "
+                         "mapping: one against eight lanes per node over node sets of 4k-262k nodes")
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-test", type=int, default=200)
     ap.add_argument("--ws-epochs", type=int, default=20)
@@ -882,7 +957,11 @@ def main():
         print(json.dumps(batched_intervals(M, nodesets, np, torch)), flush=True)
         return
     if args.workload == "warmstart":
-        print(json.dumps(warmstart_workload(args, np, torch)), flush=True)
+        print(json.dumps(warmstart_workload(np, torch, args.ws_train, args.ws_test, args.ws_epochs, save=args.ws_save)),
+              flush=True)
+        return
+    if args.workload == "mapping":
+        print(json.dumps(mapping_workload(M, nodesets, np, torch)), flush=True)
         return
     if args.workload == "unet":
         print(json.dumps(unet_workload(np, torch, steps=args.steps, warmup=args.warmup)), flush=True)
@@ -932,6 +1011,10 @@ def main():
         print(f"# oracle on the host: {cpu_out['value']:.3f} MNUPS on 1 core, "
               f"{cpu_out.get('all_cores', {}).get('value', float('nan')):.3f} on {workers}", file=sys.stderr,
               flush=True)
+    ws_geoms = None
+    if not args.no_warm_start:
+        # the warm-start media, also before the GPU is touched (worker processes)
+        ws_geoms = warmstart_geometries(WS_BENCH[0] + WS_BENCH[1])
     sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS,
                        storage=storage, tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm],
                        block=args.block, xcd_remap=args.xcd, scale_exp=12,
@@ -1008,6 +1091,14 @@ def main():
         out["time_to_steady"] = porous_time_to_steady(M, units, nodesets, np, torch)
         out["time_to_steady_inertial"] = porous_time_to_steady(M, units, nodesets, np, torch, s=4.0,
                                                                runs=TTS_RUNS_INERTIAL)
+    if ws_geoms is not None:
+        geoms, t_geo = ws_geoms
+        ws = warmstart_workload(np, torch, WS_BENCH[0], WS_BENCH[1], WS_BENCH[2], geoms=geoms)
+        ws["data"]["geometry_s"] = round(t_geo, 1)
+        out["warm_start"] = ws
+        print(f"# warm start: steps {ws['steps_rest_mean']:.0f} -> {ws['steps_warm_mean']:.0f} "
+              f"(x{ws['step_ratio_rest_over_warm']:.3f}), k err max {ws['permeability_rel_err_max']:.2e}",
+              file=sys.stderr, flush=True)
     if cpu_out is not None:
         out["cpu_baseline"] = cpu_out
     print(json.dumps(out), flush=True)

@@ -271,6 +271,18 @@ typedef struct mlbm_step_params {
                                 saves launch overhead on node sets too small to fill
                                 the GPU.  Not with stochastic rounding (its random bits
                                 change every step): MLBM_ERR_UNSUPPORTED.           */
+    int32_t lanes_per_node;  /* mlbm_step only.  0 or 1: one lane per node.  8: a group of
+                                eight lanes per node, lane k taking arriving population
+                                (or departure point) k + 1 and the group exchanging its
+                                sums for the collision; the same sums in the same order
+                                (equal to rounding: the kernels may fuse multiply-adds
+                                differently), eight times the lanes, for node sets too
+                                small to fill the GPU.
+                                With tile 64 or 128 a workgroup holds 8 x tile lanes;
+                                with tile 0, block lanes for block / 8 nodes.  Per-node
+                                stencils with K padded to 12, 16, 28 or 32 members;
+                                hybrid sets (w_lagrange), per-departure stencils and
+                                tile 256 give MLBM_ERR_UNSUPPORTED                  */
 } mlbm_step_params;
 
 typedef struct mlbm_device_state {

@@ -64,7 +64,7 @@ class StepParams(ctypes.Structure):
                 ("fp32_arith", ctypes.c_int32), ("alternate_sweeps", ctypes.c_int32),
                 ("cached_weights", ctypes.c_int32), ("stochastic_rounding", ctypes.c_int32),
                 ("weights16", ctypes.c_int32), ("hybrid_launches", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("lanes_per_node", ctypes.c_int32)]
 
 
 class DeviceState(ctypes.Structure):

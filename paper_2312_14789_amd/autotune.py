@@ -112,6 +112,7 @@ def _reinit(batch, rho_u):
 
 
 SIM_TILES = (0, 64, 128, 256)
+SIM_LANES = (1, 8)
 SIM_SWEEPS = (1, 0)
 
 
@@ -120,16 +121,22 @@ def sim_cache_key(sim) -> str:
 
     arch = torch.cuda.get_device_properties(sim.state_d[0].device).gcnArchName.split(":")[0]
     p = sim.params
-    return f"sim|{arch}|K{sim.K}|v{p.variant}|s{p.storage}|N2^{round(math.log2(sim.n))}"
+    return f"sim2|{arch}|K{sim.K}|v{p.variant}|s{p.storage}|N2^{round(math.log2(sim.n))}"
 
 
 def tune_simulation(sim, steps=200, cache_path=None, use_cache=True):
-    """Picks tile size (0 = gathers from global memory, else LDS-staged tiles
+    """Picks the mapping (one lane per node, or a group of eight lanes per
+    node), tile size (0 = gathers from global memory, else LDS-staged tiles
     of that many nodes), XCD-contiguous tiles and alternating sweeps for a
     Simulation by timing mlbm_step on its own node set, and applies them.
-    The state is advanced by the timing runs; re-initialise it afterwards.
-    Returns {"tile", "xcd", "sweeps", "ms_per_step", "timings", "cached"}."""
+    Shapes the library refuses for this set (eight lanes on hybrid or
+    per-departure sets, with 256-node tiles, or for stencil sizes without an
+    eight-lane kernel) are skipped.  The state is advanced by the timing runs;
+    re-initialise it afterwards.  Returns {"lanes", "tile", "xcd", "sweeps",
+    "ms_per_step", "timings", "cached"}."""
     import torch
+
+    from .mlbm import MlbmError
 
     cache_path = cache_path or default_cache_path()
     key = sim_cache_key(sim)
@@ -142,28 +149,36 @@ def tune_simulation(sim, steps=200, cache_path=None, use_cache=True):
     else:
         timings = []
         stream = torch.cuda.current_stream()
-        for tile in SIM_TILES:
-            sim.set_tile(tile)
-            for xcd in XCD:
-                for sweeps in SIM_SWEEPS:
-                    sim.params.xcd_remap = xcd
-                    sim.params.alternate_sweeps = sweeps
-                    sim.step(steps // 4)
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    sim.step(steps)
-                    e1.record(stream)
-                    e1.synchronize()
-                    timings.append({"tile": tile, "xcd": xcd, "sweeps": sweeps,
-                                    "ms_per_step": e0.elapsed_time(e1) / steps})
+        for lanes in SIM_LANES:
+            sim.params.lanes_per_node = lanes
+            for tile in SIM_TILES:
+                sim.set_tile(tile)
+                for xcd in XCD:
+                    for sweeps in SIM_SWEEPS:
+                        sim.params.xcd_remap = xcd
+                        sim.params.alternate_sweeps = sweeps
+                        try:
+                            sim.step(steps // 4)
+                        except MlbmError as e:
+                            if e.code != -5:    # only unsupported shapes are skipped
+                                raise
+                            continue
+                        e0 = torch.cuda.Event(enable_timing=True)
+                        e1 = torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        sim.step(steps)
+                        e1.record(stream)
+                        e1.synchronize()
+                        timings.append({"lanes": lanes, "tile": tile, "xcd": xcd, "sweeps": sweeps,
+                                        "ms_per_step": e0.elapsed_time(e1) / steps})
         best = dict(min(timings, key=lambda r: r["ms_per_step"]))
         best["timings"] = timings
-        cache[key] = {k: best[k] for k in ("tile", "xcd", "sweeps", "ms_per_step")}
+        cache[key] = {k: best[k] for k in ("lanes", "tile", "xcd", "sweeps", "ms_per_step")}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
         best["cached"] = False
+    sim.params.lanes_per_node = best.get("lanes", 1)
     sim.set_tile(best["tile"])
     sim.params.xcd_remap = best["xcd"]
     sim.params.alternate_sweeps = best["sweeps"]

@@ -22,7 +22,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", 
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
 HOST_SOURCES = ["stencil_build.cpp", "mlbm_common.cpp"]
-HIP_SOURCES = ["mlbm_step.hip", "unet.hip"]
+HIP_SOURCES = ["mlbm_step.hip", "mlbm_lanes.hip", "unet.hip"]
 # a bandwidth measurement helper, linked into a library of its own
 PROBE_SOURCES = ["bw_probe.hip"]
 
@@ -39,24 +39,21 @@ def _link(objs, out):
 
 
 def build(verbose: bool = True) -> str:
-    """Compiles every source, links LIB and PROBE_LIB; returns LIB's path."""
+    """Compiles every source (in parallel), links LIB and PROBE_LIB; returns
+    LIB's path."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in HOST_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-    for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-    _link(objs, LIB)
-    probe_objs = []
-    for src in PROBE_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        probe_objs.append(obj)
-    _link(probe_objs, PROBE_LIB)
+        jobs.append(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
+    for src in HIP_SOURCES + PROBE_SOURCES:
+        jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")])
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(_run, jobs))
+    _link([os.path.join(BUILD, s + ".o") for s in HOST_SOURCES + HIP_SOURCES], LIB)
+    _link([os.path.join(BUILD, s + ".o") for s in PROBE_SOURCES], PROBE_LIB)
     return LIB
 
 

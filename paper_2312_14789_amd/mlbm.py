@@ -148,7 +148,7 @@ class Simulation:
                  tau_minus=None, g=(0.0, 0.0), bc=None, scale_exp=0, block=256, xcd_remap=1,
                  fp32_arith=0, alternate_sweeps=1, cached_weights=0, tile=256, device="cuda",
                  packed=None, lagrange=None, w_lagrange=None, stochastic_rounding=0, weights16=0,
-                 hybrid_launches=0, box_area=0.0, graph_steps=0):
+                 hybrid_launches=0, box_area=0.0, graph_steps=0, lanes_per_node=1):
         import torch
 
         self.torch = torch
@@ -209,6 +209,7 @@ class Simulation:
         self.params.weights16 = int(bool(weights16))
         self.params.hybrid_launches = int(hybrid_launches)
         self.params.graph_steps = int(graph_steps)
+        self.params.lanes_per_node = int(lanes_per_node)
         self.ds = DeviceState()
         self.ds.n = n
         self.ds.K = K

@@ -1,8 +1,9 @@
 """Autotuner for single node sets: it times every launch shape on the node set
-itself and applies the fastest; the shapes it chooses among compute the same
-sums in the same order (only the data movement differs), so the tuned run
-agrees with the default shape to rounding (kernels built for different shapes
-may fuse multiply-adds differently)."""
+itself (one or eight lanes per node, tile, XCD order, sweeps) and applies the
+fastest; the shapes it chooses among compute the same sums in the same order
+(only the data movement differs), so the tuned run agrees with the default
+shape to rounding (kernels built for different shapes may fuse multiply-adds
+differently)."""
 import numpy as np
 import pytest
 
@@ -40,10 +41,15 @@ def test_tuned_simulation_matches_default_shape(M, variant, tmp_path):
     ref.step(100)
     sim = make()
     best = autotune.tune_simulation(sim, steps=40, cache_path=str(tmp_path / "tune.json"))
-    print(f"[autotune] variant={variant} best tile={best['tile']} xcd={best['xcd']} sweeps={best['sweeps']} "
-          f"{best['ms_per_step'] * 1e3:.1f} us/step over {len(best['timings'])} shapes", flush=True)
-    assert len(best["timings"]) == len(autotune.SIM_TILES) * len(autotune.XCD) * len(autotune.SIM_SWEEPS)
-    assert sim.ds.tile == best["tile"]
+    print(f"[autotune] variant={variant} best lanes={best['lanes']} tile={best['tile']} xcd={best['xcd']} "
+          f"sweeps={best['sweeps']} {best['ms_per_step'] * 1e3:.1f} us/step over {len(best['timings'])} shapes",
+          flush=True)
+    # one lane per node with every tile; eight lanes per node with the tiles
+    # it supports (global gathers, 64 and 128 nodes)
+    per_tile = len(autotune.XCD) * len(autotune.SIM_SWEEPS)
+    assert len(best["timings"]) == (len(autotune.SIM_TILES) + 3) * per_tile
+    assert {r["lanes"] for r in best["timings"]} == {1, 8}
+    assert sim.ds.tile == best["tile"] and sim.params.lanes_per_node == best["lanes"]
     sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
     sim.step(100)
     _, u, _ = sim.macroscopic(ns.h_min)
@@ -51,4 +57,4 @@ def test_tuned_simulation_matches_default_shape(M, variant, tmp_path):
     u, u_ref = u.cpu().numpy(), u_ref.cpu().numpy()
     assert np.linalg.norm(u - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
     again = autotune.tune_simulation(make(), steps=40, cache_path=str(tmp_path / "tune.json"))
-    assert again["cached"] and again["tile"] == best["tile"]
+    assert again["cached"] and again["tile"] == best["tile"] and again["lanes"] == best["lanes"]

@@ -22,6 +22,8 @@ from gpu_util import (assert_fields_close, initial_fields, lagrange_last, morton
 pytestmark = pytest.mark.gpu
 
 BAR = {0: 1e-12, 1: 1e-5}
+# eight lanes per node against one lane per node (same sums, rounding only)
+LANES_BAR = {0: 1e-13, 1: 3e-6}
 
 
 @pytest.fixture(scope="module")
@@ -429,6 +431,90 @@ def test_zero_steps_and_errors(M):
     sim.ds.n = 0
     with pytest.raises(M.MlbmError):
         sim.step(1)
+
+
+@pytest.mark.parametrize("name", ["tgv64", "channel_trt", "karman_small", "porous_fields", "k25_fields"])
+@pytest.mark.parametrize("storage,tile", [(0, 0), (1, 0), (0, 64), (1, 64), (1, 128)])
+def test_eight_lanes_per_node_equal_one_lane(M, name, storage, tile):
+    # the same steps with a group of eight lanes per node: parity with the
+    # oracle at the same bar, and agreement with one lane per node to rounding
+    # (the two kernels compute the same sums in the same order; the compiler
+    # may fuse their multiply-adds differently)
+    print(f"[lanes] case={name} storage={storage} tile={tile}", flush=True)
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, r_ref, u_ref, _ = _case(name)
+    us = []
+    for lanes in (1, 8):
+        sim = sim_from_oracle(M, ns, st, var, storage, tp, tm, g, tile=tile, lanes_per_node=lanes)
+        sim.init_state(rho0, u0)
+        sim.step(steps)
+        _, u, _ = sim.macroscopic(dx)
+        us.append(u.cpu().numpy())
+    e2, em = assert_fields_close(us[1], u_ref, BAR[storage], name)
+    d2, dm = assert_fields_close(us[1], us[0], LANES_BAR[storage], name + " eight vs one lane")
+    print(f"[lanes] case={name} storage={storage} tile={tile} vs oracle {e2:.2e}/{em:.2e} "
+          f"vs one lane {d2:.2e}/{dm:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("name,storage,kw", [("channel_trt", 2, dict(stochastic_rounding=1, scale_exp=12)),
+                                              ("porous_fields", 2, dict(stochastic_rounding=1, scale_exp=16)),
+                                              ("porous_fields", 3, dict(stochastic_rounding=1, weights16=1)),
+                                              ("channel_trt", 2, dict(stochastic_rounding=1, scale_exp=12,
+                                                                      weights16=1))])
+def test_eight_lanes_per_node_16bit_states(M, name, storage, kw):
+    # 16-bit states: the two mappings agree to the storage's rounding (a
+    # last-bit difference before a store can move a value by one ulp)
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case(name)
+    us = []
+    for lanes in (1, 8):
+        sim = sim_from_oracle(M, ns, st, var, storage, tp, tm, g, tile=64, lanes_per_node=lanes, **kw)
+        sim.init_state(rho0, u0)
+        sim.step(50)
+        _, u, _ = sim.macroscopic(dx)
+        us.append(u.cpu().numpy())
+    d2, dm = assert_fields_close(us[1], us[0], 2e-3, f"{name} storage {storage} eight vs one lane")
+    print(f"[lanes] {name} storage={storage} {kw}: eight vs one lane {d2:.2e}/{dm:.2e}", flush=True)
+
+
+def test_eight_lanes_per_node_graph_replay(M):
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case("karman_small")
+    import torch
+
+    states = []
+    for gsteps in (0, 10):
+        sim = sim_from_oracle(M, ns, st, var, 1, tp, tm, g, tile=128, lanes_per_node=8, graph_steps=gsteps)
+        sim.init_state(rho0, u0)
+        stream = torch.cuda.Stream()
+        for _ in range(3):
+            sim.step(35, stream=stream)
+        stream.synchronize()
+        states.append(sim.state_bytes())
+    # the same kernels replayed: bit for bit
+    np.testing.assert_array_equal(states[1], states[0])
+
+
+def test_eight_lanes_per_node_refusals(M):
+    # hybrid sets, per-departure stencils, 256-node tiles and stencil sizes
+    # without an eight-lane kernel are refused, not launched
+    for name, kw in (("hybrid_tgv", dict(tile=64)), ("pd_tgv", dict(tile=64)), ("tgv64", dict(tile=256))):
+        ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case(name)
+        sim = sim_from_oracle(M, ns, st, var, 1, tp, tm, g, lanes_per_node=8, **kw)
+        sim.init_state(rho0, u0)
+        with pytest.raises(M.MlbmError) as e:
+            sim.step(1)
+        assert e.value.code == -5, name
+    ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case("tgv64")
+    sim = sim_from_oracle(M, ns, st, var, 1, tp, tm, g, tile=64, lanes_per_node=4)
+    sim.init_state(rho0, u0)
+    with pytest.raises(M.MlbmError) as e:
+        sim.step(1)
+    assert e.value.code == -1
+    ns20 = nodesets.jittered_grid(20, seed=30)
+    st20 = omlbm.build_stencils(ns20, 20, 1.0 / 30)     # K = 20: five member quads, no eight-lane kernel
+    sim = sim_from_oracle(M, ns20, st20, 0, 1, 0.8, 0.8, (0.0, 0.0), tile=64, lanes_per_node=8)
+    sim.init_state(np.ones(ns20.n), np.zeros((ns20.n, 2)))
+    with pytest.raises(M.MlbmError) as e:
+        sim.step(1)
+    assert e.value.code == -5
 
 
 _K25K = {}
