@@ -45,22 +45,29 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
 
 // ---- convolution tiles (forward and data gradient) ----------------------------------------
 // One workgroup computes a TH x TW pixel tile of one image for BN output
-// channels, as an implicit GEMM on v_mfma_f32_32x32x16_bf16: each wave owns 32
-// pixels x 32 channels.  Per 32-channel slice of the input, the tile's input
-// halo ((TH + 2) x (TW + 2) pixels, periodic) and the slice of the weights for
-// every tap are staged in LDS with 16-byte copies, so each staged input value
-// feeds all taps and every MFMA operand is one 16-byte LDS read.  Row pitches
-// of 40 halves (80 B) keep the 16 lanes of each LDS read on distinct banks.
+// channels, as an implicit GEMM on v_mfma_f32_32x32x16_bf16: each wave owns
+// PM x 32 pixels x PN x 32 channels (PM x PN accumulator tiles, so each
+// operand fragment read from LDS feeds PN or PM products).  Per 32-channel
+// slice of the input, the tile's input halo ((TH + 2) x (TW + 2) pixels,
+// periodic) and the slice of the weights for every tap are staged in LDS with
+// 16-byte copies, so each staged input value feeds all taps and every MFMA
+// operand is one 16-byte LDS read.  Row pitches of 40 halves (80 B) keep the
+// 16 lanes of each LDS read on distinct banks.
 // Epilogue: bias, ReLU, and optionally a gate (the ReLU gradient of the layer
 // whose output gradient this is: zero where that layer's output is <= 0).
 constexpr int KC = 32, XP = KC + 8;
 
-template <int TH, int TW, int BN>
-__global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
+template <int TH, int TW, int BN, int PM, int PN>
+constexpr int conv_threads() { return 64 * (TH * TW / (32 * PM)) * (BN / (32 * PN)); }
+
+template <int TH, int TW, int BN, int PM = 1, int PN = 1>
+__global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     k_conv_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                 const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
                 const unsigned short *__restrict__ gate, int gate_stride, int gate_offset) {
-    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = 64 * WPX * (BN / 32);
+    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / (32 * PM);
+    constexpr int NT = conv_threads<TH, TW, BN, PM, PN>();
+    static_assert(BM % (32 * PM) == 0 && BN % (32 * PN) == 0, "wave tiles must divide the block");
     __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
     __shared__ __align__(16) unsigned short wsm[9 * BN * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -71,9 +78,20 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     const int co0 = blockIdx.y * BN;
     const int ks = d.ksize, r = ks >> 1, taps = ks * ks;
     const int row = lane & 31, kh = (lane >> 5) * 8;
-    const int pb = wp * 32 + row;
-    const int py = pb / TW, px = pb % TW;
-    f32x16 acc = {};
+    // LDS offsets of this lane's A rows (pixels) at tap offset (0, 0) and B rows (channels)
+    int aoff[PM], boff[PN];
+#pragma unroll
+    for (int pm = 0; pm < PM; ++pm) {
+        const int pb = (wp * PM + pm) * 32 + row;
+        aoff[pm] = ((pb / TW + 1) * HWD + (pb % TW + 1)) * XP + kh;
+    }
+#pragma unroll
+    for (int pn = 0; pn < PN; ++pn) boff[pn] = ((wc * PN + pn) * 32 + row) * XP + kh;
+    f32x16 acc[PM][PN];
+#pragma unroll
+    for (int pm = 0; pm < PM; ++pm)
+#pragma unroll
+        for (int pn = 0; pn < PN; ++pn) acc[pm][pn] = f32x16{};
     for (int c0 = 0; c0 < d.c_in; c0 += KC) {
         __syncthreads();
         for (int it = threadIdx.x; it < HH * HWD * 4; it += NT) {
@@ -95,28 +113,43 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
         }
         __syncthreads();
         for (int t = 0; t < taps; ++t) {
-            const int oy = t / ks - r, ox = t % ks - r;
-            const unsigned short *ap = &xs[((py + 1 + oy) * HWD + (px + 1 + ox)) * XP + kh];
-            const unsigned short *bp = &wsm[(t * BN + wc * 32 + row) * XP + kh];
+            const int toff = ((t / ks - r) * HWD + (t % ks - r)) * XP;
+            const unsigned short *wt = &wsm[t * BN * XP];
 #pragma unroll
-            for (int kk = 0; kk < KC; kk += 16)
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf8(ap + kk), load_bf8(bp + kk), acc, 0, 0, 0);
+            for (int kk = 0; kk < KC; kk += 16) {
+                bf16x8 a[PM], b[PN];
+#pragma unroll
+                for (int pm = 0; pm < PM; ++pm) a[pm] = load_bf8(&xs[aoff[pm] + toff + kk]);
+#pragma unroll
+                for (int pn = 0; pn < PN; ++pn) b[pn] = load_bf8(wt + boff[pn] + kk);
+#pragma unroll
+                for (int pm = 0; pm < PM; ++pm)
+#pragma unroll
+                    for (int pn = 0; pn < PN; ++pn)
+                        acc[pm][pn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[pm], b[pn], acc[pm][pn], 0, 0, 0);
+            }
         }
     }
-    const int col = co0 + wc * 32 + row;
-    const float bv = bias ? bias[col] : 0.0f;
-    if (col >= d.c_store) return;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int pt = wp * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
-        const int ty = pt / TW, tx = pt % TW;
-        const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
-        float v = acc[q] + bv;
-        if (relu) v = fmaxf(v, 0.0f);
-        if (gate && !(bf2f(gate[gp * gate_stride + gate_offset + col]) > 0.0f)) v = 0.0f;
-        const int64_t o = gp * d.y_stride + d.y_offset + col;
-        if (y_f32) ((float *)y)[o] = v;
-        else ((unsigned short *)y)[o] = f2bf(v);
+    for (int pn = 0; pn < PN; ++pn) {
+        const int col = co0 + (wc * PN + pn) * 32 + row;
+        if (col >= d.c_store) continue;
+        const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+        for (int pm = 0; pm < PM; ++pm) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int pt = (wp * PM + pm) * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+                const int ty = pt / TW, tx = pt % TW;
+                const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
+                float v = acc[pm][pn][q] + bv;
+                if (relu) v = fmaxf(v, 0.0f);
+                if (gate && !(bf2f(gate[gp * gate_stride + gate_offset + col]) > 0.0f)) v = 0.0f;
+                const int64_t o = gp * d.y_stride + d.y_offset + col;
+                if (y_f32) ((float *)y)[o] = v;
+                else ((unsigned short *)y)[o] = f2bf(v);
+            }
+        }
     }
 }
 
@@ -129,8 +162,10 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
 // copies, copy s holding halo columns s .. s + TW - 1 of each halo row, so the
 // operand of any tap starts on a 16-byte boundary.  Transposes run in
 // registers on 8 x 8 blocks (8 pixels x 8 channels, one 16-byte load each)
-// and are written with 16-byte LDS stores.  Wave (co half h, tap row j) sums
-// the KS taps of its row.  Partials per split go to ws[split][c_out][taps][c_in].
+// and are written with 16-byte LDS stores.  Wave (co group h, tap row j) sums
+// the KS taps of its row for CB blocks of 32 output channels, so each output
+// gradient fragment feeds KS products and each input fragment CB.  Partials
+// per split go to ws[split][c_out][taps][c_in].
 
 // in[r] = 8 values of row r (value 2k in the low half of dword k); out[c] = column c
 __device__ __forceinline__ void transpose8x8(const u4 in[8], u4 out[8]) {
@@ -148,12 +183,13 @@ __device__ __forceinline__ void transpose8x8(const u4 in[8], u4 out[8]) {
 
 constexpr int XTS = 16 * 10 + 8;  // halves per channel of a transposed halo copy (up to 10 rows of 16, padded)
 
-template <int TH, int TW, int BCO, int KS>
-__global__ void __launch_bounds__(64 * (BCO / 32) * KS)
+template <int TH, int TW, int BCO, int KS, int CB = 1>
+__global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
     k_wgrad_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
                  float *__restrict__ ws, float *__restrict__ wsb, int tiles_per_split) {
-    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / 32) * KS, PP = BM + 8;
+    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / (32 * CB)) * KS, PP = BM + 8;
     static_assert(HH <= 10 && TW <= 16, "transposed halo copies hold up to 10 rows of 16");
+    static_assert(BCO % (32 * CB) == 0 && NT >= BCO, "wave groups must divide the block; one thread per bias sum");
     __shared__ __align__(16) unsigned short dyT[BCO * PP];
     __shared__ __align__(16) unsigned short xT[KS * 32 * XTS];
     __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
@@ -165,9 +201,11 @@ __global__ void __launch_bounds__(64 * (BCO / 32) * KS)
     const int n_tiles = d.n * tiles_img;
     const int ta = split * tiles_per_split, tb = min(n_tiles, ta + tiles_per_split);
     const int row = lane & 31, kh = (lane >> 5) * 8;
-    f32x16 acc[KS];
+    f32x16 acc[CB][KS];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) acc[s] = f32x16{};
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) acc[cb][s] = f32x16{};
     // bias gradient: the first input-channel block's workgroups also sum dy over their pixels
     const bool bias_sum = wsb && blockIdx.y == 0 && (int)threadIdx.x < BCO;
     float bsum = 0.0f;
@@ -227,23 +265,30 @@ __global__ void __launch_bounds__(64 * (BCO / 32) * KS)
         for (int kb = 0; kb < BM / 16; ++kb) {
             const int p0 = kb * 16 + kh;
             const int ty = p0 / TW, tx = p0 % TW;
-            const bf16x8 a = load_bf8(&dyT[(ch * 32 + row) * PP + p0]);
+            bf16x8 a[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) a[cb] = load_bf8(&dyT[((ch * CB + cb) * 32 + row) * PP + p0]);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const bf16x8 b = load_bf8(&xT[(s * 32 + row) * XTS + (ty + 1 + oy) * 16 + tx]);
-                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[s], 0, 0, 0);
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    acc[cb][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], b, acc[cb][s], 0, 0, 0);
             }
         }
     }
     if (bias_sum) wsb[(int64_t)split * d.c_out + co0 + threadIdx.x] = bsum;
     const int ci = ci0 + row;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        const int t = trow * KS + s;
+    for (int cb = 0; cb < CB; ++cb) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int co = co0 + ch * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
-            ws[(((int64_t)split * d.c_out + co) * taps + t) * d.c_in + ci] = acc[s][q];
+        for (int s = 0; s < KS; ++s) {
+            const int t = trow * KS + s;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int co = co0 + (ch * CB + cb) * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+                ws[(((int64_t)split * d.c_out + co) * taps + t) * d.c_in + ci] = acc[cb][s][q];
+            }
         }
     }
 }
@@ -656,20 +701,18 @@ namespace {
 // tile shape: 8 x 16 pixels, or 8 x 8 for images 8 pixels wide
 int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const float *bias, void *y, int relu, int y_f32,
                 const void *gate, int gate_stride, int gate_offset, hipStream_t s) {
-    const bool narrow = d.w == 8;
-    const unsigned tiles = (unsigned)((int64_t)d.n * (d.h / 8) * (d.w / (narrow ? 8 : 16)));
-    const bool wide_n = d.c_out % 64 == 0;
-    const dim3 grid(tiles, d.c_out / (wide_n ? 64 : 32));
     const auto *xx = (const unsigned short *)x, *ww = (const unsigned short *)w, *gg = (const unsigned short *)gate;
-#define MLBM_CONV(TH, TW, BN)                                                                                    \
-    hipLaunchKernelGGL((k_conv_tile<TH, TW, BN>), grid, dim3(64 * (TH * TW / 32) * (BN / 32)), 0, s, d, xx, ww, \
-                       bias, y, relu, y_f32, gg, gate_stride, gate_offset)
-    if (narrow) {
-        if (wide_n) MLBM_CONV(8, 8, 64);
-        else MLBM_CONV(8, 8, 32);
+#define MLBM_CONV(TH, TW, BN, PM, PN)                                                                               \
+    hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, PM, PN>),                                                           \
+                       dim3((unsigned)((int64_t)d.n * (d.h / TH) * (d.w / TW)), d.c_out / BN),                     \
+                       dim3(conv_threads<TH, TW, BN, PM, PN>()), 0, s, d, xx, ww, bias, y, relu, y_f32, gg,        \
+                       gate_stride, gate_offset)
+    if (d.w == 8) {
+        if (d.c_out % 64 == 0) MLBM_CONV(8, 8, 64, 1, 1);
+        else MLBM_CONV(8, 8, 32, 1, 1);
     } else {
-        if (wide_n) MLBM_CONV(8, 16, 64);
-        else MLBM_CONV(8, 16, 32);
+        if (d.c_out % 64 == 0) MLBM_CONV(8, 16, 64, 1, 1);
+        else MLBM_CONV(8, 16, 32, 1, 1);
     }
 #undef MLBM_CONV
     return check("mlbm_conv_forward");
@@ -694,24 +737,26 @@ int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *
     const bool narrow = d.w == 8, wide = d.c_out % 64 == 0;
     const auto *xx = (const unsigned short *)x, *yy = (const unsigned short *)dy;
     float *wsb = db ? ws + m * sp : nullptr;  // bias partials [split][c_out]
-#define MLBM_WG(TH, TW, BCO, KS)                                                                                  \
-    hipLaunchKernelGGL((k_wgrad_tile<TH, TW, BCO, KS>), dim3(d.c_out / BCO, d.c_in / 32, sp),                     \
-                       dim3(64 * (BCO / 32) * KS), 0, s, d, xx, yy, ws, wsb, per)
+#define MLBM_WG(TH, TW, BCO, KS, CB)                                                                              \
+    hipLaunchKernelGGL((k_wgrad_tile<TH, TW, BCO, KS, CB>), dim3(d.c_out / BCO, d.c_in / 32, sp),                 \
+                       dim3(64 * (BCO / (32 * CB)) * KS), 0, s, d, xx, yy, ws, wsb, per)
     if (d.ksize == 3) {
         if (narrow) {
-            if (wide) MLBM_WG(8, 8, 64, 3);
-            else MLBM_WG(8, 8, 32, 3);
+            if (wide) MLBM_WG(8, 8, 64, 3, 1);
+            else MLBM_WG(8, 8, 32, 3, 1);
         } else {
-            if (wide) MLBM_WG(8, 16, 64, 3);
-            else MLBM_WG(8, 16, 32, 3);
+            // 128 (or 64) output channels per workgroup, two 32-channel blocks per wave
+            if (d.c_out % 128 == 0) MLBM_WG(8, 16, 128, 3, 2);
+            else if (wide) MLBM_WG(8, 16, 64, 3, 2);
+            else MLBM_WG(8, 16, 32, 3, 1);
         }
     } else {
         if (narrow) {
-            if (wide) MLBM_WG(8, 8, 64, 1);
-            else MLBM_WG(8, 8, 32, 1);
+            if (wide) MLBM_WG(8, 8, 64, 1, 1);
+            else MLBM_WG(8, 8, 32, 1, 1);
         } else {
-            if (wide) MLBM_WG(8, 16, 64, 1);
-            else MLBM_WG(8, 16, 32, 1);
+            if (wide) MLBM_WG(8, 16, 64, 1, 1);
+            else MLBM_WG(8, 16, 32, 1, 1);
         }
     }
 #undef MLBM_WG

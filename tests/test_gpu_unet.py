@@ -32,14 +32,17 @@ def _bf(U, a):
     return U.from_bf16_bits(U.to_bf16_bits(a)).astype(np.float64)
 
 
-@pytest.mark.parametrize("k,ci,co", [(3, 32, 64), (3, 96, 32), (1, 32, 32)])
-def test_conv_layer_forward_and_gradients(U, k, ci, co):
+# widths 8 and 16 run the 8 x 8 and 8 x 16 pixel tiles, multiples of 32 the
+# 8 x 32 tiles with 2 x 2 (64 output channels) or 2 x 1 (32) MFMA tiles per wave
+@pytest.mark.parametrize("k,ci,co,w", [(3, 32, 64, 8), (3, 96, 32, 8), (1, 32, 32, 8), (3, 64, 128, 32),
+                                       (3, 96, 64, 32), (1, 32, 32, 32), (3, 32, 96, 64), (3, 64, 32, 16)])
+def test_conv_layer_forward_and_gradients(U, k, ci, co, w):
     import torch
 
     from paper_2312_14789_amd._lib import ConvDesc, check, lib
 
-    rng = np.random.default_rng(k * 1000 + ci + co)
-    n, h, w = 2, 16, 8
+    rng = np.random.default_rng(k * 1000 + ci + co + w)
+    n, h = 2, 16
     x = _bf(U, rng.normal(size=(n, h, w, ci)))
     wt = _bf(U, rng.normal(scale=0.2, size=(k, k, ci, co)))
     b = rng.normal(size=co).astype(np.float32).astype(np.float64)
