@@ -51,7 +51,8 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
 // slice of the input, the tile's input halo ((TH + 2) x (TW + 2) pixels,
 // periodic) and the slice of the weights for every tap are staged in LDS with
 // 16-byte copies, so each staged input value feeds all taps and every MFMA
-// operand is one 16-byte LDS read.  Row pitches of 40 halves (80 B) keep the
+// operand is one 16-byte LDS read; the next slice's pieces are loaded into
+// registers while the current slice is multiplied.  Row pitches of 40 halves (80 B) keep the
 // 16 lanes of each LDS read on distinct banks.
 // Epilogue: bias, ReLU, and optionally a gate (the ReLU gradient of the layer
 // whose output gradient this is: zero where that layer's output is <= 0).
@@ -92,9 +93,19 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     for (int pm = 0; pm < PM; ++pm)
 #pragma unroll
         for (int pn = 0; pn < PN; ++pn) acc[pm][pn] = f32x16{};
-    for (int c0 = 0; c0 < d.c_in; c0 += KC) {
-        __syncthreads();
-        for (int it = threadIdx.x; it < HH * HWD * 4; it += NT) {
+    // This thread's share of a slice's staging: global offsets (without the
+    // slice's first channel c0) and LDS destinations of its 16-byte pieces of
+    // the halo and of the weights of every tap; -1 marks no piece.
+    constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT, WR = (9 * BN * 4 + NT - 1) / NT;
+    const int WN = taps * BN * 4;
+    int64_t xo[XR], wo[WR];
+    int xd[XR], wd[WR];
+#pragma unroll
+    for (int j = 0; j < XR; ++j) {
+        const int it = (int)threadIdx.x + j * NT;
+        xo[j] = -1;
+        xd[j] = 0;
+        if (it < XN) {
             const int hp = it >> 2, q = it & 3;
             const int hy = hp / HWD, hx = hp - hy * HWD;
             int gy = y0 + hy - 1, gx = x0 + hx - 1;
@@ -103,15 +114,43 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
             gx += gx < 0 ? d.w : 0;
             gx -= gx >= d.w ? d.w : 0;
             const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
-            *(u4 *)&xs[hp * XP + 8 * q] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + c0 + 8 * q);
+            xo[j] = gp * d.x_stride + d.x_offset + 8 * q;
+            xd[j] = hp * XP + 8 * q;
         }
-        for (int it = threadIdx.x; it < taps * BN * 4; it += NT) {
+    }
+#pragma unroll
+    for (int j = 0; j < WR; ++j) {
+        const int it = (int)threadIdx.x + j * NT;
+        wo[j] = -1;
+        wd[j] = 0;
+        if (it < WN) {
             const int q = it & 3, rest = it >> 2;
             const int t = rest % taps, co = rest / taps;
-            *(u4 *)&wsm[(t * BN + co) * XP + 8 * q] =
-                *(const u4 *)(w + ((int64_t)(co0 + co) * taps + t) * d.c_in + c0 + 8 * q);
+            wo[j] = ((int64_t)(co0 + co) * taps + t) * d.c_in + 8 * q;
+            wd[j] = (t * BN + co) * XP + 8 * q;
         }
+    }
+    // the next slice is read into registers while the current one is multiplied
+    u4 xr[XR], wr[WR];
+    auto fetch = [&](int c0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < XR; ++j)
+            if (xo[j] >= 0) xr[j] = *(const u4 *)(x + xo[j] + c0);
+#pragma unroll
+        for (int j = 0; j < WR; ++j)
+            if (wo[j] >= 0) wr[j] = *(const u4 *)(w + wo[j] + c0);
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < d.c_in; c0 += KC) {
+        __syncthreads();  // the previous slice's products are done with the LDS
+#pragma unroll
+        for (int j = 0; j < XR; ++j)
+            if (xo[j] >= 0) *(u4 *)&xs[xd[j]] = xr[j];
+#pragma unroll
+        for (int j = 0; j < WR; ++j)
+            if (wo[j] >= 0) *(u4 *)&wsm[wd[j]] = wr[j];
         __syncthreads();
+        if (c0 + KC < d.c_in) fetch(c0 + KC);
         for (int t = 0; t < taps; ++t) {
             const int toff = ((t / ks - r) * HWD + (t % ks - r)) * XP;
             const unsigned short *wt = &wsm[t * BN * XP];
@@ -209,35 +248,66 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
     // bias gradient: the first input-channel block's workgroups also sum dy over their pixels
     const bool bias_sum = wsb && blockIdx.y == 0 && (int)threadIdx.x < BCO;
     float bsum = 0.0f;
-    for (int tile = ta; tile < tb; ++tile) {
+    // This thread's pieces of a tile: 8 pixels x 8 channels of the output
+    // gradient (8 16-byte loads, transposed on the way to dyT) and 16-byte
+    // pieces of the input halo.  The next tile's pieces are loaded into
+    // registers while the current tile is multiplied.
+    constexpr int DN = (BM / 8) * (BCO / 8), DI = (DN + NT - 1) / NT;
+    constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT;
+    u4 dr[DI][8], xr[XR];
+    auto fetch = [&](int tile) __attribute__((always_inline)) {
         const int n = tile / tiles_img, rem = tile % tiles_img;
         const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
-        __syncthreads();
-        // output gradient: 8 pixels x 8 channels per item, transposed into dyT
-        for (int it = threadIdx.x; it < (BM / 8) * (BCO / 8); it += NT) {
-            const int g = it % (BM / 8), c8 = it / (BM / 8);
-            const int p0 = g * 8, ty = p0 / TW, tx = p0 % TW;
-            const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
-            u4 in[8], out[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) in[j] = *(const u4 *)(dy + (gp + j) * d.y_stride + d.y_offset + co0 + 8 * c8);
-            transpose8x8(in, out);
+        for (int i = 0; i < DI; ++i) {
+            const int it = (int)threadIdx.x + i * NT;
+            if (it < DN) {
+                const int g = it % (BM / 8), c8 = it / (BM / 8);
+                const int p0 = g * 8, ty = p0 / TW, tx = p0 % TW;
+                const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) *(u4 *)&dyT[(c8 * 8 + c) * PP + p0] = out[c];
+                for (int j = 0; j < 8; ++j)
+                    dr[i][j] = *(const u4 *)(dy + (gp + j) * d.y_stride + d.y_offset + co0 + 8 * c8);
+            }
         }
-        // input halo, pixel-major
-        for (int it = threadIdx.x; it < HH * HWD * 4; it += NT) {
-            const int hp = it >> 2, q = it & 3;
-            const int hy = hp / HWD, hx = hp - hy * HWD;
-            int gy = y0 + hy - 1, gx = x0 + hx - 1;
-            gy += gy < 0 ? d.h : 0;
-            gy -= gy >= d.h ? d.h : 0;
-            gx += gx < 0 ? d.w : 0;
-            gx -= gx >= d.w ? d.w : 0;
-            const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
-            *(u4 *)&xs[hp * XP + 8 * q] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
+#pragma unroll
+        for (int j = 0; j < XR; ++j) {
+            const int it = (int)threadIdx.x + j * NT;
+            if (it < XN) {
+                const int hp = it >> 2, q = it & 3;
+                const int hy = hp / HWD, hx = hp - hy * HWD;
+                int gy = y0 + hy - 1, gx = x0 + hx - 1;
+                gy += gy < 0 ? d.h : 0;
+                gy -= gy >= d.h ? d.h : 0;
+                gx += gx < 0 ? d.w : 0;
+                gx -= gx >= d.w ? d.w : 0;
+                const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+                xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
+            }
+        }
+    };
+    if (ta < tb) fetch(ta);
+    for (int tile = ta; tile < tb; ++tile) {
+        __syncthreads();  // the previous tile's products are done with the LDS
+        // output gradient transposed into dyT ([channel][pixel]); input halo pixel-major into xs
+#pragma unroll
+        for (int i = 0; i < DI; ++i) {
+            const int it = (int)threadIdx.x + i * NT;
+            if (it < DN) {
+                const int g = it % (BM / 8), c8 = it / (BM / 8);
+                u4 out[8];
+                transpose8x8(dr[i], out);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) *(u4 *)&dyT[(c8 * 8 + c) * PP + g * 8] = out[c];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < XR; ++j) {
+            const int it = (int)threadIdx.x + j * NT;
+            if (it < XN) *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
         }
         __syncthreads();
+        if (tile + 1 < tb) fetch(tile + 1);
         if (bias_sum) {
 #pragma unroll
             for (int p8 = 0; p8 < BM; p8 += 8) {
