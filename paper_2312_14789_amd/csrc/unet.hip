@@ -192,6 +192,94 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     }
 }
 
+// Layers with a single 32-channel input slice (c_in = 32): the weights of
+// every tap are staged once per workgroup and serve TPW consecutive pixel
+// tiles; each tile's input halo is loaded into registers while the previous
+// tile is multiplied.  Same tiles, operand layout and epilogue as k_conv_tile.
+template <int TH, int TW, int BN, int TPW>
+__global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
+    k_conv_tile_s1(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
+                   const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
+                   const unsigned short *__restrict__ gate, int gate_stride, int gate_offset) {
+    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = 64 * WPX * (BN / 32);
+    constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT;
+    __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
+    __shared__ __align__(16) unsigned short wsm[9 * BN * XP];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wp = wave % WPX, wc = wave / WPX;
+    const int tiles_x = d.w / TW, tiles_img = tiles_x * (d.h / TH), n_tiles = d.n * tiles_img;
+    const int ta = blockIdx.x * TPW, tb = min(n_tiles, ta + TPW);
+    const int co0 = blockIdx.y * BN;
+    const int ks = d.ksize, r = ks >> 1, taps = ks * ks;
+    const int row = lane & 31, kh = (lane >> 5) * 8;
+    const int pb = wp * 32 + row;
+    const int aoff = ((pb / TW + 1) * HWD + (pb % TW + 1)) * XP + kh;
+    const int boff = (wc * 32 + row) * XP + kh;
+    for (int it = threadIdx.x; it < taps * BN * 4; it += NT) {
+        const int q = it & 3, rest = it >> 2;
+        const int t = rest % taps, co = rest / taps;
+        *(u4 *)&wsm[(t * BN + co) * XP + 8 * q] = *(const u4 *)(w + ((int64_t)(co0 + co) * taps + t) * d.c_in + 8 * q);
+    }
+    u4 xr[XR];
+    auto fetch = [&](int tile) __attribute__((always_inline)) {
+        const int n = tile / tiles_img, rem = tile % tiles_img;
+        const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
+#pragma unroll
+        for (int j = 0; j < XR; ++j) {
+            const int it = (int)threadIdx.x + j * NT;
+            if (it < XN) {
+                const int hp = it >> 2, q = it & 3;
+                const int hy = hp / HWD, hx = hp - hy * HWD;
+                int gy = y0 + hy - 1, gx = x0 + hx - 1;
+                gy += gy < 0 ? d.h : 0;
+                gy -= gy >= d.h ? d.h : 0;
+                gx += gx < 0 ? d.w : 0;
+                gx -= gx >= d.w ? d.w : 0;
+                const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+                xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + 8 * q);
+            }
+        }
+    };
+    if (ta < tb) fetch(ta);
+    const int col = co0 + wc * 32 + row;
+    const float bv = bias ? bias[col] : 0.0f;
+    for (int tile = ta; tile < tb; ++tile) {
+        __syncthreads();  // the previous tile's products are done with the halo
+#pragma unroll
+        for (int j = 0; j < XR; ++j) {
+            const int it = (int)threadIdx.x + j * NT;
+            if (it < XN) *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
+        }
+        __syncthreads();
+        if (tile + 1 < tb) fetch(tile + 1);
+        f32x16 acc = {};
+        for (int t = 0; t < taps; ++t) {
+            const int toff = ((t / ks - r) * HWD + (t % ks - r)) * XP;
+            const unsigned short *wt = &wsm[t * BN * XP];
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 16)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf8(&xs[aoff + toff + kk]), load_bf8(wt + boff + kk),
+                                                              acc, 0, 0, 0);
+        }
+        if (col < d.c_store) {
+            const int n = tile / tiles_img, rem = tile % tiles_img;
+            const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int pt = wp * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+                const int ty = pt / TW, tx = pt % TW;
+                const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
+                float v = acc[q] + bv;
+                if (relu) v = fmaxf(v, 0.0f);
+                if (gate && !(bf2f(gate[gp * gate_stride + gate_offset + col]) > 0.0f)) v = 0.0f;
+                const int64_t o = gp * d.y_stride + d.y_offset + col;
+                if (y_f32) ((float *)y)[o] = v;
+                else ((unsigned short *)y)[o] = f2bf(v);
+            }
+        }
+    }
+}
+
 // ---- weight gradient -------------------------------------------------------------------------
 // dw[o][tap][i] = sum_p dy[p, o] x[p + tap, i]: an MFMA product whose summed
 // index is the pixel, so both operands need 8 consecutive pixels of one
@@ -777,7 +865,17 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
                        dim3((unsigned)((int64_t)d.n * (d.h / TH) * (d.w / TW)), d.c_out / BN),                     \
                        dim3(conv_threads<TH, TW, BN, PM, PN>()), 0, s, d, xx, ww, bias, y, relu, y_f32, gg,        \
                        gate_stride, gate_offset)
-    if (d.w == 8) {
+    if (d.c_in == KC && d.w % 16 == 0) {
+        // one input slice: weights staged once per workgroup for 4 consecutive tiles
+        constexpr int TPW = 4;
+        const unsigned wgs = (unsigned)(((int64_t)d.n * (d.h / 8) * (d.w / 16) + TPW - 1) / TPW);
+        if (d.c_out % 64 == 0)
+            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, 64, TPW>), dim3(wgs, d.c_out / 64), dim3(512), 0, s, d, xx, ww, bias,
+                               y, relu, y_f32, gg, gate_stride, gate_offset);
+        else
+            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, 32, TPW>), dim3(wgs, d.c_out / 32), dim3(256), 0, s, d, xx, ww, bias,
+                               y, relu, y_f32, gg, gate_stride, gate_offset);
+    } else if (d.w == 8) {
         if (d.c_out % 64 == 0) MLBM_CONV(8, 8, 64, 1, 1);
         else MLBM_CONV(8, 8, 32, 1, 1);
     } else {
