@@ -757,6 +757,9 @@ def warmstart_workload(np, torch, n_train, n_test, epochs, save="", geoms=None):
     rest_s = np.array([r["rest"]["seconds"] for r in rows])
     warm_s = np.array([r["warm"]["seconds"] for r in rows])
     kerr = np.array([abs(r["warm"]["permeability"] / r["rest"]["permeability"] - 1) for r in rows])
+    pe = np.array([r["prediction"]["rel_err"] for r in rows])
+    pf = np.array([r["prediction"]["flux_ratio"] for r in rows])
+    ps = np.array([r["prediction"]["rel_err_flux_matched"] for r in rows])
     if save:
         np.savez(save, **net.state_dict())
     fl = 0.0
@@ -770,6 +773,9 @@ def warmstart_workload(np, torch, n_train, n_test, epochs, save="", geoms=None):
             "seconds_rest_mean": float(rest_s.mean()), "seconds_warm_mean_incl_inference": float(warm_s.mean()),
             "inference_ms_per_sample": round(1e3 * infer, 3),
             "permeability_rel_err_max": float(kerr.max()), "permeability_within_0.5pct": bool(kerr.max() <= 5e-3),
+            "prediction": {"rel_err_mean": float(pe.mean()), "flux_ratio_mean": float(pf.mean()),
+                           "flux_ratio_abs_dev_mean": float(np.abs(pf - 1).mean()),
+                           "rel_err_flux_matched_mean": float(ps.mean())},
             "steps_saved_mean": float((rest_steps - warm_steps).mean()),
             "seconds_saved_mean": float((rest_s - warm_s).mean()),
             "train": {"epochs": epochs, "loss_first": hist[0], "loss_last": hist[-1], "seconds": round(t_train, 1),

@@ -31,12 +31,12 @@ def _p(t):
 
 
 class UNet:
-    def __init__(self, channels=(32, 64, 128, 256, 256), res=256, batch=16, c_out=3, seed=0, device="cuda"):
+    def __init__(self, channels=(32, 64, 128, 256, 256), res=256, batch=16, c_in=1, c_out=3, seed=0, device="cuda"):
         import torch
 
         self.torch = torch
         self.channels = list(channels)
-        self.res, self.batch, self.c_out = res, batch, c_out
+        self.res, self.batch, self.c_in, self.c_out = res, batch, c_in, c_out
         self.L = len(channels)
         self.dev = torch.device(device)
         self.desc = UNetDesc()
@@ -44,7 +44,7 @@ class UNet:
         d.levels = self.L
         for i, c in enumerate(self.channels):
             d.channels[i] = c
-        d.batch, d.res, d.c_in, d.c_out = batch, res, 1, c_out
+        d.batch, d.res, d.c_in, d.c_out = batch, res, c_in, c_out
         sz = UNetBuffers()
         check(lib.mlbm_unet_sizes(ctypes.byref(d), ctypes.byref(sz)))
         self.n_params = int(sz.n_params)
@@ -81,10 +81,10 @@ class UNet:
         rng = np.random.default_rng(seed)
         host = np.zeros(self.n_params, np.float32)
         for nm, k, ci, co, wo, bo in self.layers:
-            fan = k * k * (1 if nm == "enc0a" else ci)
+            fan = k * k * (c_in if nm == "enc0a" else ci)
             w = rng.normal(0.0, np.sqrt(2.0 / fan), size=(co, k * k, ci)).astype(np.float32)
             if nm == "enc0a":
-                w[:, :, 1:] = 0.0
+                w[:, :, c_in:] = 0.0
             if nm == "head":
                 w[c_out:] = 0.0
             host[wo:wo + w.size] = w.ravel()

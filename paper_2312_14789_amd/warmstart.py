@@ -209,7 +209,8 @@ def compare_runs(ns, field, res, g, K=16, tol=1e-6, check_every=100, max_steps=2
     b = M.build_stencils_for(ns, K, ns.h)
     perm = b["perm"]
     res_out = {}
-    for name, init in (("rest", (np.ones(ns.n), np.zeros((ns.n, 2)))), ("warm", node_fields(ns, res, field))):
+    pred = node_fields(ns, res, field)
+    for name, init in (("rest", (np.ones(ns.n), np.zeros((ns.n, 2)))), ("warm", pred)):
         sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.FIELDS, storage=M.F32,
                            tau_plus=1.0, g=(g, 0.0), box_area=float(np.prod(ns.hi - ns.lo)))
         sim.init_state(init[0][perm], init[1][perm])
@@ -220,5 +221,18 @@ def compare_runs(ns, field, res, g, K=16, tol=1e-6, check_every=100, max_steps=2
         dt = time.perf_counter() - t0 + (infer_s if name == "warm" else 0.0)
         k = float(red[M._lib.RED_PERMEABILITY])
         res_out[name] = {"steps": steps, "seconds": dt, "permeability": k, "residual": r}
+        if name == "rest":
+            # the prediction against the steady state it should have been: its
+            # error, the ratio of its flux to the steady flux, and its error
+            # once rescaled to the steady flux (the error of its shape)
+            _, u_ss, _ = sim.macroscopic(ns.h)
+            u_ss = u_ss.cpu().numpy()
+            u_p = pred[1][perm]
+            fl = ns.kind[perm] == nodesets.FLUID
+            a = b["area"][fl]
+            ratio = float(np.sum(a * u_p[fl, 0]) / np.sum(a * u_ss[fl, 0]))
+            nrm = np.linalg.norm(u_ss[fl])
+            res_out["prediction"] = {"rel_err": float(np.linalg.norm(u_p[fl] - u_ss[fl]) / nrm), "flux_ratio": ratio,
+                                     "rel_err_flux_matched": float(np.linalg.norm(u_p[fl] / ratio - u_ss[fl]) / nrm)}
         del sim
     return res_out
