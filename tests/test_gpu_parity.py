@@ -3,9 +3,10 @@ the same seeded inputs.
 
 Small cases feed both sides the oracle's own stencil arrays, so a step bug
 cannot hide behind a weight difference; they run several workgroups with a
-ragged tail.  Full-size cases (the Karman channel and the porous sample)
-use the library's builder and compare sampled nodes after one step with the
-oracle computing those nodes one by one, plus invariants that hold at any
+ragged tail.  Full-size cases (the Karman channel and the porous sample):
+every node after 100 (Karman) or 10 (porous, MLBM1) steps with both sides on
+the builder's FP64 stencils, and sampled nodes after one step with the oracle
+building each sampled node's own stencil, plus invariants that hold at any
 size.  Bars: relative L2 error of the velocity field, 1e-12 for FP64 and
 1e-5 for FP32 state, both on the relative L2 error of the velocity field and
 on its largest node-wise error relative to the largest velocity."""
@@ -584,6 +585,102 @@ def _sampled(M, ns, K, dx, variant, storage, tp, tm, g, amp_u, nsample, seed, la
         pick = np.concatenate([pick, rng.choice(lag_old, 16, replace=False)])
     r_ref, u_ref = oracle_one_step_at(ns, pick, K, dx, variant, rho0, u0, tp, tm, g, lattice_h)
     return rho[inv[pick]], u[inv[pick]], r_ref, u_ref, red.cpu().numpy(), sim, b
+
+
+def _builder_stencils_for_oracle(b):
+    """The library builder's FP64 arrays in the oracle's format (source
+    population k' where the bounce-back bit is set).  Both sides of the
+    all-node parity runs take these, as the parity protocol allows; the
+    builder's stencils themselves are compared with the oracle's own on
+    smaller sets (CPU tests, weights to 1e-10)."""
+    flip = (b["bb"][:, None] >> np.arange(8)[None, :]) & 1
+    src = np.where(flip, omlbm.lt.OPP[np.arange(1, 9)][None, :], np.arange(1, 9)[None, :])
+    return omlbm.Stencils(idx=b["idx"].astype(np.int64), w=b["w"], src=src, point=None, area=b["area"])
+
+
+def _permuted(ns, perm):
+    import copy
+
+    out = copy.copy(ns)
+    out.xy = ns.xy[perm]
+    out.kind = ns.kind[perm]
+    out.bc = ns.boundary_values()[perm]
+    return out
+
+
+_ALL_NODES = {}
+
+
+def _karman_all_nodes(M, steps):
+    """The bench's Karman set (~5e5 Poisson-disk nodes, s = 1, Re 100, BGK),
+    builder stencils in Morton order, smooth seeded initial fields; the
+    oracle's fields after `steps` steps on every node (cached)."""
+    if "karman" not in _ALL_NODES:
+        from paper_2312_14789_amd import units
+
+        ns = nodesets.karman(poisson=True)
+        dx = units.delta_x(ns.h_min, 1.0)
+        tau = units.tau_for_reynolds(0.05, 1.0, dx, 100.0)
+        b = M.build_stencils_for(ns, 16, dx)
+        nsp = _permuted(ns, b["perm"])
+        rho0, u0 = initial_fields(nsp, 31, 0.05, 0.002)
+        st = _builder_stencils_for_oracle(b)
+        f = omlbm.init_populations(rho0, u0)
+        for t in range(steps):
+            f = omlbm.step(f, nsp, st, tau, tau)
+            if t % 20 == 19:
+                print(f"[all-nodes] karman oracle step {t + 1}/{steps}", flush=True)
+        r_ref, u_ref = omlbm.macroscopic(f, nsp)
+        _ALL_NODES["karman"] = (nsp, b, dx, tau, rho0, u0, r_ref, u_ref)
+    return _ALL_NODES["karman"]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage", [1, 0])
+def test_karman_full_size_100_steps_all_nodes(M, storage):
+    # the bench's workload at full size, every node compared after 100 steps
+    # (the bench's launch shape: 256-node LDS tiles, XCD-contiguous tiles,
+    # alternating sweeps)
+    steps = 100
+    nsp, b, dx, tau, rho0, u0, r_ref, u_ref = _karman_all_nodes(M, steps)
+    print(f"[all-nodes] karman n={nsp.n} storage={storage}", flush=True)
+    sim = M.Simulation(b["idx"], b["w"], b["bb"], nsp.kind, b["area"], variant=0, storage=storage, tau_plus=tau,
+                       tau_minus=tau, bc=nsp.bc, tile=256)
+    sim.init_state(rho0, u0)
+    sim.step(steps)
+    rho, u, red = sim.macroscopic(dx)
+    e2, em = assert_fields_close(u.cpu().numpy(), u_ref, BAR[storage], "karman all nodes")
+    print(f"[all-nodes] karman storage={storage} rel_l2 {e2:.2e} rel_max {em:.2e}", flush=True)
+    assert np.abs(rho.cpu().numpy() - r_ref).max() < (1e-12 if storage == 0 else 1e-6)
+    assert red.cpu().numpy()[M._lib.RED_N_BAD] == 0
+
+
+@pytest.mark.timeout(600)
+def test_porous_full_size_10_steps_all_nodes(M):
+    # the 1e6-node porous sample, MLBM1 with a body force, every node
+    # compared after 10 steps (FP32 fields; the oracle takes ~8 s per step
+    # here)
+    ns = nodesets.porous()
+    dx = ns.h
+    g = (1e-5, 0.0)
+    b = M.build_stencils_for(ns, 16, dx)
+    nsp = _permuted(ns, b["perm"])
+    rho0, u0 = initial_fields(nsp, 33, 0.01, 0.002)
+    st = _builder_stencils_for_oracle(b)
+    r, u = rho0.copy(), u0.copy()
+    steps = 10
+    for t in range(steps):
+        r, u = omlbm.mlbm1_step(r, u, nsp, st, g)
+        if t % 2 == 1:
+            print(f"[all-nodes] porous oracle step {t + 1}/{steps}", flush=True)
+    sim = M.Simulation(b["idx"], b["w"], b["bb"], nsp.kind, b["area"], variant=1, storage=1, tau_plus=1.0, g=g,
+                       tile=256)
+    sim.init_state(rho0, u0)
+    sim.step(steps)
+    rho, ug, red = sim.macroscopic(dx)
+    e2, em = assert_fields_close(ug.cpu().numpy(), u, 1e-5, "porous all nodes")
+    print(f"[all-nodes] porous n={ns.n} rel_l2 {e2:.2e} rel_max {em:.2e}", flush=True)
+    assert np.abs(rho.cpu().numpy() - r).max() < 1e-6
 
 
 @pytest.mark.parametrize("s,reorder", [(1.0, 1), (4.0, 1), (1.0, 2)])
