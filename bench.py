@@ -27,10 +27,11 @@ METRIC = "MNUPS and HBM fraction of fused step; time-to-steady-state plain vs wa
 
 
 def kernel_source_digest():
-    """Digest of what decides a step kernel's traffic: the device code of
-    mlbm_step.hip (everything before its dispatch section), mlbm_step's
-    launch logic, the shared device helpers and the eight-lane kernels;
-    host-only entry points elsewhere do not void the stored counters."""
+    """Digest of what decides the one-lane step kernels' traffic: the device
+    code of mlbm_step.hip (everything before its dispatch section),
+    mlbm_step's launch logic and the device helpers they include; host-only
+    entry points and the eight-lane kernels (a file of their own) do not void
+    the stored counters."""
     csrc = os.path.join(ROOT, "paper_2312_14789_amd", "csrc")
     with open(os.path.join(csrc, "mlbm_step.hip")) as f:
         src = f.read()
@@ -40,9 +41,8 @@ def kernel_source_digest():
     h = hashlib.sha256()
     h.update(device.encode())
     h.update(launch.encode())
-    for name in ("mlbm_device.h", "mlbm_lanes.hip"):
-        with open(os.path.join(csrc, name)) as f:
-            h.update(f.read().encode())
+    with open(os.path.join(csrc, "mlbm_device.h")) as f:
+        h.update(f.read().encode())
     return h.hexdigest()[:16]
 
 
