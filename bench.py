@@ -825,8 +825,39 @@ def mapping_workload(M, nodesets, np, torch, sides=(64, 128, 256, 512), steps=20
             print(f"# {ns.n} nodes {row['variant']}: one lane {best1[0]} us ({best1[1]}), eight lanes "
                   f"{best8[0]} us ({best8[1]})", file=sys.stderr, flush=True)
             rows.append(row)
+    # the paper's coarsened cylinder channel: a hybrid set (block centres and
+    # scattered nodes in one launch), K = 25, TRT, Re 105 (the Strouhal set)
+    ns = nodesets.karman_paper()
+    tau = 0.53
+    tau_m = 0.5 + (3.0 / 16.0) / (tau - 0.5)
+    dx = 1e-2 * 0.14 / (105.0 * (tau - 0.5) / 3.0)
+    b = M.build_stencils_for(ns, 25, dx, lattice_h=ns.h, simple_bounce_back=True)
+    perm = b["perm"]
+    row = {"nodes": ns.n, "variant": "populations, hybrid cylinder channel (K=25, TRT)", "us_per_step": {}}
+    for lanes, tile in [(1, 64), (1, 128), (1, 256), (8, 64), (8, 128)]:
+        sim = M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=M.POPULATIONS, storage=M.F32,
+                           tau_plus=tau, tau_minus=tau_m, bc=ns.boundary_values()[perm], tile=tile,
+                           lagrange=b["lagrange"], w_lagrange=b["w_lagrange"], lanes_per_node=lanes, graph_steps=100)
+        sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
+        sim.step(warmup, stream=stream)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        row["us_per_step"][f"lanes{lanes}-tile{tile}"] = round(e0.elapsed_time(e1) * 1e3 / steps, 2)
+        del sim
+    best1 = min((v, k) for k, v in row["us_per_step"].items() if k.startswith("lanes1"))
+    best8 = min((v, k) for k, v in row["us_per_step"].items() if k.startswith("lanes8"))
+    row.update(best_one_lane=best1[1], best_eight_lanes=best8[1], speedup_eight_lanes=round(best1[0] / best8[0], 3),
+               block_centres=int(b["n_lagrange"]))
+    print(f"# {ns.n} nodes hybrid cylinder channel: one lane {best1[0]} us ({best1[1]}), eight lanes "
+          f"{best8[0]} us ({best8[1]})", file=sys.stderr, flush=True)
+    rows.append(row)
     return {"metric": "step time, one lane vs eight lanes per node",
-            "workload": "periodic jittered grids (jitter 0.3 h), K=16, s=1.5, FP32, graph replay of 100 steps",
+            "workload": "periodic jittered grids (jitter 0.3 h), K=16, s=1.5, FP32, graph replay of 100 steps; "
+                        "the paper's coarsened cylinder channel (hybrid, K=25, TRT, Re 105)",
             "rows": rows}
 
 

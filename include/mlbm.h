@@ -280,9 +280,11 @@ typedef struct mlbm_step_params {
                                 small to fill the GPU.
                                 With tile 64 or 128 a workgroup holds 8 x tile lanes;
                                 with tile 0, block lanes for block / 8 nodes.  Per-node
-                                stencils with K padded to 12, 16, 28 or 32 members;
-                                hybrid sets (w_lagrange), per-departure stencils and
-                                tile 256 give MLBM_ERR_UNSUPPORTED                  */
+                                stencils with K padded to 12, 16, 28 or 32 members, and
+                                hybrid sets (w_lagrange) in one launch per step with
+                                tile 64 or 128; per-departure stencils, tile 256, and
+                                hybrid sets without tiles or with hybrid_launches = 2
+                                give MLBM_ERR_UNSUPPORTED                            */
 } mlbm_step_params;
 
 typedef struct mlbm_device_state {

@@ -485,5 +485,8 @@ using StepFn = void (*)(const StepArgs);
 // form, any storage, per-node stencils of kq member quads (3, 4, 7 or 8),
 // LDS-staged tiles or global gathers; nullptr if there is none.
 StepFn pick_step_lanes_any(int storage, int variant, int kq, bool lds, int w16);
+// The same for a hybrid set in one launch per step (per-node tiles first,
+// then the block-centre tiles; LDS-staged tiles).
+StepFn pick_step_lanes_hyb_any(int storage, int variant, int kq, int w16);
 
 }  // namespace mlbm_dev

@@ -19,8 +19,10 @@
 //
 // Workgroups: with LDS-staged tiles of T nodes (64 or 128), 8 T lanes per
 // workgroup staging the tile's halo exactly as the one-lane kernels do;
-// with global gathers, `block` lanes for block / 8 nodes.  Per-node stencils
-// only (not hybrid block centres, not one stencil per departure point).
+// with global gathers, `block` lanes for block / 8 nodes.  Per-node stencils,
+// and hybrid sets in one launch per step (the block centres gather their
+// eight lattice neighbours and themselves with the shared biquadratic
+// weights, Sec. 2.2); not one stencil per departure point.
 
 #include <hip/hip_runtime.h>
 
@@ -90,11 +92,45 @@ __device__ __forceinline__ C collide_lane(const C *f, int k, C mine, C opp, C om
     return first ? fa + sym + asy : fb + sym - asy;
 }
 
+// The tile's halo into LDS as the one-lane kernels stage it; the tile holds
+// T = blockDim.x / 8 nodes and *self0 receives the halo position of its first
+// node (its nodes sit at consecutive positions of the sorted halo).
+template <int NB>
+__device__ __forceinline__ void stage_halo_self(const StepArgs &a, int64_t tile, void *smem, int *self0) {
+    __syncthreads();
+    const int h0 = a.halo_off[tile], hn = a.halo_off[tile + 1] - h0;
+    const int64_t first = tile * (int64_t)(blockDim.x >> 3);
+    if constexpr (NB >= 16) {
+        constexpr int U = NB / 16;
+        const u4 *src = (const u4 *)a.in;
+        u4 *dst = (u4 *)smem;
+        for (int e = threadIdx.x; e < hn * U; e += blockDim.x) {
+            const int h = e / U, c = e - h * U;
+            const int node = a.halo[h0 + h];
+            if (c == 0 && node == first) *self0 = h;
+            dst[e] = src[(int64_t)node * U + c];
+        }
+    } else {
+        const u2 *src = (const u2 *)a.in;
+        u2 *dst = (u2 *)smem;
+        for (int h = threadIdx.x; h < hn; h += blockDim.x) {
+            const int node = a.halo[h0 + h];
+            if (node == first) *self0 = h;
+            dst[h] = src[node];
+        }
+    }
+    __syncthreads();
+}
+
 // first lane of this lane's group of eight in the wavefront
 __device__ __forceinline__ int group_base() { return (int)(threadIdx.x & 63u) & ~7; }
 
+// KQ = 0: a block centre of a hybrid set (members: its eight lattice
+// neighbours, then itself at position self); the node ranges split at lag0 as
+// in the one-lane kernels.
 template <int S, class CG, class C, int KQ, bool LDS, bool W16>
-__device__ __forceinline__ void pop_lanes(const StepArgs &a, const void *src, int64_t i, int k) {
+__device__ __forceinline__ void pop_lanes(const StepArgs &a, const void *src, int64_t i, int k, int self) {
+    if ((KQ == 0) != (i >= a.lag0)) return;  // the other part's node (the whole group)
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     if (kind_of(fl) == MLBM_DIRICHLET) {
@@ -109,19 +145,32 @@ __device__ __forceinline__ void pop_lanes(const StepArgs &a, const void *src, in
     const int c = ((bb >> k) & 1u) ? (k ^ 2) : k;
     constexpr bool kWsum = S == MLBM_F64;  // as the one-lane kernels (interpolated weight sum)
     CG acc = CG(0), sw = CG(0);
-    u4 lv;
-    for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
-        constexpr int q = decltype(qc)::value;
-        int m[4];
-        members<LDS, q>(a, n, i, lv, m);
-        CG wv[4];
-        load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
+    if constexpr (KQ == 0) {
+        // the shared biquadratic weights of population k + 1 (no bounce-back here)
+        if (!(fl & MLBM_FLAG_LAGRANGE)) acc = CG(NAN);
+        int m[9];
+        block_members<LDS>(a, n, i, self, m);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc = fma(wv[j], load_comp<S, CG>(src, m[j], c, a.inv_scale), acc);
-            if constexpr (kWsum) sw += wv[j];
+        for (int j = 0; j < 9; ++j) {
+            const CG wv = block_weight<S, CG>(a, k * 9 + j);
+            acc = fma(wv, load_comp<S, CG>(src, m[j], k, a.inv_scale), acc);
+            if constexpr (kWsum) sw += wv;
         }
-    });
+    } else {
+        u4 lv;
+        for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            int m[4];
+            members<LDS, q>(a, n, i, lv, m);
+            CG wv[4];
+            load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc = fma(wv[j], load_comp<S, CG>(src, m[j], c, a.inv_scale), acc);
+                if constexpr (kWsum) sw += wv[j];
+            }
+        });
+    }
     const int base = group_base();
     C f[9];
     f[0] = load1<S, C>(a.in, n, i, a.inv_scale);
@@ -150,7 +199,8 @@ __device__ __forceinline__ void pop_lanes(const StepArgs &a, const void *src, in
 }
 
 template <int S, class CG, class C, int KQ, bool LDS, bool W16>
-__device__ __forceinline__ void fields_lanes(const StepArgs &a, const void *src, int64_t i, int k) {
+__device__ __forceinline__ void fields_lanes(const StepArgs &a, const void *src, int64_t i, int k, int self) {
+    if ((KQ == 0) != (i >= a.lag0)) return;  // the other part's node (the whole group)
     const int64_t n = a.n;
     const unsigned fl = a.flags[i];
     if (kind_of(fl) == MLBM_DIRICHLET) {
@@ -165,24 +215,41 @@ __device__ __forceinline__ void fields_lanes(const StepArgs &a, const void *src,
     const unsigned bb = fl & 0xffu;
     constexpr bool kWsum = S == MLBM_F64;  // interpolate rho itself, not rho - 1
     CG ar = CG(0), au = CG(0), av = CG(0), sw = CG(0);
-    u4 lv;
-    for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
-        constexpr int q = decltype(qc)::value;
-        int mi[4];
-        members<LDS, q>(a, n, i, lv, mi);
-        CG m[4][3];
+    if constexpr (KQ == 0) {
+        // the shared biquadratic weights of departure point k + 1
+        if (!(fl & MLBM_FLAG_LAGRANGE)) ar = CG(NAN);
+        int mi[9];
+        block_members<LDS>(a, n, i, self, mi);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) load3<S>(src, mi[j], m[j], a.inv_scale);
-        CG wv[4];
-        load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            ar = fma(wv[j], m[j][0], ar);
-            au = fma(wv[j], m[j][1], au);
-            av = fma(wv[j], m[j][2], av);
-            if constexpr (kWsum) sw += wv[j];
+        for (int j = 0; j < 9; ++j) {
+            CG m[3];
+            load3<S>(src, mi[j], m, a.inv_scale);
+            const CG wv = block_weight<S, CG>(a, k * 9 + j);
+            ar = fma(wv, m[0], ar);
+            au = fma(wv, m[1], au);
+            av = fma(wv, m[2], av);
+            if constexpr (kWsum) sw += wv;
         }
-    });
+    } else {
+        u4 lv;
+        for_quads<0, KQ>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            int mi[4];
+            members<LDS, q>(a, n, i, lv, mi);
+            CG m[4][3];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) load3<S>(src, mi[j], m[j], a.inv_scale);
+            CG wv[4];
+            load_w4<S, KQ, W16>(a.w, n, i, k, q, wv, a.cached);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ar = fma(wv[j], m[j][0], ar);
+                au = fma(wv[j], m[j][1], au);
+                av = fma(wv[j], m[j][2], av);
+                if constexpr (kWsum) sw += wv[j];
+            }
+        });
+    }
     if constexpr (kWsum) ar += sw - CG(1);
     const C gx = (C)a.gx, gy = (C)a.gy;
     // equilibrium (plus half the force) of the interpolated fields for the
@@ -228,7 +295,7 @@ __global__ void __launch_bounds__(1024) k_step_pop_l8(const StepArgs a) {
     if (tile >= a.tile1) return;
     if constexpr (LDS) stage_halo<pop_bytes<S>(), false>(a, tile, smem, &unused);
     const int64_t i = tile * (int64_t)(blockDim.x >> 3) + (threadIdx.x >> 3);
-    if (i < a.n) pop_lanes<S, CG, C, KQ, LDS, W16>(a, LDS ? (const void *)smem : a.in, i, (int)(threadIdx.x & 7u));
+    if (i < a.n) pop_lanes<S, CG, C, KQ, LDS, W16>(a, LDS ? (const void *)smem : a.in, i, (int)(threadIdx.x & 7u), (int)i);
 }
 
 template <int S, class CG, class C, int KQ, bool LDS, bool W16>
@@ -239,7 +306,77 @@ __global__ void __launch_bounds__(1024) k_step_fields_l8(const StepArgs a) {
     if (tile >= a.tile1) return;
     if constexpr (LDS) stage_halo<field_bytes<S>(), false>(a, tile, smem, &unused);
     const int64_t i = tile * (int64_t)(blockDim.x >> 3) + (threadIdx.x >> 3);
-    if (i < a.n) fields_lanes<S, CG, C, KQ, LDS, W16>(a, LDS ? (const void *)smem : a.in, i, (int)(threadIdx.x & 7u));
+    if (i < a.n) fields_lanes<S, CG, C, KQ, LDS, W16>(a, LDS ? (const void *)smem : a.in, i, (int)(threadIdx.x & 7u), (int)i);
+}
+
+// Hybrid sets in one launch (as the one-lane k_step_pop_hyb): workgroups
+// [0, split) take the tiles of the nodes with per-node weights (LDS staged),
+// the later ones the block-centre tiles, which 16-bit states stage in LDS and
+// 32- and 64-bit states gather from global memory.
+template <int S> constexpr bool block_tiles_staged_l8() { return Fmt<S>::TB == 2; }
+
+template <bool POP, int S, class CG, class C, int KQ, bool W16>
+__device__ __forceinline__ void hyb_lanes(const StepArgs &a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int self0;
+    constexpr int NB = POP ? pop_bytes<S>() : field_bytes<S>();
+    const int64_t b = blockIdx.x;
+    const int64_t tn = blockDim.x >> 3;
+    const int k = (int)(threadIdx.x & 7u), loc = (int)(threadIdx.x >> 3);
+    auto node = [&](auto kq, bool lds, const void *src, int64_t i, int self) __attribute__((always_inline)) {
+        constexpr int Q = decltype(kq)::value;
+        if (lds) {
+            if constexpr (POP) pop_lanes<S, CG, C, Q, true, Q == 0 ? false : W16>(a, src, i, k, self);
+            else fields_lanes<S, CG, C, Q, true, Q == 0 ? false : W16>(a, src, i, k, self);
+        } else {
+            if constexpr (POP) pop_lanes<S, CG, C, Q, false, false>(a, src, i, k, self);
+            else fields_lanes<S, CG, C, Q, false, false>(a, src, i, k, self);
+        }
+    };
+    if (b < a.split) {
+        const int64_t tile = a.tile0 + tile_at(a, b, a.grid8);
+        if (tile >= a.tile1) return;
+        stage_halo<NB, false>(a, tile, smem, &self0);
+        const int64_t i = tile * tn + loc;
+        if (i < a.n) node(std::integral_constant<int, KQ>{}, true, (const void *)smem, i, (int)i);
+    } else {
+        const int64_t tile = a.tile0b + tile_at(a, b - a.split, a.grid8b);
+        if (tile >= a.tile1b) return;
+        const int64_t i = tile * tn + loc;
+        if constexpr (block_tiles_staged_l8<S>()) {
+            stage_halo_self<NB>(a, tile, smem, &self0);
+            if (i < a.n) node(std::integral_constant<int, 0>{}, true, (const void *)smem, i, self0 + loc);
+        } else {
+            if (i < a.n) node(std::integral_constant<int, 0>{}, false, a.in, i, (int)i);
+        }
+    }
+}
+
+template <int S, class CG, class C, int KQ, bool W16>
+__global__ void __launch_bounds__(1024) k_step_pop_hyb_l8(const StepArgs a) {
+    hyb_lanes<true, S, CG, C, KQ, W16>(a);
+}
+
+template <int S, class CG, class C, int KQ, bool W16>
+__global__ void __launch_bounds__(1024) k_step_fields_hyb_l8(const StepArgs a) {
+    hyb_lanes<false, S, CG, C, KQ, W16>(a);
+}
+
+template <int S, class CG, class C, bool W16 = false>
+StepFn pick_lanes_hyb(int variant, int kq) {
+#define MLBM_CASE(Q)                                                                              \
+    case Q:                                                                                       \
+        return variant == MLBM_POPULATIONS ? (StepFn)k_step_pop_hyb_l8<S, CG, C, Q, W16>          \
+                                           : (StepFn)k_step_fields_hyb_l8<S, CG, C, Q, W16>;
+    switch (kq) {
+        MLBM_CASE(3)
+        MLBM_CASE(4)
+        MLBM_CASE(7)
+        MLBM_CASE(8)
+        default:
+            return nullptr;
+    }
+#undef MLBM_CASE
 }
 
 template <int S, class CG, class C, bool W16 = false>
@@ -276,6 +413,20 @@ StepFn pick_step_lanes_any(int storage, int variant, int kq, bool lds, int w16) 
         case MLBM_BF16:
             return w16 ? pick_lanes<MLBM_BF16, float, float, true>(variant, kq, lds)
                        : pick_lanes<MLBM_BF16, float, float>(variant, kq, lds);
+    }
+    return nullptr;
+}
+
+StepFn pick_step_lanes_hyb_any(int storage, int variant, int kq, int w16) {
+    switch (storage) {
+        case MLBM_F64: return pick_lanes_hyb<MLBM_F64, double, double>(variant, kq);
+        case MLBM_F32: return pick_lanes_hyb<MLBM_F32, float, double>(variant, kq);
+        case MLBM_F16S:
+            return w16 ? pick_lanes_hyb<MLBM_F16S, float, float, true>(variant, kq)
+                       : pick_lanes_hyb<MLBM_F16S, float, float>(variant, kq);
+        case MLBM_BF16:
+            return w16 ? pick_lanes_hyb<MLBM_BF16, float, float, true>(variant, kq)
+                       : pick_lanes_hyb<MLBM_BF16, float, float>(variant, kq);
     }
     return nullptr;
 }

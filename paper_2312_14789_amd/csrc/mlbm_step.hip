@@ -983,7 +983,8 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     const int lanes = p->lanes_per_node == 0 ? 1 : p->lanes_per_node;
     if (lanes != 1 && lanes != 8) return fail(MLBM_ERR_ARG, "lanes_per_node must be 0, 1 or 8");
     if (lanes == 8) {
-        if (st->w_lagrange) return fail(MLBM_ERR_UNSUPPORTED, "eight lanes per node: not for hybrid sets (block weights)");
+        if (st->w_lagrange && (!lds || p->hybrid_launches != 0))
+            return fail(MLBM_ERR_UNSUPPORTED, "eight lanes per node on a hybrid set: one launch per step with tiles only");
         if (st->per_departure) return fail(MLBM_ERR_UNSUPPORTED, "eight lanes per node: not for per-departure stencils");
         if (lds && st->tile > 128)
             return fail(MLBM_ERR_UNSUPPORTED, "eight lanes per node need tiles of 64 or 128 nodes (8 x tile <= 1024 lanes)");
@@ -1055,8 +1056,11 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
     const bool fuse = fb && lds && p->hybrid_launches == 0 && ranges[0][1] > 0;
     a.split = 0;
     a.tile0b = a.tile1b = a.grid8b = 0;
+    if (lanes == 8 && fb && !fuse)
+        return fail(MLBM_ERR_UNSUPPORTED, "eight lanes per node on a hybrid set needs nodes with per-node weights");
     if (fuse) {
-        fns[0] = pick_step_hyb_any(p->storage, p->variant, kq, p->weights16);
+        fns[0] = lanes == 8 ? pick_step_lanes_hyb_any(p->storage, p->variant, kq, p->weights16)
+                            : pick_step_hyb_any(p->storage, p->variant, kq, p->weights16);
         if (!fns[0]) return fail(MLBM_ERR_UNSUPPORTED, "no hybrid kernel for storage %d, K=%d", p->storage, st->K);
         fns[1] = nullptr;
         const int64_t cb = ranges[1][1] - ranges[1][0];

@@ -434,8 +434,11 @@ def test_zero_steps_and_errors(M):
         sim.step(1)
 
 
-@pytest.mark.parametrize("name", ["tgv64", "channel_trt", "karman_small", "porous_fields", "k25_fields"])
-@pytest.mark.parametrize("storage,tile", [(0, 0), (1, 0), (0, 64), (1, 64), (1, 128)])
+@pytest.mark.parametrize("name,storage,tile", [(n, s_, t) for n in ("tgv64", "channel_trt", "karman_small",
+                                                                      "porous_fields", "k25_fields")
+                                                for s_, t in ((0, 0), (1, 0), (0, 64), (1, 64), (1, 128))]
+                         + [(n, s_, t) for n in ("hybrid_tgv", "hybrid_pixels_fields")
+                            for s_, t in ((0, 64), (1, 64), (1, 128))])
 def test_eight_lanes_per_node_equal_one_lane(M, name, storage, tile):
     # the same steps with a group of eight lanes per node: parity with the
     # oracle at the same bar, and agreement with one lane per node to rounding
@@ -460,7 +463,10 @@ def test_eight_lanes_per_node_equal_one_lane(M, name, storage, tile):
                                               ("porous_fields", 2, dict(stochastic_rounding=1, scale_exp=16)),
                                               ("porous_fields", 3, dict(stochastic_rounding=1, weights16=1)),
                                               ("channel_trt", 2, dict(stochastic_rounding=1, scale_exp=12,
-                                                                      weights16=1))])
+                                                                      weights16=1)),
+                                              ("hybrid_tgv", 2, dict(stochastic_rounding=1, scale_exp=12,
+                                                                     weights16=1)),
+                                              ("hybrid_pixels_fields", 2, dict(stochastic_rounding=1, scale_exp=16))])
 def test_eight_lanes_per_node_16bit_states(M, name, storage, kw):
     # 16-bit states: the two mappings agree to the storage's rounding (a
     # last-bit difference before a store can move a value by one ulp)
@@ -494,9 +500,11 @@ def test_eight_lanes_per_node_graph_replay(M):
 
 
 def test_eight_lanes_per_node_refusals(M):
-    # hybrid sets, per-departure stencils, 256-node tiles and stencil sizes
-    # without an eight-lane kernel are refused, not launched
-    for name, kw in (("hybrid_tgv", dict(tile=64)), ("pd_tgv", dict(tile=64)), ("tgv64", dict(tile=256))):
+    # hybrid sets without tiles or in two launches, per-departure stencils,
+    # 256-node tiles and stencil sizes without an eight-lane kernel are
+    # refused, not launched
+    for name, kw in (("hybrid_tgv", dict(tile=0)), ("hybrid_tgv", dict(tile=64, hybrid_launches=2)),
+                     ("pd_tgv", dict(tile=64)), ("tgv64", dict(tile=256))):
         ns, st, var, tp, tm, g, steps, rho0, u0, dx, *_ = _case(name)
         sim = sim_from_oracle(M, ns, st, var, 1, tp, tm, g, lanes_per_node=8, **kw)
         sim.init_state(rho0, u0)
