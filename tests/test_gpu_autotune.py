@@ -23,18 +23,19 @@ def M():
     return mlbm
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-def test_tuned_simulation_matches_default_shape(M, variant, tmp_path):
+@pytest.mark.parametrize("variant,hybrid", [(0, False), (1, False), (0, True)])
+def test_tuned_simulation_matches_default_shape(M, variant, hybrid, tmp_path):
     from paper_2312_14789_amd import autotune
 
-    ns = nodesets.karman(n_target=20000, seed=9)
-    b = M.build_stencils_for(ns, 16, ns.h_min)
+    ns = nodesets.karman(n_target=20000, seed=9, hybrid=hybrid)
+    b = M.build_stencils_for(ns, 16, ns.h_min, lattice_h=ns.h if hybrid else 0.0)
     perm = b["perm"]
     tau = 1.0 if variant == 1 else 0.7
+    lag = dict(lagrange=b["lagrange"], w_lagrange=b["w_lagrange"]) if hybrid else {}
 
     def make():
         return M.Simulation(b["idx"], b["w"], b["bb"], ns.kind[perm], b["area"], variant=variant, storage=M.F32,
-                            tau_plus=tau, bc=ns.boundary_values()[perm])
+                            tau_plus=tau, bc=ns.boundary_values()[perm], **lag)
 
     ref = make()
     ref.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))
@@ -45,9 +46,9 @@ def test_tuned_simulation_matches_default_shape(M, variant, tmp_path):
           f"sweeps={best['sweeps']} {best['ms_per_step'] * 1e3:.1f} us/step over {len(best['timings'])} shapes",
           flush=True)
     # one lane per node with every tile; eight lanes per node with the tiles
-    # it supports (global gathers, 64 and 128 nodes)
+    # it supports (global gathers, 64 and 128 nodes; hybrid sets: 64 and 128)
     per_tile = len(autotune.XCD) * len(autotune.SIM_SWEEPS)
-    assert len(best["timings"]) == (len(autotune.SIM_TILES) + 3) * per_tile
+    assert len(best["timings"]) == (len(autotune.SIM_TILES) + (2 if hybrid else 3)) * per_tile
     assert {r["lanes"] for r in best["timings"]} == {1, 8}
     assert sim.ds.tile == best["tile"] and sim.params.lanes_per_node == best["lanes"]
     sim.init_state(np.ones(ns.n), np.zeros((ns.n, 2)))

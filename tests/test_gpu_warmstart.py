@@ -46,6 +46,9 @@ def test_warm_start_gains_over_rest(W):
     for (ns, _), f in zip(test_g, preds):
         r = W.compare_runs(ns, f, res, g, infer_s=infer)
         rel = abs(r["warm"]["permeability"] / r["rest"]["permeability"] - 1)
+        p = r["prediction"]
+        # the prediction against the steady state: a finite error, a flux of the right sign and size
+        assert np.isfinite(p["rel_err"]) and p["rel_err"] < 1.0 and 0.5 < p["flux_ratio"] < 1.5
         print(f"[warm] steps rest {r['rest']['steps']} warm {r['warm']['steps']} k err {rel:.2e}", flush=True)
         assert rel <= 5e-3
         gains.append(r["rest"]["steps"] / r["warm"]["steps"])
