@@ -942,6 +942,24 @@ int64_t wgrad_workspace(const mlbm_conv_desc &d, int splits) {
     return (m + d.c_out) * sp * (int64_t)sizeof(float);
 }
 
+// Pixel splits of a weight gradient: one round of workgroups (as many as the
+// GPU holds at once for the configuration wgrad_launch picks, set by the LDS
+// each takes) spread over the output blocks, and further whole rounds while a
+// workgroup would sweep more than 24 pixel tiles.  One round keeps the split
+// partials, which are written and read back once more to be summed, smallest;
+// a part of a round leaves some compute units a workgroup more than others.
+int wgrad_splits(const mlbm_conv_desc &d) {
+    const bool wide = d.c_out % 64 == 0;
+    int bco = wide ? 64 : 32, round = 512;
+    if (d.ksize == 3 && d.w != 8 && d.c_out % 128 == 0) bco = 128, round = 256;
+    else if (d.ksize == 1) round = 1024;
+    const int64_t tiles = conv_tiles(d), blocks = (int64_t)(d.c_out / bco) * (d.c_in / 32);
+    const int64_t per_round = std::max<int64_t>(1, (round + blocks - 1) / blocks);
+    int64_t sp = per_round;
+    while ((tiles + sp - 1) / sp > 24 && sp < tiles) sp += per_round;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, sp));
+}
+
 // 8-channel paths when every channel count, stride and offset is a multiple of 8
 bool v8(int c, int a, int b, int e, int f) { return ((c | a | b | e | f) & 7) == 0; }
 
@@ -1188,7 +1206,6 @@ int net_plan(const mlbm_unet *u, Net &n) {
         ly.wf_off = ph;
         ly.wd_off = ph + m;
         ph += 2 * m;
-        // enough weight-gradient workgroups to fill the GPU several times over
         mlbm_conv_desc d{};
         const int Rl = n.R >> ly.level;
         d.n = n.B;
@@ -1196,8 +1213,7 @@ int net_plan(const mlbm_unet *u, Net &n) {
         d.c_in = ly.c_in;
         d.c_out = ly.c_out;
         d.ksize = ly.ksize;
-        const int64_t blocks_per_split = (int64_t)(ly.c_out / (ly.c_out % 64 == 0 ? 64 : 32)) * (ly.c_in / 32);
-        ly.splits = (int)std::max<int64_t>(1, std::min<int64_t>(conv_tiles(d), (1024 + blocks_per_split - 1) / blocks_per_split));
+        ly.splits = wgrad_splits(d);
         ws = std::max(ws, wgrad_workspace(d, ly.splits));
     }
     n.n_params = pf;
