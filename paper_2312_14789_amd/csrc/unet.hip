@@ -61,7 +61,7 @@ constexpr int KC = 32, XP = KC + 8;
 template <int TH, int TW, int BN, int PM, int PN>
 constexpr int conv_threads() { return 64 * (TH * TW / (32 * PM)) * (BN / (32 * PN)); }
 
-template <int TH, int TW, int BN, int PM = 1, int PN = 1>
+template <int TH, int TW, int BN, int KS, int PM = 1, int PN = 1>
 __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     k_conv_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                 const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
@@ -70,14 +70,14 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     constexpr int NT = conv_threads<TH, TW, BN, PM, PN>();
     static_assert(BM % (32 * PM) == 0 && BN % (32 * PN) == 0, "wave tiles must divide the block");
     __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
-    __shared__ __align__(16) unsigned short wsm[9 * BN * XP];
+    __shared__ __align__(16) unsigned short wsm[KS * KS * BN * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wp = wave % WPX, wc = wave / WPX;
     const int tiles_x = d.w / TW, tiles_img = tiles_x * (d.h / TH);
     const int n = blockIdx.x / tiles_img, rem = blockIdx.x % tiles_img;
     const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
     const int co0 = blockIdx.y * BN;
-    const int ks = d.ksize, r = ks >> 1, taps = ks * ks;
+    constexpr int ks = KS, r = KS >> 1, taps = KS * KS;
     const int row = lane & 31, kh = (lane >> 5) * 8;
     // LDS offsets of this lane's A rows (pixels) at tap offset (0, 0) and B rows (channels)
     int aoff[PM], boff[PN];
@@ -151,6 +151,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
             if (wo[j] >= 0) *(u4 *)&wsm[wd[j]] = wr[j];
         __syncthreads();
         if (c0 + KC < d.c_in) fetch(c0 + KC);
+#pragma unroll
         for (int t = 0; t < taps; ++t) {
             const int toff = ((t / ks - r) * HWD + (t % ks - r)) * XP;
             const unsigned short *wt = &wsm[t * BN * XP];
@@ -196,7 +197,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
 // every tap are staged once per workgroup and serve TPW consecutive pixel
 // tiles; each tile's input halo is loaded into registers while the previous
 // tile is multiplied.  Same tiles, operand layout and epilogue as k_conv_tile.
-template <int TH, int TW, int BN, int TPW>
+template <int TH, int TW, int BN, int KS, int TPW>
 __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     k_conv_tile_s1(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                    const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
@@ -204,13 +205,13 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = 64 * WPX * (BN / 32);
     constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT;
     __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
-    __shared__ __align__(16) unsigned short wsm[9 * BN * XP];
+    __shared__ __align__(16) unsigned short wsm[KS * KS * BN * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wp = wave % WPX, wc = wave / WPX;
     const int tiles_x = d.w / TW, tiles_img = tiles_x * (d.h / TH), n_tiles = d.n * tiles_img;
     const int ta = blockIdx.x * TPW, tb = min(n_tiles, ta + TPW);
     const int co0 = blockIdx.y * BN;
-    const int ks = d.ksize, r = ks >> 1, taps = ks * ks;
+    constexpr int ks = KS, r = KS >> 1, taps = KS * KS;
     const int row = lane & 31, kh = (lane >> 5) * 8;
     const int pb = wp * 32 + row;
     const int aoff = ((pb / TW + 1) * HWD + (pb % TW + 1)) * XP + kh;
@@ -253,6 +254,7 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
         __syncthreads();
         if (tile + 1 < tb) fetch(tile + 1);
         f32x16 acc = {};
+#pragma unroll
         for (int t = 0; t < taps; ++t) {
             const int toff = ((t / ks - r) * HWD + (t % ks - r)) * XP;
             const unsigned short *wt = &wsm[t * BN * XP];
@@ -860,21 +862,31 @@ namespace {
 int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const float *bias, void *y, int relu, int y_f32,
                 const void *gate, int gate_stride, int gate_offset, hipStream_t s) {
     const auto *xx = (const unsigned short *)x, *ww = (const unsigned short *)w, *gg = (const unsigned short *)gate;
-#define MLBM_CONV(TH, TW, BN, PM, PN)                                                                               \
-    hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, PM, PN>),                                                           \
+#define MLBM_CONV_K(TH, TW, BN, KS, PM, PN)                                                                         \
+    hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, KS, PM, PN>),                                                       \
                        dim3((unsigned)((int64_t)d.n * (d.h / TH) * (d.w / TW)), d.c_out / BN),                     \
                        dim3(conv_threads<TH, TW, BN, PM, PN>()), 0, s, d, xx, ww, bias, y, relu, y_f32, gg,        \
                        gate_stride, gate_offset)
+#define MLBM_CONV(TH, TW, BN, PM, PN)                                                                               \
+    do {                                                                                                            \
+        if (d.ksize == 3) MLBM_CONV_K(TH, TW, BN, 3, PM, PN);                                                       \
+        else MLBM_CONV_K(TH, TW, BN, 1, PM, PN);                                                                    \
+    } while (0)
+#define MLBM_CONV_S1(BN, TPW)                                                                                       \
+    do {                                                                                                            \
+        if (d.ksize == 3)                                                                                           \
+            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 3, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
+                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset);                        \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 1, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
+                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset);                        \
+    } while (0)
     if (d.c_in == KC && d.w % 16 == 0) {
         // one input slice: weights staged once per workgroup for 4 consecutive tiles
         constexpr int TPW = 4;
         const unsigned wgs = (unsigned)(((int64_t)d.n * (d.h / 8) * (d.w / 16) + TPW - 1) / TPW);
-        if (d.c_out % 64 == 0)
-            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, 64, TPW>), dim3(wgs, d.c_out / 64), dim3(512), 0, s, d, xx, ww, bias,
-                               y, relu, y_f32, gg, gate_stride, gate_offset);
-        else
-            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, 32, TPW>), dim3(wgs, d.c_out / 32), dim3(256), 0, s, d, xx, ww, bias,
-                               y, relu, y_f32, gg, gate_stride, gate_offset);
+        if (d.c_out % 64 == 0) MLBM_CONV_S1(64, TPW);
+        else MLBM_CONV_S1(32, TPW);
     } else if (d.w == 8) {
         if (d.c_out % 64 == 0) MLBM_CONV(8, 8, 64, 1, 1);
         else MLBM_CONV(8, 8, 32, 1, 1);
@@ -882,7 +894,9 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
         if (d.c_out % 64 == 0) MLBM_CONV(8, 16, 64, 1, 1);
         else MLBM_CONV(8, 16, 32, 1, 1);
     }
+#undef MLBM_CONV_S1
 #undef MLBM_CONV
+#undef MLBM_CONV_K
     return check("mlbm_conv_forward");
 }
 
