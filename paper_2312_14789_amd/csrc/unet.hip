@@ -293,8 +293,9 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
 // registers on 8 x 8 blocks (8 pixels x 8 channels, one 16-byte load each)
 // and are written with 16-byte LDS stores.  Wave (co group h, tap row j) sums
 // the KS taps of its row for CB blocks of 32 output channels, so each output
-// gradient fragment feeds KS products and each input fragment CB.  Partials
-// per split go to ws[split][c_out][taps][c_in].
+// gradient fragment feeds KS products and each input fragment CB.  Split k's
+// partials go to ws + k * row_stride as [c_out][taps][c_in], its bias sums to
+// wsb + k * row_stride.
 
 // in[r] = 8 values of row r (value 2k in the low half of dword k); out[c] = column c
 __device__ __forceinline__ void transpose8x8(const u4 in[8], u4 out[8]) {
@@ -315,7 +316,7 @@ constexpr int XTS = 16 * 10 + 8;  // halves per channel of a transposed halo cop
 template <int TH, int TW, int BCO, int KS, int CB = 1>
 __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
     k_wgrad_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
-                 float *__restrict__ ws, float *__restrict__ wsb, int tiles_per_split) {
+                 float *__restrict__ ws, float *__restrict__ wsb, int64_t row_stride, int tiles_per_split) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / (32 * CB)) * KS, PP = BM + 8;
     static_assert(HH <= 10 && TW <= 16, "transposed halo copies hold up to 10 rows of 16");
     static_assert(BCO % (32 * CB) == 0 && NT >= BCO, "wave groups must divide the block; one thread per bias sum");
@@ -437,7 +438,7 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
             }
         }
     }
-    if (bias_sum) wsb[(int64_t)split * d.c_out + co0 + threadIdx.x] = bsum;
+    if (bias_sum) wsb[split * row_stride + co0 + threadIdx.x] = bsum;
     const int ci = ci0 + row;
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -447,25 +448,25 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int co = co0 + (ch * CB + cb) * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
-                ws[(((int64_t)split * d.c_out + co) * taps + t) * d.c_in + ci] = acc[cb][s][q];
+                ws[split * row_stride + ((int64_t)co * taps + t) * d.c_in + ci] = acc[cb][s][q];
             }
         }
     }
 }
 
-// sum of the split partials, dw[c_out][taps][c_in]: G lanes per element, lane
-// group g sums splits g, g + G, ..., then the G sums are added in a fixed tree
-// order (deterministic)
+// sum of the split partials (split k's m values at ws + k * stride): G lanes
+// per element, lane group g sums splits g, g + G, ..., then the G sums are
+// added in a fixed tree order (deterministic)
 template <int G>
 __global__ void __launch_bounds__(64 * G) k_sum_splits_g(const float *__restrict__ ws, int splits, int64_t m,
-                                                        float *__restrict__ dw) {
+                                                        int64_t stride, float *__restrict__ dw) {
     __shared__ float part[G][64];
     const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + e;
     float s = 0.0f;
     if (i < m) {
 #pragma unroll 8
-        for (int k = g; k < splits; k += G) s += ws[(int64_t)k * m + i];
+        for (int k = g; k < splits; k += G) s += ws[(int64_t)k * stride + i];
     }
     part[g][e] = s;
     __syncthreads();
@@ -477,11 +478,11 @@ __global__ void __launch_bounds__(64 * G) k_sum_splits_g(const float *__restrict
     if (g == 0 && i < m) dw[i] = part[0][e];
 }
 
-void sum_splits(const float *ws, int splits, int64_t m, float *dw, hipStream_t s) {
+void sum_splits(const float *ws, int splits, int64_t m, int64_t stride, float *dw, hipStream_t s) {
     const dim3 grid((unsigned)((m + 63) / 64));
-    if (splits >= 64) hipLaunchKernelGGL(k_sum_splits_g<16>, grid, dim3(1024), 0, s, ws, splits, m, dw);
-    else if (splits >= 8) hipLaunchKernelGGL(k_sum_splits_g<4>, grid, dim3(256), 0, s, ws, splits, m, dw);
-    else hipLaunchKernelGGL(k_sum_splits_g<1>, grid, dim3(64), 0, s, ws, splits, m, dw);
+    if (splits >= 64) hipLaunchKernelGGL(k_sum_splits_g<16>, grid, dim3(1024), 0, s, ws, splits, m, stride, dw);
+    else if (splits >= 8) hipLaunchKernelGGL(k_sum_splits_g<4>, grid, dim3(256), 0, s, ws, splits, m, stride, dw);
+    else hipLaunchKernelGGL(k_sum_splits_g<1>, grid, dim3(64), 0, s, ws, splits, m, stride, dw);
 }
 
 // ---- weights: FP32 master -> bf16 forward layout and flipped data-gradient layout ------
@@ -496,6 +497,27 @@ __global__ void k_weights_bf16(const float *wm, int c_out, int taps, int c_in, u
     const unsigned short v = f2bf(wm[i]);
     if (wf) wf[i] = v;
     if (wd) wd[((int64_t)ci * taps + (taps - 1 - t)) * c_out + co] = v;
+}
+
+// every layer's conversion in one launch: layer j covers elements [start[j], start[j + 1])
+constexpr int MAX_WJOBS = 4 * MLBM_UNET_MAX_LEVELS;
+struct WeightJobs {
+    int n;
+    int64_t start[MAX_WJOBS + 1];
+    int64_t w_off[MAX_WJOBS], wf_off[MAX_WJOBS], wd_off[MAX_WJOBS];
+    int c_out[MAX_WJOBS], taps[MAX_WJOBS], c_in[MAX_WJOBS];
+};
+
+__global__ void k_weights_all(const float *__restrict__ params, unsigned short *__restrict__ wbf, const WeightJobs jb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= jb.start[jb.n]) return;
+    int j = 0;
+    while (i >= jb.start[j + 1]) ++j;
+    const int k = (int)(i - jb.start[j]), c_in = jb.c_in[j], taps = jb.taps[j];
+    const int ci = k % c_in, t = (k / c_in) % taps, co = k / (c_in * taps);
+    const unsigned short v = f2bf(params[jb.w_off[j] + k]);
+    wbf[jb.wf_off[j] + k] = v;
+    wbf[jb.wd_off[j] + ((int64_t)ci * taps + (taps - 1 - t)) * jb.c_out[j] + co] = v;
 }
 
 // ---- elementwise layers -------------------------------------------------------------------
@@ -918,10 +940,12 @@ int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *
     const int64_t m = (int64_t)d.c_out * taps * d.c_in;
     const bool narrow = d.w == 8, wide = d.c_out % 64 == 0;
     const auto *xx = (const unsigned short *)x, *yy = (const unsigned short *)dy;
-    float *wsb = db ? ws + m * sp : nullptr;  // bias partials [split][c_out]
+    // split k's partials: ws[k * row][0, m) weights, [m, m + c_out) bias
+    const int64_t row = m + d.c_out;
+    float *wsb = db ? ws + m : nullptr;
 #define MLBM_WG(TH, TW, BCO, KS, CB)                                                                              \
     hipLaunchKernelGGL((k_wgrad_tile<TH, TW, BCO, KS, CB>), dim3(d.c_out / BCO, d.c_in / 32, sp),                 \
-                       dim3(64 * (BCO / (32 * CB)) * KS), 0, s, d, xx, yy, ws, wsb, per)
+                       dim3(64 * (BCO / (32 * CB)) * KS), 0, s, d, xx, yy, ws, wsb, row, per)
     if (d.ksize == 3) {
         if (narrow) {
             if (wide) MLBM_WG(8, 8, 64, 3, 1);
@@ -944,8 +968,12 @@ int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *
 #undef MLBM_WG
     int rc = check("mlbm_conv_wgrad");
     if (rc) return rc;
-    sum_splits(ws, sp, m, dw, s);
-    if (db) sum_splits(wsb, sp, d.c_out, db, s);
+    if (db == dw + m) {
+        sum_splits(ws, sp, row, row, dw, s);  // weights and bias in one pass
+    } else {
+        sum_splits(ws, sp, m, row, dw, s);
+        if (db) sum_splits(wsb, sp, d.c_out, row, db, s);
+    }
     return check("mlbm_conv_wgrad");
 }
 
@@ -1346,12 +1374,21 @@ extern "C" int mlbm_unet_refresh(const mlbm_unet *u, void *stream) {
     int rc = net_plan(u, n);
     if (rc) return rc;
     if (!u->params || !u->w_bf16) return mlbm::fail(MLBM_ERR_ARG, "null params or w_bf16");
-    unsigned short *wbf = (unsigned short *)u->w_bf16;
-    for (const Layer &ly : n.layers) {
-        const int64_t m = (int64_t)ly.c_out * ly.ksize * ly.ksize * ly.c_in;
-        hipLaunchKernelGGL(k_weights_bf16, dim3(blocks(m)), dim3(256), 0, (hipStream_t)stream, u->params + ly.w_off,
-                           ly.c_out, ly.ksize * ly.ksize, ly.c_in, wbf + ly.wf_off, wbf + ly.wd_off);
+    WeightJobs jb{};
+    if ((int)n.layers.size() > MAX_WJOBS) return mlbm::fail(MLBM_ERR_ARG, "too many layers");
+    jb.n = (int)n.layers.size();
+    for (int j = 0; j < jb.n; ++j) {
+        const Layer &ly = n.layers[j];
+        jb.w_off[j] = ly.w_off;
+        jb.wf_off[j] = ly.wf_off;
+        jb.wd_off[j] = ly.wd_off;
+        jb.c_out[j] = ly.c_out;
+        jb.taps[j] = ly.ksize * ly.ksize;
+        jb.c_in[j] = ly.c_in;
+        jb.start[j + 1] = jb.start[j] + (int64_t)ly.c_out * jb.taps[j] * ly.c_in;
     }
+    hipLaunchKernelGGL(k_weights_all, dim3(blocks(jb.start[jb.n])), dim3(256), 0, (hipStream_t)stream, u->params,
+                       (unsigned short *)u->w_bf16, jb);
     return check("mlbm_unet_refresh");
 }
 
