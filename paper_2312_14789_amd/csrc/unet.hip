@@ -58,6 +58,49 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
 // whose output gradient this is: zero where that layer's output is <= 0).
 constexpr int KC = 32, XP = KC + 8;
 
+// Epilogue of one 32 x 32 MFMA result of a forward tile: bias, ReLU, the
+// gate (zero where the gate value is not positive) and the store of channel
+// col at the lane's 16 pixels pt0 + (q / 4) * 8 + (lane >> 5) * 4 + q % 4 of the
+// TW-wide tile at (y0, x0) of image n.  The gate values are all loaded before
+// any is used, so their loads overlap.
+template <int TW>
+__device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16 &acc, int n, int y0, int x0, int pt0,
+                                           int col, float bv, int relu, int y_f32, void *__restrict__ y,
+                                           const unsigned short *__restrict__ gate, int gate_stride, int gate_offset,
+                                           int lane) {
+    if (col >= d.c_store) return;
+    const int64_t g0 = ((int64_t)n * d.h + y0) * d.w + x0;
+    int off[16];  // pixels from the tile's origin
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int pt = pt0 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+        off[q] = (pt / TW) * d.w + pt % TW;
+    }
+    float gv[16];
+    if (gate) {
+        const unsigned short *gb = gate + g0 * gate_stride + gate_offset + col;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) gv[q] = bf2f(gb[off[q] * gate_stride]);
+    }
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        v[q] = acc[q] + bv;
+        if (relu) v[q] = fmaxf(v[q], 0.0f);
+        if (gate && !(gv[q] > 0.0f)) v[q] = 0.0f;
+    }
+    const int64_t o0 = g0 * d.y_stride + d.y_offset + col;
+    if (y_f32) {
+        float *yb = (float *)y + o0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) yb[off[q] * d.y_stride] = v[q];
+    } else {
+        unsigned short *yb = (unsigned short *)y + o0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) yb[off[q] * d.y_stride] = f2bf(v[q]);
+    }
+}
+
 template <int TH, int TW, int BN, int PM, int PN>
 constexpr int conv_threads() { return 64 * (TH * TW / (32 * PM)) * (BN / (32 * PN)); }
 
@@ -95,60 +138,49 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
         for (int pn = 0; pn < PN; ++pn) acc[pm][pn] = f32x16{};
     // This thread's share of a slice's staging: global offsets (without the
     // slice's first channel c0) and LDS destinations of its 16-byte pieces of
-    // the halo and of the weights of every tap; -1 marks no piece.
-    constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT, WR = (9 * BN * 4 + NT - 1) / NT;
-    const int WN = taps * BN * 4;
+    // the halo and of the weights of every tap.  Threads past the last piece
+    // repeat it (the same bytes to the same place), so loads and stores need no
+    // branches: a load under a branch waits for every load before it.
+    constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT, WN = taps * BN * 4, WR = (WN + NT - 1) / NT;
     int64_t xo[XR], wo[WR];
     int xd[XR], wd[WR];
 #pragma unroll
     for (int j = 0; j < XR; ++j) {
-        const int it = (int)threadIdx.x + j * NT;
-        xo[j] = -1;
-        xd[j] = 0;
-        if (it < XN) {
-            const int hp = it >> 2, q = it & 3;
-            const int hy = hp / HWD, hx = hp - hy * HWD;
-            int gy = y0 + hy - 1, gx = x0 + hx - 1;
-            gy += gy < 0 ? d.h : 0;
-            gy -= gy >= d.h ? d.h : 0;
-            gx += gx < 0 ? d.w : 0;
-            gx -= gx >= d.w ? d.w : 0;
-            const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
-            xo[j] = gp * d.x_stride + d.x_offset + 8 * q;
-            xd[j] = hp * XP + 8 * q;
-        }
+        const int it = min((int)threadIdx.x + j * NT, XN - 1);
+        const int hp = it >> 2, q = it & 3;
+        const int hy = hp / HWD, hx = hp - hy * HWD;
+        int gy = y0 + hy - 1, gx = x0 + hx - 1;
+        gy += gy < 0 ? d.h : 0;
+        gy -= gy >= d.h ? d.h : 0;
+        gx += gx < 0 ? d.w : 0;
+        gx -= gx >= d.w ? d.w : 0;
+        const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+        xo[j] = gp * d.x_stride + d.x_offset + 8 * q;
+        xd[j] = hp * XP + 8 * q;
     }
 #pragma unroll
     for (int j = 0; j < WR; ++j) {
-        const int it = (int)threadIdx.x + j * NT;
-        wo[j] = -1;
-        wd[j] = 0;
-        if (it < WN) {
-            const int q = it & 3, rest = it >> 2;
-            const int t = rest % taps, co = rest / taps;
-            wo[j] = ((int64_t)(co0 + co) * taps + t) * d.c_in + 8 * q;
-            wd[j] = (t * BN + co) * XP + 8 * q;
-        }
+        const int it = min((int)threadIdx.x + j * NT, WN - 1);
+        const int q = it & 3, rest = it >> 2;
+        const int t = rest % taps, co = rest / taps;
+        wo[j] = ((int64_t)(co0 + co) * taps + t) * d.c_in + 8 * q;
+        wd[j] = (t * BN + co) * XP + 8 * q;
     }
     // the next slice is read into registers while the current one is multiplied
     u4 xr[XR], wr[WR];
     auto fetch = [&](int c0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < XR; ++j)
-            if (xo[j] >= 0) xr[j] = *(const u4 *)(x + xo[j] + c0);
+        for (int j = 0; j < XR; ++j) xr[j] = *(const u4 *)(x + xo[j] + c0);
 #pragma unroll
-        for (int j = 0; j < WR; ++j)
-            if (wo[j] >= 0) wr[j] = *(const u4 *)(w + wo[j] + c0);
+        for (int j = 0; j < WR; ++j) wr[j] = *(const u4 *)(w + wo[j] + c0);
     };
     fetch(0);
     for (int c0 = 0; c0 < d.c_in; c0 += KC) {
         __syncthreads();  // the previous slice's products are done with the LDS
 #pragma unroll
-        for (int j = 0; j < XR; ++j)
-            if (xo[j] >= 0) *(u4 *)&xs[xd[j]] = xr[j];
+        for (int j = 0; j < XR; ++j) *(u4 *)&xs[xd[j]] = xr[j];
 #pragma unroll
-        for (int j = 0; j < WR; ++j)
-            if (wo[j] >= 0) *(u4 *)&wsm[wd[j]] = wr[j];
+        for (int j = 0; j < WR; ++j) *(u4 *)&wsm[wd[j]] = wr[j];
         __syncthreads();
         if (c0 + KC < d.c_in) fetch(c0 + KC);
 #pragma unroll
@@ -173,23 +205,11 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
 #pragma unroll
     for (int pn = 0; pn < PN; ++pn) {
         const int col = co0 + (wc * PN + pn) * 32 + row;
-        if (col >= d.c_store) continue;
-        const float bv = bias ? bias[col] : 0.0f;
+        const float bv = bias && col < d.c_store ? bias[col] : 0.0f;
 #pragma unroll
-        for (int pm = 0; pm < PM; ++pm) {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int pt = (wp * PM + pm) * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
-                const int ty = pt / TW, tx = pt % TW;
-                const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
-                float v = acc[pm][pn][q] + bv;
-                if (relu) v = fmaxf(v, 0.0f);
-                if (gate && !(bf2f(gate[gp * gate_stride + gate_offset + col]) > 0.0f)) v = 0.0f;
-                const int64_t o = gp * d.y_stride + d.y_offset + col;
-                if (y_f32) ((float *)y)[o] = v;
-                else ((unsigned short *)y)[o] = f2bf(v);
-            }
-        }
+        for (int pm = 0; pm < PM; ++pm)
+            store_tile<TW>(d, acc[pm][pn], n, y0, x0, (wp * PM + pm) * 32, col, bv, relu, y_f32, y, gate, gate_stride,
+                           gate_offset, lane);
     }
 }
 
@@ -216,10 +236,23 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     const int pb = wp * 32 + row;
     const int aoff = ((pb / TW + 1) * HWD + (pb % TW + 1)) * XP + kh;
     const int boff = (wc * 32 + row) * XP + kh;
-    for (int it = threadIdx.x; it < taps * BN * 4; it += NT) {
-        const int q = it & 3, rest = it >> 2;
-        const int t = rest % taps, co = rest / taps;
-        *(u4 *)&wsm[(t * BN + co) * XP + 8 * q] = *(const u4 *)(w + ((int64_t)(co0 + co) * taps + t) * d.c_in + 8 * q);
+    {
+        // every piece loaded before any is stored, so the loads overlap; threads
+        // past the last piece repeat it
+        constexpr int WN = taps * BN * 4, WR = (WN + NT - 1) / NT;
+        u4 wr[WR];
+#pragma unroll
+        for (int j = 0; j < WR; ++j) {
+            const int it = min((int)threadIdx.x + j * NT, WN - 1);
+            const int q = it & 3, rest = it >> 2;
+            wr[j] = *(const u4 *)(w + ((int64_t)(co0 + rest / taps) * taps + rest % taps) * d.c_in + 8 * q);
+        }
+#pragma unroll
+        for (int j = 0; j < WR; ++j) {
+            const int it = min((int)threadIdx.x + j * NT, WN - 1);
+            const int q = it & 3, rest = it >> 2;
+            *(u4 *)&wsm[((rest % taps) * BN + rest / taps) * XP + 8 * q] = wr[j];
+        }
     }
     u4 xr[XR];
     auto fetch = [&](int tile) __attribute__((always_inline)) {
@@ -227,18 +260,17 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
         const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
 #pragma unroll
         for (int j = 0; j < XR; ++j) {
-            const int it = (int)threadIdx.x + j * NT;
-            if (it < XN) {
-                const int hp = it >> 2, q = it & 3;
-                const int hy = hp / HWD, hx = hp - hy * HWD;
-                int gy = y0 + hy - 1, gx = x0 + hx - 1;
-                gy += gy < 0 ? d.h : 0;
-                gy -= gy >= d.h ? d.h : 0;
-                gx += gx < 0 ? d.w : 0;
-                gx -= gx >= d.w ? d.w : 0;
-                const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
-                xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + 8 * q);
-            }
+            // threads past the last piece repeat it: no branch around the loads
+            const int it = min((int)threadIdx.x + j * NT, XN - 1);
+            const int hp = it >> 2, q = it & 3;
+            const int hy = hp / HWD, hx = hp - hy * HWD;
+            int gy = y0 + hy - 1, gx = x0 + hx - 1;
+            gy += gy < 0 ? d.h : 0;
+            gy -= gy >= d.h ? d.h : 0;
+            gx += gx < 0 ? d.w : 0;
+            gx -= gx >= d.w ? d.w : 0;
+            const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+            xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + 8 * q);
         }
     };
     if (ta < tb) fetch(ta);
@@ -248,8 +280,8 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
         __syncthreads();  // the previous tile's products are done with the halo
 #pragma unroll
         for (int j = 0; j < XR; ++j) {
-            const int it = (int)threadIdx.x + j * NT;
-            if (it < XN) *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
+            const int it = min((int)threadIdx.x + j * NT, XN - 1);
+            *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
         }
         __syncthreads();
         if (tile + 1 < tb) fetch(tile + 1);
@@ -263,22 +295,9 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf8(&xs[aoff + toff + kk]), load_bf8(wt + boff + kk),
                                                               acc, 0, 0, 0);
         }
-        if (col < d.c_store) {
-            const int n = tile / tiles_img, rem = tile % tiles_img;
-            const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int pt = wp * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
-                const int ty = pt / TW, tx = pt % TW;
-                const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
-                float v = acc[q] + bv;
-                if (relu) v = fmaxf(v, 0.0f);
-                if (gate && !(bf2f(gate[gp * gate_stride + gate_offset + col]) > 0.0f)) v = 0.0f;
-                const int64_t o = gp * d.y_stride + d.y_offset + col;
-                if (y_f32) ((float *)y)[o] = v;
-                else ((unsigned short *)y)[o] = f2bf(v);
-            }
-        }
+        const int n = tile / tiles_img, rem = tile % tiles_img;
+        store_tile<TW>(d, acc, n, (rem / tiles_x) * TH, (rem % tiles_x) * TW, wp * 32, col, bv, relu, y_f32, y, gate,
+                       gate_stride, gate_offset, lane);
     }
 }
 
@@ -349,6 +368,22 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
     auto fetch = [&](int tile) __attribute__((always_inline)) {
         const int n = tile / tiles_img, rem = tile % tiles_img;
         const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
+        // halo pieces without a branch (threads past the last piece repeat it):
+        // a load under a branch waits for every load before it
+#pragma unroll
+        for (int j = 0; j < XR; ++j) {
+            const int it = min((int)threadIdx.x + j * NT, XN - 1);
+            const int hp = it >> 2, q = it & 3;
+            const int hy = hp / HWD, hx = hp - hy * HWD;
+            int gy = y0 + hy - 1, gx = x0 + hx - 1;
+            gy += gy < 0 ? d.h : 0;
+            gy -= gy >= d.h ? d.h : 0;
+            gx += gx < 0 ? d.w : 0;
+            gx -= gx >= d.w ? d.w : 0;
+            const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+            xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
+        }
+        // output-gradient blocks: whole waves have none when DN < NT
 #pragma unroll
         for (int i = 0; i < DI; ++i) {
             const int it = (int)threadIdx.x + i * NT;
@@ -359,21 +394,6 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
                     dr[i][j] = *(const u4 *)(dy + (gp + j) * d.y_stride + d.y_offset + co0 + 8 * c8);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < XR; ++j) {
-            const int it = (int)threadIdx.x + j * NT;
-            if (it < XN) {
-                const int hp = it >> 2, q = it & 3;
-                const int hy = hp / HWD, hx = hp - hy * HWD;
-                int gy = y0 + hy - 1, gx = x0 + hx - 1;
-                gy += gy < 0 ? d.h : 0;
-                gy -= gy >= d.h ? d.h : 0;
-                gx += gx < 0 ? d.w : 0;
-                gx -= gx >= d.w ? d.w : 0;
-                const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
-                xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
             }
         }
     };
@@ -394,8 +414,8 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
         }
 #pragma unroll
         for (int j = 0; j < XR; ++j) {
-            const int it = (int)threadIdx.x + j * NT;
-            if (it < XN) *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
+            const int it = min((int)threadIdx.x + j * NT, XN - 1);
+            *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
         }
         __syncthreads();
         if (tile + 1 < tb) fetch(tile + 1);
