@@ -82,7 +82,8 @@ int mlbm_unet_layer(const mlbm_unet *net, int32_t index, mlbm_unet_layer_info *o
 int mlbm_unet_refresh(const mlbm_unet *net, void *hip_stream);
 
 /* Forward pass of x (bf16 [batch][res][res][32]) into out (FP32
- * [batch][res][res][32]); keeps the activations in act. */
+ * [batch][res][res][32]; channels c_out .. 31 are not written); keeps the
+ * activations in act. */
 int mlbm_unet_forward(const mlbm_unet *net, const void *x, float *out, void *hip_stream);
 
 /* loss = sum_p mask[p] sum_{c < c_out} (out[p, c] - target[p, c])^2 / (c_out

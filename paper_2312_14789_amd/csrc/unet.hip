@@ -58,16 +58,25 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
 // whose output gradient this is: zero where that layer's output is <= 0).
 constexpr int KC = 32, XP = KC + 8;
 
+// 2 x 2 average pooling of a layer's stored (bf16) output, written by its
+// epilogue: pooled pixel (y, x) of channel c at p[(n, y, x) * stride + offset + c]
+struct PoolOut {
+    unsigned short *p;
+    int stride, offset;
+};
+
 // Epilogue of one 32 x 32 MFMA result of a forward tile: bias, ReLU, the
 // gate (zero where the gate value is not positive) and the store of channel
 // col at the lane's 16 pixels pt0 + (q / 4) * 8 + (lane >> 5) * 4 + q % 4 of the
 // TW-wide tile at (y0, x0) of image n.  The gate values are all loaded before
-// any is used, so their loads overlap.
+// any is used, so their loads overlap.  With po.p set (bf16 output, 16-wide
+// tiles), the lane also writes the 2 x 2 averages of its pixels: q, q + 1,
+// q + 8 and q + 9 (q = 0, 2, 4, 6) are the corners of one block.
 template <int TW>
 __device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16 &acc, int n, int y0, int x0, int pt0,
                                            int col, float bv, int relu, int y_f32, void *__restrict__ y,
                                            const unsigned short *__restrict__ gate, int gate_stride, int gate_offset,
-                                           int lane) {
+                                           int lane, const PoolOut &po) {
     if (col >= d.c_store) return;
     const int64_t g0 = ((int64_t)n * d.h + y0) * d.w + x0;
     int off[16];  // pixels from the tile's origin
@@ -98,6 +107,21 @@ __device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16
         unsigned short *yb = (unsigned short *)y + o0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) yb[off[q] * d.y_stride] = f2bf(v[q]);
+        if constexpr (TW == 16) {
+            if (po.p) {
+                // the same sum order as the pooling layer: (x00 + x01) + x10, then + x11
+                const int w2 = d.w / 2;
+                const int64_t pb = ((int64_t)n * (d.h / 2) + y0 / 2) * w2 + x0 / 2;
+#pragma unroll
+                for (int q = 0; q < 8; q += 2) {
+                    const int pt = pt0 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4);
+                    float a = bf2f(f2bf(v[q])) + bf2f(f2bf(v[q + 1]));
+                    a += bf2f(f2bf(v[q + 8]));
+                    a = 0.25f * (a + bf2f(f2bf(v[q + 9])));
+                    po.p[(pb + (int64_t)(pt / 32) * w2 + (pt % 16) / 2) * po.stride + po.offset + col] = f2bf(a);
+                }
+            }
+        }
     }
 }
 
@@ -108,7 +132,7 @@ template <int TH, int TW, int BN, int KS, int PM = 1, int PN = 1>
 __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     k_conv_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                 const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
-                const unsigned short *__restrict__ gate, int gate_stride, int gate_offset) {
+                const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / (32 * PM);
     constexpr int NT = conv_threads<TH, TW, BN, PM, PN>();
     static_assert(BM % (32 * PM) == 0 && BN % (32 * PN) == 0, "wave tiles must divide the block");
@@ -209,7 +233,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
 #pragma unroll
         for (int pm = 0; pm < PM; ++pm)
             store_tile<TW>(d, acc[pm][pn], n, y0, x0, (wp * PM + pm) * 32, col, bv, relu, y_f32, y, gate, gate_stride,
-                           gate_offset, lane);
+                           gate_offset, lane, po);
     }
 }
 
@@ -221,7 +245,7 @@ template <int TH, int TW, int BN, int KS, int TPW>
 __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     k_conv_tile_s1(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                    const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
-                   const unsigned short *__restrict__ gate, int gate_stride, int gate_offset) {
+                   const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = 64 * WPX * (BN / 32);
     constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT;
     __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
@@ -297,7 +321,7 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
         }
         const int n = tile / tiles_img, rem = tile % tiles_img;
         store_tile<TW>(d, acc, n, (rem / tiles_x) * TH, (rem % tiles_x) * TW, wp * 32, col, bv, relu, y_f32, y, gate,
-                       gate_stride, gate_offset, lane);
+                       gate_stride, gate_offset, lane, po);
     }
 }
 
@@ -798,11 +822,22 @@ __global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *
         const float m = mask[p];
         for (int c8 = 0; c8 < ps; c8 += 8) {
             unsigned w[4] = {0u, 0u, 0u, 0u};
-            for (int j = 0; j < 8 && c8 + j < C; ++j) {
-                const int c = c8 + j;
-                const float d = (pred[p * ps + c] - target[p * C + c]) * m;
-                e += (double)d * d;
-                w[j >> 1] |= (unsigned)f2bf(2.0f * d * ic) << (16 * (j & 1));
+            if (c8 < C) {
+                // all 8 loads issued before use (past C: the last channel again, weighted 0)
+                float pv[8], tv[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = min(c8 + j, C - 1);
+                    pv[j] = pred[p * ps + c];
+                    tv[j] = target[p * C + c];
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (c8 + j >= C) break;
+                    const float d = (pv[j] - tv[j]) * m;
+                    e += (double)d * d;
+                    w[j >> 1] |= (unsigned)f2bf(2.0f * d * ic) << (16 * (j & 1));
+                }
             }
             *(u4 *)(dpred + p * ps + c8) = u4{w[0], w[1], w[2], w[3]};
         }
@@ -900,15 +935,21 @@ int check_desc(const mlbm_conv_desc *d) {
 
 namespace {
 
-// tile shape: 8 x 16 pixels, or 8 x 8 for images 8 pixels wide
+void pool_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs, int xo, unsigned short *y, int ys,
+                     int yo, hipStream_t s);
+
+// tile shape: 8 x 16 pixels, or 8 x 8 for images 8 pixels wide; with pool.p
+// set (bf16 output only) the 2 x 2 averages of the stored output are written
+// too, by the epilogue of 16-wide tiles or by the pooling layer after 8-wide ones
 int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const float *bias, void *y, int relu, int y_f32,
-                const void *gate, int gate_stride, int gate_offset, hipStream_t s) {
+                const void *gate, int gate_stride, int gate_offset, hipStream_t s, PoolOut pool = PoolOut{nullptr, 0, 0}) {
     const auto *xx = (const unsigned short *)x, *ww = (const unsigned short *)w, *gg = (const unsigned short *)gate;
+    const PoolOut po = (y_f32 || d.w == 8) ? PoolOut{nullptr, 0, 0} : pool;
 #define MLBM_CONV_K(TH, TW, BN, KS, PM, PN)                                                                         \
     hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, KS, PM, PN>),                                                       \
                        dim3((unsigned)((int64_t)d.n * (d.h / TH) * (d.w / TW)), d.c_out / BN),                     \
                        dim3(conv_threads<TH, TW, BN, PM, PN>()), 0, s, d, xx, ww, bias, y, relu, y_f32, gg,        \
-                       gate_stride, gate_offset)
+                       gate_stride, gate_offset, po)
 #define MLBM_CONV(TH, TW, BN, PM, PN)                                                                               \
     do {                                                                                                            \
         if (d.ksize == 3) MLBM_CONV_K(TH, TW, BN, 3, PM, PN);                                                       \
@@ -918,10 +959,10 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
     do {                                                                                                            \
         if (d.ksize == 3)                                                                                           \
             hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 3, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
-                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset);                        \
+                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po);                    \
         else                                                                                                        \
             hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 1, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
-                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset);                        \
+                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po);                    \
     } while (0)
     if (d.c_in == KC && d.w % 16 == 0) {
         // one input slice: weights staged once per workgroup for 4 consecutive tiles
@@ -939,6 +980,9 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
 #undef MLBM_CONV_S1
 #undef MLBM_CONV
 #undef MLBM_CONV_K
+    if (pool.p && !po.p)
+        pool_fwd_launch(d.n, d.h / 2, d.w / 2, d.c_store, (const unsigned short *)y, d.y_stride, d.y_offset, pool.p,
+                        pool.stride, pool.offset, s);
     return check("mlbm_conv_forward");
 }
 
@@ -1422,23 +1466,26 @@ extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, 
     hipStream_t s = (hipStream_t)stream;
     const Ptrs q = net_ptrs(u, n);
     const float *prm = u->params;
-    auto conv = [&](const char *name, const void *xin, int xs, int xo, void *y, int ys, int yo, int relu, int f32) {
+    auto conv = [&](const char *name, const void *xin, int xs, int xo, void *y, int ys, int yo, int relu, int f32,
+                    int c_store = 0, PoolOut pool = PoolOut{nullptr, 0, 0}) {
         const Layer &ly = layer(n, name);
-        const mlbm_conv_desc d = desc_of(n, ly, xs, xo, ys, yo);
-        return conv_launch(d, xin, q.wbf + ly.wf_off, prm + ly.b_off, y, relu, f32, nullptr, 0, 0, s);
+        mlbm_conv_desc d = desc_of(n, ly, xs, xo, ys, yo);
+        if (c_store) d.c_store = c_store;
+        return conv_launch(d, xin, q.wbf + ly.wf_off, prm + ly.b_off, y, relu, f32, nullptr, 0, 0, s, pool);
     };
     char nm[8];
     const void *h = x;
     int hs = PADC;
     for (int l = 0; l < n.L; ++l) {
-        const int R = n.R >> l, c = n.c[l];
+        const int c = n.c[l];
         std::snprintf(nm, sizeof(nm), "enc%da", l);
         if ((rc = conv(nm, h, hs, 0, q.act + n.a.enc_a[l], c, 0, 1, 0))) return rc;
         std::snprintf(nm, sizeof(nm), "enc%db", l);
         if (l < n.L - 1) {
             const int cu = n.c[l + 1], cc = cu + c;
-            if ((rc = conv(nm, q.act + n.a.enc_a[l], c, 0, q.act + n.a.cat[l], cc, cu, 1, 0))) return rc;
-            pool_fwd_launch(n.B, R / 2, R / 2, c, q.act + n.a.cat[l], cc, cu, q.act + n.a.pool[l], c, 0, s);
+            // the skip copy, and its 2 x 2 average as the next level's input
+            const PoolOut pool{q.act + n.a.pool[l], c, 0};
+            if ((rc = conv(nm, q.act + n.a.enc_a[l], c, 0, q.act + n.a.cat[l], cc, cu, 1, 0, 0, pool))) return rc;
             h = q.act + n.a.pool[l];
         } else {
             if ((rc = conv(nm, q.act + n.a.enc_a[l], c, 0, q.act + n.a.bottom, c, 0, 1, 0))) return rc;
@@ -1456,7 +1503,8 @@ extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, 
         h = q.act + n.a.dec_b[l];
         hs = c;
     }
-    if ((rc = conv("head", h, hs, 0, out, PADC, 0, 0, 1))) return rc;
+    // only the real output channels are stored (the padded ones have zero weights)
+    if ((rc = conv("head", h, hs, 0, out, PADC, 0, 0, 1, n.c_real_out))) return rc;
     return check("mlbm_unet_forward");
 }
 
