@@ -82,12 +82,11 @@ int mlbm_unet_layer(const mlbm_unet *net, int32_t index, mlbm_unet_layer_info *o
 int mlbm_unet_refresh(const mlbm_unet *net, void *hip_stream);
 
 /* Forward pass of x (bf16 [batch][res][res][32]) into out (FP32
- * [batch][res][res][32]; channels c_out .. 31 are not written); keeps the
- * activations in act. */
+ * [batch][res][res][c_out]); keeps the activations in act. */
 int mlbm_unet_forward(const mlbm_unet *net, const void *x, float *out, void *hip_stream);
 
 /* loss = sum_p mask[p] sum_{c < c_out} (out[p, c] - target[p, c])^2 / (c_out
- * sum_p mask[p]) (device FP32 scalar), with out FP32 [P][32], target FP32
+ * sum_p mask[p]) (device FP32 scalar), with out FP32 [P][c_out], target FP32
  * [P][c_out], mask FP32 [P] (P = batch res^2); the gradient with respect to
  * out is left in act_grad for mlbm_unet_backward.  The normalisation is
  * formed on the device. */

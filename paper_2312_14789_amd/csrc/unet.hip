@@ -674,6 +674,17 @@ __global__ void k_relu_bwd_v8(int64_t P, int C8, const unsigned short *y, int y_
     *dp = g;
 }
 
+// 8 bf16 gradients zeroed where the layer's output (8 bf16 values) is not positive
+__device__ __forceinline__ u4 relu_gate8(u4 g, const u4 yv) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned keep_lo = __uint_as_float(yv[k] << 16) > 0.0f ? 0x0000ffffu : 0u;
+        const unsigned keep_hi = __uint_as_float(yv[k] & 0xffff0000u) > 0.0f ? 0xffff0000u : 0u;
+        g[k] &= keep_lo | keep_hi;
+    }
+    return g;
+}
+
 __global__ void k_pool_fwd_v8(int n, int h, int w, int C8, const unsigned short *x, int xs, int xo, unsigned short *y,
                               int ys, int yo) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -700,7 +711,8 @@ __global__ void k_pool_fwd_v8(int n, int h, int w, int C8, const unsigned short 
 }
 
 __global__ void k_pool_bwd_v8(int n, int h, int w, int C8, const unsigned short *dy, int dys, int dyo, unsigned short *dx,
-                              int dxs, int dxo, const unsigned short *add, int as, int ao) {
+                              int dxs, int dxo, const unsigned short *add, int as, int ao, const unsigned short *gate,
+                              int gs, int go) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)n * 4 * h * w * C8;
     if (i >= tot) return;
@@ -711,15 +723,20 @@ __global__ void k_pool_bwd_v8(int n, int h, int w, int C8, const unsigned short 
     const int64_t nn = q / ((int64_t)W2 * 2 * h);
     const int64_t src = (nn * h + yy / 2) * w + xx / 2;
     float v[8], a[8];
-    unpack8(*(const u4 *)(dy + src * dys + dyo + c), v);
+    const u4 dv = *(const u4 *)(dy + src * dys + dyo + c);
+    const u4 av = add ? *(const u4 *)(add + q * as + ao + c) : u4{0u, 0u, 0u, 0u};
+    const u4 gv = gate ? *(const u4 *)(gate + q * gs + go + c) : u4{0u, 0u, 0u, 0u};
+    unpack8(dv, v);
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] *= 0.25f;
     if (add) {
-        unpack8(*(const u4 *)(add + q * as + ao + c), a);
+        unpack8(av, a);
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] += a[k];
     }
-    *(u4 *)(dx + q * dxs + dxo + c) = pack8(v);
+    u4 r = pack8(v);
+    if (gate) r = relu_gate8(r, gv);
+    *(u4 *)(dx + q * dxs + dxo + c) = r;
 }
 
 __global__ void k_up_fwd_v8(int n, int h, int w, int C8, const unsigned short *x, int xs, int xo, unsigned short *y,
@@ -737,7 +754,7 @@ __global__ void k_up_fwd_v8(int n, int h, int w, int C8, const unsigned short *x
 }
 
 __global__ void k_up_bwd_v8(int n, int h, int w, int C8, const unsigned short *dy, int dys, int dyo, unsigned short *dx,
-                            int dxs, int dxo) {
+                            int dxs, int dxo, const unsigned short *gate, int gs, int go) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)n * h * w * C8;
     if (i >= tot) return;
@@ -758,7 +775,9 @@ __global__ void k_up_bwd_v8(int n, int h, int w, int C8, const unsigned short *d
     unpack8(*(const u4 *)(dy + (b + W2 + 1) * dys + dyo + c), t);
 #pragma unroll
     for (int k = 0; k < 8; ++k) a[k] += t[k];
-    *(u4 *)(dx + q * dxs + dxo + c) = pack8(a);
+    u4 r = pack8(a);
+    if (gate) r = relu_gate8(r, *(const u4 *)(gate + q * gs + go + c));
+    *(u4 *)(dx + q * dxs + dxo + c) = r;
 }
 
 // masked MSE over the first C channels of pred (fp32 [P][ps]): per-block partial
@@ -810,8 +829,9 @@ __global__ void k_adam(int64_t m, float *p, const float *g, float *mo, float *vo
 }
 
 // masked MSE with the normalisation 1 / (C sum mask) read from the device;
-// pred FP32 [P][ps], dpred bf16 [P][ps] (ps a multiple of 8, zero past C)
-__global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *pred, int ps, const float *target,
+// pred FP32 [P][pred_stride], dpred bf16 [P][ps] (ps a multiple of 8, zero past C)
+__global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *pred, int pred_stride, int ps,
+                                                const float *target,
                                                 const float *mask, const float *inv_count, unsigned short *dpred,
                                                 double *partial) {
     __shared__ double s1[256];
@@ -828,7 +848,7 @@ __global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int c = min(c8 + j, C - 1);
-                    pv[j] = pred[p * ps + c];
+                    pv[j] = pred[p * pred_stride + c];
                     tv[j] = target[p * C + c];
                 }
 #pragma unroll
@@ -1087,14 +1107,18 @@ void pool_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs
                            ys, yo);
 }
 
+// gate (optional): the ReLU gradient of the layer whose output dx is, applied to dx
 void pool_bwd_launch(int n, int h, int w, int c, const unsigned short *dy, int dys, int dyo, unsigned short *dx, int dxs,
-                     int dxo, const unsigned short *add, int as, int ao, hipStream_t s) {
-    if (v8(c, dys, dyo, dxs, dxo) && (!add || v8(as, ao, 0, 0, 0)))
+                     int dxo, const unsigned short *add, int as, int ao, hipStream_t s, const unsigned short *gate = nullptr,
+                     int gs = 0, int go = 0) {
+    if (v8(c, dys, dyo, dxs, dxo) && (!add || v8(as, ao, 0, 0, 0)) && (!gate || v8(gs, go, 0, 0, 0))) {
         hipLaunchKernelGGL(k_pool_bwd_v8, dim3(blocks((int64_t)n * 4 * h * w * (c / 8))), dim3(256), 0, s, n, h, w,
-                           c / 8, dy, dys, dyo, dx, dxs, dxo, add, as, ao);
-    else
+                           c / 8, dy, dys, dyo, dx, dxs, dxo, add, as, ao, gate, gs, go);
+    } else {
         hipLaunchKernelGGL(k_pool_bwd, dim3(blocks((int64_t)n * 4 * h * w * c)), dim3(256), 0, s, n, h, w, c, dy, dys,
                            dyo, dx, dxs, dxo, add, as, ao);
+        if (gate) relu_bwd_launch((int64_t)n * 4 * h * w, c, gate, gs, go, dx, dxs, dxo, s);
+    }
 }
 
 void up_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs, int xo, unsigned short *y, int ys,
@@ -1107,14 +1131,17 @@ void up_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs, 
                            y, ys, yo);
 }
 
+// gate (optional): the ReLU gradient of the layer whose output dx is, applied to dx
 void up_bwd_launch(int n, int h, int w, int c, const unsigned short *dy, int dys, int dyo, unsigned short *dx, int dxs,
-                   int dxo, hipStream_t s) {
-    if (v8(c, dys, dyo, dxs, dxo))
+                   int dxo, hipStream_t s, const unsigned short *gate = nullptr, int gs = 0, int go = 0) {
+    if (v8(c, dys, dyo, dxs, dxo) && (!gate || v8(gs, go, 0, 0, 0))) {
         hipLaunchKernelGGL(k_up_bwd_v8, dim3(blocks((int64_t)n * h * w * (c / 8))), dim3(256), 0, s, n, h, w, c / 8, dy,
-                           dys, dyo, dx, dxs, dxo);
-    else
+                           dys, dyo, dx, dxs, dxo, gate, gs, go);
+    } else {
         hipLaunchKernelGGL(k_up_bwd, dim3(blocks((int64_t)n * h * w * c)), dim3(256), 0, s, n, h, w, c, dy, dys, dyo, dx,
                            dxs, dxo);
+        if (gate) relu_bwd_launch((int64_t)n * h * w, c, gate, gs, go, dx, dxs, dxo, s);
+    }
 }
 
 }  // namespace
@@ -1503,8 +1530,8 @@ extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, 
         h = q.act + n.a.dec_b[l];
         hs = c;
     }
-    // only the real output channels are stored (the padded ones have zero weights)
-    if ((rc = conv("head", h, hs, 0, out, PADC, 0, 0, 1, n.c_real_out))) return rc;
+    // only the real output channels are stored, packed (the padded ones have zero weights)
+    if ((rc = conv("head", h, hs, 0, out, n.c_real_out, 0, 0, 1, n.c_real_out))) return rc;
     return check("mlbm_unet_forward");
 }
 
@@ -1521,7 +1548,8 @@ extern "C" int mlbm_unet_loss(const mlbm_unet *u, const float *out, const float 
     hipLaunchKernelGGL(k_mask_partial, dim3((unsigned)n.loss_blocks), dim3(256), 0, s, P, mask, q.mask_part);
     hipLaunchKernelGGL(k_inv_count, dim3(1), dim3(256), 0, s, (const double *)q.mask_part, n.loss_blocks, n.c_real_out,
                        q.inv);
-    hipLaunchKernelGGL(k_mse_dev, dim3((unsigned)n.loss_blocks), dim3(256), 0, s, P, n.c_real_out, out, PADC, target,
+    hipLaunchKernelGGL(k_mse_dev, dim3((unsigned)n.loss_blocks), dim3(256), 0, s, P, n.c_real_out, out, n.c_real_out, PADC,
+                       target,
                        mask, (const float *)q.inv, q.grad + n.a.dout, q.loss_part);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, (const double *)q.loss_part, n.loss_blocks,
                        (const float *)q.inv, loss);
@@ -1555,51 +1583,43 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
         d.c_store = ly.c_in;
         return conv_launch(d, dy, q.wbf + ly.wd_off, nullptr, dx, 0, 0, gate, gs, go, s);
     };
-    auto relu_bwd = [&](int64_t P, int C, const void *y, int ys, int yo, void *dy, int dys, int dyo) {
-        relu_bwd_launch(P, C, (const unsigned short *)y, ys, yo, (unsigned short *)dy, dys, dyo, s);
-    };
     char nm[8];
     const int c0 = n.c[0];
     if ((rc = wgrad("head", A + n.a.dec_b[0], c0, 0, G + n.a.dout, PADC, 0))) return rc;
     if ((rc = dgrad("head", G + n.a.dout, PADC, 0, G + n.a.dec_b[0], c0, 0, A + n.a.dec_b[0], c0, 0))) return rc;
     for (int l = 0; l < n.L - 1; ++l) {
         const int R = n.R >> l, c = n.c[l], cu = n.c[l + 1], cc = cu + c;
-        const int64_t P = (int64_t)n.B * R * R;
-        if (l > 0) relu_bwd(P, c, A + n.a.dec_b[l], c, 0, G + n.a.dec_b[l], c, 0);
         std::snprintf(nm, sizeof(nm), "dec%db", l);
         if ((rc = wgrad(nm, A + n.a.dec_a[l], c, 0, G + n.a.dec_b[l], c, 0))) return rc;
         if ((rc = dgrad(nm, G + n.a.dec_b[l], c, 0, G + n.a.dec_a[l], c, 0, A + n.a.dec_a[l], c, 0))) return rc;
         std::snprintf(nm, sizeof(nm), "dec%da", l);
         if ((rc = wgrad(nm, A + n.a.cat[l], cc, 0, G + n.a.dec_a[l], c, 0))) return rc;
         if ((rc = dgrad(nm, G + n.a.dec_a[l], c, 0, G + n.a.cat[l], cc, 0, nullptr, 0, 0))) return rc;
-        // the upsampled channels' gradient goes to this level's input: the decoder
-        // output of the level below, or the bottleneck
-        unsigned short *below = l + 1 <= n.L - 2 ? G + n.a.dec_b[l + 1] : G + n.a.bottom;
-        up_bwd_launch(n.B, R / 2, R / 2, cu, (const unsigned short *)(G + n.a.cat[l]), cc, 0, below, cu, 0, s);
+        // the upsampled channels' gradient goes to this level's input, the decoder
+        // output of the level below or the bottleneck, through that layer's ReLU
+        const int64_t bl = l + 1 <= n.L - 2 ? n.a.dec_b[l + 1] : n.a.bottom;
+        up_bwd_launch(n.B, R / 2, R / 2, cu, (const unsigned short *)(G + n.a.cat[l]), cc, 0, G + bl, cu, 0, s, A + bl, cu,
+                      0);
     }
     for (int l = n.L - 1; l >= 0; --l) {
         const int R = n.R >> l, c = n.c[l];
-        const int64_t P = (int64_t)n.B * R * R;
-        const unsigned short *yb;
         unsigned short *gb;
         int bs, bo;
         if (l < n.L - 1) {
             const int cu = n.c[l + 1], cc = cu + c;
             // d(enc_b output) = the pooled path's gradient + the skip gradient, which
-            // sits in the skip channels of the concatenation's gradient
+            // sits in the skip channels of the concatenation's gradient, through the ReLU
             pool_bwd_launch(n.B, R / 2, R / 2, c, (const unsigned short *)(G + n.a.pool[l]), c, 0, G + n.a.cat[l], cc, cu,
-                            (const unsigned short *)(G + n.a.cat[l]), cc, cu, s);
-            yb = A + n.a.cat[l];
+                            (const unsigned short *)(G + n.a.cat[l]), cc, cu, s, A + n.a.cat[l], cc, cu);
             gb = G + n.a.cat[l];
             bs = cc;
             bo = cu;
         } else {
-            yb = A + n.a.bottom;
             gb = G + n.a.bottom;
             bs = c;
             bo = 0;
         }
-        relu_bwd(P, c, yb, bs, bo, gb, bs, bo);
+        // (the ReLU gradient was applied by the pooling or upsampling gradient above)
         std::snprintf(nm, sizeof(nm), "enc%db", l);
         if ((rc = wgrad(nm, A + n.a.enc_a[l], c, 0, gb, bs, bo))) return rc;
         if ((rc = dgrad(nm, gb, bs, bo, G + n.a.enc_a[l], c, 0, A + n.a.enc_a[l], c, 0))) return rc;

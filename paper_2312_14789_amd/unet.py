@@ -13,7 +13,7 @@ Shape: per encoder level two 3x3 convolutions with ReLU (average pooling
 between levels), per decoder level a nearest upsampling, a concatenation with
 the encoder output of that level and two 3x3 convolutions with ReLU, then a
 1x1 head.  The input is padded to 32 channels and the head to 32 output
-channels (only the first `c_out` are used).
+channels, of which the first `c_out` are stored.
 """
 from __future__ import annotations
 
@@ -64,7 +64,7 @@ class UNet:
         self.act = torch.zeros(int(sz.act_bytes), dtype=u8, device=self.dev)
         self.act_grad = torch.zeros(int(sz.act_bytes), dtype=u8, device=self.dev)
         self.work = torch.zeros(int(sz.work_bytes), dtype=u8, device=self.dev)
-        self.out = torch.zeros((batch, res, res, PAD), dtype=f32, device=self.dev)
+        self.out = torch.zeros((batch, res, res, c_out), dtype=f32, device=self.dev)
         self.loss = torch.zeros(1, dtype=f32, device=self.dev)
         d.params, d.grads, d.adam_m, d.adam_v = (self.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(),
                                                  self.v.data_ptr())
@@ -118,8 +118,7 @@ class UNet:
 
     def forward(self, x):
         """mlbm_unet_forward of x (int16-viewed bf16 (B, res, res, 32)); returns
-        the FP32 head output (B, res, res, 32) whose first c_out channels are the
-        prediction."""
+        the FP32 head output (B, res, res, c_out), the prediction."""
         self.x = x.contiguous()
         check(lib.mlbm_unet_forward(ctypes.byref(self.desc), _p(self.x), _p(self.out), self._stream()))
         return self.out
