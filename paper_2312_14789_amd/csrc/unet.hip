@@ -58,6 +58,15 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
 // whose output gradient this is: zero where that layer's output is <= 0).
 constexpr int KC = 32, XP = KC + 8;
 
+// A layer input whose first `split` channels are the nearest 2x upsampling of
+// a half-resolution tensor: channel c < split of pixel (y, x) of image n is
+// lo[((n * h / 2 + y / 2) * w / 2 + x / 2) * stride + c]; channels from split on
+// come from the layer's own input view.  lo = null: no such channels.
+struct UpIn {
+    const unsigned short *lo;
+    int stride, split;
+};
+
 // 2 x 2 average pooling of a layer's stored (bf16) output, written by its
 // epilogue: pooled pixel (y, x) of channel c at p[(n, y, x) * stride + offset + c]
 struct PoolOut {
@@ -132,7 +141,8 @@ template <int TH, int TW, int BN, int KS, int PM = 1, int PN = 1>
 __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     k_conv_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                 const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
-                const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po) {
+                const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po,
+                const UpIn up) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / (32 * PM);
     constexpr int NT = conv_threads<TH, TW, BN, PM, PN>();
     static_assert(BM % (32 * PM) == 0 && BN % (32 * PN) == 0, "wave tiles must divide the block");
@@ -166,7 +176,8 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     // repeat it (the same bytes to the same place), so loads and stores need no
     // branches: a load under a branch waits for every load before it.
     constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT, WN = taps * BN * 4, WR = (WN + NT - 1) / NT;
-    int64_t xo[XR], wo[WR];
+    // (xl: the same pieces in the half-resolution part of the input, if any)
+    int64_t xo[XR], xl[XR], wo[WR];
     int xd[XR], wd[WR];
 #pragma unroll
     for (int j = 0; j < XR; ++j) {
@@ -180,6 +191,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
         gx -= gx >= d.w ? d.w : 0;
         const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
         xo[j] = gp * d.x_stride + d.x_offset + 8 * q;
+        xl[j] = (((int64_t)n * (d.h / 2) + gy / 2) * (d.w / 2) + gx / 2) * up.stride + 8 * q;
         xd[j] = hp * XP + 8 * q;
     }
 #pragma unroll
@@ -193,8 +205,13 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     // the next slice is read into registers while the current one is multiplied
     u4 xr[XR], wr[WR];
     auto fetch = [&](int c0) __attribute__((always_inline)) {
+        if (c0 < up.split) {
 #pragma unroll
-        for (int j = 0; j < XR; ++j) xr[j] = *(const u4 *)(x + xo[j] + c0);
+            for (int j = 0; j < XR; ++j) xr[j] = *(const u4 *)(up.lo + xl[j] + c0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < XR; ++j) xr[j] = *(const u4 *)(x + xo[j] + c0);
+        }
 #pragma unroll
         for (int j = 0; j < WR; ++j) wr[j] = *(const u4 *)(w + wo[j] + c0);
     };
@@ -359,7 +376,8 @@ constexpr int XTS = 16 * 10 + 8;  // halves per channel of a transposed halo cop
 template <int TH, int TW, int BCO, int KS, int CB = 1>
 __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
     k_wgrad_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
-                 float *__restrict__ ws, float *__restrict__ wsb, int64_t row_stride, int tiles_per_split) {
+                 float *__restrict__ ws, float *__restrict__ wsb, int64_t row_stride, int tiles_per_split,
+                 const UpIn up) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / (32 * CB)) * KS, PP = BM + 8;
     static_assert(HH <= 10 && TW <= 16, "transposed halo copies hold up to 10 rows of 16");
     static_assert(BCO % (32 * CB) == 0 && NT >= BCO, "wave groups must divide the block; one thread per bias sum");
@@ -404,8 +422,13 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
             gy -= gy >= d.h ? d.h : 0;
             gx += gx < 0 ? d.w : 0;
             gx -= gx >= d.w ? d.w : 0;
-            const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
-            xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
+            if (ci0 < up.split) {
+                const int64_t gl = ((int64_t)n * (d.h / 2) + gy / 2) * (d.w / 2) + gx / 2;
+                xr[j] = *(const u4 *)(up.lo + gl * up.stride + ci0 + 8 * q);
+            } else {
+                const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
+                xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
+            }
         }
         // output-gradient blocks: whole waves have none when DN < NT
 #pragma unroll
@@ -961,15 +984,20 @@ void pool_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs
 // tile shape: 8 x 16 pixels, or 8 x 8 for images 8 pixels wide; with pool.p
 // set (bf16 output only) the 2 x 2 averages of the stored output are written
 // too, by the epilogue of 16-wide tiles or by the pooling layer after 8-wide ones
+// up.lo set: the first up.split input channels are upsampled from up.lo (16-wide
+// tiles with more than one input slice only)
 int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const float *bias, void *y, int relu, int y_f32,
-                const void *gate, int gate_stride, int gate_offset, hipStream_t s, PoolOut pool = PoolOut{nullptr, 0, 0}) {
+                const void *gate, int gate_stride, int gate_offset, hipStream_t s, PoolOut pool = PoolOut{nullptr, 0, 0},
+                UpIn up = UpIn{nullptr, 0, 0}) {
     const auto *xx = (const unsigned short *)x, *ww = (const unsigned short *)w, *gg = (const unsigned short *)gate;
     const PoolOut po = (y_f32 || d.w == 8) ? PoolOut{nullptr, 0, 0} : pool;
+    if (up.lo && (d.w == 8 || d.c_in == KC || up.split % KC || up.split > d.c_in))
+        return mlbm::fail(MLBM_ERR_ARG, "upsampled input channels need 16-wide tiles and whole 32-channel slices");
 #define MLBM_CONV_K(TH, TW, BN, KS, PM, PN)                                                                         \
     hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, KS, PM, PN>),                                                       \
                        dim3((unsigned)((int64_t)d.n * (d.h / TH) * (d.w / TW)), d.c_out / BN),                     \
                        dim3(conv_threads<TH, TW, BN, PM, PN>()), 0, s, d, xx, ww, bias, y, relu, y_f32, gg,        \
-                       gate_stride, gate_offset, po)
+                       gate_stride, gate_offset, po, up)
 #define MLBM_CONV(TH, TW, BN, PM, PN)                                                                               \
     do {                                                                                                            \
         if (d.ksize == 3) MLBM_CONV_K(TH, TW, BN, 3, PM, PN);                                                       \
@@ -1016,8 +1044,11 @@ int wgrad_split(const mlbm_conv_desc &d, int splits, int *per) {
     return (int)((tiles + *per - 1) / *per);
 }
 
+// up.lo set: the first up.split input channels are upsampled from up.lo
 int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *dw, float *db, int splits, float *ws,
-                 hipStream_t s) {
+                 hipStream_t s, UpIn up = UpIn{nullptr, 0, 0}) {
+    if (up.lo && (up.split % 32 || up.split > d.c_in))
+        return mlbm::fail(MLBM_ERR_ARG, "upsampled input channels must be whole 32-channel blocks");
     int per = 0;
     const int sp = wgrad_split(d, splits, &per);
     const int taps = d.ksize * d.ksize;
@@ -1029,14 +1060,15 @@ int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *
     float *wsb = db ? ws + m : nullptr;
 #define MLBM_WG(TH, TW, BCO, KS, CB)                                                                              \
     hipLaunchKernelGGL((k_wgrad_tile<TH, TW, BCO, KS, CB>), dim3(d.c_out / BCO, d.c_in / 32, sp),                 \
-                       dim3(64 * (BCO / (32 * CB)) * KS), 0, s, d, xx, yy, ws, wsb, row, per)
+                       dim3(64 * (BCO / (32 * CB)) * KS), 0, s, d, xx, yy, ws, wsb, row, per, up)
     if (d.ksize == 3) {
         if (narrow) {
             if (wide) MLBM_WG(8, 8, 64, 3, 1);
             else MLBM_WG(8, 8, 32, 3, 1);
         } else {
-            // 128 (or 64) output channels per workgroup, two 32-channel blocks per wave
-            if (d.c_out % 128 == 0) MLBM_WG(8, 16, 128, 3, 2);
+            // 128 output channels per workgroup, one 32-channel block per wave (12
+            // waves); 64 channels with two blocks per wave
+            if (d.c_out % 128 == 0) MLBM_WG(8, 16, 128, 3, 1);
             else if (wide) MLBM_WG(8, 16, 64, 3, 2);
             else MLBM_WG(8, 16, 32, 3, 1);
         }
@@ -1494,11 +1526,11 @@ extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, 
     const Ptrs q = net_ptrs(u, n);
     const float *prm = u->params;
     auto conv = [&](const char *name, const void *xin, int xs, int xo, void *y, int ys, int yo, int relu, int f32,
-                    int c_store = 0, PoolOut pool = PoolOut{nullptr, 0, 0}) {
+                    int c_store = 0, PoolOut pool = PoolOut{nullptr, 0, 0}, UpIn up = UpIn{nullptr, 0, 0}) {
         const Layer &ly = layer(n, name);
         mlbm_conv_desc d = desc_of(n, ly, xs, xo, ys, yo);
         if (c_store) d.c_store = c_store;
-        return conv_launch(d, xin, q.wbf + ly.wf_off, prm + ly.b_off, y, relu, f32, nullptr, 0, 0, s, pool);
+        return conv_launch(d, xin, q.wbf + ly.wf_off, prm + ly.b_off, y, relu, f32, nullptr, 0, 0, s, pool, up);
     };
     char nm[8];
     const void *h = x;
@@ -1521,10 +1553,12 @@ extern "C" int mlbm_unet_forward(const mlbm_unet *u, const void *x, float *out, 
         hs = c;
     }
     for (int l = n.L - 2; l >= 0; --l) {
-        const int R = n.R >> l, c = n.c[l], cu = n.c[l + 1], cc = cu + c;
-        up_fwd_launch(n.B, R / 2, R / 2, cu, (const unsigned short *)h, hs, 0, q.act + n.a.cat[l], cc, 0, s);
+        const int c = n.c[l], cu = n.c[l + 1], cc = cu + c;
+        // input: the level below upsampled (read from there by the staging) and the skip copy
         std::snprintf(nm, sizeof(nm), "dec%da", l);
-        if ((rc = conv(nm, q.act + n.a.cat[l], cc, 0, q.act + n.a.dec_a[l], c, 0, 1, 0))) return rc;
+        const UpIn up{(const unsigned short *)h, hs, cu};
+        if ((rc = conv(nm, q.act + n.a.cat[l], cc, 0, q.act + n.a.dec_a[l], c, 0, 1, 0, 0, PoolOut{nullptr, 0, 0}, up)))
+            return rc;
         std::snprintf(nm, sizeof(nm), "dec%db", l);
         if ((rc = conv(nm, q.act + n.a.dec_a[l], c, 0, q.act + n.a.dec_b[l], c, 0, 1, 0))) return rc;
         h = q.act + n.a.dec_b[l];
@@ -1567,10 +1601,11 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
     const Ptrs q = net_ptrs(u, n);
     unsigned short *A = q.act, *G = q.grad;
     float *gp = u->grads;
-    auto wgrad = [&](const char *name, const void *xin, int xs, int xo, const void *dy, int ys, int yo) {
+    auto wgrad = [&](const char *name, const void *xin, int xs, int xo, const void *dy, int ys, int yo,
+                     UpIn up = UpIn{nullptr, 0, 0}) {
         const Layer &ly = layer(n, name);
         const mlbm_conv_desc d = desc_of(n, ly, xs, xo, ys, yo);
-        return wgrad_launch(d, xin, dy, gp + ly.w_off, gp + ly.b_off, ly.splits, q.ws, s);
+        return wgrad_launch(d, xin, dy, gp + ly.w_off, gp + ly.b_off, ly.splits, q.ws, s, up);
     };
     // data gradient: the forward product with the mirrored weights, c_in and c_out exchanged;
     // gate = the output of the layer below (its ReLU gradient), or NULL
@@ -1593,11 +1628,12 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
         if ((rc = wgrad(nm, A + n.a.dec_a[l], c, 0, G + n.a.dec_b[l], c, 0))) return rc;
         if ((rc = dgrad(nm, G + n.a.dec_b[l], c, 0, G + n.a.dec_a[l], c, 0, A + n.a.dec_a[l], c, 0))) return rc;
         std::snprintf(nm, sizeof(nm), "dec%da", l);
-        if ((rc = wgrad(nm, A + n.a.cat[l], cc, 0, G + n.a.dec_a[l], c, 0))) return rc;
-        if ((rc = dgrad(nm, G + n.a.dec_a[l], c, 0, G + n.a.cat[l], cc, 0, nullptr, 0, 0))) return rc;
-        // the upsampled channels' gradient goes to this level's input, the decoder
-        // output of the level below or the bottleneck, through that layer's ReLU
+        // this level's input, the decoder output of the level below or the
+        // bottleneck: its upsampling is read from there (the concatenation holds
+        // only the skip copy), and its gradient goes back there through its ReLU
         const int64_t bl = l + 1 <= n.L - 2 ? n.a.dec_b[l + 1] : n.a.bottom;
+        if ((rc = wgrad(nm, A + n.a.cat[l], cc, 0, G + n.a.dec_a[l], c, 0, UpIn{A + bl, cu, cu}))) return rc;
+        if ((rc = dgrad(nm, G + n.a.dec_a[l], c, 0, G + n.a.cat[l], cc, 0, nullptr, 0, 0))) return rc;
         up_bwd_launch(n.B, R / 2, R / 2, cu, (const unsigned short *)(G + n.a.cat[l]), cc, 0, G + bl, cu, 0, s, A + bl, cu,
                       0);
     }
