@@ -74,6 +74,17 @@ struct PoolOut {
     int stride, offset;
 };
 
+// Gradient of a nearest 2x upsampling, formed by the epilogue of the product
+// that yields the gradient of the upsampled channels (those below split): the
+// 2 x 2 sum of each block, zeroed where gate (the half-resolution layer output
+// that was upsampled) is not positive, goes to g[(n, y, x) * stride + c]; the
+// full-resolution values of those channels are not stored.
+struct UpGrad {
+    unsigned short *g;
+    int stride, split;
+    const unsigned short *gate;
+};
+
 // Epilogue of one 32 x 32 MFMA result of a forward tile: bias, ReLU, the
 // gate (zero where the gate value is not positive) and the store of channel
 // col at the lane's 16 pixels pt0 + (q / 4) * 8 + (lane >> 5) * 4 + q % 4 of the
@@ -85,7 +96,7 @@ template <int TW>
 __device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16 &acc, int n, int y0, int x0, int pt0,
                                            int col, float bv, int relu, int y_f32, void *__restrict__ y,
                                            const unsigned short *__restrict__ gate, int gate_stride, int gate_offset,
-                                           int lane, const PoolOut &po) {
+                                           int lane, const PoolOut &po, const UpGrad &ug) {
     if (col >= d.c_store) return;
     const int64_t g0 = ((int64_t)n * d.h + y0) * d.w + x0;
     int off[16];  // pixels from the tile's origin
@@ -106,6 +117,30 @@ __device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16
         v[q] = acc[q] + bv;
         if (relu) v[q] = fmaxf(v[q], 0.0f);
         if (gate && !(gv[q] > 0.0f)) v[q] = 0.0f;
+    }
+    if constexpr (TW == 16) {
+        if (ug.g && col < ug.split) {  // the same for the whole wave: split is a multiple of 32
+            // the same sum order as the upsampling gradient: ((x00 + x01) + x10) + x11
+            const int w2 = d.w / 2;
+            const int64_t pb = ((int64_t)n * (d.h / 2) + y0 / 2) * w2 + x0 / 2;
+            int64_t gi[4];
+            float gt[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int pt = pt0 + (k / 2) * 8 + (lane >> 5) * 4 + (k % 2) * 2;
+                gi[k] = (pb + (int64_t)(pt / 32) * w2 + (pt % 16) / 2) * ug.stride + col;
+                gt[k] = bf2f(ug.gate[gi[k]]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int q = 2 * k;
+                float a = bf2f(f2bf(v[q])) + bf2f(f2bf(v[q + 1]));
+                a += bf2f(f2bf(v[q + 8]));
+                a += bf2f(f2bf(v[q + 9]));
+                ug.g[gi[k]] = gt[k] > 0.0f ? f2bf(a) : (unsigned short)0;
+            }
+            return;
+        }
     }
     const int64_t o0 = g0 * d.y_stride + d.y_offset + col;
     if (y_f32) {
@@ -142,7 +177,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
     k_conv_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                 const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
                 const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po,
-                const UpIn up) {
+                const UpIn up, const UpGrad ug) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / (32 * PM);
     constexpr int NT = conv_threads<TH, TW, BN, PM, PN>();
     static_assert(BM % (32 * PM) == 0 && BN % (32 * PN) == 0, "wave tiles must divide the block");
@@ -250,7 +285,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
 #pragma unroll
         for (int pm = 0; pm < PM; ++pm)
             store_tile<TW>(d, acc[pm][pn], n, y0, x0, (wp * PM + pm) * 32, col, bv, relu, y_f32, y, gate, gate_stride,
-                           gate_offset, lane, po);
+                           gate_offset, lane, po, ug);
     }
 }
 
@@ -262,7 +297,8 @@ template <int TH, int TW, int BN, int KS, int TPW>
 __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     k_conv_tile_s1(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                    const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
-                   const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po) {
+                   const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po,
+                   const UpGrad ug) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = 64 * WPX * (BN / 32);
     constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT;
     __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
@@ -338,7 +374,7 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
         }
         const int n = tile / tiles_img, rem = tile % tiles_img;
         store_tile<TW>(d, acc, n, (rem / tiles_x) * TH, (rem % tiles_x) * TW, wp * 32, col, bv, relu, y_f32, y, gate,
-                       gate_stride, gate_offset, lane, po);
+                       gate_stride, gate_offset, lane, po, ug);
     }
 }
 
@@ -988,16 +1024,18 @@ void pool_fwd_launch(int n, int h, int w, int c, const unsigned short *x, int xs
 // tiles with more than one input slice only)
 int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const float *bias, void *y, int relu, int y_f32,
                 const void *gate, int gate_stride, int gate_offset, hipStream_t s, PoolOut pool = PoolOut{nullptr, 0, 0},
-                UpIn up = UpIn{nullptr, 0, 0}) {
+                UpIn up = UpIn{nullptr, 0, 0}, UpGrad ug = UpGrad{nullptr, 0, 0, nullptr}) {
     const auto *xx = (const unsigned short *)x, *ww = (const unsigned short *)w, *gg = (const unsigned short *)gate;
     const PoolOut po = (y_f32 || d.w == 8) ? PoolOut{nullptr, 0, 0} : pool;
     if (up.lo && (d.w == 8 || d.c_in == KC || up.split % KC || up.split > d.c_in))
         return mlbm::fail(MLBM_ERR_ARG, "upsampled input channels need 16-wide tiles and whole 32-channel slices");
+    if (ug.g && (d.w == 8 || y_f32 || ug.split % 32 || ug.split > d.c_store))
+        return mlbm::fail(MLBM_ERR_ARG, "an upsampling gradient needs 16-wide tiles, bf16 output and 32-channel blocks");
 #define MLBM_CONV_K(TH, TW, BN, KS, PM, PN)                                                                         \
     hipLaunchKernelGGL((k_conv_tile<TH, TW, BN, KS, PM, PN>),                                                       \
                        dim3((unsigned)((int64_t)d.n * (d.h / TH) * (d.w / TW)), d.c_out / BN),                     \
                        dim3(conv_threads<TH, TW, BN, PM, PN>()), 0, s, d, xx, ww, bias, y, relu, y_f32, gg,        \
-                       gate_stride, gate_offset, po, up)
+                       gate_stride, gate_offset, po, up, ug)
 #define MLBM_CONV(TH, TW, BN, PM, PN)                                                                               \
     do {                                                                                                            \
         if (d.ksize == 3) MLBM_CONV_K(TH, TW, BN, 3, PM, PN);                                                       \
@@ -1007,10 +1045,10 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
     do {                                                                                                            \
         if (d.ksize == 3)                                                                                           \
             hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 3, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
-                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po);                    \
+                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po, ug);                \
         else                                                                                                        \
             hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 1, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
-                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po);                    \
+                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po, ug);                \
     } while (0)
     if (d.c_in == KC && d.w % 16 == 0) {
         // one input slice: weights staged once per workgroup for 4 consecutive tiles
@@ -1610,20 +1648,21 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
     // data gradient: the forward product with the mirrored weights, c_in and c_out exchanged;
     // gate = the output of the layer below (its ReLU gradient), or NULL
     auto dgrad = [&](const char *name, const void *dy, int ys, int yo, void *dx, int xs, int xo, const void *gate,
-                     int gs, int go) {
+                     int gs, int go, UpGrad ug = UpGrad{nullptr, 0, 0, nullptr}) {
         const Layer &ly = layer(n, name);
         mlbm_conv_desc d = desc_of(n, ly, ys, yo, xs, xo);
         d.c_in = ly.c_out;
         d.c_out = ly.c_in;
         d.c_store = ly.c_in;
-        return conv_launch(d, dy, q.wbf + ly.wd_off, nullptr, dx, 0, 0, gate, gs, go, s);
+        return conv_launch(d, dy, q.wbf + ly.wd_off, nullptr, dx, 0, 0, gate, gs, go, s, PoolOut{nullptr, 0, 0},
+                           UpIn{nullptr, 0, 0}, ug);
     };
     char nm[8];
     const int c0 = n.c[0];
     if ((rc = wgrad("head", A + n.a.dec_b[0], c0, 0, G + n.a.dout, PADC, 0))) return rc;
     if ((rc = dgrad("head", G + n.a.dout, PADC, 0, G + n.a.dec_b[0], c0, 0, A + n.a.dec_b[0], c0, 0))) return rc;
     for (int l = 0; l < n.L - 1; ++l) {
-        const int R = n.R >> l, c = n.c[l], cu = n.c[l + 1], cc = cu + c;
+        const int c = n.c[l], cu = n.c[l + 1], cc = cu + c;
         std::snprintf(nm, sizeof(nm), "dec%db", l);
         if ((rc = wgrad(nm, A + n.a.dec_a[l], c, 0, G + n.a.dec_b[l], c, 0))) return rc;
         if ((rc = dgrad(nm, G + n.a.dec_b[l], c, 0, G + n.a.dec_a[l], c, 0, A + n.a.dec_a[l], c, 0))) return rc;
@@ -1633,9 +1672,9 @@ extern "C" int mlbm_unet_backward(const mlbm_unet *u, const void *x, void *strea
         // only the skip copy), and its gradient goes back there through its ReLU
         const int64_t bl = l + 1 <= n.L - 2 ? n.a.dec_b[l + 1] : n.a.bottom;
         if ((rc = wgrad(nm, A + n.a.cat[l], cc, 0, G + n.a.dec_a[l], c, 0, UpIn{A + bl, cu, cu}))) return rc;
-        if ((rc = dgrad(nm, G + n.a.dec_a[l], c, 0, G + n.a.cat[l], cc, 0, nullptr, 0, 0))) return rc;
-        up_bwd_launch(n.B, R / 2, R / 2, cu, (const unsigned short *)(G + n.a.cat[l]), cc, 0, G + bl, cu, 0, s, A + bl, cu,
-                      0);
+        // (the upsampled channels' gradient is summed into G + bl by the epilogue)
+        if ((rc = dgrad(nm, G + n.a.dec_a[l], c, 0, G + n.a.cat[l], cc, 0, nullptr, 0, 0, UpGrad{G + bl, cu, cu, A + bl})))
+            return rc;
     }
     for (int l = n.L - 1; l >= 0; --l) {
         const int R = n.R >> l, c = n.c[l];
