@@ -53,7 +53,10 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
 // 16-byte copies, so each staged input value feeds all taps and every MFMA
 // operand is one 16-byte LDS read; the next slice's pieces are loaded into
 // registers while the current slice is multiplied.  Row pitches of 40 halves (80 B) keep the
-// 16 lanes of each LDS read on distinct banks.
+// 16 lanes of each LDS read on distinct banks.  k_conv_tile serves images 8
+// pixels wide; 16-wide tiles with more than one input slice go to k_conv_dma
+// (the same product, staged by direct global-to-LDS loads), and single-slice
+// layers to k_conv_tile_s1.
 // Epilogue: bias, ReLU, and optionally a gate (the ReLU gradient of the layer
 // whose output gradient this is: zero where that layer's output is <= 0).
 constexpr int KC = 32, XP = KC + 8;
@@ -287,6 +290,98 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
             store_tile<TW>(d, acc[pm][pn], n, y0, x0, (wp * PM + pm) * 32, col, bv, relu, y_f32, y, gate, gate_stride,
                            gate_offset, lane, po, ug);
     }
+}
+
+// The forward product of k_conv_tile with each slice staged by direct global
+// to LDS loads (16 bytes per lane, written at consecutive LDS slots of the
+// issuing wave): no staging registers and no LDS stores, so more waves fit.
+// Rows are 64 bytes (one pixel's or one output channel's 32 halves) with the
+// four 16-byte chunks of row r permuted as c -> c ^ ((r >> 2) & 3); a lane
+// loads the global chunk that belongs at its slot.
+__device__ __forceinline__ int dma_pos(int r, int c) { return r * KC + 8 * (c ^ ((r >> 2) & 3)); }
+
+template <int TH, int TW, int BN, int KS>
+__global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
+    k_conv_dma(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
+               const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
+               const unsigned short *__restrict__ gate, int gate_stride, int gate_offset, const PoolOut po,
+               const UpIn up, const UpGrad ug) {
+    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = conv_threads<TH, TW, BN, 1, 1>();
+    constexpr int NW = NT / 64, taps = KS * KS, r = KS >> 1;
+    // slots (16 bytes each): the halo rounded up to whole waves, then the weights
+    constexpr int XN = HH * HWD * 4, XS = (XN + 63) / 64 * 64, WN = taps * BN * 4;
+    static_assert(WN % 64 == 0, "weight slots fill whole waves");
+    __shared__ __align__(16) unsigned short lds[(XS + WN) * 8];
+    unsigned short *xs = lds, *wsm = lds + XS * 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int wp = wave % WPX, wc = wave / WPX;
+    const int tiles_x = d.w / TW, tiles_img = tiles_x * (d.h / TH);
+    const int n = blockIdx.x / tiles_img, rem = blockIdx.x % tiles_img;
+    const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
+    const int co0 = blockIdx.y * BN;
+    const int row = lane & 31, kc = lane >> 5;
+    const int pb = wp * 32 + row;
+    const int arow = (pb / TW + 1) * HWD + (pb % TW + 1), brow = wc * 32 + row;
+    // this lane's global offsets (without the slice's first channel) for each of
+    // its wave's halo and weight instructions
+    constexpr int XI = (XS / 64 + NW - 1) / NW, WI = (WN / 64 + NW - 1) / NW;
+    int64_t xo[XI], xl[XI], wo[WI];
+#pragma unroll
+    for (int i = 0; i < XI; ++i) {
+        const int slot = min((i * NW + wave) * 64 + lane, XN - 1);  // slots past the halo repeat its last piece
+        const int hp = slot >> 2, c = (slot & 3) ^ ((hp >> 2) & 3);
+        const int hy = hp / HWD, hx = hp - hy * HWD;
+        int gy = y0 + hy - 1, gx = x0 + hx - 1;
+        gy += gy < 0 ? d.h : 0;
+        gy -= gy >= d.h ? d.h : 0;
+        gx += gx < 0 ? d.w : 0;
+        gx -= gx >= d.w ? d.w : 0;
+        xo[i] = (((int64_t)n * d.h + gy) * d.w + gx) * d.x_stride + d.x_offset + 8 * c;
+        xl[i] = (((int64_t)n * (d.h / 2) + gy / 2) * (d.w / 2) + gx / 2) * up.stride + 8 * c;
+    }
+#pragma unroll
+    for (int i = 0; i < WI; ++i) {
+        const int slot = min((i * NW + wave) * 64 + lane, WN - 1);
+        const int wr = slot >> 2, c = (slot & 3) ^ ((wr >> 2) & 3);
+        const int t = wr / BN, co = wr % BN;
+        wo[i] = ((int64_t)(co0 + co) * taps + t) * d.c_in + 8 * c;
+    }
+    f32x16 acc = {};
+    for (int c0 = 0; c0 < d.c_in; c0 += KC) {
+        __syncthreads();  // the previous slice's products are done with the LDS
+        const bool lo = c0 < up.split;
+#pragma unroll
+        for (int i = 0; i < XI; ++i) {
+            const int base = (i * NW + wave) * 64;
+            if (base < XS) {
+                const unsigned short *src = lo ? up.lo + xl[i] + c0 : x + xo[i] + c0;
+                __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)(xs + base * 8),
+                                                 16, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < WI; ++i) {
+            const int base = (i * NW + wave) * 64;
+            if (base < WN)
+                __builtin_amdgcn_global_load_lds((const void *)(w + wo[i] + c0),
+                                                 (__attribute__((address_space(3))) void *)(wsm + base * 8), 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < taps; ++t) {
+            const int trow = arow + (t / KS - r) * HWD + (t % KS - r), wrow = t * BN + brow;
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 16) {
+                const int ch = kc + kk / 8;
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf8(&xs[dma_pos(trow, ch)]),
+                                                              load_bf8(&wsm[dma_pos(wrow, ch)]), acc, 0, 0, 0);
+            }
+        }
+    }
+    const int col = co0 + wc * 32 + row;
+    const float bv = bias && col < d.c_store ? bias[col] : 0.0f;
+    store_tile<TW>(d, acc, n, y0, x0, wp * 32, col, bv, relu, y_f32, y, gate, gate_stride, gate_offset, lane, po, ug);
 }
 
 // Layers with a single 32-channel input slice (c_in = 32): the weights of
@@ -1050,6 +1145,16 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
             hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 1, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
                                xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po, ug);                \
     } while (0)
+#define MLBM_DMA(BN)                                                                                                \
+    do {                                                                                                            \
+        const dim3 g((unsigned)((int64_t)d.n * (d.h / 8) * (d.w / 16)), d.c_out / BN);                               \
+        if (d.ksize == 3)                                                                                           \
+            hipLaunchKernelGGL((k_conv_dma<8, 16, BN, 3>), g, dim3(8 * BN), 0, s, d, xx, ww, bias, y, relu, y_f32, gg, \
+                               gate_stride, gate_offset, po, up, ug);                                              \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_conv_dma<8, 16, BN, 1>), g, dim3(8 * BN), 0, s, d, xx, ww, bias, y, relu, y_f32, gg, \
+                               gate_stride, gate_offset, po, up, ug);                                              \
+    } while (0)
     if (d.c_in == KC && d.w % 16 == 0) {
         // one input slice: weights staged once per workgroup for 4 consecutive tiles
         constexpr int TPW = 4;
@@ -1060,10 +1165,11 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
         if (d.c_out % 64 == 0) MLBM_CONV(8, 8, 64, 1, 1);
         else MLBM_CONV(8, 8, 32, 1, 1);
     } else {
-        if (d.c_out % 64 == 0) MLBM_CONV(8, 16, 64, 1, 1);
-        else MLBM_CONV(8, 16, 32, 1, 1);
+        if (d.c_out % 64 == 0) MLBM_DMA(64);
+        else MLBM_DMA(32);
     }
 #undef MLBM_CONV_S1
+#undef MLBM_DMA
 #undef MLBM_CONV
 #undef MLBM_CONV_K
     if (pool.p && !po.p)
