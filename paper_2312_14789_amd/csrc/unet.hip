@@ -368,14 +368,29 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-#pragma unroll
-        for (int t = 0; t < taps; ++t) {
+        // the next tap's operands are read while the current tap is multiplied
+        bf16x8 ca[2], cb[2], na[2], nb[2];
+        auto operands = [&](int t, bf16x8 *a, bf16x8 *b) __attribute__((always_inline)) {
             const int trow = arow + (t / KS - r) * HWD + (t % KS - r), wrow = t * BN + brow;
 #pragma unroll
-            for (int kk = 0; kk < KC; kk += 16) {
-                const int ch = kc + kk / 8;
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf8(&xs[dma_pos(trow, ch)]),
-                                                              load_bf8(&wsm[dma_pos(wrow, ch)]), acc, 0, 0, 0);
+            for (int h = 0; h < 2; ++h) {
+                a[h] = load_bf8(&xs[dma_pos(trow, kc + 2 * h)]);
+                b[h] = load_bf8(&wsm[dma_pos(wrow, kc + 2 * h)]);
+            }
+        };
+        operands(0, ca, cb);
+        __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave the LDS reads with the products
+#pragma unroll
+        for (int t = 0; t < taps; ++t) {
+            if (t + 1 < taps) operands(t + 1, na, nb);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ca[h], cb[h], acc, 0, 0, 0);
+            if (t + 1 < taps) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    ca[h] = na[h];
+                    cb[h] = nb[h];
+                }
             }
         }
     }
