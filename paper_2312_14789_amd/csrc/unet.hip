@@ -95,7 +95,7 @@ struct UpGrad {
 // any is used, so their loads overlap.  With po.p set (bf16 output, 16-wide
 // tiles), the lane also writes the 2 x 2 averages of its pixels: q, q + 1,
 // q + 8 and q + 9 (q = 0, 2, 4, 6) are the corners of one block.
-template <int TW>
+template <int TW, bool GATE = true>
 __device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16 &acc, int n, int y0, int x0, int pt0,
                                            int col, float bv, int relu, int y_f32, void *__restrict__ y,
                                            const unsigned short *__restrict__ gate, int gate_stride, int gate_offset,
@@ -109,7 +109,7 @@ __device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16
         off[q] = (pt / TW) * d.w + pt % TW;
     }
     float gv[16];
-    if (gate) {
+    if (GATE && gate) {
         const unsigned short *gb = gate + g0 * gate_stride + gate_offset + col;
 #pragma unroll
         for (int q = 0; q < 16; ++q) gv[q] = bf2f(gb[off[q] * gate_stride]);
@@ -119,7 +119,7 @@ __device__ __forceinline__ void store_tile(const mlbm_conv_desc &d, const f32x16
     for (int q = 0; q < 16; ++q) {
         v[q] = acc[q] + bv;
         if (relu) v[q] = fmaxf(v[q], 0.0f);
-        if (gate && !(gv[q] > 0.0f)) v[q] = 0.0f;
+        if (GATE && gate && !(gv[q] > 0.0f)) v[q] = 0.0f;
     }
     if constexpr (TW == 16) {
         if (ug.g && col < ug.split) {  // the same for the whole wave: split is a multiple of 32
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
 // every tap are staged once per workgroup and serve TPW consecutive pixel
 // tiles; each tile's input halo is loaded into registers while the previous
 // tile is multiplied.  Same tiles, operand layout and epilogue as k_conv_tile.
-template <int TH, int TW, int BN, int KS, int TPW>
+template <int TH, int TW, int BN, int KS, int TPW, bool GATE>
 __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     k_conv_tile_s1(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
                    const float *__restrict__ bias, void *__restrict__ y, int relu, int y_f32,
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
                                                               acc, 0, 0, 0);
         }
         const int n = tile / tiles_img, rem = tile % tiles_img;
-        store_tile<TW>(d, acc, n, (rem / tiles_x) * TH, (rem % tiles_x) * TW, wp * 32, col, bv, relu, y_f32, y, gate,
+        store_tile<TW, GATE>(d, acc, n, (rem / tiles_x) * TH, (rem % tiles_x) * TW, wp * 32, col, bv, relu, y_f32, y, gate,
                        gate_stride, gate_offset, lane, po, ug);
     }
 }
@@ -1151,14 +1151,19 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
         if (d.ksize == 3) MLBM_CONV_K(TH, TW, BN, 3, PM, PN);                                                       \
         else MLBM_CONV_K(TH, TW, BN, 1, PM, PN);                                                                    \
     } while (0)
+#define MLBM_CONV_S1_G(BN, KS, TPW, G)                                                                              \
+    hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, KS, TPW, G>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d, xx, ww, \
+                       bias, y, relu, y_f32, gg, gate_stride, gate_offset, po, ug)
+    // (the gate's registers are only allocated where a gate is applied)
 #define MLBM_CONV_S1(BN, TPW)                                                                                       \
     do {                                                                                                            \
-        if (d.ksize == 3)                                                                                           \
-            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 3, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
-                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po, ug);                \
-        else                                                                                                        \
-            hipLaunchKernelGGL((k_conv_tile_s1<8, 16, BN, 1, TPW>), dim3(wgs, d.c_out / BN), dim3(8 * BN), 0, s, d,    \
-                               xx, ww, bias, y, relu, y_f32, gg, gate_stride, gate_offset, po, ug);                \
+        if (d.ksize == 3) {                                                                                         \
+            if (gg) MLBM_CONV_S1_G(BN, 3, TPW, true);                                                               \
+            else MLBM_CONV_S1_G(BN, 3, TPW, false);                                                                 \
+        } else {                                                                                                    \
+            if (gg) MLBM_CONV_S1_G(BN, 1, TPW, true);                                                               \
+            else MLBM_CONV_S1_G(BN, 1, TPW, false);                                                                 \
+        }                                                                                                           \
     } while (0)
 #define MLBM_DMA(BN)                                                                                                \
     do {                                                                                                            \
@@ -1184,6 +1189,7 @@ int conv_launch(const mlbm_conv_desc &d, const void *x, const void *w, const flo
         else MLBM_DMA(32);
     }
 #undef MLBM_CONV_S1
+#undef MLBM_CONV_S1_G
 #undef MLBM_DMA
 #undef MLBM_CONV
 #undef MLBM_CONV_K
