@@ -492,167 +492,142 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
 // dw[o][tap][i] = sum_p dy[p, o] x[p + tap, i]: an MFMA product whose summed
 // index is the pixel, so both operands need 8 consecutive pixels of one
 // channel per lane.  One workgroup takes BCO output x 32 input channels and
-// every tap, over a range of TH x TW pixel tiles: it stages the tile's output
-// gradient transposed ([channel][pixel]) and the input halo transposed in KS
-// copies, copy s holding halo columns s .. s + TW - 1 of each halo row, so the
-// operand of any tap starts on a 16-byte boundary.  Transposes run in
-// registers on 8 x 8 blocks (8 pixels x 8 channels, one 16-byte load each)
-// and are written with 16-byte LDS stores.  Wave (co group h, tap row j) sums
-// the KS taps of its row for CB blocks of 32 output channels, so each output
-// gradient fragment feeds KS products and each input fragment CB.  Split k's
-// partials go to ws + k * row_stride as [c_out][taps][c_in], its bias sums to
+// every tap, over a range of TH x TW pixel tiles.  Wave (co group h, tap row j)
+// sums the KS taps of its row for CB blocks of 32 output channels, so each
+// output-gradient fragment feeds KS products.  Split k's partials go to
+// ws + k * row_stride as [c_out][taps][c_in], its bias sums to
 // wsb + k * row_stride.
 
-// in[r] = 8 values of row r (value 2k in the low half of dword k); out[c] = column c
-__device__ __forceinline__ void transpose8x8(const u4 in[8], u4 out[8]) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        unsigned o[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const unsigned lo = in[2 * k][c >> 1], hi = in[2 * k + 1][c >> 1];
-            o[k] = (c & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
-        }
-        out[c] = u4{o[0], o[1], o[2], o[3]};
-    }
-}
+// The weight gradient without transposes: the output-gradient tile and the
+// input halo are staged in their natural pixel-major layout by direct
+// global-to-LDS loads, and the MFMA operands (8 consecutive pixels of one
+// channel per lane) are read with gfx950's transposing LDS read
+// (ds_read_b64_tr_b16): within each group of 16 lanes, lane i receives, as its
+// element j, half i % 4 of the 8 bytes that lane 4 j + i / 4 addressed.  So
+// lane 4 j + q of a group reads pixel P + j, channels C + 4 q .. C + 4 q + 3,
+// and lane 4 q + h gets pixels P .. P + 3 of channel C + 4 q + h; two such
+// reads give the 8 pixels of an operand.  The tap column is a pixel offset
+// into the natural halo, so no shifted copies are needed.  16-byte chunks of
+// an LDS row (one pixel) are permuted as c -> c ^ (pixel % chunks) to spread
+// the banks.  The bias gradient comes from the same operand fragments,
+// multiplied by a column of ones.
+typedef short v4i16 __attribute__((ext_vector_type(4)));
 
-constexpr int XTS = 16 * 10 + 8;  // halves per channel of a transposed halo copy (up to 10 rows of 16, padded)
+template <int NCH>
+__device__ __forceinline__ int tr_pos(int row, int c) { return (row * NCH + (c ^ (row % NCH))) * 8; }
+
+// bf16x8 operand: pixels rbase + 0..7 (rows of an LDS buffer of NCH 16-byte
+// chunks per row), channel block cb (16 lanes: channels cb .. cb + 15)
+template <int NCH>
+__device__ __forceinline__ bf16x8 tr_operand(const unsigned short *buf, int rbase, int cbase, int lane) {
+    const int s = lane & 15, rr = rbase + (s >> 2), ch = cbase + 4 * (s & 3);
+    typedef __attribute__((address_space(3))) v4i16 lds_v4;
+    const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4 *)(buf + tr_pos<NCH>(rr, ch >> 3) + (ch & 7)));
+    const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4 *)(buf + tr_pos<NCH>(rr + 4, ch >> 3) + (ch & 7)));
+    typedef short v8i16 __attribute__((ext_vector_type(8)));
+    const v8i16 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    return __builtin_bit_cast(bf16x8, v);
+}
 
 template <int TH, int TW, int BCO, int KS, int CB = 1>
 __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
-    k_wgrad_tile(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
-                 float *__restrict__ ws, float *__restrict__ wsb, int64_t row_stride, int tiles_per_split,
-                 const UpIn up) {
-    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / (32 * CB)) * KS, PP = BM + 8;
-    static_assert(HH <= 10 && TW <= 16, "transposed halo copies hold up to 10 rows of 16");
-    static_assert(BCO % (32 * CB) == 0 && NT >= BCO, "wave groups must divide the block; one thread per bias sum");
-    __shared__ __align__(16) unsigned short dyT[BCO * PP];
-    __shared__ __align__(16) unsigned short xT[KS * 32 * XTS];
-    __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    k_wgrad_tr(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
+               float *__restrict__ ws, float *__restrict__ wsb, int64_t row_stride, int tiles_per_split, const UpIn up) {
+    constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, NT = 64 * (BCO / (32 * CB)) * KS, NW = NT / 64;
+    constexpr int DCH = BCO / 8, XCH = 4;                        // 16-byte chunks per LDS row
+    constexpr int DN = BM * DCH, XN = HH * HWD * XCH, XS = (XN + 63) / 64 * 64;
+    static_assert(DN % 64 == 0 && BCO % (32 * CB) == 0, "whole waves of slots, wave groups divide the block");
+    static_assert(TW % 8 == 0, "8 consecutive pixels of an operand lie in one tile row");
+    __shared__ __align__(16) unsigned short lds[(DN + XS) * 8];
+    unsigned short *dyN = lds, *xN = lds + DN * 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int ch = wave / KS, trow = wave % KS;
     const int co0 = blockIdx.x * BCO, ci0 = blockIdx.y * 32, split = blockIdx.z;
     const int r = KS >> 1, taps = KS * KS;
     const int tiles_x = d.w / TW, tiles_img = tiles_x * (d.h / TH);
     const int n_tiles = d.n * tiles_img;
     const int ta = split * tiles_per_split, tb = min(n_tiles, ta + tiles_per_split);
-    const int row = lane & 31, kh = (lane >> 5) * 8;
-    f32x16 acc[CB][KS];
+    const int kh = (lane >> 5) * 8, cl = (lane & 16);  // this lane's first pixel and 16-channel half of its block
+    f32x16 acc[CB][KS], accb[CB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
+    for (int cb = 0; cb < CB; ++cb) {
+        accb[cb] = f32x16{};
 #pragma unroll
         for (int s = 0; s < KS; ++s) acc[cb][s] = f32x16{};
-    // bias gradient: the first input-channel block's workgroups also sum dy over their pixels
-    const bool bias_sum = wsb && blockIdx.y == 0 && (int)threadIdx.x < BCO;
-    float bsum = 0.0f;
-    // This thread's pieces of a tile: 8 pixels x 8 channels of the output
-    // gradient (8 16-byte loads, transposed on the way to dyT) and 16-byte
-    // pieces of the input halo.  The next tile's pieces are loaded into
-    // registers while the current tile is multiplied.
-    constexpr int DN = (BM / 8) * (BCO / 8), DI = (DN + NT - 1) / NT;
-    constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT;
-    u4 dr[DI][8], xr[XR];
-    auto fetch = [&](int tile) __attribute__((always_inline)) {
+    }
+    // the bias gradient: waves of tap row 0 in the first input-channel block's workgroups
+    const bool bias_sum = wsb && blockIdx.y == 0 && trow == 0;
+    typedef short v8i16 __attribute__((ext_vector_type(8)));
+    const v8i16 ones8 = {0x3f80, 0x3f80, 0x3f80, 0x3f80, 0x3f80, 0x3f80, 0x3f80, 0x3f80};  // bf16 1.0
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, ones8);
+    constexpr int DI = (DN / 64 + NW - 1) / NW, XI = (XS / 64 + NW - 1) / NW;
+    for (int tile = ta; tile < tb; ++tile) {
         const int n = tile / tiles_img, rem = tile % tiles_img;
         const int y0 = (rem / tiles_x) * TH, x0 = (rem % tiles_x) * TW;
-        // halo pieces without a branch (threads past the last piece repeat it):
-        // a load under a branch waits for every load before it
-#pragma unroll
-        for (int j = 0; j < XR; ++j) {
-            const int it = min((int)threadIdx.x + j * NT, XN - 1);
-            const int hp = it >> 2, q = it & 3;
-            const int hy = hp / HWD, hx = hp - hy * HWD;
-            int gy = y0 + hy - 1, gx = x0 + hx - 1;
-            gy += gy < 0 ? d.h : 0;
-            gy -= gy >= d.h ? d.h : 0;
-            gx += gx < 0 ? d.w : 0;
-            gx -= gx >= d.w ? d.w : 0;
-            if (ci0 < up.split) {
-                const int64_t gl = ((int64_t)n * (d.h / 2) + gy / 2) * (d.w / 2) + gx / 2;
-                xr[j] = *(const u4 *)(up.lo + gl * up.stride + ci0 + 8 * q);
-            } else {
-                const int64_t gp = ((int64_t)n * d.h + gy) * d.w + gx;
-                xr[j] = *(const u4 *)(x + gp * d.x_stride + d.x_offset + ci0 + 8 * q);
-            }
-        }
-        // output-gradient blocks: whole waves have none when DN < NT
-#pragma unroll
-        for (int i = 0; i < DI; ++i) {
-            const int it = (int)threadIdx.x + i * NT;
-            if (it < DN) {
-                const int g = it % (BM / 8), c8 = it / (BM / 8);
-                const int p0 = g * 8, ty = p0 / TW, tx = p0 % TW;
-                const int64_t gp = ((int64_t)n * d.h + y0 + ty) * d.w + x0 + tx;
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    dr[i][j] = *(const u4 *)(dy + (gp + j) * d.y_stride + d.y_offset + co0 + 8 * c8);
-            }
-        }
-    };
-    if (ta < tb) fetch(ta);
-    for (int tile = ta; tile < tb; ++tile) {
         __syncthreads();  // the previous tile's products are done with the LDS
-        // output gradient transposed into dyT ([channel][pixel]); input halo pixel-major into xs
 #pragma unroll
         for (int i = 0; i < DI; ++i) {
-            const int it = (int)threadIdx.x + i * NT;
-            if (it < DN) {
-                const int g = it % (BM / 8), c8 = it / (BM / 8);
-                u4 out[8];
-                transpose8x8(dr[i], out);
-#pragma unroll
-                for (int c = 0; c < 8; ++c) *(u4 *)&dyT[(c8 * 8 + c) * PP + g * 8] = out[c];
+            const int base = (i * NW + wave) * 64;
+            if (base < DN) {
+                const int slot = base + lane, p = slot / DCH, c = (slot % DCH) ^ (p % DCH);
+                const int64_t gp = ((int64_t)n * d.h + y0 + p / TW) * d.w + x0 + p % TW;
+                __builtin_amdgcn_global_load_lds((const void *)(dy + gp * d.y_stride + d.y_offset + co0 + 8 * c),
+                                                 (__attribute__((address_space(3))) void *)(dyN + base * 8), 16, 0, 0);
             }
         }
 #pragma unroll
-        for (int j = 0; j < XR; ++j) {
-            const int it = min((int)threadIdx.x + j * NT, XN - 1);
-            *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
-        }
-        __syncthreads();
-        if (tile + 1 < tb) fetch(tile + 1);
-        if (bias_sum) {
-#pragma unroll
-            for (int p8 = 0; p8 < BM; p8 += 8) {
-                const u4 v = *(const u4 *)&dyT[threadIdx.x * PP + p8];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) bsum += bf2f((unsigned short)(v[k] & 0xffffu)) + bf2f((unsigned short)(v[k] >> 16));
+        for (int i = 0; i < XI; ++i) {
+            const int base = (i * NW + wave) * 64;
+            if (base < XS) {
+                const int slot = min(base + lane, XN - 1);  // slots past the halo repeat its last piece
+                const int hp = slot / XCH, c = (slot % XCH) ^ (hp % XCH);
+                const int hy = hp / HWD, hx = hp - hy * HWD;
+                int gy = y0 + hy - 1, gx = x0 + hx - 1;
+                gy += gy < 0 ? d.h : 0;
+                gy -= gy >= d.h ? d.h : 0;
+                gx += gx < 0 ? d.w : 0;
+                gx -= gx >= d.w ? d.w : 0;
+                const unsigned short *src;
+                if (ci0 < up.split)
+                    src = up.lo + (((int64_t)n * (d.h / 2) + gy / 2) * (d.w / 2) + gx / 2) * up.stride + ci0 + 8 * c;
+                else
+                    src = x + (((int64_t)n * d.h + gy) * d.w + gx) * d.x_stride + d.x_offset + ci0 + 8 * c;
+                __builtin_amdgcn_global_load_lds((const void *)src,
+                                                 (__attribute__((address_space(3))) void *)(xN + base * 8), 16, 0, 0);
             }
         }
-        // transposed copies: copy s holds halo columns (s + c), c < TW (KS = 1: the centre column c + 1)
-        for (int it = threadIdx.x; it < KS * 4 * HH * (TW / 8); it += NT) {
-            const int cg = it % (TW / 8), rest = it / (TW / 8);
-            const int hy = rest % HH, rest2 = rest / HH;
-            const int c8 = rest2 % 4, s = rest2 / 4;
-            const int hx0 = cg * 8 + (KS == 1 ? 1 : s);
-            u4 in[8], out[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) in[j] = *(const u4 *)&xs[(hy * HWD + hx0 + j) * XP + 8 * c8];
-            transpose8x8(in, out);
-#pragma unroll
-            for (int c = 0; c < 8; ++c) *(u4 *)&xT[(s * 32 + c8 * 8 + c) * XTS + hy * 16 + cg * 8] = out[c];
-        }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         const int oy = trow - r;
 #pragma unroll
         for (int kb = 0; kb < BM / 16; ++kb) {
-            const int p0 = kb * 16 + kh;
-            const int ty = p0 / TW, tx = p0 % TW;
+            const int p0 = kb * 16 + kh, ty = p0 / TW, tx = p0 % TW;
             bf16x8 a[CB];
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) a[cb] = load_bf8(&dyT[((ch * CB + cb) * 32 + row) * PP + p0]);
+            for (int cb = 0; cb < CB; ++cb) a[cb] = tr_operand<DCH>(dyN, p0, (ch * CB + cb) * 32 + cl, lane);
+            if (bias_sum) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) accb[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], ones, accb[cb], 0, 0, 0);
+            }
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
-                const bf16x8 b = load_bf8(&xT[(s * 32 + row) * XTS + (ty + 1 + oy) * 16 + tx]);
+                const int hx = tx + s + 1 - r;  // halo column of the tap's first pixel
+                const bf16x8 b = tr_operand<XCH>(xN, (ty + 1 + oy) * HWD + hx, cl, lane);
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb)
                     acc[cb][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], b, acc[cb][s], 0, 0, 0);
             }
         }
     }
-    if (bias_sum) wsb[split * row_stride + co0 + threadIdx.x] = bsum;
-    const int ci = ci0 + row;
+    // bias: column 0 of the product with ones holds every row's sum (lanes 0 and 32)
+    if (bias_sum && (lane & 31) == 0) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                wsb[split * row_stride + co0 + (ch * CB + cb) * 32 + (q / 4) * 8 + (lane >> 5) * 4 + (q % 4)] = accb[cb][q];
+    }
+    const int ci = ci0 + (lane & 31);
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
 #pragma unroll
@@ -1224,17 +1199,16 @@ int wgrad_launch(const mlbm_conv_desc &d, const void *x, const void *dy, float *
     const int64_t row = m + d.c_out;
     float *wsb = db ? ws + m : nullptr;
 #define MLBM_WG(TH, TW, BCO, KS, CB)                                                                              \
-    hipLaunchKernelGGL((k_wgrad_tile<TH, TW, BCO, KS, CB>), dim3(d.c_out / BCO, d.c_in / 32, sp),                 \
+    hipLaunchKernelGGL((k_wgrad_tr<TH, TW, BCO, KS, CB>), dim3(d.c_out / BCO, d.c_in / 32, sp),                   \
                        dim3(64 * (BCO / (32 * CB)) * KS), 0, s, d, xx, yy, ws, wsb, row, per, up)
     if (d.ksize == 3) {
         if (narrow) {
             if (wide) MLBM_WG(8, 8, 64, 3, 1);
             else MLBM_WG(8, 8, 32, 3, 1);
         } else {
-            // 128 output channels per workgroup, one 32-channel block per wave (12
-            // waves); 64 channels with two blocks per wave
+            // 128 (or 64) output channels per workgroup, one 32-channel block per wave
             if (d.c_out % 128 == 0) MLBM_WG(8, 16, 128, 3, 1);
-            else if (wide) MLBM_WG(8, 16, 64, 3, 2);
+            else if (wide) MLBM_WG(8, 16, 64, 3, 1);
             else MLBM_WG(8, 16, 32, 3, 1);
         }
     } else {
