@@ -508,13 +508,17 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
 // and lane 4 q + h gets pixels P .. P + 3 of channel C + 4 q + h; two such
 // reads give the 8 pixels of an operand.  The tap column is a pixel offset
 // into the natural halo, so no shifted copies are needed.  16-byte chunks of
-// an LDS row (one pixel) are permuted as c -> c ^ (pixel % chunks) to spread
-// the banks.  The bias gradient comes from the same operand fragments,
+// an LDS row (one pixel p) are permuted as c -> c ^ s(p), s(p) = p % chunks for
+// rows of 4 chunks and 2 p % chunks for wider rows, so the 4 pixels x 2 chunks
+// of one 16-lane transposing read fall on distinct banks.  The bias gradient
+// comes from the same operand fragments,
 // multiplied by a column of ones.
 typedef short v4i16 __attribute__((ext_vector_type(4)));
 
 template <int NCH>
-__device__ __forceinline__ int tr_pos(int row, int c) { return (row * NCH + (c ^ (row % NCH))) * 8; }
+__device__ __forceinline__ int tr_swz(int row) { return (NCH >= 8 ? 2 * row : row) % NCH; }
+template <int NCH>
+__device__ __forceinline__ int tr_pos(int row, int c) { return (row * NCH + (c ^ tr_swz<NCH>(row))) * 8; }
 
 // bf16x8 operand: pixels rbase + 0..7 (rows of an LDS buffer of NCH 16-byte
 // chunks per row), channel block cb (16 lanes: channels cb .. cb + 15)
@@ -569,7 +573,7 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
         for (int i = 0; i < DI; ++i) {
             const int base = (i * NW + wave) * 64;
             if (base < DN) {
-                const int slot = base + lane, p = slot / DCH, c = (slot % DCH) ^ (p % DCH);
+                const int slot = base + lane, p = slot / DCH, c = (slot % DCH) ^ tr_swz<DCH>(p);
                 const int64_t gp = ((int64_t)n * d.h + y0 + p / TW) * d.w + x0 + p % TW;
                 __builtin_amdgcn_global_load_lds((const void *)(dy + gp * d.y_stride + d.y_offset + co0 + 8 * c),
                                                  (__attribute__((address_space(3))) void *)(dyN + base * 8), 16, 0, 0);
@@ -580,7 +584,7 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
             const int base = (i * NW + wave) * 64;
             if (base < XS) {
                 const int slot = min(base + lane, XN - 1);  // slots past the halo repeat its last piece
-                const int hp = slot / XCH, c = (slot % XCH) ^ (hp % XCH);
+                const int hp = slot / XCH, c = (slot % XCH) ^ tr_swz<XCH>(hp);
                 const int hy = hp / HWD, hx = hp - hy * HWD;
                 int gy = y0 + hy - 1, gx = x0 + hx - 1;
                 gy += gy < 0 ? d.h : 0;
