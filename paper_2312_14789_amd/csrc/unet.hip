@@ -52,8 +52,8 @@ __device__ __forceinline__ bf16x8 load_bf8(const unsigned short *p) {
 // periodic) and the slice of the weights for every tap are staged in LDS with
 // 16-byte copies, so each staged input value feeds all taps and every MFMA
 // operand is one 16-byte LDS read; the next slice's pieces are loaded into
-// registers while the current slice is multiplied.  Row pitches of 40 halves (80 B) keep the
-// 16 lanes of each LDS read on distinct banks.  k_conv_tile serves images 8
+// registers while the current slice is multiplied.  LDS rows are padded to 40
+// halves (80 B) to spread consecutive rows over the banks.  k_conv_tile serves images 8
 // pixels wide; 16-wide tiles with more than one input slice go to k_conv_dma
 // (the same product, staged by direct global-to-LDS loads), and single-slice
 // layers to k_conv_tile_s1.
