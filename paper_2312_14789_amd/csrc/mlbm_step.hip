@@ -927,7 +927,7 @@ void graph_cache_put(const GraphKey &k, hipGraphExec_t exec) {
         slot = 0;
         for (int i = 1; i < kGraphCacheSize; ++i)
             if (g_graphs[i].used < g_graphs[slot].used) slot = i;
-        hipGraphExecDestroy(g_graphs[slot].exec);
+        (void)hipGraphExecDestroy(g_graphs[slot].exec);  // eviction: a failure here changes nothing for the caller
     } else {
         ++g_graph_count;
     }
@@ -1132,12 +1132,12 @@ extern "C" int mlbm_step(const mlbm_step_params *p, mlbm_device_state *st, int32
             st->cur = cur0;
             st->step_count = count0;
             if (rcc) {
-                if (graph) hipGraphDestroy(graph);
+                if (graph) (void)hipGraphDestroy(graph);  // the launch error is the one reported
                 return rcc;
             }
             if (ec != hipSuccess || !graph) return fail(MLBM_ERR_HIP, "mlbm_step: hipStreamEndCapture: %s", hipGetErrorString(ec));
             const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);  // the executable graph does not need it
             if (ei != hipSuccess) return fail(MLBM_ERR_HIP, "mlbm_step: hipGraphInstantiate: %s", hipGetErrorString(ei));
             graph_cache_put(key, exec);
         }
