@@ -295,10 +295,17 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, PM, PN>()))
 // The forward product of k_conv_tile with each slice staged by direct global
 // to LDS loads (16 bytes per lane, written at consecutive LDS slots of the
 // issuing wave): no staging registers and no LDS stores, so more waves fit.
-// Rows are 64 bytes (one pixel's or one output channel's 32 halves) with the
-// four 16-byte chunks of row r permuted as c -> c ^ ((r >> 2) & 3); a lane
-// loads the global chunk that belongs at its slot.
+// Rows are 64 bytes (one pixel's or one output channel's 32 halves), and a
+// lane loads the global chunk that belongs at its slot.  A 16-byte LDS read
+// serves 16 lanes per cycle from 64 four-byte banks, the lanes grouped by bit
+// 5 of the lane index and the parity of bits 2 - 4; the chunk permutations
+// below give every such group 16 distinct bank quads.  Weight row r (32
+// consecutive rows per wave) holds chunk c at c ^ ((r >> 2) & 3); halo pixel
+// hp in halo row hy holds it at c ^ ((hy + 2 (hp >> 2)) & 3), which keeps the
+// operand reads of every tap free of conflicts for 16-pixel-wide tiles
+// (18-pixel halo rows).
 __device__ __forceinline__ int dma_pos(int r, int c) { return r * KC + 8 * (c ^ ((r >> 2) & 3)); }
+__device__ __forceinline__ int halo_pos(int hp, int hy, int c) { return hp * KC + 8 * (c ^ ((hy + 2 * (hp >> 2)) & 3)); }
 
 template <int TH, int TW, int BN, int KS>
 __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
@@ -321,7 +328,7 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
     const int co0 = blockIdx.y * BN;
     const int row = lane & 31, kc = lane >> 5;
     const int pb = wp * 32 + row;
-    const int arow = (pb / TW + 1) * HWD + (pb % TW + 1), brow = wc * 32 + row;
+    const int ay = pb / TW + 1, arow = ay * HWD + (pb % TW + 1), brow = wc * 32 + row;
     // this lane's global offsets (without the slice's first channel) for each of
     // its wave's halo and weight instructions
     constexpr int XI = (XS / 64 + NW - 1) / NW, WI = (WN / 64 + NW - 1) / NW;
@@ -329,8 +336,8 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
 #pragma unroll
     for (int i = 0; i < XI; ++i) {
         const int slot = min((i * NW + wave) * 64 + lane, XN - 1);  // slots past the halo repeat its last piece
-        const int hp = slot >> 2, c = (slot & 3) ^ ((hp >> 2) & 3);
-        const int hy = hp / HWD, hx = hp - hy * HWD;
+        const int hp = slot >> 2, hy = hp / HWD, hx = hp - hy * HWD;
+        const int c = (slot & 3) ^ ((hy + 2 * (hp >> 2)) & 3);
         int gy = y0 + hy - 1, gx = x0 + hx - 1;
         gy += gy < 0 ? d.h : 0;
         gy -= gy >= d.h ? d.h : 0;
@@ -371,10 +378,10 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
         // the next tap's operands are read while the current tap is multiplied
         bf16x8 ca[2], cb[2], na[2], nb[2];
         auto operands = [&](int t, bf16x8 *a, bf16x8 *b) __attribute__((always_inline)) {
-            const int trow = arow + (t / KS - r) * HWD + (t % KS - r), wrow = t * BN + brow;
+            const int ty = ay + t / KS - r, trow = arow + (t / KS - r) * HWD + (t % KS - r), wrow = t * BN + brow;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                a[h] = load_bf8(&xs[dma_pos(trow, kc + 2 * h)]);
+                a[h] = load_bf8(&xs[halo_pos(trow, ty, kc + 2 * h)]);
                 b[h] = load_bf8(&wsm[dma_pos(wrow, kc + 2 * h)]);
             }
         };
@@ -507,16 +514,18 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
 // lane 4 j + q of a group reads pixel P + j, channels C + 4 q .. C + 4 q + 3,
 // and lane 4 q + h gets pixels P .. P + 3 of channel C + 4 q + h; two such
 // reads give the 8 pixels of an operand.  The tap column is a pixel offset
-// into the natural halo, so no shifted copies are needed.  16-byte chunks of
-// an LDS row (one pixel p) are permuted as c -> c ^ s(p), s(p) = p % chunks for
-// rows of 4 chunks and 2 p % chunks for wider rows, so the 4 pixels x 2 chunks
-// of one 16-lane transposing read fall on distinct banks.  The bias gradient
+// into the natural halo, so no shifted copies are needed.  A transposing read
+// serves 32 consecutive lanes per cycle from 64 four-byte banks: 4 pixels x 4
+// chunks x 2 eight-byte halves.  16-byte chunks of an LDS row (one pixel p)
+// are permuted as c -> c ^ s(p), s(p) = p % 4 for rows of 4 chunks, 2 p % 8
+// for rows of 8 and 4 (p % 4) for rows of 16, so those 32 words fall on
+// distinct banks.  The bias gradient
 // comes from the same operand fragments,
 // multiplied by a column of ones.
 typedef short v4i16 __attribute__((ext_vector_type(4)));
 
 template <int NCH>
-__device__ __forceinline__ int tr_swz(int row) { return (NCH >= 8 ? 2 * row : row) % NCH; }
+__device__ __forceinline__ int tr_swz(int row) { return NCH >= 16 ? 4 * (row & 3) : (NCH >= 8 ? 2 * row : row) % NCH; }
 template <int NCH>
 __device__ __forceinline__ int tr_pos(int row, int c) { return (row * NCH + (c ^ tr_swz<NCH>(row))) * 8; }
 
