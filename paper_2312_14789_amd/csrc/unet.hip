@@ -418,7 +418,12 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
                    const UpGrad ug) {
     constexpr int BM = TH * TW, HH = TH + 2, HWD = TW + 2, WPX = BM / 32, NT = 64 * WPX * (BN / 32);
     constexpr int XN = HH * HWD * 4, XR = (XN + NT - 1) / NT;
-    __shared__ __align__(16) unsigned short xs[HH * HWD * XP];
+    // halo rows of HWD pixels at an 80-byte pitch, each padded by 48 halves:
+    // with the 16-lane groups of a 16-byte LDS read (lanes of equal bit 5 and
+    // equal parity of bits 2 - 4) no operand read of any tap meets a bank
+    // conflict for 16-pixel-wide tiles, and the tap offsets stay constants
+    constexpr int XRS = HWD * XP + 48;
+    __shared__ __align__(16) unsigned short xs[HH * XRS];
     __shared__ __align__(16) unsigned short wsm[KS * KS * BN * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wp = wave % WPX, wc = wave / WPX;
@@ -428,7 +433,7 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     constexpr int ks = KS, r = KS >> 1, taps = KS * KS;
     const int row = lane & 31, kh = (lane >> 5) * 8;
     const int pb = wp * 32 + row;
-    const int aoff = ((pb / TW + 1) * HWD + (pb % TW + 1)) * XP + kh;
+    const int aoff = (pb / TW + 1) * XRS + (pb % TW + 1) * XP + kh;
     const int boff = (wc * 32 + row) * XP + kh;
     {
         // every piece loaded before any is stored, so the loads overlap; threads
@@ -475,14 +480,15 @@ __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
 #pragma unroll
         for (int j = 0; j < XR; ++j) {
             const int it = min((int)threadIdx.x + j * NT, XN - 1);
-            *(u4 *)&xs[(it >> 2) * XP + 8 * (it & 3)] = xr[j];
+            const int hp = it >> 2, hy = hp / HWD;
+            *(u4 *)&xs[hy * XRS + (hp - hy * HWD) * XP + 8 * (it & 3)] = xr[j];
         }
         __syncthreads();
         if (tile + 1 < tb) fetch(tile + 1);
         f32x16 acc = {};
 #pragma unroll
         for (int t = 0; t < taps; ++t) {
-            const int toff = ((t / ks - r) * HWD + (t % ks - r)) * XP;
+            const int toff = (t / ks - r) * XRS + (t % ks - r) * XP;
             const unsigned short *wt = &wsm[t * BN * XP];
 #pragma unroll
             for (int kk = 0; kk < KC; kk += 16)
