@@ -409,7 +409,8 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
 // Layers with a single 32-channel input slice (c_in = 32): the weights of
 // every tap are staged once per workgroup and serve TPW consecutive pixel
 // tiles; each tile's input halo is loaded into registers while the previous
-// tile is multiplied.  Same tiles, operand layout and epilogue as k_conv_tile.
+// tile is multiplied.  Same tiles, operand layout and epilogue as k_conv_tile;
+// only the halo rows are padded (below).
 template <int TH, int TW, int BN, int KS, int TPW, bool GATE>
 __global__ void __launch_bounds__(64 * (TH * TW / 32) * (BN / 32))
     k_conv_tile_s1(const mlbm_conv_desc d, const unsigned short *__restrict__ x, const unsigned short *__restrict__ w,
