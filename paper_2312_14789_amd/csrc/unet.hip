@@ -375,30 +375,26 @@ __global__ void __launch_bounds__((conv_threads<TH, TW, BN, 1, 1>()))
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        // the next tap's operands are read while the current tap is multiplied
-        bf16x8 ca[2], cb[2], na[2], nb[2];
-        auto operands = [&](int t, bf16x8 *a, bf16x8 *b) __attribute__((always_inline)) {
+        // product k (tap k / 2, 16-channel half k % 2) is multiplied while the
+        // operands of product k + 1 are read; the scheduling barriers keep those
+        // reads ahead of the product (left alone, the compiler moves every read to
+        // just before its own product and waits for it there)
+        bf16x8 ca, cb, na, nb;
+        auto operands = [&](int k, bf16x8 &a, bf16x8 &b) __attribute__((always_inline)) {
+            const int t = k >> 1, h = k & 1;
             const int ty = ay + t / KS - r, trow = arow + (t / KS - r) * HWD + (t % KS - r), wrow = t * BN + brow;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                a[h] = load_bf8(&xs[halo_pos(trow, ty, kc + 2 * h)]);
-                b[h] = load_bf8(&wsm[dma_pos(wrow, kc + 2 * h)]);
-            }
+            a = load_bf8(&xs[halo_pos(trow, ty, kc + 2 * h)]);
+            b = load_bf8(&wsm[dma_pos(wrow, kc + 2 * h)]);
         };
         operands(0, ca, cb);
-        __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave the LDS reads with the products
 #pragma unroll
-        for (int t = 0; t < taps; ++t) {
-            if (t + 1 < taps) operands(t + 1, na, nb);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ca[h], cb[h], acc, 0, 0, 0);
-            if (t + 1 < taps) {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    ca[h] = na[h];
-                    cb[h] = nb[h];
-                }
-            }
+        for (int k = 0; k < 2 * taps; ++k) {
+            if (k + 1 < 2 * taps) operands(k + 1, na, nb);
+            __builtin_amdgcn_sched_barrier(0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ca, cb, acc, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            ca = na;
+            cb = nb;
         }
     }
     const int col = co0 + wc * 32 + row;
