@@ -615,23 +615,55 @@ __global__ void __launch_bounds__(64 * (BCO / (32 * CB)) * KS)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         const int oy = trow - r;
+        if constexpr (BCO == 32 && CB == 1 && TW == 16) {
+            // one output block per wave and registers to spare: each product's
+            // operands are read while the previous product runs (the scheduling
+            // barriers keep the compiler from moving the reads down to their use)
+            auto opa = [&](int kb) __attribute__((always_inline)) {
+                return tr_operand<DCH>(dyN, kb * 16 + kh, ch * 32 + cl, lane);
+            };
+            auto opb = [&](int kb, int s) __attribute__((always_inline)) {
+                const int p0 = kb * 16 + kh;
+                return tr_operand<XCH>(xN, (p0 / TW + 1 + oy) * HWD + p0 % TW + s + 1 - r, cl, lane);
+            };
+            bf16x8 a0 = opa(0), b0 = opb(0, 0), a1 = a0, b1 = b0;
 #pragma unroll
-        for (int kb = 0; kb < BM / 16; ++kb) {
-            const int p0 = kb * 16 + kh, ty = p0 / TW, tx = p0 % TW;
-            bf16x8 a[CB];
+            for (int kb = 0; kb < BM / 16; ++kb) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) a[cb] = tr_operand<DCH>(dyN, p0, (ch * CB + cb) * 32 + cl, lane);
-            if (bias_sum) {
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) accb[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], ones, accb[cb], 0, 0, 0);
+                for (int s = 0; s < KS; ++s) {
+                    if (s + 1 < KS) b1 = opb(kb, s + 1);
+                    else if (kb + 1 < BM / 16) {
+                        a1 = opa(kb + 1);
+                        b1 = opb(kb + 1, 0);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (s == 0 && bias_sum) accb[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, ones, accb[0], 0, 0, 0);
+                    acc[0][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][s], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    b0 = b1;
+                    if (s + 1 == KS) a0 = a1;
+                }
             }
+        } else {
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const int hx = tx + s + 1 - r;  // halo column of the tap's first pixel
-                const bf16x8 b = tr_operand<XCH>(xN, (ty + 1 + oy) * HWD + hx, cl, lane);
+            for (int kb = 0; kb < BM / 16; ++kb) {
+                const int p0 = kb * 16 + kh, ty = p0 / TW, tx = p0 % TW;
+                bf16x8 a[CB];
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-                    acc[cb][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], b, acc[cb][s], 0, 0, 0);
+                for (int cb = 0; cb < CB; ++cb) a[cb] = tr_operand<DCH>(dyN, p0, (ch * CB + cb) * 32 + cl, lane);
+                if (bias_sum) {
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        accb[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], ones, accb[cb], 0, 0, 0);
+                }
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const int hx = tx + s + 1 - r;  // halo column of the tap's first pixel
+                    const bf16x8 b = tr_operand<XCH>(xN, (ty + 1 + oy) * HWD + hx, cl, lane);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[cb][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], b, acc[cb][s], 0, 0, 0);
+                }
             }
         }
     }
