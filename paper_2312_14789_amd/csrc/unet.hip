@@ -995,7 +995,7 @@ __global__ void __launch_bounds__(256) k_mse(int64_t P, int C, const float *pred
     s1[threadIdx.x] = e;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
+        if ((int)threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = s1[0];
@@ -1057,7 +1057,7 @@ __global__ void __launch_bounds__(256) k_mse_dev(int64_t P, int C, const float *
     s1[threadIdx.x] = e;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
+        if ((int)threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = s1[0];
@@ -1070,7 +1070,7 @@ __global__ void __launch_bounds__(256) k_mask_partial(int64_t P, const float *ma
     s1[threadIdx.x] = p < P ? (double)mask[p] : 0.0;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
+        if ((int)threadIdx.x < o) s1[threadIdx.x] += s1[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = s1[0];
